@@ -1,0 +1,517 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints (tests/golden/paper_constants.txt), closed-form solutions,
+invariants, library routines (scipy spherical harmonics, Legendre and
+Gegenbauer polynomials, dense eigen-decompositions) or brute force on tiny
+grids.  None of these tests needs a GPU.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.special as sps
+
+import oracle
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.txt")
+
+
+def golden():
+    out = {}
+    for line in open(GOLD):
+        if line.startswith("#") or not line.strip():
+            continue
+        name, val = line.split()[:2]
+        out[name] = float(val)
+    return out
+
+
+def grid(nt, np_):
+    th = (np.arange(nt) + 0.5) * np.pi / nt
+    ph = (np.arange(np_) + 0.5) * 2 * np.pi / np_
+    return np.meshgrid(th, ph, indexing="ij")
+
+
+def weights(nt, np_):
+    th = (np.arange(nt) + 0.5) * np.pi / nt
+    return np.sin(th) * (np.pi / nt) * (2 * np.pi / np_)
+
+
+def dense(op, nt, np_):
+    """Dense matrix of a linear grid operator by applying it to unit vectors."""
+    n = nt * np_
+    M = np.empty((n, n))
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        M[:, i] = op(e.reshape(nt, np_)).ravel()
+    return M
+
+
+# ------------------------------------------------------------------ units
+def test_units_match_paper():
+    g = golden()
+    ms, k2 = oracle.units()
+    assert ms == pytest.approx(g["m_s_to_rs_hr"], rel=1e-15)
+    assert k2 == pytest.approx(g["km2_s_to_rs2_hr"], rel=1e-14)
+
+
+def test_rigid_rotation_period_from_flow_form():
+    """eq. dr with d0 = 1807.66 m/s and d2 = d4 = 0 turns once in 672 h."""
+    g = golden()
+    nt = 16
+    vph, vth = oracle.flows(nt, (g["rigid_rotation_km_s"] * 1000.0, 0, 0, 0, 0, 0))
+    th = (np.arange(nt) + 0.5) * np.pi / nt
+    omega = vph / np.sin(th)          # rad/h on the unit sphere
+    assert np.allclose(omega, omega[0], rtol=1e-14)
+    assert 2 * np.pi / omega[0] == pytest.approx(g["rigid_rotation_period_h"], rel=1e-5)
+    assert np.all(vth == 0.0)
+
+
+def test_flow_shapes():
+    nt = 32
+    d = (46.0, -262.0, -379.0, 22.0, 11.0, -28.0)     # the paper's defaults
+    vph, vth = oracle.flows(nt, d)
+    ms, _ = oracle.units()
+    # DR symmetric about the equator, MF antisymmetric and zero at the poles
+    assert np.allclose(vph, vph[::-1], rtol=1e-13, atol=0)
+    assert np.allclose(vth, -vth[::-1], atol=1e-18)
+    assert vth[0] == 0.0 and vth[-1] == 0.0
+    # equator face: v_theta = 0, v_phi at the row nearest the equator ~ d0
+    assert abs(vth[nt // 2]) < 1e-20
+    # poleward flow for positive m1 (northern faces move towards theta = 0)
+    d1 = (0, 0, 0, 30.0, 0, 0)
+    _, v1 = oracle.flows(nt, d1)
+    assert np.all(v1[1:nt // 2] < 0) and np.all(v1[nt // 2 + 1:-1] > 0)
+    # the m1 term alone peaks at 45 degrees with amplitude m1/2 (sin 2 lambda form)
+    f = np.arange(nt + 1) * np.pi / nt
+    assert np.allclose(v1, -30.0 * ms * np.cos(f) * np.sin(f) * (f > 0) * (f < np.pi), atol=1e-18)
+
+
+def test_cfl_limits_rigid_rotation():
+    nt, np_ = 24, 48
+    omega = 2 * np.pi / 672.0
+    th = (np.arange(nt) + 0.5) * np.pi / nt
+    vph = omega * np.sin(th)
+    vth = np.zeros(nt + 1)
+    dph = 2 * np.pi / np_
+    lim = oracle.cfl_dt(nt, np_, vph, vth, oracle.SSPRK43)
+    assert lim == pytest.approx(dph / omega, rel=1e-13)
+    assert oracle.cfl_dt(nt, np_, vph, vth, oracle.FE) == pytest.approx(0.5 * dph / omega, rel=1e-13)
+    assert oracle.cfl_dt(nt, np_, vph * 0, vth, oracle.SSPRK43) == math.inf
+
+
+# --------------------------------------------------------------- WENO3
+@pytest.mark.parametrize("nonuniform", [False, True])
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_weno_exact_for_linear_data(nonuniform, sign):
+    """Both WENO3 candidate reconstructions are exact for linear data, on any
+    grid, whatever the nonlinear weights: the face value is the line through
+    the cell centres.  This pins the D-factor index reading of App. B."""
+    rng = np.random.default_rng(1)
+    n = 24
+    dx = 1.0 + 0.4 * rng.random(n) if nonuniform else np.ones(n)
+    dx *= 0.01
+    xf = np.concatenate([[0.0], np.cumsum(dx)])
+    xc = 0.5 * (xf[1:] + xf[:-1])
+    a, b = 0.7, 3.0
+    B = a + b * xc
+    v = np.full(n + 1, 0.3 * sign)
+    F = oracle.line_flux(B, dx, v, periodic=False)
+    exact = 0.3 * sign * (a + b * xf)
+    assert np.allclose(F[2:n - 1], exact[2:n - 1], rtol=1e-13, atol=1e-15)
+    # pole-adjacent faces are upwind, pole faces carry nothing
+    up = 0.3 * sign * (B[0] if sign > 0 else B[1])
+    assert F[1] == pytest.approx(up, rel=1e-15)
+    assert F[0] == 0.0 and F[n] == 0.0
+
+
+def test_weno_linear_weights_when_smoothness_equal():
+    """With beta0 = beta1 on a uniform grid the nonlinear weights equal the
+    linear ones (1/3, 2/3) and the reconstruction is -1/6, 5/6, 1/3."""
+    n = 16
+    B = np.zeros(n)
+    B[7] = 1.0       # LM_{i-2}=0, LM_{i-1}=1, LM_i=0 at face 8 -> beta0 = beta1
+    dx = np.full(n, 0.05)
+    v = np.full(n + 1, 2.0)
+    F = oracle.line_flux(B, dx, v, periodic=True)
+    assert F[8] == pytest.approx(2.0 * 5.0 / 6.0, rel=1e-14)
+    # mirror: leftward flow reconstructs from the right
+    F2 = oracle.line_flux(B, dx, -v, periodic=True)
+    assert F2[7] == pytest.approx(-2.0 * 5.0 / 6.0, rel=1e-14)
+
+
+def test_weno_mirror_symmetry():
+    """Reversing a periodic line and the flow direction mirrors the fluxes."""
+    rng = np.random.default_rng(2)
+    n = 20
+    B = rng.standard_normal(n)
+    dx = np.full(n, 0.1)
+    v = np.full(n + 1, 0.8)
+    F = oracle.line_flux(B, dx, v, periodic=True)
+    Fr = oracle.line_flux(B[::-1].copy(), dx, -v, periodic=True)
+    assert np.allclose(Fr[::-1], -F, rtol=1e-13, atol=1e-15)
+
+
+# ------------------------------------------------------------ advection
+def test_advection_conserves_flux_and_constants():
+    nt, np_ = 20, 40
+    rng = np.random.default_rng(3)
+    B = rng.standard_normal((nt, np_))
+    vph, vth = oracle.flows(nt, (46.0, -262.0, -379.0, 22.0, 11.0, -28.0))
+    w = weights(nt, np_)
+    for scheme in (oracle.WENO3CSH, oracle.UPWIND):
+        A = oracle.adv_operator(B, vph, vth, scheme)
+        assert abs((A * w[:, None]).sum()) < 1e-14 * (np.abs(A) * w[:, None]).sum()
+    # differential rotation is divergence free: a constant stays constant
+    A = oracle.adv_operator(np.full((nt, np_), 3.0), vph, 0 * vth)
+    assert np.abs(A).max() < 1e-15
+
+
+def test_upwind_euler_courant_one_is_a_shift():
+    nt, np_ = 8, 32
+    omega = 2 * np.pi / 672.0
+    th = (np.arange(nt) + 0.5) * np.pi / nt
+    vph, vth = omega * np.sin(th), np.zeros(nt + 1)
+    dt = (2 * np.pi / np_) / omega
+    B = np.random.default_rng(4).standard_normal((nt, np_))
+    B1 = oracle.adv_step(B, vph, vth, dt, oracle.UPWIND, oracle.FE)
+    assert np.allclose(B1, np.roll(B, 1, axis=1), atol=1e-13)
+
+
+@pytest.mark.parametrize("time_scheme,coefs", [
+    (oracle.SSPRK43, [1, 1, 1 / 2, 1 / 6, 1 / 48]),
+    (oracle.SSPRK33, [1, 1, 1 / 2, 1 / 6]),
+    (oracle.FE, [1, 1]),
+])
+def test_ssprk_stability_polynomial(time_scheme, coefs):
+    """On a linear operator one step is P(-dt M) with the scheme's stability
+    polynomial: Taylor coefficients of exp up to third order, and z^4/48 for
+    SSPRK(4,3).  M is the dense upwind operator (with both flows)."""
+    nt, np_ = 6, 10
+    vph, vth = oracle.flows(nt, (800.0, -300.0, 0.0, 400.0, 0.0, 0.0))
+    M = dense(lambda x: oracle.adv_operator(x, vph, vth, oracle.UPWIND), nt, np_)
+    dt = 0.3 * oracle.cfl_dt(nt, np_, vph, vth)
+    Z = -dt * M
+    P = np.zeros_like(Z)
+    Zk = np.eye(Z.shape[0])
+    for c in coefs:
+        P += c * Zk
+        Zk = Zk @ Z
+    B = np.random.default_rng(5).standard_normal((nt, np_))
+    got = oracle.adv_step(B, vph, vth, dt, oracle.UPWIND, time_scheme)
+    assert np.allclose(got.ravel(), P @ B.ravel(), rtol=1e-12, atol=1e-13)
+
+
+def blob_field(th, ph, t, vth_c, om, sigma=0.03):
+    """Eq. testblob (App. C exact solution), with periodic phi distance."""
+    def d(a):
+        return (a + np.pi) % (2 * np.pi) - np.pi
+    g = th - np.pi / 4 - vth_c * t
+    e1 = np.exp(-g ** 2 / sigma - d(ph - np.pi / 2 - om * t) ** 2 / sigma)
+    e2 = np.exp(-g ** 2 / sigma - d(ph - 3 * np.pi / 2 - om * t) ** 2 / sigma)
+    return (-e1 + e2) / np.sin(th)
+
+
+def run_blob(nt, np_, vth_c, om, T, scheme=oracle.WENO3CSH, eps_mode=0.0):
+    TH, PH = grid(nt, np_)
+    B = blob_field(TH, PH, 0.0, vth_c, om)
+    th = (np.arange(nt) + 0.5) * np.pi / nt
+    vph = om * np.sin(th)
+    vth = np.full(nt + 1, vth_c)
+    vth[0] = vth[-1] = 0.0
+    cfl = 0.9 * oracle.cfl_dt(nt, np_, vph, vth)
+    nsteps = int(math.ceil(T / cfl))
+    dt = T / nsteps
+    for _ in range(nsteps):
+        B = oracle.adv_step(B, vph, vth, dt, scheme, oracle.SSPRK43, eps_mode)
+    return oracle.hh(B, blob_field(TH, PH, T, vth_c, om))
+
+
+def order(errs, ns):
+    return [math.log(errs[i] / errs[i + 1]) / math.log(ns[i + 1] / ns[i]) for i in range(len(ns) - 1)]
+
+
+def test_phi_rotation_convergence_orders():
+    """App. B: WENO3-CS(h) converges at third order on the phi-rotation
+    Gaussian test; WENO3 with a constant eps = 1e-12 loses that order and
+    upwinding is far less accurate (first order, pre-asymptotic here)."""
+    om = 2 * np.pi / 672.0
+    ns = [256, 512, 1024]
+    e_h = [run_blob(16, n, 0.0, om, 672.0) for n in ns]
+    e_e = [run_blob(16, n, 0.0, om, 672.0, eps_mode=1e-12) for n in ns]
+    e_u = [run_blob(16, n, 0.0, om, 672.0, oracle.UPWIND) for n in ns]
+    o_h, o_e, o_u = order(e_h, ns), order(e_e, ns), order(e_u, ns)
+    assert o_h[-1] > 2.7, (e_h, o_h)
+    assert 1.2 < o_e[-1] < 2.3, (e_e, o_e)
+    assert e_e[-1] > 5 * e_h[-1]
+    assert 0.3 < o_u[-1] < 1.2 and e_u[-1] > 50 * e_h[-1], (e_u, o_u)
+
+
+def test_theta_advection_exact_solution():
+    """App. C: (1/sin theta) B0(theta - v t) is exact for constant v_theta;
+    the pair moves from 45 degrees north to 45 degrees south in 672 h and
+    the error falls at high order."""
+    vt = (np.pi / 2) / 672.0
+    ns = [128, 256, 512]
+    e = [run_blob(n, 64, vt, 0.0, 672.0) for n in ns]
+    assert e[-1] < 1e-3
+    assert order(e, ns)[-1] > 2.7, e
+
+
+# ------------------------------------------------------------ diffusion
+def test_diffusion_matrix_symmetry_and_constants():
+    nt, np_ = 12, 24
+    nu = 3.7e-6
+    a_up, a_dn, a_ph, a_d = oracle.diff_coefs(nt, np_, nu)
+    w = weights(nt, np_)
+    # weighted symmetry w_j a_{j,j+1} = w_{j+1} a_{j+1,j}
+    assert np.allclose(w[:-1] * a_dn[:-1], w[1:] * a_up[1:], rtol=1e-14)
+    assert a_up[0] == 0.0 and a_dn[-1] == 0.0
+    L = oracle.diff_operator(np.full((nt, np_), 2.5), nu)
+    assert np.abs(L).max() < 1e-12 * np.abs(a_d).max()
+    # self-adjoint in the weighted inner product, negative semi-definite
+    M = dense(lambda x: oracle.diff_operator(x, nu), nt, np_)
+    W = np.repeat(w, np_)
+    S = np.sqrt(W)[:, None] * M / np.sqrt(W)[None, :]
+    assert np.allclose(S, S.T, rtol=1e-12, atol=1e-12 * np.abs(S).max())
+    ev = np.linalg.eigvalsh(0.5 * (S + S.T))
+    assert ev.max() < 1e-9 * abs(ev.min())
+    # Euler limit reading: dt_E * spectral radius <= 2 (forward Euler stable)
+    dtE = oracle.euler_limit(nt, np_, nu)
+    assert dtE == pytest.approx(1.0 / np.abs(a_d).max(), rel=1e-15)
+    assert dtE * abs(ev.min()) <= 2.0 + 1e-12
+
+
+def real_ylm(l, m, th, ph):
+    y = sps.sph_harm_y(l, abs(m), th, ph)
+    return y.real if m >= 0 else y.imag
+
+
+def soccer(th, ph):
+    return real_ylm(6, 0, th, ph) + math.sqrt(14.0 / 11.0) * real_ylm(6, 5, th, ph)
+
+
+@pytest.mark.parametrize("scheme", [oracle.RKG2, oracle.RKL2])
+def test_soccer_ball_decay_second_order(scheme):
+    """Eq. soccerball: exp(-42 nu t) decay of an l = 6 mode; the spatial error
+    falls as O(h^2)."""
+    _, k2 = oracle.units()
+    nu = 500.0 * k2
+    tau, ncall = 168.0, 80      # 20 rotations in short calls: time error small
+    errs = []
+    ns = [24, 48]
+    for nt in ns:
+        TH, PH = grid(nt, 2 * nt)
+        u0 = soccer(TH, PH)
+        u = u0
+        for _ in range(ncall):
+            u, st = oracle.diffuse(u, nu, tau, scheme)
+        exact = math.exp(-42.0 * nu * tau * ncall) * u0
+        errs.append(oracle.hh(u, exact))
+    assert math.exp(-42.0 * nu * tau * ncall) < 0.2
+    assert errs[-1] < 5e-2
+    assert order(errs, ns)[0] > 1.8, errs
+
+
+def test_y10_decay_and_flux_conservation():
+    _, k2 = oracle.units()
+    nu = 600.0 * k2
+    nt, np_ = 64, 128
+    TH, PH = grid(nt, np_)
+    u0 = np.cos(TH)
+    T = 5000.0
+    u, _ = oracle.diffuse(u0, nu, T)
+    ratio = (u * u0).sum() / (u0 * u0).sum()
+    assert ratio == pytest.approx(math.exp(-2.0 * nu * T), rel=2e-3)
+    w = weights(nt, np_)
+    v0 = (np.random.default_rng(6).standard_normal((nt, np_)))
+    v1, _ = oracle.diffuse(v0, nu, 3.0)
+    assert abs(((v1 - v0) * w[:, None]).sum()) < 1e-13 * (np.abs(v0) * w[:, None]).sum()
+
+
+def sts_poly(s, scheme):
+    """The STS stability polynomial from its defining conditions: R(z) = a +
+    b P_s(1 + w z) with R(0) = R'(0) = R''(0) = 1, P = Legendre (RKL2) or
+    Gegenbauer(3/2) (RKG2), evaluated with scipy's polynomial routines."""
+    if scheme == oracle.RKL2:
+        P = sps.legendre(s)
+    else:
+        P = sps.gegenbauer(s, 1.5)
+    p1, d1, d2 = P(1.0), P.deriv(1)(1.0), P.deriv(2)(1.0)
+    w = d1 / d2
+    b = 1.0 / (w * d1)
+    a = 1.0 - b * p1
+    return (lambda z: a + b * P(1.0 + w * z)), w
+
+
+@pytest.mark.parametrize("scheme", [oracle.RKG2, oracle.RKL2])
+@pytest.mark.parametrize("tau", [0.05, 0.7, 9.0])
+def test_sts_matches_stability_polynomial_brute_force(scheme, tau):
+    """One STS call equals R_s(tau M) Y0 for the dense operator M of a tiny
+    grid (eigen-decomposition), with s the fewest stages whose stability
+    interval [-2/w, 0] covers the Gershgorin bound."""
+    nt, np_ = 6, 12
+    _, k2 = oracle.units()
+    nu = 400.0 * k2 * 1e3
+    M = dense(lambda x: oracle.diff_operator(x, nu), nt, np_)
+    dtE = oracle.euler_limit(nt, np_, nu)
+    s = oracle.sts_stages(tau, dtE, scheme)
+    R, w = sts_poly(s, scheme)
+    lam_bound = 2.0 / dtE
+    assert 2.0 / w >= tau * lam_bound * (1 - 1e-12)
+    if s > 2:
+        _, w_prev = sts_poly(s - 1, scheme)
+        assert 2.0 / w_prev < tau * lam_bound
+    ev, V = sla.eig(M)
+    ev, V = ev.real, V.real
+    Y0 = np.random.default_rng(7).standard_normal(nt * np_)
+    exact = V @ (R(tau * ev) * np.linalg.solve(V, Y0))
+    got, st = oracle.diffuse(Y0.reshape(nt, np_), nu, tau, scheme)
+    assert st == s
+    assert np.allclose(got.ravel(), exact, rtol=1e-11, atol=1e-11 * np.abs(Y0).max())
+    assert np.all(np.abs(R(tau * ev)) <= 1 + 1e-12)
+
+
+def test_forward_euler_diffusion_reference():
+    nt, np_ = 6, 12
+    nu = 0.3
+    M = dense(lambda x: oracle.diff_operator(x, nu), nt, np_)
+    dtE = oracle.euler_limit(nt, np_, nu)
+    tau = 3.3 * dtE
+    n = math.ceil(tau / dtE)
+    Y0 = np.random.default_rng(8).standard_normal(nt * np_)
+    exact = np.linalg.matrix_power(np.eye(nt * np_) + (tau / n) * M, n) @ Y0
+    got, st = oracle.diffuse(Y0.reshape(nt, np_), nu, tau, oracle.DIFF_FE)
+    assert st == n
+    assert np.allclose(got.ravel(), exact, rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------------------------- assimilation
+def test_mu_disk_is_cosine_of_angle_to_disk_centre():
+    nt, np_ = 18, 36
+    b0, l0 = math.radians(7.0), math.radians(100.0)
+    TH, PH = grid(nt, np_)
+    cell = np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)], -1)
+    lat0 = b0
+    centre = np.array([math.cos(lat0) * math.cos(l0), math.cos(lat0) * math.sin(l0), math.sin(lat0)])
+    assert np.allclose(oracle.mu_disk(nt, np_, b0, l0), cell @ centre, atol=1e-15)
+
+
+def test_weight_function():
+    nt, np_ = 18, 36
+    mu = oracle.mu_disk(nt, np_, 0.0, math.pi)
+    F = oracle.weight_from_mu(mu, 4.0, 0.0, math.pi / 2)
+    assert np.allclose(F, np.where(mu > 0, mu ** 4, 0.0), rtol=1e-14)
+    TH, _ = grid(nt, np_)
+    lat = np.pi / 2 - TH
+    F2 = oracle.weight_from_mu(mu, 2.0, 0.3, math.radians(60))
+    ref = np.where((mu > 0.3) & (np.abs(lat) < math.radians(60)), mu ** 2, 0.0)
+    assert np.allclose(F2, ref, rtol=1e-13)
+
+
+def test_assimilation_limits_and_balance():
+    nt, np_ = 16, 32
+    rng = np.random.default_rng(9)
+    B = rng.standard_normal((nt, np_)) * 50
+    D = rng.standard_normal((nt, np_)) * 50 + 5.0
+    assert np.array_equal(oracle.assimilate(B, D, np.ones_like(B)), D)
+    assert np.array_equal(oracle.assimilate(B, D, np.zeros_like(B)), B)
+    F = rng.random((nt, np_))
+    Bn = oracle.assimilate(B, D, F, flux_balance=True)
+    dB = Bn - B
+    raw = F * (D - B)
+    w = weights(nt, np_)[:, None]
+    pp, pm = (dB * w)[dB > 0].sum(), (dB * w)[dB < 0].sum()
+    assert pp == pytest.approx(-pm, rel=1e-12)
+    assert np.array_equal(np.sign(dB), np.sign(raw))
+    rp, rm = (raw * w)[raw > 0].sum(), (raw * w)[raw < 0].sum()
+    assert pp == pytest.approx(math.sqrt(abs(rp * rm)), rel=1e-12)
+
+
+# ----------------------------------------------------------- diagnostics
+def test_diagnostics_dipoles_and_fluxes():
+    nt, np_ = 90, 180
+    TH, PH = grid(nt, np_)
+    d = oracle.diagnostics(np.cos(TH))
+    assert d["dax"] == pytest.approx(1.0, abs=5e-4)
+    assert d["phi_pos"] == pytest.approx(np.pi, rel=5e-4)
+    assert d["phi_neg"] == pytest.approx(-np.pi, rel=5e-4)
+    assert abs(d["phi_net"]) < 1e-12
+    d1 = oracle.diagnostics(np.sin(TH) * np.cos(PH))
+    assert d1["h1"] == pytest.approx(1.0, abs=5e-4) and abs(d1["h2"]) < 1e-12
+    d2 = oracle.diagnostics(np.sin(TH) * np.sin(PH))
+    assert d2["h2"] == pytest.approx(1.0, abs=5e-4) and abs(d2["h1"]) < 1e-12
+    B = np.zeros((nt, np_))
+    B[3, 4], B[10, 7] = -7.0, 9.0
+    d3 = oracle.diagnostics(B)
+    assert d3["bmin"] == -7.0 and d3["bmax"] == 9.0 and d3["babs_min"] == 0.0
+
+
+def test_hh_metric():
+    assert oracle.hh(np.array([1.0, 2.0]), np.array([1.0, 1.0])) == pytest.approx(math.sqrt(1 / 3))
+
+
+# -------------------------------------------------------------- time loop
+def test_time_loop_dt_rule_and_conservation():
+    nt, np_ = 32, 64
+    prm = (0.0, -337.4, -253.1, 30.0, 0.0, 0.0)
+    vph, vth = oracle.flows(nt, prm)
+    cfl = oracle.cfl_dt(nt, np_, vph, vth)
+    B0 = np.random.default_rng(10).standard_normal((nt, np_)) * 30
+    T = 3.7 * cfl
+    B, st = oracle.advance(B0, prm, 500.0, 0.0, T)
+    assert st["steps"] == math.ceil(T / (0.9 * cfl))
+    assert st["dt_last"] == pytest.approx(T - (st["steps"] - 1) * 0.9 * cfl, rel=1e-9)
+    w = weights(nt, np_)[:, None]
+    assert abs(((B - B0) * w).sum()) < 1e-13 * (np.abs(B0) * w).sum()
+    # the same interval in two calls lands at the same state up to the split
+    Ba, _ = oracle.advance(B0, prm, 500.0, 0.0, 0.5 * T)
+    Ba, _ = oracle.advance(Ba, prm, 500.0, 0.5 * T, T)
+    assert np.allclose(Ba, B, atol=1e-2 * np.abs(B0).max())
+
+
+def test_rigid_rotation_returns_map():
+    """A full rigid rotation (Sec. "Test cases", v_phi = 1.80766 km/s sin
+    theta for 672 h) through the full time loop returns the soccer-ball map
+    with third-order convergence."""
+    g = golden()
+    errs, ns = [], [128, 256]
+    for np_ in ns:
+        TH, PH = grid(16, np_)
+        u0 = soccer(TH, PH)
+        B, st = oracle.advance(u0, (g["rigid_rotation_km_s"] * 1000.0, 0, 0, 0, 0, 0), 0.0, 0.0,
+                               g["rigid_rotation_period_h"])
+        errs.append(oracle.hh(B, u0))
+    assert errs[-1] < 3e-3
+    assert order(errs, ns)[0] > 2.7, errs
+
+
+def test_meridional_divergence_converges():
+    """With the LLF split read literally (one-sided face velocities, per-cell
+    alpha over a six-face window), the divergence of a constant field under
+    the meridional flow of eq. mf converges to the analytic
+    (1/sin) d(sin v_theta)/dtheta at second order away from the pole-adjacent
+    rows and the equator.  At the equator v_theta changes sign and the
+    per-cell alpha has a kink, which leaves an error confined to a few rows
+    whose area-weighted L1 norm still falls at first order."""
+    ms, _ = oracle.units()
+    m1 = 30.0
+    e_max, e_l1, ns = [], [], [64, 128, 256]
+    for nt in ns:
+        vph, vth = oracle.flows(nt, (0, 0, 0, m1, 0, 0))
+        A = oracle.adv_operator(np.ones((nt, 8)), vph, vth)
+        th = (np.arange(nt) + 0.5) * np.pi / nt
+        exact = m1 * ms * (np.sin(th) ** 2 - 2 * np.cos(th) ** 2)
+        err = np.abs(A[:, 0] - exact) / np.abs(exact).max()
+        keep = np.ones(nt, bool)
+        keep[:3] = keep[-3:] = False
+        keep[nt // 2 - 4:nt // 2 + 4] = False
+        e_max.append(err[keep].max())
+        e_l1.append((err * np.sin(th)).sum() / np.sin(th).sum())
+    assert e_max[-1] < 1e-3
+    assert order(e_max, ns)[-1] > 0.9, e_max
+    assert order(e_l1, ns)[-1] > 0.9, e_l1
