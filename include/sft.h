@@ -1,0 +1,232 @@
+/*
+ * sft.h -- C ABI of the MI355X (gfx950) surface-flux-transport library.
+ *
+ * The library steps the radial photospheric field B_r(theta, phi) of many
+ * ensemble realizations at once through the split operators of the HipFT
+ * paper (Caplan et al., "Open-source Flux Transport I: HipFT"):
+ *   - advection by differential rotation and meridional flow
+ *     (eq. advection, eq. dr, eq. mf; WENO3-CS(h) fluxes of App. B with the
+ *     upwind pole rows and finite-volume pole closure of App. A;
+ *     SSPRK(4,3) or forward-Euler time stepping, Sec. "Advection temporal
+ *     schemes"),
+ *   - surface diffusion (eq. diffusion, eq. diffusion_matrix) advanced by
+ *     super time stepping (RKG2(3/2) default, RKL2, or forward Euler,
+ *     Sec. "Diffusion temporal schemes"),
+ *   - data assimilation (eq. data_assim, eq. data_assim_f, with the optional
+ *     flux balance of eqs. data_assim_deltab / fluxbal),
+ *   - FP64 analysis reductions (Sec. "Analysis").
+ * Steps are operator split without Strang splitting (eq.
+ * num_opsplit_nostrang); assimilation happens at the end of an advance.
+ *
+ * Grid: uniform cell-centred finite-volume grid of the unit sphere, nt rows
+ * in colatitude (theta_j = (j+1/2) pi/nt) and np periodic columns in
+ * longitude (phi_k = (k+1/2) 2 pi/np).  A field of one realization is nt*np
+ * values, row-major, phi contiguous: B[j*np + k].  A grid class holds R
+ * realizations stored back to back: B[(r*nt + j)*np + k].
+ *
+ * Units at the boundary are the paper's input units (Sec. "Units"):
+ * diffusivity km^2/s, flow coefficients m/s, field gauss, time hours,
+ * angles degrees.  Internally lengths are solar radii (6.96e8 m).
+ *
+ * Conventions for every call:
+ *  - Status codes only; nothing throws across the ABI.  sft_last_error()
+ *    returns a text description of the last failure on a context.
+ *  - The caller owns every pointer it passes; pointers are borrowed for the
+ *    duration of the call.  Device pointers (on_device = 1) must live on the
+ *    context's device; the library reads/writes them in stream order on the
+ *    context's stream, so the caller must keep them alive until that stream
+ *    has passed the call.  Host pointers are read/written before the call
+ *    returns.
+ *  - A context is single-threaded: calls on one context must not overlap.
+ *    Several contexts may coexist.
+ *  - All work is enqueued on the context's HIP stream; only calls that
+ *    return host data (sft_get_state to host memory, sft_diagnostics,
+ *    sft_sync) wait for it.
+ */
+#ifndef SFT_H
+#define SFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sft_status;
+#define SFT_OK 0
+#define SFT_ERR_ARG (-1)          /* invalid argument value or null pointer      */
+#define SFT_ERR_SHAPE (-2)        /* array shape does not match the grid         */
+#define SFT_ERR_OOM (-3)          /* device or host allocation failed            */
+#define SFT_ERR_HIP (-4)          /* a HIP runtime call failed                   */
+#define SFT_ERR_NOT_FINITE (-5)   /* the field holds NaN or Inf                  */
+#define SFT_ERR_STATE (-6)        /* call not valid in the context's state       */
+#define SFT_ERR_UNSUPPORTED (-7)  /* option combination not implemented          */
+
+/* precision */
+#define SFT_FP64 0          /* every stencil and reduction in FP64                */
+#define SFT_FP32_MIXED 1    /* FP32 stencil arithmetic, FP64 state and reductions */
+/* advection spatial scheme */
+#define SFT_WENO3CSH 0
+#define SFT_UPWIND 1
+/* advection time scheme */
+#define SFT_SSPRK43 0
+#define SFT_FE 1
+/* diffusion time scheme */
+#define SFT_RKG2 0
+#define SFT_RKL2 1
+#define SFT_DIFF_FE 2
+/* element types of state / observation arrays */
+#define SFT_DTYPE_F64 0
+#define SFT_DTYPE_F32 1
+/* meaning of the weight array passed to sft_assimilate */
+#define SFT_WEIGHT_F 0      /* the assimilation weight F itself (eq. data_assim)              */
+#define SFT_WEIGHT_MU 1     /* mu = cos(disk-centre angle); F from eq. data_assim_f            */
+#define SFT_WEIGHT_DISK 2   /* no array: mu from the observer's (b0, l0), then eq. data_assim_f */
+
+typedef struct {
+    int32_t precision;    /* SFT_FP64 (default) or SFT_FP32_MIXED                          */
+    int32_t adv_scheme;   /* SFT_WENO3CSH (default) or SFT_UPWIND                          */
+    int32_t adv_time;     /* SFT_SSPRK43 (default) or SFT_FE                               */
+    int32_t diff_time;    /* SFT_RKG2 (default), SFT_RKL2 or SFT_DIFF_FE                   */
+    double cfl_safety;    /* safety factor on the flow CFL limit (default 0.9)             */
+    double dt_max;        /* upper bound on a step, hours; 0 = none (default)              */
+    double ptl_dt;        /* > 0 splits each diffusion advance into ceil(dt/ptl_dt) calls  */
+    int32_t use_graphs;   /* 1 = capture each distinct advance plan in a HIP graph         */
+    int32_t sts_fuse;     /* STS stages per kernel launch: 0 = autotune (default), 1 = one */
+    int32_t diag_every_call; /* 1 (default) = refresh diagnostics after advance/assimilate */
+    int32_t reserved[7];
+} sft_options;
+
+/* Per-realization parameters (Sec. "Multiple Realizations"). */
+typedef struct {
+    double nu_km2_s;      /* diffusivity (eq. diffusion), scalar per realization, >= 0   */
+    double d0, d2, d4;    /* differential rotation, eq. dr, m/s                          */
+    double m1, m3, m5;    /* meridional flow, eq. mf, m/s                                */
+    double alpha_mu;      /* weight exponent alpha_mu of eq. data_assim_f                */
+    double mu_lim;        /* mu limit of eq. data_assim_f                                */
+    double lat_lim_deg;   /* latitude limit of eq. data_assim_f, degrees                 */
+    int32_t flux_balance; /* 1 = balance the assimilation increment (eq. fluxbal)        */
+    int32_t reserved[3];
+} sft_params;
+
+/* Analysis record of one realization (Sec. "Analysis"); FP64 reductions. */
+typedef struct {
+    double t;             /* context time of the record, hours                     */
+    double dt_last;       /* last step length used, hours                          */
+    int64_t steps;        /* split steps taken since creation                      */
+    int64_t stages;       /* stencil stage applications since creation             */
+    double phi_pos, phi_neg, phi_net; /* flux integrals of B dOmega (G sr)         */
+    double h1, h2, dax;   /* equatorial (h1, h2) and axial (D) dipole strengths    */
+    double bmin, bmax, babs_min;
+    int32_t nonfinite;    /* number of cells holding NaN or Inf                    */
+    int32_t pad;
+    int64_t surr_accept, surr_reject;  /* surrogate intervals accepted / rejected  */
+} sft_diag;
+
+typedef struct sft_ctx sft_ctx;   /* opaque; owns every internal device buffer */
+
+/* Fills *opt with the defaults listed above.  Errors: SFT_ERR_ARG if opt is NULL. */
+sft_status sft_options_default(sft_options* opt);
+
+/* Creates a context on the current HIP device.  hip_stream is a hipStream_t
+ * the context enqueues all work on; the context does not own it.  With NULL
+ * the context creates (and later destroys) its own blocking stream, which is
+ * ordered with the null stream.  opt may be NULL for the defaults.  On success *ctx receives the
+ * handle and the context time is 0 h.  Errors: SFT_ERR_ARG (bad option value),
+ * SFT_ERR_HIP, SFT_ERR_OOM. */
+sft_status sft_create(sft_ctx** ctx, const sft_options* opt, void* hip_stream);
+
+/* Adds a grid class of nt x np cells (Sec. "Grid": resolution is fixed per
+ * map and every input map must match it).  nt >= 8, np >= 8, np even.
+ * *grid_id receives the class index.  Allowed only before the first advance.
+ * Errors: SFT_ERR_ARG, SFT_ERR_STATE. */
+sft_status sft_add_grid(sft_ctx* ctx, int32_t ntheta, int32_t nphi, int32_t* grid_id);
+
+/* Adds n realizations with parameters prm[0..n-1] to a grid class (Sec.
+ * "Multiple Realizations").  Their fields start at zero.  *first_id receives
+ * the global id of the first one; ids are consecutive.  Allocates the class's
+ * device memory.  Allowed only before the first advance.
+ * Errors: SFT_ERR_ARG (negative diffusivity, bad limits), SFT_ERR_STATE,
+ * SFT_ERR_OOM. */
+sft_status sft_add_realizations(sft_ctx* ctx, int32_t grid_id, int32_t n, const sft_params* prm,
+                                int32_t* first_id);
+
+/* Copies one realization's field in (set) or out (get).  br points to nt*np
+ * values of dtype SFT_DTYPE_F64 or SFT_DTYPE_F32, on the device when
+ * on_device = 1, else in host memory.  Errors: SFT_ERR_ARG (bad id/dtype,
+ * NULL), SFT_ERR_HIP. */
+sft_status sft_set_state(sft_ctx* ctx, int32_t real_id, const void* br, int32_t dtype,
+                         int32_t on_device);
+sft_status sft_get_state(sft_ctx* ctx, int32_t real_id, void* br_out, int32_t dtype,
+                         int32_t on_device);
+
+/* The same for all R realizations of a grid class at once: br holds R*nt*np
+ * values in the class layout [r][j][k]. */
+sft_status sft_set_states(sft_ctx* ctx, int32_t grid_id, const void* br, int32_t dtype,
+                          int32_t on_device);
+sft_status sft_get_states(sft_ctx* ctx, int32_t grid_id, void* br_out, int32_t dtype,
+                          int32_t on_device);
+
+/* Advances every realization from the context time t to t_end (hours),
+ * landing exactly on t_end (Sec. "Time steps": each realization takes steps
+ * dt = min(t_end - t, cfl_safety * flow CFL limit, dt_max); a step that would
+ * leave less than 1e-10 h is stretched to t_end).  Each step applies
+ * advection then diffusion (eq. num_opsplit_nostrang).  Stream-ordered; does
+ * not wait for the GPU.  Errors: SFT_ERR_ARG (t_end < t), SFT_ERR_STATE (no
+ * realizations), SFT_ERR_HIP. */
+sft_status sft_advance(sft_ctx* ctx, double t_end_hours);
+
+/* Assimilates an observed map into every realization of a grid class at the
+ * current time (eq. data_assim, eq. data_assim_f, eqs. data_assim_deltab and
+ * fluxbal when a realization's flux_balance is set).
+ *   data     nt*np observed field values (gauss), dtype SFT_DTYPE_F64/F32;
+ *   weight   nt*np values of the same dtype: F itself (SFT_WEIGHT_F) or mu
+ *            (SFT_WEIGHT_MU); ignored (may be NULL) for SFT_WEIGHT_DISK, where
+ *            mu is the cosine of the angle between a cell and the disk centre
+ *            of an observer at latitude b0_deg and longitude l0_deg;
+ *   F from mu: F = mu^alpha_mu where mu > mu_lim and |latitude| < lat_lim,
+ *            else 0, with each realization's own parameters.
+ * Flux sums of the balance are FP64 and deterministic.  Stream-ordered.
+ * Errors: SFT_ERR_ARG, SFT_ERR_HIP. */
+sft_status sft_assimilate(sft_ctx* ctx, int32_t grid_id, const void* data, const void* weight,
+                          int32_t dtype, int32_t weight_kind, double b0_deg, double l0_deg,
+                          int32_t on_device);
+
+/* Returns the latest analysis record of one realization (computed in FP64 on
+ * the device after the last advance/assimilate, or now if none is pending).
+ * Waits for the stream.  Returns SFT_ERR_NOT_FINITE (with *out filled) when
+ * the field holds NaN or Inf.  Errors: SFT_ERR_ARG, SFT_ERR_HIP. */
+sft_status sft_diagnostics(sft_ctx* ctx, int32_t real_id, sft_diag* out);
+
+/* Context time in hours. */
+sft_status sft_time(sft_ctx* ctx, double* t_hours);
+
+/* Sets the context time (hours) without touching the fields: with
+ * sft_set_state(s) this restores a checkpoint taken with sft_get_state(s) and
+ * sft_time. */
+sft_status sft_set_time(sft_ctx* ctx, double t_hours);
+
+/* Waits for all work enqueued by the context. */
+sft_status sft_sync(sft_ctx* ctx);
+
+/* Work counters of one realization since the context was created: split
+ * steps, diffusion stages (operator applications of the STS or Euler
+ * stages), advection stages (flux-divergence evaluations) and assimilation
+ * passes.  Any output pointer may be NULL.  Errors: SFT_ERR_ARG. */
+sft_status sft_counts(sft_ctx* ctx, int32_t real_id, int64_t* steps, int64_t* stages,
+                      int64_t* adv_stages, int64_t* assim);
+
+/* Releases the context and its device memory (after waiting for its work). */
+sft_status sft_destroy(sft_ctx* ctx);
+
+/* Static text for a status code; never NULL. */
+const char* sft_status_string(sft_status st);
+
+/* Text of the last error on ctx (empty if none); valid until the next call. */
+const char* sft_last_error(const sft_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFT_H */

@@ -714,9 +714,11 @@ double or_hh(long n, const double *X, const double *Y)
 
 /* ------------------------------------------------------------- time loop */
 /* Sec. "Time steps" and "Operator splitting" (no Strang): each step takes
- * dt = min(t_end - t, safety * CFL limit, dt_max), then B* = A(B, dt),
- * B** = D(B*, dt); the source term is absent.  A step that would leave less
- * than 1e-10 h before t_end is stretched to land on t_end.
+ * dt = min(time left in the interval, safety * CFL limit, dt_max), then
+ * B* = A(B, dt), B** = D(B*, dt); the source term is absent.  Reading: the
+ * time left is measured from the start of the interval (elapsed time is
+ * accumulated from zero, the interval length is t_end - t0), and a step that
+ * would leave less than 1e-10 h before t_end is stretched to land on t_end.
  * prm = {d0, d2, d4, m1, m3, m5} (m/s), nu_km2_s scalar diffusivity.
  * opts = {adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt}
  * stats = {steps, diffusion stages, last dt}.  Returns 0. */
@@ -735,11 +737,12 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
     for (int j = 0; j < nt; ++j) has_flow |= vph[j] != 0.0;
     for (int f = 0; f <= nt; ++f) has_flow |= vth[f] != 0.0;
     double cfl = or_cfl_dt(nt, np, vph, vth, adv_time);
-    double t = t0;
+    double len = t_end - t0;
+    double el = 0.0;
     long steps = 0, stages = 0;
     double last = 0.0;
-    while (t < t_end) {
-        double rem = t_end - t;
+    while (el < len) {
+        double rem = len - el;
         double dt = rem;
         if (safety * cfl < dt) dt = safety * cfl;
         if (dt_max > 0.0 && dt_max < dt) dt = dt_max;
@@ -750,7 +753,7 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
         }
         if (has_flow) or_adv_step(nt, np, B, vph, vth, dt, adv_scheme, adv_time, eps_mode);
         stages += or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
-        t = final ? t_end : t + dt;
+        el = final ? len : el + dt;
         last = dt;
         ++steps;
     }

@@ -1,0 +1,154 @@
+"""MI355X-native surface flux transport (HipFT method) behind a C ABI.
+
+``Ensemble`` marshals numpy arrays / torch device tensors to the functions of
+``include/sft.h``; the HIP library does all the work.  torch is used only for
+device memory and the HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, Optional
+
+import numpy as np
+
+from . import _abi
+from ._abi import *  # noqa: F401,F403  (constants and structures)
+from ._abi import check, load
+
+__all__ = ["Ensemble", "load", "make_params", "make_options"]
+
+
+def make_options(**kw) -> _abi.sft_options:
+    o = _abi.sft_options()
+    check(load().sft_options_default(ctypes.byref(o)), None, "sft_options_default")
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def make_params(r) -> _abi.sft_params:
+    """sft_params from any object with the realization attributes (km^2/s, m/s)."""
+    p = _abi.sft_params()
+    for name in ("nu_km2_s", "d0", "d2", "d4", "m1", "m3", "m5", "alpha_mu", "mu_lim", "lat_lim_deg"):
+        setattr(p, name, float(getattr(r, name)))
+    p.flux_balance = int(getattr(r, "flux_balance", 0))
+    return p
+
+
+def _ptr(a):
+    """(pointer, dtype code, on_device) of a numpy array or torch tensor."""
+    try:
+        import torch
+        if isinstance(a, torch.Tensor):
+            if not a.is_contiguous():
+                raise ValueError("tensor must be contiguous")
+            code = {torch.float64: _abi.SFT_DTYPE_F64, torch.float32: _abi.SFT_DTYPE_F32}[a.dtype]
+            return ctypes.c_void_p(a.data_ptr()), code, int(a.is_cuda)
+    except ImportError:
+        pass
+    if not (isinstance(a, np.ndarray) and a.flags["C_CONTIGUOUS"]):
+        raise ValueError("expected a C-contiguous numpy array or torch tensor")
+    code = {np.dtype(np.float64): _abi.SFT_DTYPE_F64, np.dtype(np.float32): _abi.SFT_DTYPE_F32}[a.dtype]
+    return ctypes.c_void_p(a.ctypes.data), code, 0
+
+
+class Ensemble:
+    """One library context: grid classes with realizations, advanced together."""
+
+    def __init__(self, options: Optional[_abi.sft_options] = None, stream=None, **kw):
+        self.L = load()
+        self.opt = options if options is not None else make_options(**kw)
+        # stream=None: the library creates its own blocking stream, ordered
+        # with the null stream (torch's default stream)
+        self.ctx = ctypes.c_void_p()
+        check(self.L.sft_create(ctypes.byref(self.ctx), ctypes.byref(self.opt),
+                                ctypes.c_void_p(stream or 0)), None, "sft_create")
+        self.grids = []      # (nt, np, first_id, R)
+
+    def _chk(self, st, what):
+        return check(st, self.ctx, what)
+
+    def add_grid(self, nt: int, np_: int, realizations: Iterable) -> int:
+        gid = ctypes.c_int32()
+        self._chk(self.L.sft_add_grid(self.ctx, nt, np_, ctypes.byref(gid)), "sft_add_grid")
+        rs = list(realizations)
+        arr = (_abi.sft_params * len(rs))(*[make_params(r) for r in rs])
+        first = ctypes.c_int32()
+        self._chk(self.L.sft_add_realizations(self.ctx, gid.value, len(rs), arr, ctypes.byref(first)),
+                  "sft_add_realizations")
+        self.grids.append((nt, np_, first.value, len(rs)))
+        return gid.value
+
+    def set_state(self, rid: int, br):
+        p, code, dev = _ptr(br)
+        self._chk(self.L.sft_set_state(self.ctx, rid, p, code, dev), "sft_set_state")
+
+    def get_state(self, rid: int, out):
+        p, code, dev = _ptr(out)
+        self._chk(self.L.sft_get_state(self.ctx, rid, p, code, dev), "sft_get_state")
+        return out
+
+    def set_states(self, gid: int, br):
+        p, code, dev = _ptr(br)
+        self._chk(self.L.sft_set_states(self.ctx, gid, p, code, dev), "sft_set_states")
+
+    def get_states(self, gid: int, out=None):
+        if out is None:
+            nt, np_, _, R = self.grids[gid]
+            out = np.empty((R, nt, np_))
+        p, code, dev = _ptr(out)
+        self._chk(self.L.sft_get_states(self.ctx, gid, p, code, dev), "sft_get_states")
+        return out
+
+    def advance(self, t_end: float):
+        self._chk(self.L.sft_advance(self.ctx, float(t_end)), "sft_advance")
+
+    def assimilate(self, gid: int, data, weight=None, kind: int = _abi.SFT_WEIGHT_DISK,
+                   b0_deg: float = 0.0, l0_deg: float = 0.0):
+        p, code, dev = _ptr(data)
+        if weight is not None:
+            w, wcode, wdev = _ptr(weight)
+            if wcode != code or wdev != dev:
+                raise ValueError("data and weight must share dtype and device")
+        else:
+            w = ctypes.c_void_p(0)
+        self._chk(self.L.sft_assimilate(self.ctx, gid, p, w, code, kind, float(b0_deg), float(l0_deg),
+                                        dev), "sft_assimilate")
+
+    def diagnostics(self, rid: int) -> dict:
+        d = _abi.sft_diag()
+        st = self.L.sft_diagnostics(self.ctx, rid, ctypes.byref(d))
+        out = {name: getattr(d, name) for name, _ in _abi.sft_diag._fields_ if name != "pad"}
+        out["status"] = st
+        if st not in (_abi.SFT_OK, _abi.SFT_ERR_NOT_FINITE):
+            self._chk(st, "sft_diagnostics")
+        return out
+
+    def time(self) -> float:
+        t = ctypes.c_double()
+        self._chk(self.L.sft_time(self.ctx, ctypes.byref(t)), "sft_time")
+        return t.value
+
+    def set_time(self, t: float):
+        self._chk(self.L.sft_set_time(self.ctx, float(t)), "sft_set_time")
+
+    def sync(self):
+        self._chk(self.L.sft_sync(self.ctx), "sft_sync")
+
+    def counts(self, rid: int) -> dict:
+        v = [ctypes.c_int64() for _ in range(4)]
+        self._chk(self.L.sft_counts(self.ctx, rid, *[ctypes.byref(x) for x in v]), "sft_counts")
+        return dict(zip(("steps", "stages", "adv_stages", "assim"), [x.value for x in v]))
+
+    def close(self):
+        if self.ctx:
+            self.L.sft_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

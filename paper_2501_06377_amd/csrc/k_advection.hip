@@ -1,0 +1,234 @@
+// Advection stage kernels: WENO3-CS(h) face fluxes in theta and phi (App. B),
+// upwind pole-adjacent theta faces and zero-flux pole faces (App. A and the
+// advection boundary conditions), the spherical divergence of the flux
+// (Sec. "Advection spatial schemes") and one SSPRK(4,3) / forward-Euler stage
+// combination (Sec. "Advection temporal schemes"), fused in one LDS-tiled
+// kernel per stage.
+//
+// Tile: ATY rows x ATX columns of output cells per 256-thread block, staged
+// in LDS with a 2-cell halo (WENO3 needs cells i-2..i+1 for face i-1/2); phi
+// wraps periodically, rows outside the sphere are never used by a face flux
+// (pole faces carry no flux, pole-adjacent faces are upwind).
+//
+// The FP64 kernel evaluates the paper's formulas in their printed order with
+// no FMA contraction (the library is built with -ffp-contract=off), so its
+// results match a plain serial evaluation of the same formulas to the bit.
+#include "sft_internal.h"
+
+namespace sft {
+
+constexpr int ATX = 64;
+constexpr int ATY = 8;
+constexpr int AH = 2;
+constexpr int AW = ATX + 2 * AH;
+constexpr int AHT = ATY + 2 * AH;
+
+__device__ __forceinline__ int wrap_col(int k, int np)
+{
+    k %= np;
+    return k < 0 ? k + np : k;
+}
+
+// App. B on a uniform grid: u^- from LM_{i-2}, LM_{i-1}, LM_i and u^+ from
+// LP_{i-1}, LP_i, LP_{i+1}; F_{i-1/2} = u^+ + u^-.
+template <typename T>
+__device__ __forceinline__ T weno_face(T lm2, T lm1, T lm0, T lpm1, T lp0, T lpp1,
+                                       const WenoConst<T>& c)
+{
+    const T one = T(1), four = T(4);
+    T p0m = (one + c.half) * lm1 - c.half * lm2;
+    T p1m = c.half * lm1 + c.half * lm0;
+    T t0m = c.half * (lm1 - lm2);
+    T t1m = c.half * (lm0 - lm1);
+    T b0m = four * t0m * t0m;
+    T b1m = four * t1m * t1m;
+    T w0m = c.third / ((c.eps + b0m) * (c.eps + b0m));
+    T w1m = c.twothird / ((c.eps + b1m) * (c.eps + b1m));
+    T um = (w0m / (w0m + w1m)) * p0m + (w1m / (w0m + w1m)) * p1m;
+
+    T p0p = (one + c.half) * lp0 - c.half * lpp1;
+    T p1p = c.half * lp0 + c.half * lpm1;
+    T t0p = c.half * (lpp1 - lp0);
+    T t1p = c.half * (lp0 - lpm1);
+    T b0p = four * t0p * t0p;
+    T b1p = four * t1p * t1p;
+    T w0p = c.third / ((c.eps + b0p) * (c.eps + b0p));
+    T w1p = c.twothird / ((c.eps + b1p) * (c.eps + b1p));
+    T up = (w0p / (w0p + w1p)) * p0p + (w1p / (w0p + w1p)) * p1p;
+    return up + um;
+}
+
+// Upwind face flux: F = v (1/2)[(1-uw) B_right + (1+uw) B_left], uw = sign(v).
+template <typename T>
+__device__ __forceinline__ T upwind_face(T v, T bl, T br)
+{
+    const T one = T(1);
+    T sg = v > T(0) ? one : (v < T(0) ? -one : T(0));
+    T uw = one * sg;
+    return v * T(0.5) * ((one - uw) * br + (one + uw) * bl);
+}
+
+// MIXED = false: T = double, stage values read from fin (FP64 fields).
+// MIXED = true : T = float, stage value = (float)(fn + din) (din absent at
+//                stage 0), increments written to dout.
+template <typename T, bool MIXED>
+__global__ __launch_bounds__(256) void adv_stage_kernel(
+    const Entry* __restrict__ ents, int stage, int time_scheme, int upwind,
+    const AdvRow<T>* __restrict__ rows, Geom<T> g, WenoConst<T> wth, WenoConst<T> wph,
+    const double* __restrict__ fn, const T* __restrict__ fin, T* __restrict__ fout, int nt, int np)
+{
+    __shared__ T tile[AHT][AW];
+    __shared__ T fph[ATY][ATX + 1];
+    __shared__ T fth[ATY + 1][ATX];
+    __shared__ T cthM[AHT], cthP[AHT];
+
+    const Entry e = ents[blockIdx.z];
+    const size_t base = (size_t)e.r * nt * np;
+    const int k0 = blockIdx.x * ATX, j0 = blockIdx.y * ATY;
+    const AdvRow<T>* rw = rows + (size_t)e.r * (nt + 1);
+    const int tid = threadIdx.x;
+
+    for (int idx = tid; idx < AHT * AW; idx += 256) {
+        const int tj = idx / AW, tk = idx - (idx / AW) * AW;
+        const int j = j0 + tj - AH;
+        const int k = wrap_col(k0 + tk - AH, np);
+        T v = T(0);
+        if (j >= 0 && j < nt) {
+            const size_t i = base + (size_t)j * np + k;
+            if constexpr (MIXED) {
+                double x = fn[i];
+                if (stage > 0) x += (double)fin[i];
+                v = (T)x;
+            } else {
+                v = fin[i];
+            }
+        }
+        tile[tj][tk] = v;
+    }
+    if (tid < AHT) {
+        const int j = j0 + tid - AH;
+        T m = T(0), p = T(0);
+        if (j >= 0 && j < nt) {
+            m = rw[j].cthM;
+            p = rw[j].cthP;
+        }
+        cthM[tid] = m;
+        cthP[tid] = p;
+    }
+    __syncthreads();
+
+    // phi faces: face fk of tile row tj lies between cells k0+fk-1 and k0+fk
+    for (int idx = tid; idx < ATY * (ATX + 1); idx += 256) {
+        const int tj = idx / (ATX + 1), fk = idx - (idx / (ATX + 1)) * (ATX + 1);
+        const int j = j0 + tj;
+        T F = T(0);
+        if (j < nt) {
+            const AdvRow<T> a = rw[j];
+            const T* t = &tile[tj + AH][fk];   // t[0..3] = cells fk-2 .. fk+1
+            if (upwind) {
+                F = upwind_face(a.vph, t[1], t[2]);
+            } else {
+                F = weno_face(t[0] * a.cphM, t[1] * a.cphM, t[2] * a.cphM, t[1] * a.cphP,
+                              t[2] * a.cphP, t[3] * a.cphP, wph);
+            }
+        }
+        fph[tj][fk] = F;
+    }
+    // theta faces: face f = j0+fj lies between rows f-1 and f
+    for (int idx = tid; idx < (ATY + 1) * ATX; idx += 256) {
+        const int fj = idx / ATX, c = idx - (idx / ATX) * ATX;
+        const int f = j0 + fj;
+        T F = T(0);
+        if (f > 0 && f < nt) {
+            const int tc = c + AH;
+            const T bm1 = tile[fj + 1][tc], b0 = tile[fj + 2][tc];   // rows f-1, f
+            if (upwind || f == 1 || f == nt - 1) {
+                F = upwind_face(rw[f].vth, bm1, b0);
+            } else {
+                const T bm2 = tile[fj][tc], bp1 = tile[fj + 3][tc];  // rows f-2, f+1
+                F = weno_face(bm2 * cthM[fj], bm1 * cthM[fj + 1], b0 * cthM[fj + 2],
+                              bm1 * cthP[fj + 1], b0 * cthP[fj + 2], bp1 * cthP[fj + 3], wth);
+            }
+        }
+        fth[fj][c] = F;
+    }
+    __syncthreads();
+
+    const T hdt = T(0.5) * (T)e.dt;
+    for (int idx = tid; idx < ATY * ATX; idx += 256) {
+        const int tj = idx / ATX, c = idx - (idx / ATX) * ATX;
+        const int j = j0 + tj, k = k0 + c;
+        if (j >= nt || k >= np) continue;
+        const T dthf = (g.sf[j + 1] * fth[tj + 1][c] - g.sf[j] * fth[tj][c]) / g.den_th[j];
+        const T dphf = (fph[tj][c + 1] - fph[tj][c]) / g.den_ph[j];
+        const T op = dthf + dphf;
+        const size_t i = base + (size_t)j * np + k;
+        if constexpr (MIXED) {
+            const T dt = (T)e.dt;
+            T d;
+            if (time_scheme == 1) {
+                d = -(dt * op);
+            } else if (stage == 0) {
+                d = -(hdt * op);
+            } else if (stage == 1) {
+                d = fin[i] - hdt * op;
+            } else if (stage == 2) {
+                d = (T(1) / T(3)) * fin[i] - ((T(1) / T(6)) * dt) * op;
+            } else {
+                d = fin[i] - hdt * op;
+            }
+            fout[i] = d;
+        } else {
+            const T dt = (T)e.dt;
+            const T cur = tile[tj + AH][c + AH];
+            T v;
+            if (time_scheme == 1) {
+                v = cur - dt * op;
+            } else if (stage == 2) {
+                v = (T(2) / T(3)) * (T)fn[i] + (T(1) / T(3)) * cur - ((T(1) / T(6)) * dt) * op;
+            } else {
+                v = cur - hdt * op;
+            }
+            fout[i] = v;
+        }
+    }
+}
+
+__global__ void copy_entries_kernel(const Entry* __restrict__ ents, const double* __restrict__ src,
+                                    double* __restrict__ dst, size_t cells)
+{
+    const size_t base = (size_t)ents[blockIdx.y].r * cells;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[base + i] = src[base + i];
+}
+
+void launch_adv_stage_f64(hipStream_t st, const Entry* ents, int n_ent, int stage, int time_scheme,
+                          int upwind, const AdvRow<double>* rows, Geom<double> g,
+                          WenoConst<double> wth, WenoConst<double> wph, const double* fn,
+                          const double* fin, double* fout, int nt, int np)
+{
+    dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
+    hipLaunchKernelGGL((adv_stage_kernel<double, false>), grid, dim3(256), 0, st, ents, stage,
+                       time_scheme, upwind, rows, g, wth, wph, fn, fin, fout, nt, np);
+}
+
+void launch_adv_stage_mixed(hipStream_t st, const Entry* ents, int n_ent, int stage, int time_scheme,
+                            int upwind, const AdvRow<float>* rows, Geom<float> g,
+                            WenoConst<float> wth, WenoConst<float> wph, double* fn,
+                            const float* din, float* dout, int nt, int np)
+{
+    dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
+    hipLaunchKernelGGL((adv_stage_kernel<float, true>), grid, dim3(256), 0, st, ents, stage,
+                       time_scheme, upwind, rows, g, wth, wph, fn, din, dout, nt, np);
+}
+
+void launch_copy_f64(hipStream_t st, const Entry* ents, int n_ent, const double* src, double* dst,
+                     size_t cells)
+{
+    int bx = (int)((cells + 255) / 256);
+    if (bx > 1024) bx = 1024;
+    hipLaunchKernelGGL(copy_entries_kernel, dim3(bx, n_ent), dim3(256), 0, st, ents, src, dst, cells);
+}
+
+}  // namespace sft

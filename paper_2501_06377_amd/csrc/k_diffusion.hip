@@ -1,0 +1,206 @@
+// Diffusion kernels: the five-diagonal operator of eq. diffusion_matrix
+// (scalar diffusivity per realization, per-row coefficients, periodic phi,
+// no flux through the pole faces) and the stages of the super-time-stepping
+// schemes of Sec. "Diffusion temporal schemes" (RKG2(3/2), RKL2, or forward
+// Euler expressed as stages with mu = 1, nu = 0).
+//
+// FP64 ("paper form"): Y_j = mu Y_{j-1} + nu Y_{j-2} + cy0 Y0 + cL L(Y_{j-1})
+//                            + cLY0 L(Y0), evaluated in that order.
+// FP32 mixed ("increment form", algebraically identical because L is linear):
+//   d_j = Y_j - Y0 = mu d_{j-1} + nu d_{j-2} + cL L(d_{j-1}) + (cL + cLY0) L(Y0),
+//   with Y0 and the result kept in FP64 and L(Y0) formed in FP64 arithmetic.
+//
+// Layout: fields [r][j][k] (k = phi contiguous).  Entries of a launch are the
+// realizations still active at stage j (blockIdx.z indexes them).
+#include "sft_internal.h"
+
+namespace sft {
+
+constexpr int DTX = 64;   // unfused kernels: 64 x 4 threads, one cell each
+constexpr int DTY = 4;
+
+// L(y) at (j, k) in the table's order k-1, j-1, centre, j+1, k+1.  Pole rows
+// have a zero up/down coefficient; their out-of-sphere neighbour index is
+// clamped to a real row and multiplied by that zero.
+template <typename T, typename Y>
+__device__ __forceinline__ T apply_L(const DiffRow<T>& d, const Y* __restrict__ y, int j, int k,
+                                     int nt, int np)
+{
+    const int km = k == 0 ? np - 1 : k - 1;
+    const int kp = k == np - 1 ? 0 : k + 1;
+    const int ju = j > 0 ? j - 1 : 0;
+    const int jd = j < nt - 1 ? j + 1 : nt - 1;
+    const size_t row = (size_t)j * np;
+    T v = d.ph * (T)y[row + km];
+    v += d.up * (T)y[(size_t)ju * np + k];
+    v += d.d * (T)y[row + k];
+    v += d.dn * (T)y[(size_t)jd * np + k];
+    v += d.ph * (T)y[row + kp];
+    return v;
+}
+
+// ------------------------------------------------------------------ FP64
+__global__ __launch_bounds__(256) void diff_first_f64_kernel(
+    const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs,
+    const DiffRow<double>* __restrict__ drow, const double* __restrict__ B,
+    double* __restrict__ ly0, double* __restrict__ y1, int nt, int np)
+{
+    const Entry e = ents[blockIdx.z];
+    const int k = blockIdx.x * DTX + threadIdx.x;
+    const int j = blockIdx.y * DTY + threadIdx.y;
+    if (k >= np || j >= nt) return;
+    const size_t base = (size_t)e.r * nt * np;
+    const DiffRow<double> d = drow[(size_t)e.r * nt + j];
+    const double L = apply_L<double>(d, B + base, j, k, nt, np);
+    const size_t i = base + (size_t)j * np + k;
+    const double c1 = coefs[e.coef_off + 1].cL;
+    ly0[i] = L;
+    y1[i] = B[i] + c1 * L;
+}
+
+__global__ __launch_bounds__(256) void diff_stage_f64_kernel(
+    const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs, int jst,
+    const DiffRow<double>* __restrict__ drow, double* B, const double* __restrict__ ym1,
+    const double* ym2, const double* __restrict__ ly0, double* out, int nt, int np)
+{
+    const Entry e = ents[blockIdx.z];
+    const int k = blockIdx.x * DTX + threadIdx.x;
+    const int j = blockIdx.y * DTY + threadIdx.y;
+    if (k >= np || j >= nt) return;
+    const size_t base = (size_t)e.r * nt * np;
+    const DiffRow<double> d = drow[(size_t)e.r * nt + j];
+    const StageCoef c = coefs[e.coef_off + jst];
+    const double L = apply_L<double>(d, ym1 + base, j, k, nt, np);
+    const size_t i = base + (size_t)j * np + k;
+    const double v = c.mu * ym1[i] + c.nu * ym2[i] + c.cy0 * B[i] + c.cL * L + c.cLY0 * ly0[i];
+    double* o = (jst == e.s) ? B : out;
+    o[i] = v;
+}
+
+void launch_diff_first_f64(hipStream_t st, const Entry* ents, int n_ent, const StageCoef* coefs,
+                           const DiffRow<double>* drow, const double* B, double* ly0, double* y1,
+                           int nt, int np)
+{
+    dim3 grid((np + DTX - 1) / DTX, (nt + DTY - 1) / DTY, n_ent);
+    hipLaunchKernelGGL(diff_first_f64_kernel, grid, dim3(DTX, DTY), 0, st, ents, coefs, drow, B, ly0,
+                       y1, nt, np);
+}
+
+void launch_diff_stage_f64(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs,
+                           int j, const DiffRow<double>* drow, double* B, const double* ym1,
+                           const double* ym2, const double* ly0, double* out, int nt, int np)
+{
+    dim3 grid((np + DTX - 1) / DTX, (nt + DTY - 1) / DTY, n_act);
+    hipLaunchKernelGGL(diff_stage_f64_kernel, grid, dim3(DTX, DTY), 0, st, ents, coefs, j, drow, B,
+                       ym1, ym2, ly0, out, nt, np);
+}
+
+// ------------------------------------------------------------ FP32 mixed
+// Entry.pad = 1 when the step's advection increment (held in `adv`) must be
+// added to the FP64 state to form Y0.
+__global__ __launch_bounds__(256) void diff_first_mixed_kernel(
+    const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs,
+    const DiffRow<double>* __restrict__ drow, const double* __restrict__ B,
+    const float* __restrict__ adv, float* __restrict__ ly0, float* __restrict__ d1, int nt, int np)
+{
+    const Entry e = ents[blockIdx.z];
+    const int k = blockIdx.x * DTX + threadIdx.x;
+    const int j = blockIdx.y * DTY + threadIdx.y;
+    if (k >= np || j >= nt) return;
+    const size_t base = (size_t)e.r * nt * np;
+    const DiffRow<double> d = drow[(size_t)e.r * nt + j];
+    double L;
+    if (e.pad) {
+        const int km = k == 0 ? np - 1 : k - 1;
+        const int kp = k == np - 1 ? 0 : k + 1;
+        const int ju = j > 0 ? j - 1 : 0;
+        const int jd = j < nt - 1 ? j + 1 : nt - 1;
+        const double* b = B + base;
+        const float* a = adv + base;
+        const size_t row = (size_t)j * np;
+        L = d.ph * (b[row + km] + (double)a[row + km]);
+        L += d.up * (b[(size_t)ju * np + k] + (double)a[(size_t)ju * np + k]);
+        L += d.d * (b[row + k] + (double)a[row + k]);
+        L += d.dn * (b[(size_t)jd * np + k] + (double)a[(size_t)jd * np + k]);
+        L += d.ph * (b[row + kp] + (double)a[row + kp]);
+    } else {
+        L = apply_L<double>(d, B + base, j, k, nt, np);
+    }
+    const size_t i = base + (size_t)j * np + k;
+    const float lf = (float)L;
+    ly0[i] = lf;
+    d1[i] = (float)coefs[e.coef_off + 1].cL * lf;
+}
+
+__global__ __launch_bounds__(256) void diff_stage_mixed_kernel(
+    const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs, int jst,
+    const DiffRow<float>* __restrict__ drow, double* __restrict__ B, const float* __restrict__ adv,
+    const float* __restrict__ dm1, const float* dm2, const float* __restrict__ ly0, float* out,
+    int nt, int np)
+{
+    const Entry e = ents[blockIdx.z];
+    const int k = blockIdx.x * DTX + threadIdx.x;
+    const int j = blockIdx.y * DTY + threadIdx.y;
+    if (k >= np || j >= nt) return;
+    const size_t base = (size_t)e.r * nt * np;
+    const DiffRow<float> d = drow[(size_t)e.r * nt + j];
+    const StageCoef c = coefs[e.coef_off + jst];
+    const float L = apply_L<float>(d, dm1 + base, j, k, nt, np);
+    const size_t i = base + (size_t)j * np + k;
+    float v = (float)c.mu * dm1[i];
+    if (dm2) v += (float)c.nu * dm2[i];
+    v += (float)c.cL * L + (float)(c.cL + c.cLY0) * ly0[i];
+    if (jst == e.s) {
+        double y0 = B[i];
+        if (e.pad) y0 += (double)adv[i];
+        B[i] = y0 + (double)v;
+    } else {
+        out[i] = v;
+    }
+}
+
+void launch_diff_first_mixed(hipStream_t st, const Entry* ents, int n_ent, const StageCoef* coefs,
+                             const DiffRow<double>* drow64, const double* B, const float* adv,
+                             float* ly0, float* d1, int nt, int np)
+{
+    dim3 grid((np + DTX - 1) / DTX, (nt + DTY - 1) / DTY, n_ent);
+    hipLaunchKernelGGL(diff_first_mixed_kernel, grid, dim3(DTX, DTY), 0, st, ents, coefs, drow64, B,
+                       adv, ly0, d1, nt, np);
+}
+
+void launch_diff_stage_mixed(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs,
+                             int j, const DiffRow<float>* drow, double* B, const float* adv,
+                             const float* dm1, const float* dm2, const float* ly0, float* out,
+                             int nt, int np)
+{
+    dim3 grid((np + DTX - 1) / DTX, (nt + DTY - 1) / DTY, n_act);
+    hipLaunchKernelGGL(diff_stage_mixed_kernel, grid, dim3(DTX, DTY), 0, st, ents, coefs, j, drow, B,
+                       adv, dm1, dm2, ly0, out, nt, np);
+}
+
+// Closes a step in the increment form: B = B (+ adv) (+ d).  Used for
+// realizations with flow but no diffusion, and for one-stage diffusion calls.
+__global__ void mixed_close_kernel(const Entry* __restrict__ ents, double* __restrict__ B,
+                                   const float* __restrict__ adv, const float* __restrict__ d,
+                                   size_t cells)
+{
+    const Entry e = ents[blockIdx.y];
+    const size_t base = (size_t)e.r * cells;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cells;
+         i += (size_t)gridDim.x * blockDim.x) {
+        double y = B[base + i];
+        if (e.pad) y += (double)adv[base + i];
+        if (d) y += (double)d[base + i];
+        B[base + i] = y;
+    }
+}
+
+void launch_mixed_close(hipStream_t st, const Entry* ents, int n_ent, double* B, const float* adv,
+                        const float* d, size_t cells)
+{
+    int bx = (int)((cells + 255) / 256);
+    if (bx > 1024) bx = 1024;
+    hipLaunchKernelGGL(mixed_close_kernel, dim3(bx, n_ent), dim3(256), 0, st, ents, B, adv, d, cells);
+}
+
+}  // namespace sft

@@ -1,0 +1,1122 @@
+// Host side of the surface-flux-transport library: context and grid-class
+// management, the per-realization time-step schedule (Sec. "Time steps"),
+// advance plans batched over realizations and captured in HIP graphs, data
+// assimilation and analysis calls, and the C ABI declared in include/sft.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/sft.h"
+#include "sft_internal.h"
+
+using namespace sft;
+
+namespace {
+
+// Sec. "Units": solar radius 6.96e8 m, time in hours.
+const double RSUN_M = 6.96e8;
+const double M_S_TO_RS_HR = 3600.0 / RSUN_M;
+const double KM2_S_TO_RS2_HR = 3600.0 * 1.0e6 / (RSUN_M * RSUN_M);
+
+struct Phase {
+    int kind;        // 0 advection step, 1 diffusion call, 2 copy W1->B (FP64 FE advection),
+                     // 3 one-stage diffusion close (mixed), 4 copy W1->B for one-stage
+                     // diffusion (FP64), 5 advection-only close (mixed)
+    int ent_off;     // first entry in the plan's entry table
+    int n_ent;
+    int max_s;
+    std::vector<int> n_act;   // n_act[j] = entries with s >= j
+};
+
+struct Plan {
+    std::vector<Phase> phases;
+    Entry* d_ents = nullptr;
+    StageCoef* d_coefs = nullptr;
+    // per realization of the class
+    std::vector<int64_t> steps, stages, adv_stages;
+    std::vector<double> dt_last;
+};
+
+struct GridClass {
+    int nt = 0, np = 0, R = 0, first_id = 0;
+    std::vector<sft_params> prm;
+    std::vector<double> cfl, dtE;
+    std::vector<int> has_flow;
+    // device memory
+    double* B = nullptr;
+    double* W[3] = {nullptr, nullptr, nullptr};
+    float* A[4] = {nullptr, nullptr, nullptr, nullptr};
+    double* dB = nullptr;   // FP64 assimilation increment (mixed precision only)
+    AdvRow<double>* adv64 = nullptr;
+    AdvRow<float>* adv32 = nullptr;
+    DiffRow<double>* dr64 = nullptr;
+    DiffRow<float>* dr32 = nullptr;
+    double *sf64 = nullptr, *denth64 = nullptr, *denph64 = nullptr;
+    float *sf32 = nullptr, *denth32 = nullptr, *denph32 = nullptr;
+    double *st_row = nullptr, *ct_row = nullptr, *lat_row = nullptr, *w_row = nullptr;
+    double *sph = nullptr, *cph = nullptr;
+    AssimReal* ar = nullptr;
+    double *assim_partial = nullptr, *assim_ratio = nullptr;
+    int red_nblk = 0;
+    DiagRec *diag_partial = nullptr, *diag_out = nullptr;
+    void* stage_in = nullptr;    // host-upload staging for assimilation inputs (2 maps)
+    bool diag_valid = false;
+    std::map<uint64_t, Plan*> plans;
+    // counters since creation
+    std::vector<int64_t> steps, stages, adv_stages, assim;
+    std::vector<double> dt_last;
+    size_t cells() const { return (size_t)nt * np; }
+};
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+}  // namespace
+
+struct sft_ctx {
+    sft_options opt;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    double t = 0.0;
+    bool started = false;
+    std::vector<GridClass*> grids;
+    std::map<uint64_t, GraphEntry> graphs;
+    std::string err;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+sft_status fail(sft_ctx* c, sft_status st, const char* fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return st;
+}
+
+#define HIPCHK(ctx, call)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), SFT_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));  \
+    } while (0)
+
+template <typename T>
+sft_status dalloc(sft_ctx* c, T** p, size_t n)
+{
+    *p = nullptr;
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, SFT_ERR_OOM, "hipMalloc of %zu bytes failed: %s", n * sizeof(T),
+                    hipGetErrorString(e));
+    }
+    c->allocs.push_back((void*)*p);
+    return SFT_OK;
+}
+
+template <typename T>
+sft_status upload(sft_ctx* c, T* dst, const std::vector<T>& src)
+{
+    HIPCHK(c, hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return SFT_OK;
+}
+
+#define TRY(x)                              \
+    do {                                    \
+        sft_status s_ = (x);                \
+        if (s_ != SFT_OK) return s_;        \
+    } while (0)
+
+uint64_t dbits(double x)
+{
+    uint64_t u;
+    memcpy(&u, &x, sizeof u);
+    return u;
+}
+
+// ----------------------------------------------------------- host numerics
+// Flow profiles eq. dr (at row centres) and eq. mf (at theta faces), R_sun/h.
+void flows(int nt, const sft_params& p, std::vector<double>& vph, std::vector<double>& vth)
+{
+    const double dth = M_PI / nt;
+    vph.assign(nt, 0.0);
+    vth.assign(nt + 1, 0.0);
+    for (int j = 0; j < nt; ++j) {
+        const double th = (j + 0.5) * dth;
+        const double c = cos(th), s = sin(th);
+        const double c2 = c * c;
+        const double v = (p.d0 + p.d2 * c2 + p.d4 * c2 * c2) * s;
+        vph[j] = v * M_S_TO_RS_HR;
+    }
+    for (int f = 0; f <= nt; ++f) {
+        const double th = f * dth;
+        const double c = cos(th), s = sin(th);
+        const double c2 = c * c;
+        const double v = -(p.m1 * c + p.m3 * c2 * c + p.m5 * c2 * c2 * c) * s;
+        vth[f] = v * M_S_TO_RS_HR;
+    }
+    vth[0] = 0.0;
+    vth[nt] = 0.0;
+}
+
+// Eq. ssprk43_dt (SSPRK(4,3)) or eq. advection_timestep (forward Euler): the
+// limit without safety factor, from the larger flanking face velocity.
+double cfl_limit(int nt, int np, const std::vector<double>& vph, const std::vector<double>& vth,
+                 int adv_time)
+{
+    const double dth = M_PI / nt, dph = 2.0 * M_PI / np;
+    double rmax = 0.0;
+    for (int j = 0; j < nt; ++j) {
+        const double s = sin((j + 0.5) * dth);
+        const double a = fabs(vth[j]), b = fabs(vth[j + 1]);
+        const double vt = a > b ? a : b;
+        const double vp = fabs(vph[j]);
+        const double r = vt / dth + vp / (s * dph);
+        if (r > rmax) rmax = r;
+    }
+    if (rmax == 0.0) return INFINITY;
+    double lim = 1.0 / rmax;
+    if (adv_time != SFT_SSPRK43) lim *= 0.5;
+    return lim;
+}
+
+// Eq. diffusion_matrix rows for a scalar diffusivity nu (R_sun^2/h).
+void diff_rows(int nt, int np, double nu, std::vector<DiffRow<double>>& out)
+{
+    const double dth = M_PI / nt, dph = 2.0 * M_PI / np;
+    out.resize(nt);
+    for (int j = 0; j < nt; ++j) {
+        const double s = sin((j + 0.5) * dth);
+        const double sfu = j == 0 ? 0.0 : sin(j * dth);
+        const double sfd = j == nt - 1 ? 0.0 : sin((j + 1) * dth);
+        DiffRow<double> d;
+        d.ph = (nu + nu) / (2.0 * dph * dph * s * s);
+        d.up = (nu + nu) * sfu / (2.0 * dth * dth * s);
+        d.dn = (nu + nu) * sfd / (2.0 * dth * dth * s);
+        d.d = -(d.up + d.dn + d.ph + d.ph);
+        out[j] = d;
+    }
+}
+
+// Super-time-stepping stage counts and coefficients (RKG2(3/2), RKL2) from
+// their Gegenbauer / Legendre stability polynomials; forward Euler sub-steps.
+int sts_stages(double tau, double dtE, int scheme)
+{
+    const double r = tau / dtE;
+    double s;
+    if (scheme == SFT_RKL2)
+        s = ceil((sqrt(9.0 + 16.0 * r) - 1.0) / 2.0);
+    else
+        s = ceil((sqrt(25.0 + 24.0 * r) - 3.0) / 2.0);
+    if (s < 2.0) s = 2.0;
+    return (int)s;
+}
+
+double sts_b(int j, int scheme)
+{
+    if (scheme == SFT_RKL2) {
+        if (j < 2) return 1.0 / 3.0;
+        return ((double)j * j + j - 2.0) / (2.0 * j * (j + 1.0));
+    }
+    if (j == 0) return 1.0;
+    if (j == 1) return 1.0 / 3.0;
+    return 4.0 * (j - 1.0) * (j + 4.0) / (3.0 * j * (j + 1.0) * (j + 2.0) * (j + 3.0));
+}
+
+double sts_p1(int j, int scheme) { return scheme == SFT_RKL2 ? 1.0 : (j + 1.0) * (j + 2.0) / 2.0; }
+
+void sts_coefs(int s, int scheme, double tau, std::vector<StageCoef>& out)
+{
+    out.assign(s + 1, StageCoef{0, 0, 0, 0, 0});
+    const double w1 =
+        scheme == SFT_RKL2 ? 4.0 / ((double)s * s + s - 2.0) : 6.0 / ((s + 4.0) * (s - 1.0));
+    const double mut1 = (scheme == SFT_RKL2 ? sts_b(1, scheme) : 3.0 * sts_b(1, scheme)) * w1;
+    out[1].cL = mut1 * tau;
+    for (int j = 2; j <= s; ++j) {
+        const double bj = sts_b(j, scheme), bj1 = sts_b(j - 1, scheme), bj2 = sts_b(j - 2, scheme);
+        const double cj = scheme == SFT_RKL2 ? (2.0 * j - 1.0) / j : (2.0 * j + 1.0) / j;
+        const double ej = scheme == SFT_RKL2 ? (j - 1.0) / j : (j + 1.0) / j;
+        const double aj1 = 1.0 - bj1 * sts_p1(j - 1, scheme);
+        const double mu = cj * bj / bj1;
+        const double nu = -ej * bj / bj2;
+        const double mut = mu * w1;
+        const double gamt = -aj1 * mut;
+        out[j].mu = mu;
+        out[j].nu = nu;
+        out[j].cy0 = 1.0 - mu - nu;
+        out[j].cL = mut * tau;
+        out[j].cLY0 = gamt * tau;
+    }
+}
+
+void fe_coefs(int n, double h, std::vector<StageCoef>& out)
+{
+    out.assign(n + 1, StageCoef{0, 0, 0, 0, 0});
+    out[1].cL = h;
+    for (int j = 2; j <= n; ++j) {
+        out[j].mu = 1.0;
+        out[j].cL = h;
+    }
+}
+
+// Greedy step sequence over an interval of length len (Sec. "Time steps").
+void step_sequence(double len, double lim, double dt_max, std::vector<double>& dts)
+{
+    dts.clear();
+    double el = 0.0;
+    while (el < len) {
+        const double rem = len - el;
+        double dt = rem;
+        if (lim < dt) dt = lim;
+        if (dt_max > 0.0 && dt_max < dt) dt = dt_max;
+        bool fin = false;
+        if (rem - dt < 1e-10) {
+            dt = rem;
+            fin = true;
+        }
+        dts.push_back(dt);
+        el = fin ? len : el + dt;
+    }
+}
+
+// --------------------------------------------------------------- planning
+sft_status build_plan(sft_ctx* c, GridClass* g, double len, Plan** out)
+{
+    const sft_options& o = c->opt;
+    const bool mixed = o.precision == SFT_FP32_MIXED;
+    Plan* p = new Plan();
+    p->steps.assign(g->R, 0);
+    p->stages.assign(g->R, 0);
+    p->adv_stages.assign(g->R, 0);
+    p->dt_last.assign(g->R, 0.0);
+    std::vector<std::vector<double>> seq(g->R);
+    size_t max_steps = 0;
+    for (int r = 0; r < g->R; ++r) {
+        step_sequence(len, o.cfl_safety * g->cfl[r], o.dt_max, seq[r]);
+        max_steps = std::max(max_steps, seq[r].size());
+    }
+    std::vector<Entry> ents;
+    std::vector<StageCoef> coefs;
+    std::vector<StageCoef> tmp;
+    const int adv_nst = o.adv_time == SFT_SSPRK43 ? 4 : 1;
+    for (size_t i = 0; i < max_steps; ++i) {
+        // advection phase
+        Phase pa{0, (int)ents.size(), 0, 0, {}};
+        for (int r = 0; r < g->R; ++r) {
+            if (i >= seq[r].size() || !g->has_flow[r]) continue;
+            Entry e{r, 0, 0, 0, seq[r][i]};
+            ents.push_back(e);
+            p->adv_stages[r] += adv_nst;
+        }
+        pa.n_ent = (int)ents.size() - pa.ent_off;
+        if (pa.n_ent) {
+            p->phases.push_back(pa);
+            if (!mixed && o.adv_time == SFT_FE) {
+                Phase pc{2, pa.ent_off, pa.n_ent, 0, {}};
+                p->phases.push_back(pc);
+            }
+        }
+        // diffusion calls (several when the PTL hook splits the step)
+        int ncall_max = 0;
+        std::vector<int> ncall(g->R, 0);
+        for (int r = 0; r < g->R; ++r) {
+            if (i >= seq[r].size() || !(g->prm[r].nu_km2_s > 0.0)) continue;
+            const double dt = seq[r][i];
+            int nc = 1;
+            if (o.ptl_dt > 0.0 && dt > o.ptl_dt) nc = (int)ceil(dt / o.ptl_dt);
+            ncall[r] = nc;
+            ncall_max = std::max(ncall_max, nc);
+        }
+        for (int call = 0; call < ncall_max; ++call) {
+            std::vector<Entry> de;
+            for (int r = 0; r < g->R; ++r) {
+                if (call >= ncall[r]) continue;
+                const double tc = seq[r][i] / ncall[r];
+                int s;
+                if (o.diff_time == SFT_DIFF_FE) {
+                    s = (int)ceil(tc / g->dtE[r]);
+                    fe_coefs(s, tc / s, tmp);
+                } else {
+                    s = sts_stages(tc, g->dtE[r], o.diff_time);
+                    sts_coefs(s, o.diff_time, tc, tmp);
+                }
+                Entry e{r, s, (int)coefs.size(), (mixed && call == 0 && g->has_flow[r]) ? 1 : 0, tc};
+                coefs.insert(coefs.end(), tmp.begin(), tmp.end());
+                de.push_back(e);
+                p->stages[r] += s;
+            }
+            std::stable_sort(de.begin(), de.end(), [](const Entry& a, const Entry& b) { return a.s > b.s; });
+            Phase pd{1, (int)ents.size(), (int)de.size(), de.empty() ? 0 : de[0].s, {}};
+            pd.n_act.assign(pd.max_s + 1, 0);
+            for (int j = 0; j <= pd.max_s; ++j)
+                for (auto& e : de) pd.n_act[j] += e.s >= j ? 1 : 0;
+            ents.insert(ents.end(), de.begin(), de.end());
+            p->phases.push_back(pd);
+            // one-stage calls (forward Euler only) finish outside the stage loop
+            std::vector<Entry> one;
+            for (auto& e : de)
+                if (e.s == 1) one.push_back(e);
+            if (!one.empty()) {
+                Phase po{mixed ? 3 : 4, (int)ents.size(), (int)one.size(), 0, {}};
+                ents.insert(ents.end(), one.begin(), one.end());
+                p->phases.push_back(po);
+            }
+        }
+        // mixed: realizations with flow but no diffusion fold the increment in
+        if (mixed) {
+            Phase pcl{5, (int)ents.size(), 0, 0, {}};
+            for (int r = 0; r < g->R; ++r) {
+                if (i >= seq[r].size() || !g->has_flow[r] || ncall[r] > 0) continue;
+                ents.push_back(Entry{r, 0, 0, 1, seq[r][i]});
+            }
+            pcl.n_ent = (int)ents.size() - pcl.ent_off;
+            if (pcl.n_ent) p->phases.push_back(pcl);
+        }
+        for (int r = 0; r < g->R; ++r)
+            if (i < seq[r].size()) {
+                p->steps[r] += 1;
+                p->dt_last[r] = seq[r][i];
+            }
+    }
+    if (!ents.empty()) {
+        sft_status st = dalloc(c, &p->d_ents, ents.size());
+        if (st != SFT_OK) {
+            delete p;
+            return st;
+        }
+        st = upload(c, p->d_ents, ents);
+        if (st != SFT_OK) {
+            delete p;
+            return st;
+        }
+    }
+    if (!coefs.empty()) {
+        sft_status st = dalloc(c, &p->d_coefs, coefs.size());
+        if (st != SFT_OK) {
+            delete p;
+            return st;
+        }
+        st = upload(c, p->d_coefs, coefs);
+        if (st != SFT_OK) {
+            delete p;
+            return st;
+        }
+    }
+    *out = p;
+    return SFT_OK;
+}
+
+WenoConst<double> weno_const(double x)
+{
+    WenoConst<double> w;
+    w.half = x / (x + x);
+    w.third = x / (x + x + x);
+    w.twothird = (x + x) / (x + x + x);
+    w.eps = x;
+    return w;
+}
+
+WenoConst<float> weno_const_f(double x)
+{
+    WenoConst<double> d = weno_const(x);
+    WenoConst<float> w;
+    w.half = (float)d.half;
+    w.third = (float)d.third;
+    w.twothird = (float)d.twothird;
+    w.eps = (float)d.eps;
+    return w;
+}
+
+void launch_diag_class(sft_ctx* c, GridClass* g)
+{
+    launch_diag(c->stream, g->R, g->B, g->st_row, g->ct_row, g->w_row, g->sph, g->cph, g->diag_partial,
+                g->red_nblk, g->diag_out, g->nt, g->np);
+    g->diag_valid = true;
+}
+
+// Enqueue every phase of a plan.
+void run_plan(sft_ctx* c, GridClass* g, Plan* p)
+{
+    const sft_options& o = c->opt;
+    const bool mixed = o.precision == SFT_FP32_MIXED;
+    hipStream_t st = c->stream;
+    const int nt = g->nt, np = g->np;
+    const double dth = M_PI / nt, dph = 2.0 * M_PI / np;
+    const int upwind = o.adv_scheme == SFT_UPWIND;
+    const int ts = o.adv_time == SFT_SSPRK43 ? 0 : 1;
+    for (const Phase& ph : p->phases) {
+        const Entry* E = p->d_ents + ph.ent_off;
+        if (ph.kind == 0) {
+            if (!mixed) {
+                Geom<double> geo{g->sf64, g->denth64, g->denph64};
+                WenoConst<double> wt = weno_const(dth), wp = weno_const(dph);
+                double *B = g->B, *W1 = g->W[0], *W2 = g->W[1];
+                if (ts == 1) {
+                    launch_adv_stage_f64(st, E, ph.n_ent, 0, 1, upwind, g->adv64, geo, wt, wp, B, B, W1,
+                                         nt, np);
+                } else {
+                    launch_adv_stage_f64(st, E, ph.n_ent, 0, 0, upwind, g->adv64, geo, wt, wp, B, B, W1,
+                                         nt, np);
+                    launch_adv_stage_f64(st, E, ph.n_ent, 1, 0, upwind, g->adv64, geo, wt, wp, B, W1, W2,
+                                         nt, np);
+                    launch_adv_stage_f64(st, E, ph.n_ent, 2, 0, upwind, g->adv64, geo, wt, wp, B, W2, W1,
+                                         nt, np);
+                    launch_adv_stage_f64(st, E, ph.n_ent, 3, 0, upwind, g->adv64, geo, wt, wp, B, W1, B,
+                                         nt, np);
+                }
+            } else {
+                Geom<float> geo{g->sf32, g->denth32, g->denph32};
+                WenoConst<float> wt = weno_const_f(dth), wp = weno_const_f(dph);
+                float *A0 = g->A[0], *A1 = g->A[1], *A2 = g->A[2];
+                if (ts == 1) {
+                    launch_adv_stage_mixed(st, E, ph.n_ent, 0, 1, upwind, g->adv32, geo, wt, wp, g->B,
+                                           nullptr, A0, nt, np);
+                } else {
+                    launch_adv_stage_mixed(st, E, ph.n_ent, 0, 0, upwind, g->adv32, geo, wt, wp, g->B,
+                                           nullptr, A1, nt, np);
+                    launch_adv_stage_mixed(st, E, ph.n_ent, 1, 0, upwind, g->adv32, geo, wt, wp, g->B,
+                                           A1, A2, nt, np);
+                    launch_adv_stage_mixed(st, E, ph.n_ent, 2, 0, upwind, g->adv32, geo, wt, wp, g->B,
+                                           A2, A1, nt, np);
+                    launch_adv_stage_mixed(st, E, ph.n_ent, 3, 0, upwind, g->adv32, geo, wt, wp, g->B,
+                                           A1, A0, nt, np);
+                }
+            }
+        } else if (ph.kind == 1) {
+            if (!mixed) {
+                double *B = g->B, *W1 = g->W[0], *W2 = g->W[1], *LY = g->W[2];
+                launch_diff_first_f64(st, E, ph.n_ent, p->d_coefs, g->dr64, B, LY, W1, nt, np);
+                for (int j = 2; j <= ph.max_s; ++j) {
+                    const double *ym1, *ym2;
+                    double* out;
+                    if (j == 2) {
+                        ym1 = W1;
+                        ym2 = B;
+                        out = W2;
+                    } else if (j & 1) {
+                        ym1 = W2;
+                        ym2 = W1;
+                        out = W1;
+                    } else {
+                        ym1 = W1;
+                        ym2 = W2;
+                        out = W2;
+                    }
+                    launch_diff_stage_f64(st, E, ph.n_act[j], p->d_coefs, j, g->dr64, B, ym1, ym2, LY,
+                                          out, nt, np);
+                }
+            } else {
+                float *A0 = g->A[0], *P1 = g->A[1], *P2 = g->A[2], *LY = g->A[3];
+                launch_diff_first_mixed(st, E, ph.n_ent, p->d_coefs, g->dr64, g->B, A0, LY, P1, nt, np);
+                for (int j = 2; j <= ph.max_s; ++j) {
+                    const float *dm1, *dm2;
+                    float* out;
+                    if (j == 2) {
+                        dm1 = P1;
+                        dm2 = nullptr;
+                        out = P2;
+                    } else if (j & 1) {
+                        dm1 = P2;
+                        dm2 = P1;
+                        out = P1;
+                    } else {
+                        dm1 = P1;
+                        dm2 = P2;
+                        out = P2;
+                    }
+                    launch_diff_stage_mixed(st, E, ph.n_act[j], p->d_coefs, j, g->dr32, g->B, A0, dm1,
+                                            dm2, LY, out, nt, np);
+                }
+            }
+        } else if (ph.kind == 2 || ph.kind == 4) {
+            launch_copy_f64(st, E, ph.n_ent, g->W[0], g->B, g->cells());
+        } else if (ph.kind == 3) {
+            // one-stage diffusion calls: B = Y0 + d1 (d1 in A[1])
+            launch_mixed_close(st, E, ph.n_ent, g->B, g->A[0], g->A[1], g->cells());
+        } else if (ph.kind == 5) {
+            // flow but no diffusion: B = B + advection increment
+            launch_mixed_close(st, E, ph.n_ent, g->B, g->A[0], nullptr, g->cells());
+        }
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+const char* sft_status_string(sft_status st)
+{
+    switch (st) {
+    case SFT_OK: return "ok";
+    case SFT_ERR_ARG: return "invalid argument";
+    case SFT_ERR_SHAPE: return "shape mismatch";
+    case SFT_ERR_OOM: return "out of memory";
+    case SFT_ERR_HIP: return "HIP runtime error";
+    case SFT_ERR_NOT_FINITE: return "field holds NaN or Inf";
+    case SFT_ERR_STATE: return "call not valid in this state";
+    case SFT_ERR_UNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+    }
+}
+
+const char* sft_last_error(const sft_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+sft_status sft_options_default(sft_options* opt)
+{
+    if (!opt) return SFT_ERR_ARG;
+    memset(opt, 0, sizeof *opt);
+    opt->precision = SFT_FP64;
+    opt->adv_scheme = SFT_WENO3CSH;
+    opt->adv_time = SFT_SSPRK43;
+    opt->diff_time = SFT_RKG2;
+    opt->cfl_safety = 0.9;
+    opt->dt_max = 0.0;
+    opt->ptl_dt = 0.0;
+    opt->use_graphs = 0;
+    opt->sts_fuse = 0;
+    opt->diag_every_call = 1;
+    return SFT_OK;
+}
+
+sft_status sft_create(sft_ctx** ctx, const sft_options* opt, void* hip_stream)
+{
+    if (!ctx) return SFT_ERR_ARG;
+    *ctx = nullptr;
+    sft_options o;
+    if (opt) o = *opt;
+    else sft_options_default(&o);
+    if (o.precision != SFT_FP64 && o.precision != SFT_FP32_MIXED) return SFT_ERR_ARG;
+    if (o.adv_scheme != SFT_WENO3CSH && o.adv_scheme != SFT_UPWIND) return SFT_ERR_ARG;
+    if (o.adv_time != SFT_SSPRK43 && o.adv_time != SFT_FE) return SFT_ERR_ARG;
+    if (o.diff_time != SFT_RKG2 && o.diff_time != SFT_RKL2 && o.diff_time != SFT_DIFF_FE)
+        return SFT_ERR_ARG;
+    if (!(o.cfl_safety > 0.0 && o.cfl_safety <= 1.0) || o.dt_max < 0.0 || o.ptl_dt < 0.0)
+        return SFT_ERR_ARG;
+    sft_ctx* c = new sft_ctx();
+    c->opt = o;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return SFT_ERR_HIP;
+    }
+    if (!c->stream) {
+        // an own blocking stream (default priority): it orders with the null
+        // stream and can be captured into graphs, which the null stream cannot
+        if (hipStreamCreate(&c->stream) != hipSuccess) {
+            delete c;
+            return SFT_ERR_HIP;
+        }
+        c->own_stream = true;
+    }
+    *ctx = c;
+    return SFT_OK;
+}
+
+sft_status sft_add_grid(sft_ctx* c, int32_t nt, int32_t np, int32_t* grid_id)
+{
+    if (!c || !grid_id) return SFT_ERR_ARG;
+    if (c->started) return fail(c, SFT_ERR_STATE, "grids must be added before the first advance");
+    if (nt < 8 || np < 8 || (np & 1)) return fail(c, SFT_ERR_ARG, "grid %d x %d not allowed", nt, np);
+    GridClass* g = new GridClass();
+    g->nt = nt;
+    g->np = np;
+    int first = 0;
+    for (auto* h : c->grids) first += h->R;
+    g->first_id = first;
+    c->grids.push_back(g);
+    *grid_id = (int32_t)c->grids.size() - 1;
+    return SFT_OK;
+}
+
+static sft_status class_alloc(sft_ctx* c, GridClass* g)
+{
+    const int nt = g->nt, np = g->np, R = g->R;
+    const size_t n = (size_t)R * g->cells();
+    const bool mixed = c->opt.precision == SFT_FP32_MIXED;
+    TRY(dalloc(c, &g->B, n));
+    HIPCHK(c, hipMemset(g->B, 0, n * sizeof(double)));
+    if (!mixed) {
+        for (int i = 0; i < 3; ++i) TRY(dalloc(c, &g->W[i], n));
+    } else {
+        for (int i = 0; i < 4; ++i) TRY(dalloc(c, &g->A[i], n));
+        HIPCHK(c, hipMemset(g->A[0], 0, n * sizeof(float)));
+    }
+    // per-realization tables
+    std::vector<AdvRow<double>> a64((size_t)R * (nt + 1));
+    std::vector<AdvRow<float>> a32((size_t)R * (nt + 1));
+    std::vector<DiffRow<double>> d64((size_t)R * nt);
+    std::vector<DiffRow<float>> d32((size_t)R * nt);
+    std::vector<AssimReal> ar(R);
+    g->cfl.assign(R, INFINITY);
+    g->dtE.assign(R, INFINITY);
+    g->has_flow.assign(R, 0);
+    std::vector<double> vph, vth;
+    std::vector<DiffRow<double>> drow;
+    for (int r = 0; r < R; ++r) {
+        const sft_params& p = g->prm[r];
+        flows(nt, p, vph, vth);
+        int hf = 0;
+        for (double v : vph) hf |= v != 0.0;
+        for (double v : vth) hf |= v != 0.0;
+        g->has_flow[r] = hf;
+        g->cfl[r] = cfl_limit(nt, np, vph, vth, c->opt.adv_time);
+        for (int j = 0; j <= nt; ++j) {
+            AdvRow<double> a{};
+            a.vth = vth[j];
+            if (j < nt) {
+                double al = 0.0;
+                for (int f = j - 2; f <= j + 3; ++f) {
+                    if (f < 0 || f > nt) continue;
+                    al = std::max(al, fabs(vth[f]));
+                }
+                a.cthP = 0.5 * (vth[j + 1] - al);
+                a.cthM = 0.5 * (vth[j] + al);
+                const double ap = fabs(vph[j]);
+                a.cphP = 0.5 * (vph[j] - ap);
+                a.cphM = 0.5 * (vph[j] + ap);
+                a.vph = vph[j];
+            }
+            a64[(size_t)r * (nt + 1) + j] = a;
+            AdvRow<float> b{};
+            b.cthP = (float)a.cthP;
+            b.cthM = (float)a.cthM;
+            b.cphP = (float)a.cphP;
+            b.cphM = (float)a.cphM;
+            b.vth = (float)a.vth;
+            b.vph = (float)a.vph;
+            a32[(size_t)r * (nt + 1) + j] = b;
+        }
+        const double nu = p.nu_km2_s * KM2_S_TO_RS2_HR;
+        diff_rows(nt, np, nu, drow);
+        double m = 0.0;
+        for (int j = 0; j < nt; ++j) {
+            d64[(size_t)r * nt + j] = drow[j];
+            DiffRow<float> f{(float)drow[j].up, (float)drow[j].dn, (float)drow[j].ph, (float)drow[j].d};
+            d32[(size_t)r * nt + j] = f;
+            m = std::max(m, fabs(drow[j].d));
+        }
+        g->dtE[r] = m > 0.0 ? 1.0 / m : INFINITY;
+        ar[r].alpha = p.alpha_mu;
+        ar[r].mu_lim = p.mu_lim;
+        ar[r].lat_lim_rad = p.lat_lim_deg * (M_PI / 180.0);
+        ar[r].balance = p.flux_balance ? 1 : 0;
+    }
+    TRY(dalloc(c, &g->adv64, a64.size()));
+    TRY(upload(c, g->adv64, a64));
+    TRY(dalloc(c, &g->adv32, a32.size()));
+    TRY(upload(c, g->adv32, a32));
+    TRY(dalloc(c, &g->dr64, d64.size()));
+    TRY(upload(c, g->dr64, d64));
+    TRY(dalloc(c, &g->dr32, d32.size()));
+    TRY(upload(c, g->dr32, d32));
+    TRY(dalloc(c, &g->ar, ar.size()));
+    TRY(upload(c, g->ar, ar));
+    // geometry
+    const double dth = M_PI / nt, dph = 2.0 * M_PI / np;
+    std::vector<double> sf(nt + 1), dthv(nt), dphv(nt), st(nt), ct(nt), lat(nt), w(nt), sp(np), cp(np);
+    for (int f = 0; f <= nt; ++f) sf[f] = sin(f * dth);
+    sf[0] = 0.0;
+    sf[nt] = 0.0;
+    for (int j = 0; j < nt; ++j) {
+        const double th = (j + 0.5) * dth;
+        st[j] = sin(th);
+        ct[j] = cos(th);
+        dthv[j] = st[j] * dth;
+        dphv[j] = st[j] * dph;
+        lat[j] = M_PI / 2.0 - th;
+        w[j] = sin(th) * dth * dph;
+    }
+    for (int k = 0; k < np; ++k) {
+        const double ph = (k + 0.5) * dph;
+        sp[k] = sin(ph);
+        cp[k] = cos(ph);
+    }
+    auto f32 = [](const std::vector<double>& v) {
+        std::vector<float> o(v.size());
+        for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
+        return o;
+    };
+    TRY(dalloc(c, &g->sf64, nt + 1));
+    TRY(upload(c, g->sf64, sf));
+    TRY(dalloc(c, &g->denth64, nt));
+    TRY(upload(c, g->denth64, dthv));
+    TRY(dalloc(c, &g->denph64, nt));
+    TRY(upload(c, g->denph64, dphv));
+    TRY(dalloc(c, &g->sf32, nt + 1));
+    TRY(upload(c, g->sf32, f32(sf)));
+    TRY(dalloc(c, &g->denth32, nt));
+    TRY(upload(c, g->denth32, f32(dthv)));
+    TRY(dalloc(c, &g->denph32, nt));
+    TRY(upload(c, g->denph32, f32(dphv)));
+    TRY(dalloc(c, &g->st_row, nt));
+    TRY(upload(c, g->st_row, st));
+    TRY(dalloc(c, &g->ct_row, nt));
+    TRY(upload(c, g->ct_row, ct));
+    TRY(dalloc(c, &g->lat_row, nt));
+    TRY(upload(c, g->lat_row, lat));
+    TRY(dalloc(c, &g->w_row, nt));
+    TRY(upload(c, g->w_row, w));
+    TRY(dalloc(c, &g->sph, np));
+    TRY(upload(c, g->sph, sp));
+    TRY(dalloc(c, &g->cph, np));
+    TRY(upload(c, g->cph, cp));
+    // reductions: a fixed number of blocks per realization
+    int nblk = (int)((g->cells() + 255) / 256);
+    if (nblk > 512) nblk = 512;
+    g->red_nblk = nblk;
+    TRY(dalloc(c, &g->assim_partial, (size_t)R * nblk * 2));
+    TRY(dalloc(c, &g->assim_ratio, R));
+    TRY(dalloc(c, &g->diag_partial, (size_t)R * nblk));
+    TRY(dalloc(c, &g->diag_out, R));
+    g->steps.assign(R, 0);
+    g->stages.assign(R, 0);
+    g->adv_stages.assign(R, 0);
+    g->assim.assign(R, 0);
+    g->dt_last.assign(R, 0.0);
+    return SFT_OK;
+}
+
+sft_status sft_add_realizations(sft_ctx* c, int32_t grid_id, int32_t n, const sft_params* prm,
+                                int32_t* first_id)
+{
+    if (!c || !prm || !first_id || n <= 0) return SFT_ERR_ARG;
+    if (grid_id < 0 || grid_id >= (int)c->grids.size()) return fail(c, SFT_ERR_ARG, "bad grid id");
+    if (c->started) return fail(c, SFT_ERR_STATE, "realizations must be added before the first advance");
+    GridClass* g = c->grids[grid_id];
+    if (g->R) return fail(c, SFT_ERR_STATE, "grid %d already has realizations", grid_id);
+    for (int i = 0; i < n; ++i) {
+        const sft_params& p = prm[i];
+        if (!(p.nu_km2_s >= 0.0) || !std::isfinite(p.nu_km2_s) || !(p.alpha_mu > 0.0) ||
+            !(p.lat_lim_deg >= 0.0))
+            return fail(c, SFT_ERR_ARG, "realization %d: invalid parameters", i);
+    }
+    // ids are consecutive over grid classes in creation order
+    int first = 0;
+    for (int i = 0; i < grid_id; ++i) first += c->grids[i]->R;
+    for (size_t i = grid_id + 1; i < c->grids.size(); ++i)
+        if (c->grids[i]->R) return fail(c, SFT_ERR_STATE, "add realizations in grid order");
+    g->first_id = first;
+    g->R = n;
+    g->prm.assign(prm, prm + n);
+    sft_status st = class_alloc(c, g);
+    if (st != SFT_OK) g->R = 0;
+    *first_id = first;
+    return st;
+}
+
+static bool find_real(sft_ctx* c, int32_t id, GridClass** g, int* r)
+{
+    for (auto* h : c->grids) {
+        if (id >= h->first_id && id < h->first_id + h->R) {
+            *g = h;
+            *r = id - h->first_id;
+            return true;
+        }
+    }
+    return false;
+}
+
+static sft_status copy_in(sft_ctx* c, double* dst, const void* src, size_t n, int dtype, int on_device)
+{
+    if (dtype == SFT_DTYPE_F64) {
+        HIPCHK(c, hipMemcpyAsync(dst, src, n * sizeof(double),
+                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+        if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+        return SFT_OK;
+    }
+    if (dtype != SFT_DTYPE_F32) return fail(c, SFT_ERR_ARG, "bad dtype %d", dtype);
+    if (on_device) {
+        launch_f32_to_f64(c->stream, (const float*)src, dst, n);
+        return SFT_OK;
+    }
+    std::vector<double> tmp(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = (double)((const float*)src)[i];
+    HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SFT_OK;
+}
+
+static sft_status copy_out(sft_ctx* c, void* dst, const double* src, size_t n, int dtype, int on_device)
+{
+    if (dtype == SFT_DTYPE_F64) {
+        HIPCHK(c, hipMemcpyAsync(dst, src, n * sizeof(double),
+                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+        if (!on_device) HIPCHK(c, hipStreamSynchronize(c->stream));
+        return SFT_OK;
+    }
+    if (dtype != SFT_DTYPE_F32) return fail(c, SFT_ERR_ARG, "bad dtype %d", dtype);
+    if (on_device) {
+        launch_f64_to_f32(c->stream, src, (float*)dst, n);
+        return SFT_OK;
+    }
+    std::vector<double> tmp(n);
+    HIPCHK(c, hipMemcpyAsync(tmp.data(), src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < n; ++i) ((float*)dst)[i] = (float)tmp[i];
+    return SFT_OK;
+}
+
+sft_status sft_set_state(sft_ctx* c, int32_t id, const void* br, int32_t dtype, int32_t on_device)
+{
+    if (!c || !br) return SFT_ERR_ARG;
+    GridClass* g;
+    int r;
+    if (!find_real(c, id, &g, &r)) return fail(c, SFT_ERR_ARG, "bad realization id %d", id);
+    g->diag_valid = false;
+    return copy_in(c, g->B + (size_t)r * g->cells(), br, g->cells(), dtype, on_device);
+}
+
+sft_status sft_get_state(sft_ctx* c, int32_t id, void* br, int32_t dtype, int32_t on_device)
+{
+    if (!c || !br) return SFT_ERR_ARG;
+    GridClass* g;
+    int r;
+    if (!find_real(c, id, &g, &r)) return fail(c, SFT_ERR_ARG, "bad realization id %d", id);
+    return copy_out(c, br, g->B + (size_t)r * g->cells(), g->cells(), dtype, on_device);
+}
+
+sft_status sft_set_states(sft_ctx* c, int32_t gid, const void* br, int32_t dtype, int32_t on_device)
+{
+    if (!c || !br || gid < 0 || gid >= (int)c->grids.size()) return SFT_ERR_ARG;
+    GridClass* g = c->grids[gid];
+    if (!g->R) return fail(c, SFT_ERR_STATE, "grid %d has no realizations", gid);
+    g->diag_valid = false;
+    return copy_in(c, g->B, br, (size_t)g->R * g->cells(), dtype, on_device);
+}
+
+sft_status sft_get_states(sft_ctx* c, int32_t gid, void* br, int32_t dtype, int32_t on_device)
+{
+    if (!c || !br || gid < 0 || gid >= (int)c->grids.size()) return SFT_ERR_ARG;
+    GridClass* g = c->grids[gid];
+    if (!g->R) return fail(c, SFT_ERR_STATE, "grid %d has no realizations", gid);
+    return copy_out(c, br, g->B, (size_t)g->R * g->cells(), dtype, on_device);
+}
+
+sft_status sft_advance(sft_ctx* c, double t_end)
+{
+    if (!c) return SFT_ERR_ARG;
+    if (!(t_end >= c->t) || !std::isfinite(t_end))
+        return fail(c, SFT_ERR_ARG, "t_end %.17g before context time %.17g", t_end, c->t);
+    bool any = false;
+    for (auto* g : c->grids) any |= g->R > 0;
+    if (!any) return fail(c, SFT_ERR_STATE, "no realizations");
+    c->started = true;
+    const double len = t_end - c->t;
+    if (len == 0.0) return SFT_OK;
+    std::vector<Plan*> plans;
+    for (auto* g : c->grids) {
+        if (!g->R) {
+            plans.push_back(nullptr);
+            continue;
+        }
+        const uint64_t key = dbits(len);
+        auto it = g->plans.find(key);
+        Plan* p;
+        if (it == g->plans.end()) {
+            TRY(build_plan(c, g, len, &p));
+            g->plans[key] = p;
+        } else {
+            p = it->second;
+        }
+        plans.push_back(p);
+    }
+    auto enqueue = [&]() {
+        for (size_t i = 0; i < c->grids.size(); ++i) {
+            GridClass* g = c->grids[i];
+            if (!plans[i]) continue;
+            run_plan(c, g, plans[i]);
+            if (c->opt.diag_every_call) launch_diag_class(c, g);
+        }
+    };
+    if (c->opt.use_graphs) {
+        const uint64_t key = dbits(len) ^ (c->opt.diag_every_call ? 0x5bd1e995ull : 0);
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            GraphEntry ge;
+            HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+            enqueue();
+            HIPCHK(c, hipStreamEndCapture(c->stream, &ge.graph));
+            HIPCHK(c, hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0));
+            it = c->graphs.emplace(key, ge).first;
+        }
+        HIPCHK(c, hipGraphLaunch(it->second.exec, c->stream));
+    } else {
+        enqueue();
+        HIPCHK(c, hipGetLastError());
+    }
+    for (size_t i = 0; i < c->grids.size(); ++i) {
+        GridClass* g = c->grids[i];
+        Plan* p = plans[i];
+        if (!p) continue;
+        for (int r = 0; r < g->R; ++r) {
+            g->steps[r] += p->steps[r];
+            g->stages[r] += p->stages[r];
+            g->adv_stages[r] += p->adv_stages[r];
+            if (p->steps[r]) g->dt_last[r] = p->dt_last[r];
+        }
+        if (c->opt.diag_every_call) g->diag_valid = true;
+        else g->diag_valid = false;
+    }
+    c->t = t_end;
+    return SFT_OK;
+}
+
+sft_status sft_assimilate(sft_ctx* c, int32_t gid, const void* data, const void* weight, int32_t dtype,
+                          int32_t kind, double b0_deg, double l0_deg, int32_t on_device)
+{
+    if (!c || !data || gid < 0 || gid >= (int)c->grids.size()) return SFT_ERR_ARG;
+    if (kind != SFT_WEIGHT_F && kind != SFT_WEIGHT_MU && kind != SFT_WEIGHT_DISK)
+        return fail(c, SFT_ERR_ARG, "bad weight kind %d", kind);
+    if (kind != SFT_WEIGHT_DISK && !weight) return fail(c, SFT_ERR_ARG, "weight array missing");
+    if (dtype != SFT_DTYPE_F64 && dtype != SFT_DTYPE_F32) return fail(c, SFT_ERR_ARG, "bad dtype");
+    GridClass* g = c->grids[gid];
+    if (!g->R) return fail(c, SFT_ERR_STATE, "grid %d has no realizations", gid);
+    const size_t n = g->cells();
+    const size_t esz = dtype == SFT_DTYPE_F64 ? 8 : 4;
+    const void* d_data = data;
+    const void* d_w = weight;
+    if (!on_device) {
+        if (!g->stage_in) {
+            hipError_t e = hipMalloc(&g->stage_in, 2 * n * sizeof(double));
+            if (e != hipSuccess) return fail(c, SFT_ERR_OOM, "staging allocation failed");
+            c->allocs.push_back(g->stage_in);
+        }
+        char* s = (char*)g->stage_in;
+        HIPCHK(c, hipMemcpyAsync(s, data, n * esz, hipMemcpyHostToDevice, c->stream));
+        d_data = s;
+        if (kind != SFT_WEIGHT_DISK) {
+            HIPCHK(c, hipMemcpyAsync(s + n * sizeof(double), weight, n * esz, hipMemcpyHostToDevice,
+                                     c->stream));
+            d_w = s + n * sizeof(double);
+        }
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    bool any_bal = false;
+    for (auto& p : g->prm) any_bal |= p.flux_balance != 0;
+    const double b0 = b0_deg * (M_PI / 180.0), l0 = l0_deg * (M_PI / 180.0);
+    const double sb0 = sin(b0), cb0 = cos(b0);
+    double* dB = nullptr;
+    if (any_bal) {
+        if (c->opt.precision == SFT_FP64) {
+            dB = g->W[0];
+        } else {
+            if (!g->dB) TRY(dalloc(c, &g->dB, (size_t)g->R * n));
+            dB = g->dB;
+        }
+        launch_assim_delta(c->stream, g->R, g->ar, d_data, d_w, dtype, kind, sb0, cb0, l0, g->B, g->st_row,
+                           g->ct_row, g->lat_row, g->w_row, dB, g->assim_partial, g->red_nblk, g->nt,
+                           g->np);
+        launch_assim_reduce(c->stream, g->R, g->assim_partial, g->red_nblk, g->assim_ratio);
+    }
+    launch_assim_apply(c->stream, g->R, g->ar, d_data, d_w, dtype, kind, sb0, cb0, l0, g->B, dB,
+                       g->assim_ratio, g->st_row, g->ct_row, g->lat_row, g->red_nblk, g->nt, g->np);
+    for (int r = 0; r < g->R; ++r) g->assim[r] += 1;
+    if (c->opt.diag_every_call) launch_diag_class(c, g);
+    else g->diag_valid = false;
+    HIPCHK(c, hipGetLastError());
+    return SFT_OK;
+}
+
+sft_status sft_diagnostics(sft_ctx* c, int32_t id, sft_diag* out)
+{
+    if (!c || !out) return SFT_ERR_ARG;
+    GridClass* g;
+    int r;
+    if (!find_real(c, id, &g, &r)) return fail(c, SFT_ERR_ARG, "bad realization id %d", id);
+    if (!g->diag_valid) launch_diag_class(c, g);
+    DiagRec d;
+    HIPCHK(c, hipMemcpyAsync(&d, g->diag_out + r, sizeof d, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    memset(out, 0, sizeof *out);
+    out->t = c->t;
+    out->dt_last = g->dt_last[r];
+    out->steps = g->steps[r];
+    out->stages = g->stages[r];
+    out->phi_pos = d.pp;
+    out->phi_neg = d.pm;
+    out->phi_net = d.pp + d.pm;
+    out->h1 = d.h1;
+    out->h2 = d.h2;
+    out->dax = d.dax;
+    out->bmin = d.bmin;
+    out->bmax = d.bmax;
+    out->babs_min = d.babs;
+    out->nonfinite = (int32_t)d.nonfinite;
+    if (out->nonfinite) return fail(c, SFT_ERR_NOT_FINITE, "realization %d holds %d non-finite cells", id,
+                                    out->nonfinite);
+    return SFT_OK;
+}
+
+sft_status sft_time(sft_ctx* c, double* t)
+{
+    if (!c || !t) return SFT_ERR_ARG;
+    *t = c->t;
+    return SFT_OK;
+}
+
+sft_status sft_set_time(sft_ctx* c, double t)
+{
+    if (!c || !std::isfinite(t)) return SFT_ERR_ARG;
+    c->t = t;
+    return SFT_OK;
+}
+
+sft_status sft_sync(sft_ctx* c)
+{
+    if (!c) return SFT_ERR_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SFT_OK;
+}
+
+sft_status sft_counts(sft_ctx* c, int32_t id, int64_t* steps, int64_t* stages, int64_t* adv_stages,
+                      int64_t* assim)
+{
+    if (!c) return SFT_ERR_ARG;
+    GridClass* g;
+    int r;
+    if (!find_real(c, id, &g, &r)) return fail(c, SFT_ERR_ARG, "bad realization id %d", id);
+    if (steps) *steps = g->steps[r];
+    if (stages) *stages = g->stages[r];
+    if (adv_stages) *adv_stages = g->adv_stages[r];
+    if (assim) *assim = g->assim[r];
+    return SFT_OK;
+}
+
+sft_status sft_destroy(sft_ctx* c)
+{
+    if (!c) return SFT_ERR_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    for (void* p : c->allocs) (void)hipFree(p);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    for (auto* g : c->grids) {
+        for (auto& kv : g->plans) delete kv.second;
+        delete g;
+    }
+    delete c;
+    return SFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+"""GPU (HIP library through its C ABI) vs FP64 CPU oracle, element by element.
+
+FP64 path: the kernels evaluate the paper's formulas in the oracle's order
+without FMA contraction, so fields agree to the last bit except where a
+reduction order differs (flux-balance sums, device cosine of the observer
+geometry); the bar is rel-L2 <= 1e-12 (stated in the tests), and the
+measured error is printed.  FP32 mixed path: rel-L2 <= 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import gpu_run, max_rel, oracle_run, random_field, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def reals_mix(n, nu=(250.0, 500.0, 750.0, 1000.0), amps=(10.0, 20.0)):
+    out = []
+    for i in range(n):
+        out.append(synth.Realization(nu_km2_s=nu[i % len(nu)],
+                                     **synth.dr_mf(amp_mf=amps[(i // len(nu)) % len(amps)])))
+    return out
+
+
+@pytest.mark.parametrize("nt,np_", [(64, 128), (36, 72), (21, 40)])
+def test_diffusion_only_f64(nt, np_):
+    say(f"case diffusion-only f64 {nt}x{np_}")
+    reals = [synth.Realization(nu_km2_s=nu, d0=0, d2=0, d4=0, m1=0) for nu in (200.0, 600.0, 1000.0)]
+    B0 = np.stack([random_field(nt, np_, 10, i) for i in range(3)])
+    sched = [("advance", 5.0), ("advance", 7.5)]
+    ref, st = oracle_run(B0, reals, sched)
+    got, ens = gpu_run(B0, reals, sched)
+    for r in range(3):
+        c = ens.counts(r)
+        assert c["stages"] == st[r]["stages"] and c["steps"] == st[r]["steps"]
+    e = rel_l2(got, ref)
+    say(f"  rel-L2 {e:.3e}  max-rel {max_rel(got, ref):.3e}  bitwise {np.array_equal(got, ref)}")
+    assert e <= TOL64
+
+
+@pytest.mark.parametrize("nt,np_,scheme", [(64, 128, 0), (36, 72, 0), (21, 40, 0), (36, 72, 1)])
+def test_advection_only_f64(nt, np_, scheme):
+    say(f"case advection-only f64 {nt}x{np_} scheme {scheme}")
+    reals = [synth.Realization(nu_km2_s=0.0, **synth.dr_mf(amp_mf=a)) for a in (10.0, 25.0)]
+    reals[1].d0 = 300.0
+    B0 = np.stack([random_field(nt, np_, 10, 5 + i) for i in range(2)])
+    sched = [("advance", 30.0)]
+    ref, _ = oracle_run(B0, reals, sched, {"adv_scheme": scheme})
+    got, _ = gpu_run(B0, reals, sched, adv_scheme=scheme)
+    e = rel_l2(got, ref)
+    say(f"  rel-L2 {e:.3e}  bitwise {np.array_equal(got, ref)}")
+    assert e <= TOL64
+
+
+def test_config1_plain_f64():
+    """180x360, one realization, 20 pairs, eta = 500, MF 15 m/s, 7 days."""
+    w = synth.config1()
+    nt, np_, reals = w.classes[0]
+    say(f"case {w.name}")
+    B0 = random_field(nt, np_, w.n_pairs)[None]
+    sched = [("advance", w.hours)]
+    ref, st = oracle_run(B0, reals, sched)
+    got, ens = gpu_run(B0, reals, sched)
+    e = rel_l2(got, ref)
+    say(f"  rel-L2 {e:.3e}  max-rel {max_rel(got, ref):.3e}  stages {st[0]['stages']}")
+    assert e <= TOL64
+    d = ens.diagnostics(0)
+    od = oracle.diagnostics(ref[0])
+    for k in ("phi_pos", "phi_neg", "h1", "h2", "dax"):
+        assert d[k] == pytest.approx(od[k], rel=1e-11, abs=1e-9 * abs(od["phi_pos"])), k
+    assert d["bmin"] == od["bmin"] and d["bmax"] == od["bmax"]
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("balance", [0, 1])
+def test_assimilation_f64(kind, balance):
+    nt, np_ = 40, 80
+    say(f"case assimilation kind {kind} balance {balance}")
+    reals = reals_mix(3)
+    for i, r in enumerate(reals):
+        r.flux_balance = balance
+        r.alpha_mu = (4.0, 2.5, 4.0)[i]
+        r.mu_lim = (0.0, 0.1, 0.2)[i]
+        r.lat_lim_deg = (90.0, 60.0, 75.0)[i]
+    B0 = np.stack([random_field(nt, np_, 8, 10 + i) for i in range(3)])
+    obs = synth.observation(B0[0], 2.0, 0)
+    mu = oracle.mu_disk(nt, np_, math.radians(5.0), math.radians(100.0))
+    weight = {0: np.clip(mu, 0, None) ** 3, 1: mu, 2: None}[kind]
+    sched = [("advance", 2.0), ("assim", obs, kind, weight, 5.0, 100.0), ("advance", 3.0)]
+    ref, _ = oracle_run(B0, reals, sched)
+    got, _ = gpu_run(B0, reals, sched)
+    e = rel_l2(got, ref)
+    say(f"  rel-L2 {e:.3e}")
+    assert e <= TOL64
+
+
+@pytest.mark.parametrize("opts", [
+    {"adv_time": 1}, {"diff_time": 1}, {"diff_time": 2, "dt_max": 0.05}, {"ptl_dt": 0.3},
+    {"dt_max": 0.7, "cfl_safety": 0.5}])
+def test_scheme_options_f64(opts):
+    nt, np_ = 24, 48
+    say(f"case options {opts}")
+    reals = reals_mix(2)
+    B0 = np.stack([random_field(nt, np_, 6, 20 + i) for i in range(2)])
+    sched = [("advance", 1.0), ("advance", 2.3)]
+    okw = {"adv_time": opts.get("adv_time", 0), "diff_scheme": opts.get("diff_time", 0),
+           "dt_max": opts.get("dt_max", 0.0), "ptl_dt": opts.get("ptl_dt", 0.0),
+           "safety": opts.get("cfl_safety", 0.9)}
+    ref, _ = oracle_run(B0, reals, sched, okw)
+    got, _ = gpu_run(B0, reals, sched, **opts)
+    e = rel_l2(got, ref)
+    say(f"  rel-L2 {e:.3e}")
+    assert e <= TOL64
+
+
+def test_mixed_precision_matches_oracle():
+    nt, np_ = 64, 128
+    say("case fp32 mixed 64x128, 24 h with hourly assimilation")
+    reals = reals_mix(4)
+    B0 = np.stack([random_field(nt, np_, 12, 30 + i) for i in range(4)])
+    sched = []
+    for h in range(1, 25):
+        sched.append(("advance", float(h)))
+        b0, l0 = synth.observer(h)
+        sched.append(("assim", synth.observation(B0[0], h, h), 2, None, b0, l0))
+    ref, _ = oracle_run(B0, reals, sched)
+    got, _ = gpu_run(B0, reals, sched, precision=1)
+    for r in range(4):
+        e = rel_l2(got[r], ref[r])
+        say(f"  realization {r}: rel-L2 {e:.3e}  max-abs {np.abs(got[r] - ref[r]).max():.3e} G")
+        assert e <= TOL32
+
+
+def test_graph_replay_is_bitwise_equal_to_eager():
+    nt, np_ = 48, 96
+    say("case graph replay vs eager")
+    reals = reals_mix(3)
+    B0 = np.stack([random_field(nt, np_, 6, 40 + i) for i in range(3)])
+    sched = []
+    for h in range(1, 6):
+        sched.append(("advance", float(h)))
+        b0, l0 = synth.observer(h)
+        sched.append(("assim", synth.observation(B0[0], h, h), 2, None, b0, l0))
+    for prec in (0, 1):
+        a, _ = gpu_run(B0, reals, sched, precision=prec)
+        b, _ = gpu_run(B0, reals, sched, precision=prec, use_graphs=1)
+        assert np.array_equal(a, b), prec
+
+
+def test_checkpoint_restart_bitwise():
+    nt, np_ = 32, 64
+    say("case checkpoint / restart")
+    import paper_2501_06377_amd as sft
+    reals = reals_mix(2)
+    B0 = np.stack([random_field(nt, np_, 6, 50 + i) for i in range(2)])
+    full, _ = gpu_run(B0, reals, [("advance", 3.0), ("advance", 6.0)])
+    half, ens = gpu_run(B0, reals, [("advance", 3.0)])
+    t = ens.time()
+    e2 = sft.Ensemble()
+    g = e2.add_grid(nt, np_, reals)
+    e2.set_states(g, half)
+    e2.set_time(t)
+    e2.advance(6.0)
+    assert np.array_equal(e2.get_states(g), full)
+
+
+def test_nonfinite_is_reported():
+    nt, np_ = 16, 32
+    say("case non-finite guard")
+    import paper_2501_06377_amd as sft
+    reals = reals_mix(1)
+    B0 = random_field(nt, np_, 3, 60)[None].copy()
+    B0[0, 5, 7] = np.nan
+    ens = sft.Ensemble()
+    g = ens.add_grid(nt, np_, reals)
+    ens.set_states(g, B0)
+    ens.advance(1.0)
+    d = ens.diagnostics(0)
+    assert d["status"] == sft.SFT_ERR_NOT_FINITE and d["nonfinite"] > 0
+
+
+def test_full_size_ensemble_first_hour_f64():
+    """512x1024, 8 realizations (the ensemble workload's grid and parameter
+    set), first hour plus one assimilation, against the oracle."""
+    w = synth.config2()
+    nt, np_, reals = w.classes[0]
+    say(f"case {w.name}: first hour")
+    f0 = random_field(nt, np_, w.n_pairs)
+    B0 = np.stack([f0] * len(reals))
+    b0, l0 = synth.observer(1.0)
+    sched = [("advance", 1.0), ("assim", synth.observation(f0, 1.0, 1), 2, None, b0, l0)]
+    ref, st = oracle_run(B0, reals, sched)
+    got, ens = gpu_run(B0, reals, sched)
+    for r in range(len(reals)):
+        e = rel_l2(got[r], ref[r])
+        say(f"  realization {r}: stages {st[r]['stages']} rel-L2 {e:.3e}")
+        assert e <= TOL64
