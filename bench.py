@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Benchmark of the surface-flux-transport hot path on one MI355X.
+
+Workload (the ensemble configuration): 8 realizations on a 512 x 1024 grid,
+FP64, diffusivity {250, 500, 750, 1000} km^2/s x meridional amplitude
+{10, 20} m/s, differential rotation 13.2 - 2.4 sin^2 - 1.8 sin^4 deg/day minus
+a 13.2 deg/day frame, a seeded 200-pair bipolar initial field, and hourly
+assimilation of synthetic observations (observed map + N(0, 5 G)) weighted
+mu^4 on the visible disk.  One step = one 1-hour interval for all
+realizations: advection (WENO3-CS(h) + SSPRK(4,3)), RKG2 diffusion,
+assimilation and the FP64 analysis reductions.  The default --steps 655
+covers the configuration's 27.3 days (655 one-hour intervals).
+
+Inputs (initial fields and every observation map) are resident in HBM
+before the timed region.  Every kernel launch of the timed region is
+bracketed by HIP events on the library's stream; the roofline object reports
+the dominant kernel family from those events.  The CPU baseline times the
+FP64 oracle (as is) on the first hours of the same workload.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "realization-cell-updates/s + sim-days/s at 1 GPU; surrogate vs plain @1e-3"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=655)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--graphs", action="store_true", help="replay captured graphs (no per-kernel timing)")
+    return ap.parse_args()
+
+
+def make_obs(f0, hours, dtype=np.float64):
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(max_workers=8) as ex:
+        maps = list(ex.map(lambda h: synth.observation(f0, float(h), h, dtype=dtype), hours))
+    return np.stack(maps)
+
+
+def cpu_baseline(w, f0, obs_first, max_seconds):
+    """FP64 oracle on the first hours of the workload (all realizations)."""
+    import math
+
+    import oracle
+    nt, np_, reals = w.classes[0]
+    B = [f0.copy() for _ in reals]
+    updates = 0
+    t0 = time.perf_counter()
+    hours = 0
+    while True:
+        h = hours + 1
+        b0, l0 = synth.observer(float(h))
+        mu = oracle.mu_disk(nt, np_, math.radians(b0), math.radians(l0))
+        for r, real in enumerate(reals):
+            B[r], st = oracle.advance(B[r], real.flow, real.nu_km2_s, float(hours), float(h))
+            F = oracle.weight_from_mu(mu, real.alpha_mu, real.mu_lim, math.radians(real.lat_lim_deg))
+            B[r] = oracle.assimilate(B[r], obs_first[hours], F, real.flux_balance)
+            updates += nt * np_ * (st["stages"] + 4 * st["steps"] + 1)
+        hours = h
+        el = time.perf_counter() - t0
+        if el >= max_seconds or hours >= len(obs_first):
+            break
+    return {"value": updates / el, "unit": "realization-cell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {hours} h of the ensemble workload, all {len(reals)} realizations "
+                      f"({el:.1f} s of CPU work, FP64 C oracle, OpenMP over rows)",
+            "sim_days_per_s": hours / 24.0 / el}
+
+
+def traffic_from_profiles(kernel_file):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_2501_06377_amd", "csrc", kernel_file), "rb").read()
+    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(realizations would shard across GPUs, see DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2501_06377_amd as sft
+
+    w = synth.config2()
+    nt, np_, reals = w.classes[0]
+    R = len(reals)
+    K, W = args.steps, args.warmup
+    f0 = synth.bipolar_field(nt, np_, synth.bipolar_pairs(w.n_pairs))
+    obs = make_obs(f0, range(1, max(K, W) + 1))
+    dev = torch.device("cuda:0")
+    obs_d = torch.from_numpy(obs).to(dev)
+    init_d = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(f0, (R, nt, np_)))).to(dev)
+    torch.cuda.synchronize()
+
+    ens = sft.Ensemble(use_graphs=1 if args.graphs else 0)
+    gid = ens.add_grid(nt, np_, reals)
+
+    def run(n_steps):
+        for h in range(1, n_steps + 1):
+            ens.advance(float(h))
+            b0, l0 = synth.observer(float(h))
+            ens.assimilate(gid, obs_d[h - 1], None, sft.SFT_WEIGHT_DISK, b0, l0)
+
+    ens.set_states(gid, init_d)
+    run(W)
+    ens.sync()
+    # timed region starts from the initial state at t = 0
+    ens.set_states(gid, init_d)
+    ens.set_time(0.0)
+    c0 = [ens.counts(r) for r in range(R)]
+    ens.set_timing(not args.graphs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(K)
+    ens.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    c1 = [ens.counts(r) for r in range(R)]
+    fams = ens.timing() if not args.graphs else {}
+
+    cells = nt * np_
+    updates = sum(cells * ((b["stages"] - a["stages"]) + (b["adv_stages"] - a["adv_stages"]) +
+                           (b["assim"] - a["assim"])) for a, b in zip(c0, c1))
+    value = updates / wall
+    diag = ens.diagnostics(0)
+    out = {
+        "metric": METRIC, "value": value, "unit": "realization-cell-updates/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": wall / K * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "grid": f"{nt}x{np_}", "realizations": R,
+                   "step": "1 h interval: advection + RKG2 diffusion + mu^4 assimilation + diagnostics",
+                   "simulated_hours": K, "graphs": bool(args.graphs)},
+        "sim_days_per_s": K / 24.0 / wall,
+    }
+    if fams:
+        dom = max(fams, key=lambda k: fams[k]["ms"])
+        f = fams[dom]
+        achieved = f["bytes"] / (f["ms"] * 1e-3) / 1e9
+        traffic = traffic_from_profiles("k_diffusion.hip") if dom.startswith("sts") else None
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "avg_launch_us": f["ms"] / max(f["launches"], 1) * 1e3,
+                           "alg_bytes_per_launch": f["bytes"] / max(f["launches"], 1),
+                           "launches": f["launches"]}
+        out["kernels"] = {k: {"ms": v["ms"], "launches": v["launches"],
+                              "GB_s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
+                          for k, v in fams.items() if v["launches"]}
+        out["kernel_time_frac"] = sum(v["ms"] for v in fams.values()) * 1e-3 / wall
+    out["final_diag_r0"] = {k: diag[k] for k in ("phi_pos", "phi_neg", "dax", "bmin", "bmax")}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, f0, obs[:24], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

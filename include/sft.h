@@ -216,6 +216,28 @@ sft_status sft_sync(sft_ctx* ctx);
 sft_status sft_counts(sft_ctx* ctx, int32_t real_id, int64_t* steps, int64_t* stages,
                       int64_t* adv_stages, int64_t* assim);
 
+/* Kernel families for sft_get_timing. */
+#define SFT_KFAM_STS_STAGE 0   /* diffusion stages j >= 2 (the hot loop)            */
+#define SFT_KFAM_STS_FIRST 1   /* L(Y0) and the first diffusion stage               */
+#define SFT_KFAM_ADV_STAGE 2   /* advection stages (fluxes, divergence, combination) */
+#define SFT_KFAM_ASSIM 3       /* assimilation passes                               */
+#define SFT_KFAM_DIAG 4        /* analysis reductions                               */
+#define SFT_KFAM_OTHER 5       /* copies and increment closes                       */
+#define SFT_KFAM_COUNT 6
+
+/* Turns per-launch event timing on (1) or off (0).  While on, every kernel
+ * launch is bracketed by HIP events on the context's stream and HIP graphs are
+ * not used.  Turning it on clears the accumulated totals. */
+sft_status sft_set_timing(sft_ctx* ctx, int32_t on);
+
+/* Totals for one kernel family since timing was turned on: summed event time
+ * of its launches (ms), number of launches, and the algorithmic bytes those
+ * launches move (the minimum reads and writes of the method: e.g. 40 B per
+ * cell for an FP64 diffusion stage).  Waits for the stream.
+ * Errors: SFT_ERR_ARG (bad family). */
+sft_status sft_get_timing(sft_ctx* ctx, int32_t family, double* total_ms, int64_t* launches,
+                          double* alg_bytes);
+
 /* Releases the context and its device memory (after waiting for its work). */
 sft_status sft_destroy(sft_ctx* ctx);
 

@@ -142,6 +142,18 @@ class Ensemble:
         self._chk(self.L.sft_counts(self.ctx, rid, *[ctypes.byref(x) for x in v]), "sft_counts")
         return dict(zip(("steps", "stages", "adv_stages", "assim"), [x.value for x in v]))
 
+    def set_timing(self, on: bool):
+        self._chk(self.L.sft_set_timing(self.ctx, int(bool(on))), "sft_set_timing")
+
+    def timing(self) -> dict:
+        out = {}
+        for fam, name in enumerate(_abi.KFAM_NAMES):
+            ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+            self._chk(self.L.sft_get_timing(self.ctx, fam, ctypes.byref(ms), ctypes.byref(n),
+                                            ctypes.byref(b)), "sft_get_timing")
+            out[name] = {"ms": ms.value, "launches": n.value, "bytes": b.value}
+        return out
+
     def close(self):
         if self.ctx:
             self.L.sft_destroy(self.ctx)

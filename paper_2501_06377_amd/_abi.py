@@ -21,6 +21,9 @@ SFT_SSPRK43, SFT_FE = 0, 1
 SFT_RKG2, SFT_RKL2, SFT_DIFF_FE = 0, 1, 2
 SFT_DTYPE_F64, SFT_DTYPE_F32 = 0, 1
 SFT_WEIGHT_F, SFT_WEIGHT_MU, SFT_WEIGHT_DISK = 0, 1, 2
+SFT_KFAM_STS_STAGE, SFT_KFAM_STS_FIRST, SFT_KFAM_ADV_STAGE = 0, 1, 2
+SFT_KFAM_ASSIM, SFT_KFAM_DIAG, SFT_KFAM_OTHER, SFT_KFAM_COUNT = 3, 4, 5, 6
+KFAM_NAMES = ("sts_stage", "sts_first", "adv_stage", "assim", "diag", "other")
 
 
 class sft_options(ctypes.Structure):
@@ -73,6 +76,8 @@ SIGNATURES = {
     "sft_set_time": (_I, [_P, _D]),
     "sft_sync": (_I, [_P]),
     "sft_counts": (_I, [_P, _I, _PI64, _PI64, _PI64, _PI64]),
+    "sft_set_timing": (_I, [_P, _I]),
+    "sft_get_timing": (_I, [_P, _I, ctypes.POINTER(_D), _PI64, ctypes.POINTER(_D)]),
     "sft_destroy": (_I, [_P]),
     "sft_status_string": (ctypes.c_char_p, [_I]),
     "sft_last_error": (ctypes.c_char_p, [_P]),

@@ -37,6 +37,7 @@ struct Phase {
 
 struct Plan {
     std::vector<Phase> phases;
+    std::vector<Entry> h_ents;
     Entry* d_ents = nullptr;
     StageCoef* d_coefs = nullptr;
     // per realization of the class
@@ -93,6 +94,19 @@ struct sft_ctx {
     std::map<uint64_t, GraphEntry> graphs;
     std::string err;
     std::vector<void*> allocs;
+    // per-kernel-family event timing (sft_set_timing)
+    struct Pending {
+        hipEvent_t a, b;
+        int fam;
+        double bytes;
+    };
+    bool timing = false;
+    hipEvent_t cur_a = nullptr;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> free_ev;
+    double fam_ms[SFT_KFAM_COUNT] = {};
+    int64_t fam_n[SFT_KFAM_COUNT] = {};
+    double fam_bytes[SFT_KFAM_COUNT] = {};
 };
 
 namespace {
@@ -116,6 +130,54 @@ sft_status fail(sft_ctx* c, sft_status st, const char* fmt, ...)
         if (e_ != hipSuccess)                                                                \
             return fail((ctx), SFT_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));  \
     } while (0)
+
+// ------------------------------------------------------ event timing
+hipEvent_t take_event(sft_ctx* c)
+{
+    if (!c->free_ev.empty()) {
+        hipEvent_t e = c->free_ev.back();
+        c->free_ev.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// Folds finished launches [0, upto) into the per-family totals.
+void harvest(sft_ctx* c, size_t upto)
+{
+    if (upto > c->pending.size()) upto = c->pending.size();
+    if (!upto) return;
+    (void)hipEventSynchronize(c->pending[upto - 1].b);
+    for (size_t i = 0; i < upto; ++i) {
+        auto& q = c->pending[i];
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, q.a, q.b);
+        c->fam_ms[q.fam] += ms;
+        c->fam_n[q.fam] += 1;
+        c->fam_bytes[q.fam] += q.bytes;
+        c->free_ev.push_back(q.a);
+        c->free_ev.push_back(q.b);
+    }
+    c->pending.erase(c->pending.begin(), c->pending.begin() + upto);
+}
+
+inline void tbeg(sft_ctx* c)
+{
+    if (!c->timing) return;
+    c->cur_a = take_event(c);
+    (void)hipEventRecord(c->cur_a, c->stream);
+}
+
+inline void tend(sft_ctx* c, int fam, double bytes)
+{
+    if (!c->timing) return;
+    hipEvent_t b = take_event(c);
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back(sft_ctx::Pending{c->cur_a, b, fam, bytes});
+    if (c->pending.size() > 16384) harvest(c, 8192);
+}
 
 template <typename T>
 sft_status dalloc(sft_ctx* c, T** p, size_t n)
@@ -396,6 +458,7 @@ sft_status build_plan(sft_ctx* c, GridClass* g, double len, Plan** out)
                 p->dt_last[r] = seq[r][i];
             }
     }
+    p->h_ents = ents;
     if (!ents.empty()) {
         sft_status st = dalloc(c, &p->d_ents, ents.size());
         if (st != SFT_OK) {
@@ -447,9 +510,26 @@ WenoConst<float> weno_const_f(double x)
 
 void launch_diag_class(sft_ctx* c, GridClass* g)
 {
+    tbeg(c);
     launch_diag(c->stream, g->R, g->B, g->st_row, g->ct_row, g->w_row, g->sph, g->cph, g->diag_partial,
                 g->red_nblk, g->diag_out, g->nt, g->np);
+    tend(c, SFT_KFAM_DIAG, 8.0 * (double)g->cells() * g->R);
     g->diag_valid = true;
+}
+
+// Algorithmic bytes per cell of one diffusion stage launch: the reads of
+// Y_{j-1}, Y_{j-2}, Y0, L(Y0) and the write of Y_j (FP64), or of d_{j-1},
+// d_{j-2}, L(Y0) and d_j (FP32); an entry's last FP32 stage also reads the
+// FP64 state (and the advection increment) and writes the FP64 state.
+double stage_bytes(const Plan* p, const Phase& ph, int j, bool mixed, size_t cells)
+{
+    double b = 0.0;
+    for (int i = 0; i < ph.n_act[j]; ++i) {
+        const Entry& e = p->h_ents[ph.ent_off + i];
+        if (!mixed) b += 40.0;
+        else b += (j == 2 ? 12.0 : 16.0) + (e.s == j ? 12.0 + (e.pad ? 4.0 : 0.0) : 0.0);
+    }
+    return b * (double)cells;
 }
 
 // Enqueue every phase of a plan.
@@ -459,51 +539,47 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p)
     const bool mixed = o.precision == SFT_FP32_MIXED;
     hipStream_t st = c->stream;
     const int nt = g->nt, np = g->np;
+    const double cells = (double)g->cells();
     const double dth = M_PI / nt, dph = 2.0 * M_PI / np;
     const int upwind = o.adv_scheme == SFT_UPWIND;
     const int ts = o.adv_time == SFT_SSPRK43 ? 0 : 1;
     for (const Phase& ph : p->phases) {
         const Entry* E = p->d_ents + ph.ent_off;
+        const double ne = (double)ph.n_ent;
         if (ph.kind == 0) {
             if (!mixed) {
                 Geom<double> geo{g->sf64, g->denth64, g->denph64};
                 WenoConst<double> wt = weno_const(dth), wp = weno_const(dph);
                 double *B = g->B, *W1 = g->W[0], *W2 = g->W[1];
-                if (ts == 1) {
-                    launch_adv_stage_f64(st, E, ph.n_ent, 0, 1, upwind, g->adv64, geo, wt, wp, B, B, W1,
-                                         nt, np);
-                } else {
-                    launch_adv_stage_f64(st, E, ph.n_ent, 0, 0, upwind, g->adv64, geo, wt, wp, B, B, W1,
-                                         nt, np);
-                    launch_adv_stage_f64(st, E, ph.n_ent, 1, 0, upwind, g->adv64, geo, wt, wp, B, W1, W2,
-                                         nt, np);
-                    launch_adv_stage_f64(st, E, ph.n_ent, 2, 0, upwind, g->adv64, geo, wt, wp, B, W2, W1,
-                                         nt, np);
-                    launch_adv_stage_f64(st, E, ph.n_ent, 3, 0, upwind, g->adv64, geo, wt, wp, B, W1, B,
-                                         nt, np);
+                const double* fin[4] = {B, W1, W2, W1};
+                double* fout[4] = {W1, W2, W1, B};
+                const int nst = ts == 1 ? 1 : 4;
+                for (int k = 0; k < nst; ++k) {
+                    tbeg(c);
+                    launch_adv_stage_f64(st, E, ph.n_ent, k, ts, upwind, g->adv64, geo, wt, wp, B, fin[k],
+                                         fout[k], nt, np);
+                    tend(c, SFT_KFAM_ADV_STAGE, (k == 2 ? 24.0 : 16.0) * cells * ne);
                 }
             } else {
                 Geom<float> geo{g->sf32, g->denth32, g->denph32};
                 WenoConst<float> wt = weno_const_f(dth), wp = weno_const_f(dph);
                 float *A0 = g->A[0], *A1 = g->A[1], *A2 = g->A[2];
-                if (ts == 1) {
-                    launch_adv_stage_mixed(st, E, ph.n_ent, 0, 1, upwind, g->adv32, geo, wt, wp, g->B,
-                                           nullptr, A0, nt, np);
-                } else {
-                    launch_adv_stage_mixed(st, E, ph.n_ent, 0, 0, upwind, g->adv32, geo, wt, wp, g->B,
-                                           nullptr, A1, nt, np);
-                    launch_adv_stage_mixed(st, E, ph.n_ent, 1, 0, upwind, g->adv32, geo, wt, wp, g->B,
-                                           A1, A2, nt, np);
-                    launch_adv_stage_mixed(st, E, ph.n_ent, 2, 0, upwind, g->adv32, geo, wt, wp, g->B,
-                                           A2, A1, nt, np);
-                    launch_adv_stage_mixed(st, E, ph.n_ent, 3, 0, upwind, g->adv32, geo, wt, wp, g->B,
-                                           A1, A0, nt, np);
+                const float* din[4] = {nullptr, A1, A2, A1};
+                float* dout[4] = {ts == 1 ? A0 : A1, A2, A1, A0};
+                const int nst = ts == 1 ? 1 : 4;
+                for (int k = 0; k < nst; ++k) {
+                    tbeg(c);
+                    launch_adv_stage_mixed(st, E, ph.n_ent, k, ts, upwind, g->adv32, geo, wt, wp, g->B,
+                                           din[k], dout[k], nt, np);
+                    tend(c, SFT_KFAM_ADV_STAGE, (k == 0 ? 12.0 : 16.0) * cells * ne);
                 }
             }
         } else if (ph.kind == 1) {
             if (!mixed) {
                 double *B = g->B, *W1 = g->W[0], *W2 = g->W[1], *LY = g->W[2];
+                tbeg(c);
                 launch_diff_first_f64(st, E, ph.n_ent, p->d_coefs, g->dr64, B, LY, W1, nt, np);
+                tend(c, SFT_KFAM_STS_FIRST, 24.0 * cells * ne);
                 for (int j = 2; j <= ph.max_s; ++j) {
                     const double *ym1, *ym2;
                     double* out;
@@ -520,12 +596,18 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p)
                         ym2 = W2;
                         out = W2;
                     }
+                    tbeg(c);
                     launch_diff_stage_f64(st, E, ph.n_act[j], p->d_coefs, j, g->dr64, B, ym1, ym2, LY,
                                           out, nt, np);
+                    tend(c, SFT_KFAM_STS_STAGE, stage_bytes(p, ph, j, false, g->cells()));
                 }
             } else {
                 float *A0 = g->A[0], *P1 = g->A[1], *P2 = g->A[2], *LY = g->A[3];
+                double npad = 0.0;
+                for (int i = 0; i < ph.n_ent; ++i) npad += p->h_ents[ph.ent_off + i].pad ? 1.0 : 0.0;
+                tbeg(c);
                 launch_diff_first_mixed(st, E, ph.n_ent, p->d_coefs, g->dr64, g->B, A0, LY, P1, nt, np);
+                tend(c, SFT_KFAM_STS_FIRST, (16.0 * ne + 4.0 * npad) * cells);
                 for (int j = 2; j <= ph.max_s; ++j) {
                     const float *dm1, *dm2;
                     float* out;
@@ -542,18 +624,26 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p)
                         dm2 = P2;
                         out = P2;
                     }
+                    tbeg(c);
                     launch_diff_stage_mixed(st, E, ph.n_act[j], p->d_coefs, j, g->dr32, g->B, A0, dm1,
                                             dm2, LY, out, nt, np);
+                    tend(c, SFT_KFAM_STS_STAGE, stage_bytes(p, ph, j, true, g->cells()));
                 }
             }
         } else if (ph.kind == 2 || ph.kind == 4) {
+            tbeg(c);
             launch_copy_f64(st, E, ph.n_ent, g->W[0], g->B, g->cells());
+            tend(c, SFT_KFAM_OTHER, 16.0 * cells * ne);
         } else if (ph.kind == 3) {
             // one-stage diffusion calls: B = Y0 + d1 (d1 in A[1])
+            tbeg(c);
             launch_mixed_close(st, E, ph.n_ent, g->B, g->A[0], g->A[1], g->cells());
+            tend(c, SFT_KFAM_OTHER, 24.0 * cells * ne);
         } else if (ph.kind == 5) {
             // flow but no diffusion: B = B + advection increment
+            tbeg(c);
             launch_mixed_close(st, E, ph.n_ent, g->B, g->A[0], nullptr, g->cells());
+            tend(c, SFT_KFAM_OTHER, 20.0 * cells * ne);
         }
     }
 }
@@ -947,7 +1037,7 @@ sft_status sft_advance(sft_ctx* c, double t_end)
             if (c->opt.diag_every_call) launch_diag_class(c, g);
         }
     };
-    if (c->opt.use_graphs) {
+    if (c->opt.use_graphs && !c->timing) {
         const uint64_t key = dbits(len) ^ (c->opt.diag_every_call ? 0x5bd1e995ull : 0);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
@@ -1022,13 +1112,22 @@ sft_status sft_assimilate(sft_ctx* c, int32_t gid, const void* data, const void*
             if (!g->dB) TRY(dalloc(c, &g->dB, (size_t)g->R * n));
             dB = g->dB;
         }
+        tbeg(c);
         launch_assim_delta(c->stream, g->R, g->ar, d_data, d_w, dtype, kind, sb0, cb0, l0, g->B, g->st_row,
                            g->ct_row, g->lat_row, g->w_row, dB, g->assim_partial, g->red_nblk, g->nt,
                            g->np);
         launch_assim_reduce(c->stream, g->R, g->assim_partial, g->red_nblk, g->assim_ratio);
+        tend(c, SFT_KFAM_ASSIM, (double)n * g->R * (24.0 + (kind != SFT_WEIGHT_DISK ? 8.0 : 0.0)));
     }
+    tbeg(c);
     launch_assim_apply(c->stream, g->R, g->ar, d_data, d_w, dtype, kind, sb0, cb0, l0, g->B, dB,
                        g->assim_ratio, g->st_row, g->ct_row, g->lat_row, g->red_nblk, g->nt, g->np);
+    {
+        double per = 0.0;
+        for (auto& p : g->prm)
+            per += p.flux_balance ? 24.0 : 24.0 + (kind != SFT_WEIGHT_DISK ? 8.0 : 0.0);
+        tend(c, SFT_KFAM_ASSIM, per * (double)n);
+    }
     for (int r = 0; r < g->R; ++r) g->assim[r] += 1;
     if (c->opt.diag_every_call) launch_diag_class(c, g);
     else g->diag_valid = false;
@@ -1101,6 +1200,29 @@ sft_status sft_counts(sft_ctx* c, int32_t id, int64_t* steps, int64_t* stages, i
     return SFT_OK;
 }
 
+sft_status sft_set_timing(sft_ctx* c, int32_t on)
+{
+    if (!c) return SFT_ERR_ARG;
+    harvest(c, c->pending.size());
+    for (int f = 0; f < SFT_KFAM_COUNT; ++f) {
+        c->fam_ms[f] = 0.0;
+        c->fam_n[f] = 0;
+        c->fam_bytes[f] = 0.0;
+    }
+    c->timing = on != 0;
+    return SFT_OK;
+}
+
+sft_status sft_get_timing(sft_ctx* c, int32_t fam, double* total_ms, int64_t* launches, double* bytes)
+{
+    if (!c || fam < 0 || fam >= SFT_KFAM_COUNT) return SFT_ERR_ARG;
+    harvest(c, c->pending.size());
+    if (total_ms) *total_ms = c->fam_ms[fam];
+    if (launches) *launches = c->fam_n[fam];
+    if (bytes) *bytes = c->fam_bytes[fam];
+    return SFT_OK;
+}
+
 sft_status sft_destroy(sft_ctx* c)
 {
     if (!c) return SFT_ERR_ARG;
@@ -1109,6 +1231,8 @@ sft_status sft_destroy(sft_ctx* c)
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
         if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
     }
+    harvest(c, c->pending.size());
+    for (hipEvent_t e : c->free_ev) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     for (auto* g : c->grids) {
