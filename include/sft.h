@@ -92,9 +92,13 @@ typedef struct {
     double dt_max;        /* upper bound on a step, hours; 0 = none (default)              */
     double ptl_dt;        /* > 0 splits each diffusion advance into ceil(dt/ptl_dt) calls  */
     int32_t use_graphs;   /* 1 = capture each distinct advance plan in a HIP graph         */
-    int32_t sts_fuse;     /* STS stages per kernel launch: 0 = autotune (default), 1 = one */
+    int32_t sts_fuse;     /* 0 (default) = temporally blocked STS stages, tile shape
+                             picked per grid class by the built-in autotuner;
+                             1 = one stage per kernel launch                          */
     int32_t diag_every_call; /* 1 (default) = refresh diagnostics after advance/assimilate */
-    int32_t reserved[7];
+    int32_t sts_tile;     /* -1 (default) = autotune; >= 0 forces a blocked tile shape
+                             (index into the library's table; see sft_tile_info)      */
+    int32_t reserved[6];
 } sft_options;
 
 /* Per-realization parameters (Sec. "Multiple Realizations"). */
@@ -231,12 +235,24 @@ sft_status sft_counts(sft_ctx* ctx, int32_t real_id, int64_t* steps, int64_t* st
 sft_status sft_set_timing(sft_ctx* ctx, int32_t on);
 
 /* Totals for one kernel family since timing was turned on: summed event time
- * of its launches (ms), number of launches, and the algorithmic bytes those
- * launches move (the minimum reads and writes of the method: e.g. 40 B per
- * cell for an FP64 diffusion stage).  Waits for the stream.
+ * of its launches (ms), number of launches, the algorithmic bytes of the work
+ * they did counted per unit of the method (e.g. 40 B per cell and FP64
+ * diffusion stage, whether or not stages were fused), and the smallest
+ * traffic the launches themselves need (a launch that fuses k stages reads
+ * its inputs once and writes its outputs once).  Waits for the stream.
  * Errors: SFT_ERR_ARG (bad family). */
 sft_status sft_get_timing(sft_ctx* ctx, int32_t family, double* total_ms, int64_t* launches,
-                          double* alg_bytes);
+                          double* alg_bytes, double* min_bytes);
+
+/* Describes blocked tile shape `index` of the given precision: output tile
+ * tx x ty cells, k fused stages, nthreads per block.  Returns SFT_ERR_ARG past
+ * the end of the table (use it to count the shapes). */
+sft_status sft_tile_info(int32_t precision, int32_t index, int32_t* tx, int32_t* ty, int32_t* k,
+                         int32_t* nthreads);
+
+/* Tile shape chosen for a grid class (-1 = one stage per launch), after the
+ * first advance. */
+sft_status sft_tile_choice(sft_ctx* ctx, int32_t grid_id, int32_t* index);
 
 /* Releases the context and its device memory (after waiting for its work). */
 sft_status sft_destroy(sft_ctx* ctx);

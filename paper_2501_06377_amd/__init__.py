@@ -148,11 +148,23 @@ class Ensemble:
     def timing(self) -> dict:
         out = {}
         for fam, name in enumerate(_abi.KFAM_NAMES):
-            ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+            ms, n, b, mb = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
             self._chk(self.L.sft_get_timing(self.ctx, fam, ctypes.byref(ms), ctypes.byref(n),
-                                            ctypes.byref(b)), "sft_get_timing")
-            out[name] = {"ms": ms.value, "launches": n.value, "bytes": b.value}
+                                            ctypes.byref(b), ctypes.byref(mb)), "sft_get_timing")
+            out[name] = {"ms": ms.value, "launches": n.value, "bytes": b.value, "min_bytes": mb.value}
         return out
+
+    def tile_choice(self, gid: int) -> int:
+        v = ctypes.c_int32()
+        self._chk(self.L.sft_tile_choice(self.ctx, gid, ctypes.byref(v)), "sft_tile_choice")
+        return v.value
+
+
+def tile_info(precision: int, index: int):
+    """(tx, ty, k, nthreads) of a blocked tile shape, or None past the table."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    st = load().sft_tile_info(precision, index, *[ctypes.byref(x) for x in v])
+    return tuple(x.value for x in v) if st == _abi.SFT_OK else None
 
     def close(self):
         if self.ctx:

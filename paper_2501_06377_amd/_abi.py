@@ -32,7 +32,7 @@ class sft_options(ctypes.Structure):
                 ("cfl_safety", ctypes.c_double), ("dt_max", ctypes.c_double),
                 ("ptl_dt", ctypes.c_double), ("use_graphs", ctypes.c_int32),
                 ("sts_fuse", ctypes.c_int32), ("diag_every_call", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("sts_tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class sft_params(ctypes.Structure):
@@ -77,7 +77,9 @@ SIGNATURES = {
     "sft_sync": (_I, [_P]),
     "sft_counts": (_I, [_P, _I, _PI64, _PI64, _PI64, _PI64]),
     "sft_set_timing": (_I, [_P, _I]),
-    "sft_get_timing": (_I, [_P, _I, ctypes.POINTER(_D), _PI64, ctypes.POINTER(_D)]),
+    "sft_get_timing": (_I, [_P, _I, ctypes.POINTER(_D), _PI64, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "sft_tile_info": (_I, [_I, _I, _PI, _PI, _PI, _PI]),
+    "sft_tile_choice": (_I, [_P, _I, _PI]),
     "sft_destroy": (_I, [_P]),
     "sft_status_string": (ctypes.c_char_p, [_I]),
     "sft_last_error": (ctypes.c_char_p, [_P]),

@@ -1,0 +1,41 @@
+// Per-cell arithmetic of the diffusion stages, shared by the unfused and the
+// fused (temporally blocked) kernels so that both perform identical
+// floating-point operations in the same order.
+#pragma once
+
+#include "sft_internal.h"
+
+namespace sft {
+
+// The five-diagonal operator at one cell from its neighbours, summed in the
+// table's order k-1, j-1, centre, j+1, k+1.  Every kernel below uses these
+// helpers, so the fused and unfused paths perform identical arithmetic.
+template <typename T>
+__device__ __forceinline__ T L5(const DiffRow<T>& d, T w, T n, T c, T s, T e)
+{
+    T v = d.ph * w;
+    v += d.up * n;
+    v += d.d * c;
+    v += d.dn * s;
+    v += d.ph * e;
+    return v;
+}
+
+// FP64 stage: Y_j = mu Y_{j-1} + nu Y_{j-2} + cy0 Y0 + cL L + cLY0 L(Y0).
+__device__ __forceinline__ double sts_f64(const StageCoef& c, double ym1, double ym2, double y0,
+                                          double L, double ly0)
+{
+    return c.mu * ym1 + c.nu * ym2 + c.cy0 * y0 + c.cL * L + c.cLY0 * ly0;
+}
+
+// FP32 increment stage: d_j = mu d_{j-1} [+ nu d_{j-2}] + (cL L + (cL + cLY0) L(Y0)).
+__device__ __forceinline__ float sts_mixed(const StageCoef& c, float dm1, float dm2, bool has_dm2,
+                                           float L, float ly0)
+{
+    float v = (float)c.mu * dm1;
+    if (has_dm2) v += (float)c.nu * dm2;
+    v += (float)c.cL * L + (float)(c.cL + c.cLY0) * ly0;
+    return v;
+}
+
+}  // namespace sft

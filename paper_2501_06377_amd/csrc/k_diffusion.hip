@@ -12,6 +12,7 @@
 //
 // Layout: fields [r][j][k] (k = phi contiguous).  Entries of a launch are the
 // realizations still active at stage j (blockIdx.z indexes them).
+#include "diff_common.h"
 #include "sft_internal.h"
 
 namespace sft {
@@ -19,9 +20,9 @@ namespace sft {
 constexpr int DTX = 64;   // unfused kernels: 64 x 4 threads, one cell each
 constexpr int DTY = 4;
 
-// L(y) at (j, k) in the table's order k-1, j-1, centre, j+1, k+1.  Pole rows
-// have a zero up/down coefficient; their out-of-sphere neighbour index is
-// clamped to a real row and multiplied by that zero.
+// L(y) at (j, k) read from global memory.  Pole rows have a zero up/down
+// coefficient; their out-of-sphere neighbour index is clamped to a real row
+// and multiplied by that zero.
 template <typename T, typename Y>
 __device__ __forceinline__ T apply_L(const DiffRow<T>& d, const Y* __restrict__ y, int j, int k,
                                      int nt, int np)
@@ -31,19 +32,15 @@ __device__ __forceinline__ T apply_L(const DiffRow<T>& d, const Y* __restrict__ 
     const int ju = j > 0 ? j - 1 : 0;
     const int jd = j < nt - 1 ? j + 1 : nt - 1;
     const size_t row = (size_t)j * np;
-    T v = d.ph * (T)y[row + km];
-    v += d.up * (T)y[(size_t)ju * np + k];
-    v += d.d * (T)y[row + k];
-    v += d.dn * (T)y[(size_t)jd * np + k];
-    v += d.ph * (T)y[row + kp];
-    return v;
+    return L5<T>(d, (T)y[row + km], (T)y[(size_t)ju * np + k], (T)y[row + k],
+                 (T)y[(size_t)jd * np + k], (T)y[row + kp]);
 }
 
 // ------------------------------------------------------------------ FP64
 __global__ __launch_bounds__(256) void diff_first_f64_kernel(
     const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs,
     const DiffRow<double>* __restrict__ drow, const double* __restrict__ B,
-    double* __restrict__ ly0, double* __restrict__ y1, int nt, int np)
+    double* __restrict__ ly0, double* __restrict__ y1, double* __restrict__ y0copy, int nt, int np)
 {
     const Entry e = ents[blockIdx.z];
     const int k = blockIdx.x * DTX + threadIdx.x;
@@ -56,6 +53,7 @@ __global__ __launch_bounds__(256) void diff_first_f64_kernel(
     const double c1 = coefs[e.coef_off + 1].cL;
     ly0[i] = L;
     y1[i] = B[i] + c1 * L;
+    if (y0copy) y0copy[i] = B[i];
 }
 
 __global__ __launch_bounds__(256) void diff_stage_f64_kernel(
@@ -72,18 +70,18 @@ __global__ __launch_bounds__(256) void diff_stage_f64_kernel(
     const StageCoef c = coefs[e.coef_off + jst];
     const double L = apply_L<double>(d, ym1 + base, j, k, nt, np);
     const size_t i = base + (size_t)j * np + k;
-    const double v = c.mu * ym1[i] + c.nu * ym2[i] + c.cy0 * B[i] + c.cL * L + c.cLY0 * ly0[i];
+    const double v = sts_f64(c, ym1[i], ym2[i], B[i], L, ly0[i]);
     double* o = (jst == e.s) ? B : out;
     o[i] = v;
 }
 
 void launch_diff_first_f64(hipStream_t st, const Entry* ents, int n_ent, const StageCoef* coefs,
                            const DiffRow<double>* drow, const double* B, double* ly0, double* y1,
-                           int nt, int np)
+                           double* y0copy, int nt, int np)
 {
     dim3 grid((np + DTX - 1) / DTX, (nt + DTY - 1) / DTY, n_ent);
     hipLaunchKernelGGL(diff_first_f64_kernel, grid, dim3(DTX, DTY), 0, st, ents, coefs, drow, B, ly0,
-                       y1, nt, np);
+                       y1, y0copy, nt, np);
 }
 
 void launch_diff_stage_f64(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs,
@@ -147,9 +145,7 @@ __global__ __launch_bounds__(256) void diff_stage_mixed_kernel(
     const StageCoef c = coefs[e.coef_off + jst];
     const float L = apply_L<float>(d, dm1 + base, j, k, nt, np);
     const size_t i = base + (size_t)j * np + k;
-    float v = (float)c.mu * dm1[i];
-    if (dm2) v += (float)c.nu * dm2[i];
-    v += (float)c.cL * L + (float)(c.cL + c.cLY0) * ly0[i];
+    const float v = sts_mixed(c, dm1[i], dm2 ? dm2[i] : 0.0f, dm2 != nullptr, L, ly0[i]);
     if (jst == e.s) {
         double y0 = B[i];
         if (e.pad) y0 += (double)adv[i];

@@ -1,0 +1,211 @@
+// Temporally blocked diffusion stages: one launch advances every active
+// realization by up to K super-time-stepping stages.
+//
+// A block owns a TY x TX tile of output cells and stages the tile plus a
+// K-cell halo in LDS (phi wraps periodically; rows beyond the poles are held
+// at zero and only ever meet a zero coefficient, so the pole rows stay exact).
+// Each stage recomputes the whole staged region from the previous one, in a
+// double-buffered LDS array (one barrier per stage); the region that is still
+// exact shrinks by one cell per stage, so after k <= K stages the tile
+// interior is exact.  Per cell the previous stage, the one before it, L(Y0)
+// and (paper form) Y0 live in registers.
+//
+// The per-cell arithmetic is the same helper the unfused kernels use, so the
+// results are bitwise identical to the one-stage-per-launch path for every
+// tile shape.
+//
+// FP64 paper form: inputs Y_{j0-1}, Y_{j0-2}, a copy of Y0 and L(Y0).
+// FP32 increment form: inputs d_{j0-1}, d_{j0-2} (absent when j0 = 2) and
+// L(Y0).  An entry whose last stage s falls in this launch writes the final
+// field into the FP64 state B (only the cell's own value of B is read, and
+// only in the increment form), otherwise the last two stages go to out1/out2.
+#include "diff_common.h"
+#include "sft_internal.h"
+
+namespace sft {
+
+template <bool MIXED>
+struct FT {
+    using T = double;
+};
+template <>
+struct FT<true> {
+    using T = float;
+};
+
+template <bool MIXED, int TX, int TY, int K, int NT>
+__global__ __launch_bounds__(NT) void diff_fused_kernel(
+    const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs, int j0,
+    const DiffRow<typename FT<MIXED>::T>* __restrict__ drow,
+    const typename FT<MIXED>::T* __restrict__ in1, const typename FT<MIXED>::T* __restrict__ in2,
+    const double* __restrict__ y0, const typename FT<MIXED>::T* __restrict__ ly0,
+    typename FT<MIXED>::T* __restrict__ out1, typename FT<MIXED>::T* __restrict__ out2,
+    double* __restrict__ B, const float* __restrict__ adv, int nt, int np)
+{
+    using T = typename FT<MIXED>::T;
+    constexpr int LX = TX + 2 * K, LY = TY + 2 * K, NC = LX * LY;
+    constexpr int CPT = (NC + NT - 1) / NT;
+    static_assert(CPT <= 32, "cell mask holds 32 cells per thread");
+    __shared__ T buf[2][NC];
+    __shared__ DiffRow<T> rowc[LY];
+
+    const Entry e = ents[blockIdx.z];
+    const int kk = min(K, e.s - j0 + 1);
+    const bool fin = (j0 + kk - 1 == e.s);
+    const size_t base = (size_t)e.r * nt * np;
+    const int k0 = blockIdx.x * TX, jt0 = blockIdx.y * TY;
+    const int jl0 = jt0 - K, kl0 = k0 - K;
+    const int tid = threadIdx.x;
+    const bool has_in2 = in2 != nullptr;
+
+    for (int l = tid; l < LY; l += NT) {
+        const int j = jl0 + l;
+        DiffRow<T> d;
+        d.up = d.dn = d.ph = d.d = T(0);
+        if (j >= 0 && j < nt) d = drow[(size_t)e.r * nt + j];
+        rowc[l] = d;
+    }
+
+    T ycur[CPT], ym2[CPT], lyr[CPT];
+    double y0r[MIXED ? 1 : CPT];
+    uint32_t act = 0;
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int idx = tid + m * NT;
+        T a = T(0), b = T(0), l = T(0);
+        double z = 0.0;
+        if (idx < NC) {
+            const int ly = idx / LX, lx = idx - (idx / LX) * LX;
+            const int j = jl0 + ly;
+            if (j >= 0 && j < nt) {
+                int k = (kl0 + lx) % np;
+                if (k < 0) k += np;
+                const size_t i = base + (size_t)j * np + k;
+                a = in1[i];
+                if (has_in2) b = in2[i];
+                l = ly0[i];
+                if constexpr (!MIXED) z = y0[i];
+                if (ly >= 1 && ly <= LY - 2 && lx >= 1 && lx <= LX - 2) act |= 1u << m;
+            }
+            buf[0][idx] = a;
+            buf[1][idx] = a;
+        }
+        ycur[m] = a;
+        ym2[m] = b;
+        lyr[m] = l;
+        if constexpr (!MIXED) y0r[m] = z;
+    }
+    __syncthreads();
+
+    int p = 0;
+    for (int i = 0; i < kk; ++i) {
+        const StageCoef c = coefs[e.coef_off + j0 + i];
+        const bool h2 = has_in2 || i > 0;
+        const T* cb = buf[p];
+        T* nb = buf[p ^ 1];
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            if (act & (1u << m)) {
+                const int idx = tid + m * NT;
+                const DiffRow<T> d = rowc[idx / LX];
+                const T L = L5<T>(d, cb[idx - 1], cb[idx - LX], ycur[m], cb[idx + LX], cb[idx + 1]);
+                T v;
+                if constexpr (MIXED) v = sts_mixed(c, ycur[m], ym2[m], h2, L, lyr[m]);
+                else v = sts_f64(c, ycur[m], ym2[m], y0r[m], L, lyr[m]);
+                nb[idx] = v;
+                ym2[m] = ycur[m];
+                ycur[m] = v;
+            }
+        }
+        p ^= 1;
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int idx = tid + m * NT;
+        if (idx >= NC) continue;
+        const int ly = idx / LX, lx = idx - (idx / LX) * LX;
+        if (ly < K || ly >= K + TY || lx < K || lx >= K + TX) continue;
+        const int j = jt0 + ly - K, k = k0 + lx - K;
+        if (j >= nt || k >= np) continue;
+        const size_t gi = base + (size_t)j * np + k;
+        if (fin) {
+            if constexpr (MIXED) {
+                double yv = B[gi];
+                if (e.pad) yv += (double)adv[gi];
+                B[gi] = yv + (double)ycur[m];
+            } else {
+                B[gi] = ycur[m];
+            }
+        } else {
+            out1[gi] = ycur[m];
+            out2[gi] = ym2[m];
+        }
+    }
+}
+
+// ------------------------------------------------------------ configurations
+struct FusedCfg {
+    int tx, ty, k, nt;
+};
+
+static const FusedCfg kCfg64[] = {
+    {64, 16, 4, 256}, {64, 32, 8, 256}, {128, 16, 4, 256}, {32, 32, 4, 256}, {64, 32, 6, 256}};
+static const FusedCfg kCfg32[] = {
+    {64, 16, 4, 256}, {64, 32, 8, 256}, {128, 32, 8, 256}, {128, 16, 8, 256}, {64, 64, 8, 512}};
+
+int fused_config_count(bool mixed) { return mixed ? 5 : 5; }
+
+int fused_config_k(bool mixed, int cfg) { return mixed ? kCfg32[cfg].k : kCfg64[cfg].k; }
+
+void fused_config_desc(bool mixed, int cfg, int* tx, int* ty, int* k, int* nthr)
+{
+    const FusedCfg& c = mixed ? kCfg32[cfg] : kCfg64[cfg];
+    *tx = c.tx;
+    *ty = c.ty;
+    *k = c.k;
+    *nthr = c.nt;
+}
+
+template <bool MIXED, int TX, int TY, int K, int NT>
+static void launch_one(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs, int j0,
+                       const void* drow, const void* in1, const void* in2, const double* y0,
+                       const void* ly0, void* out1, void* out2, double* B, const float* adv, int nt,
+                       int np)
+{
+    using T = typename FT<MIXED>::T;
+    dim3 grid((np + TX - 1) / TX, (nt + TY - 1) / TY, n_act);
+    hipLaunchKernelGGL((diff_fused_kernel<MIXED, TX, TY, K, NT>), grid, dim3(NT), 0, st, ents, coefs, j0,
+                       (const DiffRow<T>*)drow, (const T*)in1, (const T*)in2, y0, (const T*)ly0,
+                       (T*)out1, (T*)out2, B, adv, nt, np);
+}
+
+void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, int n_act,
+                       const StageCoef* coefs, int j0, const void* drow, const void* in1,
+                       const void* in2, const double* y0, const void* ly0, void* out1, void* out2,
+                       double* B, const float* adv, int nt, int np)
+{
+#define L1(M, a, b, c, d) \
+    launch_one<M, a, b, c, d>(st, ents, n_act, coefs, j0, drow, in1, in2, y0, ly0, out1, out2, B, adv, nt, np)
+    if (!mixed) {
+        switch (cfg) {
+        case 0: L1(false, 64, 16, 4, 256); break;
+        case 1: L1(false, 64, 32, 8, 256); break;
+        case 2: L1(false, 128, 16, 4, 256); break;
+        case 3: L1(false, 32, 32, 4, 256); break;
+        default: L1(false, 64, 32, 6, 256); break;
+        }
+    } else {
+        switch (cfg) {
+        case 0: L1(true, 64, 16, 4, 256); break;
+        case 1: L1(true, 64, 32, 8, 256); break;
+        case 2: L1(true, 128, 32, 8, 256); break;
+        case 3: L1(true, 128, 16, 8, 256); break;
+        default: L1(true, 64, 64, 8, 512); break;
+        }
+    }
+#undef L1
+}
+
+}  // namespace sft

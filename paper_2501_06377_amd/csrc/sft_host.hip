@@ -52,8 +52,10 @@ struct GridClass {
     std::vector<int> has_flow;
     // device memory
     double* B = nullptr;
-    double* W[3] = {nullptr, nullptr, nullptr};
-    float* A[4] = {nullptr, nullptr, nullptr, nullptr};
+    // FP64: W0 Y1 / ping, W1 pong, W2 L(Y0), W3 copy of Y0, W4/W5 second pair
+    double* W[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // mixed: A0 advection increment, A1 d1 / ping, A2 pong, A3 L(Y0), A4/A5 second pair
+    float* A[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     double* dB = nullptr;   // FP64 assimilation increment (mixed precision only)
     AdvRow<double>* adv64 = nullptr;
     AdvRow<float>* adv32 = nullptr;
@@ -69,6 +71,7 @@ struct GridClass {
     DiagRec *diag_partial = nullptr, *diag_out = nullptr;
     void* stage_in = nullptr;    // host-upload staging for assimilation inputs (2 maps)
     bool diag_valid = false;
+    int tile = -2;               // blocked tile shape (-1 = unfused, -2 = not chosen yet)
     std::map<uint64_t, Plan*> plans;
     // counters since creation
     std::vector<int64_t> steps, stages, adv_stages, assim;
@@ -98,7 +101,7 @@ struct sft_ctx {
     struct Pending {
         hipEvent_t a, b;
         int fam;
-        double bytes;
+        double bytes, min_bytes;
     };
     bool timing = false;
     hipEvent_t cur_a = nullptr;
@@ -107,6 +110,7 @@ struct sft_ctx {
     double fam_ms[SFT_KFAM_COUNT] = {};
     int64_t fam_n[SFT_KFAM_COUNT] = {};
     double fam_bytes[SFT_KFAM_COUNT] = {};
+    double fam_min[SFT_KFAM_COUNT] = {};
 };
 
 namespace {
@@ -157,6 +161,7 @@ void harvest(sft_ctx* c, size_t upto)
         c->fam_ms[q.fam] += ms;
         c->fam_n[q.fam] += 1;
         c->fam_bytes[q.fam] += q.bytes;
+        c->fam_min[q.fam] += q.min_bytes;
         c->free_ev.push_back(q.a);
         c->free_ev.push_back(q.b);
     }
@@ -170,12 +175,12 @@ inline void tbeg(sft_ctx* c)
     (void)hipEventRecord(c->cur_a, c->stream);
 }
 
-inline void tend(sft_ctx* c, int fam, double bytes)
+inline void tend(sft_ctx* c, int fam, double bytes, double min_bytes = -1.0)
 {
     if (!c->timing) return;
     hipEvent_t b = take_event(c);
     (void)hipEventRecord(b, c->stream);
-    c->pending.push_back(sft_ctx::Pending{c->cur_a, b, fam, bytes});
+    c->pending.push_back(sft_ctx::Pending{c->cur_a, b, fam, bytes, min_bytes < 0 ? bytes : min_bytes});
     if (c->pending.size() > 16384) harvest(c, 8192);
 }
 
@@ -532,6 +537,143 @@ double stage_bytes(const Plan* p, const Phase& ph, int j, bool mixed, size_t cel
     return b * (double)cells;
 }
 
+// Temporally blocked stages 2..s of one diffusion phase: launch g covers
+// stages j0 = 2 + gK .. j0 + K - 1 for the entries with s >= j0 (a prefix of
+// the list); an entry whose last stage falls in a launch writes the state.
+// Buffers rotate between two pairs so no launch writes what it reads.
+void run_fused_groups(sft_ctx* c, GridClass* g, Plan* p, const Phase& ph)
+{
+    const bool mixed = c->opt.precision == SFT_FP32_MIXED;
+    const int K = fused_config_k(mixed, g->tile);
+    const Entry* E = p->d_ents + ph.ent_off;
+    const double cells = (double)g->cells();
+    for (int j0 = 2, grp = 0; j0 <= ph.max_s; j0 += K, ++grp) {
+        const int n_act = ph.n_act[j0];
+        const void *in1, *in2, *ly0, *drow;
+        void *out1, *out2;
+        const double* y0 = nullptr;
+        if (!mixed) {
+            in1 = grp == 0 ? g->W[0] : (grp & 1) ? g->W[4] : g->W[0];
+            in2 = grp == 0 ? g->W[3] : (grp & 1) ? g->W[5] : g->W[1];
+            out1 = (grp & 1) ? g->W[0] : g->W[4];
+            out2 = (grp & 1) ? g->W[1] : g->W[5];
+            ly0 = g->W[2];
+            y0 = g->W[3];
+            drow = g->dr64;
+        } else {
+            in1 = grp == 0 ? g->A[1] : (grp & 1) ? g->A[4] : g->A[1];
+            in2 = grp == 0 ? nullptr : (grp & 1) ? g->A[5] : g->A[2];
+            out1 = (grp & 1) ? g->A[1] : g->A[4];
+            out2 = (grp & 1) ? g->A[2] : g->A[5];
+            ly0 = g->A[3];
+            drow = g->dr32;
+        }
+        // algorithmic bytes (per cell and stage of the method) and the
+        // launch's own minimum traffic (inputs read once, outputs written once)
+        double alg = 0.0, mn = 0.0;
+        for (int i = 0; i < n_act; ++i) {
+            const Entry& e = p->h_ents[ph.ent_off + i];
+            const int kk = std::min(K, e.s - j0 + 1);
+            const bool fin = j0 + kk - 1 == e.s;
+            for (int jj = j0; jj < j0 + kk; ++jj) {
+                if (!mixed) alg += 40.0;
+                else alg += (jj == 2 ? 12.0 : 16.0) + (jj == e.s ? 12.0 + (e.pad ? 4.0 : 0.0) : 0.0);
+            }
+            if (!mixed) mn += fin ? 40.0 : 48.0;
+            else mn += (in2 ? 12.0 : 8.0) + (fin ? 16.0 + (e.pad ? 4.0 : 0.0) : 8.0);
+        }
+        tbeg(c);
+        launch_diff_fused(c->stream, mixed, g->tile, E, n_act, p->d_coefs, j0, drow, in1, in2, y0, ly0,
+                          out1, out2, g->B, g->A[0], g->nt, g->np);
+        tend(c, SFT_KFAM_STS_STAGE, alg * cells, mn * cells);
+    }
+}
+
+// Picks the diffusion-stage kernel for a grid class: one stage per launch or
+// a blocked tile shape, by timing every candidate on the class's own buffers
+// (zeroed first) over all its realizations.  The candidates compute
+// identical results, so the choice changes speed only.
+sft_status choose_tile(sft_ctx* c, GridClass* g)
+{
+    const sft_options& o = c->opt;
+    const bool mixed = o.precision == SFT_FP32_MIXED;
+    if (o.sts_fuse == 1) {
+        g->tile = -1;
+        return SFT_OK;
+    }
+    if (o.sts_tile >= 0) {
+        g->tile = o.sts_tile;
+        return SFT_OK;
+    }
+    const int S = 1000;
+    std::vector<Entry> ents(g->R);
+    for (int r = 0; r < g->R; ++r) ents[r] = Entry{r, S, 0, 0, 1.0};
+    std::vector<StageCoef> coefs(S + 1, StageCoef{0, 0, 0, 0, 0});
+    Entry* d_ents = nullptr;
+    StageCoef* d_coefs = nullptr;
+    HIPCHK(c, hipMalloc((void**)&d_ents, ents.size() * sizeof(Entry)));
+    HIPCHK(c, hipMalloc((void**)&d_coefs, coefs.size() * sizeof(StageCoef)));
+    HIPCHK(c, hipMemcpy(d_ents, ents.data(), ents.size() * sizeof(Entry), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(d_coefs, coefs.data(), coefs.size() * sizeof(StageCoef), hipMemcpyHostToDevice));
+    const size_t n = (size_t)g->R * g->cells();
+    for (int i = 0; i < 6; ++i) {
+        if (!mixed) HIPCHK(c, hipMemsetAsync(g->W[i], 0, n * sizeof(double), c->stream));
+        else if (i != 0) HIPCHK(c, hipMemsetAsync(g->A[i], 0, n * sizeof(float), c->stream));
+    }
+    hipEvent_t ea, eb;
+    HIPCHK(c, hipEventCreate(&ea));
+    HIPCHK(c, hipEventCreate(&eb));
+    auto time_it = [&](auto&& fn, int reps) -> float {
+        fn();  // warm-up
+        (void)hipEventRecord(ea, c->stream);
+        for (int i = 0; i < reps; ++i) fn();
+        (void)hipEventRecord(eb, c->stream);
+        (void)hipEventSynchronize(eb);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ea, eb);
+        return ms / reps;
+    };
+    const int nt = g->nt, np = g->np, R = g->R;
+    float best;
+    int best_cfg = -1;
+    // one stage per launch
+    if (!mixed)
+        best = time_it([&] {
+            launch_diff_stage_f64(c->stream, d_ents, R, d_coefs, 10, g->dr64, g->B, g->W[0], g->W[1],
+                                  g->W[2], g->W[4], nt, np);
+        }, 4);
+    else
+        best = time_it([&] {
+            launch_diff_stage_mixed(c->stream, d_ents, R, d_coefs, 10, g->dr32, g->B, g->A[0], g->A[1],
+                                    g->A[2], g->A[3], g->A[4], nt, np);
+        }, 4);
+    for (int cfg = 0; cfg < fused_config_count(mixed); ++cfg) {
+        const int K = fused_config_k(mixed, cfg);
+        float t;
+        if (!mixed)
+            t = time_it([&] {
+                launch_diff_fused(c->stream, false, cfg, d_ents, R, d_coefs, 10, g->dr64, g->W[0],
+                                  g->W[1], g->W[3], g->W[2], g->W[4], g->W[5], g->B, nullptr, nt, np);
+            }, 3);
+        else
+            t = time_it([&] {
+                launch_diff_fused(c->stream, true, cfg, d_ents, R, d_coefs, 10, g->dr32, g->A[1],
+                                  g->A[2], nullptr, g->A[3], g->A[4], g->A[5], g->B, g->A[0], nt, np);
+            }, 3);
+        if (t / K < best) {
+            best = t / K;
+            best_cfg = cfg;
+        }
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    HIPCHK(c, hipGetLastError());
+    (void)hipFree(d_ents);
+    (void)hipFree(d_coefs);
+    g->tile = best_cfg;
+    return SFT_OK;
+}
+
 // Enqueue every phase of a plan.
 void run_plan(sft_ctx* c, GridClass* g, Plan* p)
 {
@@ -575,31 +717,37 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p)
                 }
             }
         } else if (ph.kind == 1) {
+            const bool fused = g->tile >= 0;
             if (!mixed) {
                 double *B = g->B, *W1 = g->W[0], *W2 = g->W[1], *LY = g->W[2];
                 tbeg(c);
-                launch_diff_first_f64(st, E, ph.n_ent, p->d_coefs, g->dr64, B, LY, W1, nt, np);
-                tend(c, SFT_KFAM_STS_FIRST, 24.0 * cells * ne);
-                for (int j = 2; j <= ph.max_s; ++j) {
-                    const double *ym1, *ym2;
-                    double* out;
-                    if (j == 2) {
-                        ym1 = W1;
-                        ym2 = B;
-                        out = W2;
-                    } else if (j & 1) {
-                        ym1 = W2;
-                        ym2 = W1;
-                        out = W1;
-                    } else {
-                        ym1 = W1;
-                        ym2 = W2;
-                        out = W2;
+                launch_diff_first_f64(st, E, ph.n_ent, p->d_coefs, g->dr64, B, LY, W1,
+                                      fused ? g->W[3] : nullptr, nt, np);
+                tend(c, SFT_KFAM_STS_FIRST, (fused ? 32.0 : 24.0) * cells * ne);
+                if (fused) {
+                    run_fused_groups(c, g, p, ph);
+                } else {
+                    for (int j = 2; j <= ph.max_s; ++j) {
+                        const double *ym1, *ym2;
+                        double* out;
+                        if (j == 2) {
+                            ym1 = W1;
+                            ym2 = B;
+                            out = W2;
+                        } else if (j & 1) {
+                            ym1 = W2;
+                            ym2 = W1;
+                            out = W1;
+                        } else {
+                            ym1 = W1;
+                            ym2 = W2;
+                            out = W2;
+                        }
+                        tbeg(c);
+                        launch_diff_stage_f64(st, E, ph.n_act[j], p->d_coefs, j, g->dr64, B, ym1, ym2,
+                                              LY, out, nt, np);
+                        tend(c, SFT_KFAM_STS_STAGE, stage_bytes(p, ph, j, false, g->cells()));
                     }
-                    tbeg(c);
-                    launch_diff_stage_f64(st, E, ph.n_act[j], p->d_coefs, j, g->dr64, B, ym1, ym2, LY,
-                                          out, nt, np);
-                    tend(c, SFT_KFAM_STS_STAGE, stage_bytes(p, ph, j, false, g->cells()));
                 }
             } else {
                 float *A0 = g->A[0], *P1 = g->A[1], *P2 = g->A[2], *LY = g->A[3];
@@ -608,26 +756,30 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p)
                 tbeg(c);
                 launch_diff_first_mixed(st, E, ph.n_ent, p->d_coefs, g->dr64, g->B, A0, LY, P1, nt, np);
                 tend(c, SFT_KFAM_STS_FIRST, (16.0 * ne + 4.0 * npad) * cells);
-                for (int j = 2; j <= ph.max_s; ++j) {
-                    const float *dm1, *dm2;
-                    float* out;
-                    if (j == 2) {
-                        dm1 = P1;
-                        dm2 = nullptr;
-                        out = P2;
-                    } else if (j & 1) {
-                        dm1 = P2;
-                        dm2 = P1;
-                        out = P1;
-                    } else {
-                        dm1 = P1;
-                        dm2 = P2;
-                        out = P2;
+                if (fused) {
+                    run_fused_groups(c, g, p, ph);
+                } else {
+                    for (int j = 2; j <= ph.max_s; ++j) {
+                        const float *dm1, *dm2;
+                        float* out;
+                        if (j == 2) {
+                            dm1 = P1;
+                            dm2 = nullptr;
+                            out = P2;
+                        } else if (j & 1) {
+                            dm1 = P2;
+                            dm2 = P1;
+                            out = P1;
+                        } else {
+                            dm1 = P1;
+                            dm2 = P2;
+                            out = P2;
+                        }
+                        tbeg(c);
+                        launch_diff_stage_mixed(st, E, ph.n_act[j], p->d_coefs, j, g->dr32, g->B, A0, dm1,
+                                                dm2, LY, out, nt, np);
+                        tend(c, SFT_KFAM_STS_STAGE, stage_bytes(p, ph, j, true, g->cells()));
                     }
-                    tbeg(c);
-                    launch_diff_stage_mixed(st, E, ph.n_act[j], p->d_coefs, j, g->dr32, g->B, A0, dm1,
-                                            dm2, LY, out, nt, np);
-                    tend(c, SFT_KFAM_STS_STAGE, stage_bytes(p, ph, j, true, g->cells()));
                 }
             }
         } else if (ph.kind == 2 || ph.kind == 4) {
@@ -684,6 +836,7 @@ sft_status sft_options_default(sft_options* opt)
     opt->use_graphs = 0;
     opt->sts_fuse = 0;
     opt->diag_every_call = 1;
+    opt->sts_tile = -1;
     return SFT_OK;
 }
 
@@ -700,6 +853,9 @@ sft_status sft_create(sft_ctx** ctx, const sft_options* opt, void* hip_stream)
     if (o.diff_time != SFT_RKG2 && o.diff_time != SFT_RKL2 && o.diff_time != SFT_DIFF_FE)
         return SFT_ERR_ARG;
     if (!(o.cfl_safety > 0.0 && o.cfl_safety <= 1.0) || o.dt_max < 0.0 || o.ptl_dt < 0.0)
+        return SFT_ERR_ARG;
+    if (o.sts_fuse < 0 || o.sts_fuse > 1 || o.sts_tile < -1 ||
+        o.sts_tile >= fused_config_count(o.precision == SFT_FP32_MIXED))
         return SFT_ERR_ARG;
     sft_ctx* c = new sft_ctx();
     c->opt = o;
@@ -745,9 +901,9 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
     TRY(dalloc(c, &g->B, n));
     HIPCHK(c, hipMemset(g->B, 0, n * sizeof(double)));
     if (!mixed) {
-        for (int i = 0; i < 3; ++i) TRY(dalloc(c, &g->W[i], n));
+        for (int i = 0; i < 6; ++i) TRY(dalloc(c, &g->W[i], n));
     } else {
-        for (int i = 0; i < 4; ++i) TRY(dalloc(c, &g->A[i], n));
+        for (int i = 0; i < 6; ++i) TRY(dalloc(c, &g->A[i], n));
         HIPCHK(c, hipMemset(g->A[0], 0, n * sizeof(float)));
     }
     // per-realization tables
@@ -1010,6 +1166,8 @@ sft_status sft_advance(sft_ctx* c, double t_end)
     for (auto* g : c->grids) any |= g->R > 0;
     if (!any) return fail(c, SFT_ERR_STATE, "no realizations");
     c->started = true;
+    for (auto* g : c->grids)
+        if (g->R && g->tile == -2) TRY(choose_tile(c, g));
     const double len = t_end - c->t;
     if (len == 0.0) return SFT_OK;
     std::vector<Plan*> plans;
@@ -1208,18 +1366,43 @@ sft_status sft_set_timing(sft_ctx* c, int32_t on)
         c->fam_ms[f] = 0.0;
         c->fam_n[f] = 0;
         c->fam_bytes[f] = 0.0;
+        c->fam_min[f] = 0.0;
     }
     c->timing = on != 0;
     return SFT_OK;
 }
 
-sft_status sft_get_timing(sft_ctx* c, int32_t fam, double* total_ms, int64_t* launches, double* bytes)
+sft_status sft_get_timing(sft_ctx* c, int32_t fam, double* total_ms, int64_t* launches, double* bytes,
+                          double* min_bytes)
 {
     if (!c || fam < 0 || fam >= SFT_KFAM_COUNT) return SFT_ERR_ARG;
     harvest(c, c->pending.size());
     if (total_ms) *total_ms = c->fam_ms[fam];
     if (launches) *launches = c->fam_n[fam];
     if (bytes) *bytes = c->fam_bytes[fam];
+    if (min_bytes) *min_bytes = c->fam_min[fam];
+    return SFT_OK;
+}
+
+sft_status sft_tile_info(int32_t precision, int32_t index, int32_t* tx, int32_t* ty, int32_t* k,
+                         int32_t* nthreads)
+{
+    const bool mixed = precision == SFT_FP32_MIXED;
+    if ((precision != SFT_FP64 && !mixed) || index < 0 || index >= fused_config_count(mixed))
+        return SFT_ERR_ARG;
+    int a, b, cc, d;
+    fused_config_desc(mixed, index, &a, &b, &cc, &d);
+    if (tx) *tx = a;
+    if (ty) *ty = b;
+    if (k) *k = cc;
+    if (nthreads) *nthreads = d;
+    return SFT_OK;
+}
+
+sft_status sft_tile_choice(sft_ctx* c, int32_t gid, int32_t* index)
+{
+    if (!c || !index || gid < 0 || gid >= (int)c->grids.size()) return SFT_ERR_ARG;
+    *index = c->grids[gid]->tile;
     return SFT_OK;
 }
 

@@ -84,7 +84,7 @@ void launch_copy_f64(hipStream_t st, const Entry* ents, int n_ent, const double*
 //   writes `out`, or B for an entry whose last stage it is.
 void launch_diff_first_f64(hipStream_t st, const Entry* ents, int n_ent, const StageCoef* coefs,
                            const DiffRow<double>* drow, const double* B, double* ly0, double* y1,
-                           int nt, int np);
+                           double* y0copy, int nt, int np);
 void launch_diff_stage_f64(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs,
                            int j, const DiffRow<double>* drow, double* B, const double* ym1,
                            const double* ym2, const double* ly0, double* out, int nt, int np);
@@ -97,6 +97,16 @@ void launch_diff_stage_mixed(hipStream_t st, const Entry* ents, int n_act, const
                              int j, const DiffRow<float>* drow, double* B, const float* adv,
                              const float* dm1, const float* dm2, const float* ly0, float* out,
                              int nt, int np);
+//   Temporally blocked stages j0 .. j0+K-1 (K of tile configuration cfg).
+//   in1/in2/ly0/out1/out2 are double (FP64) or float (mixed) arrays; y0 is the
+//   FP64 copy of Y0 (paper form only).
+int fused_config_count(bool mixed);
+int fused_config_k(bool mixed, int cfg);
+void fused_config_desc(bool mixed, int cfg, int* tx, int* ty, int* k, int* nthr);
+void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, int n_act,
+                       const StageCoef* coefs, int j0, const void* drow, const void* in1,
+                       const void* in2, const double* y0, const void* ly0, void* out1, void* out2,
+                       double* B, const float* adv, int nt, int np);
 //   B = B (+ adv when Entry.pad) (+ d when d != NULL), per entry.
 void launch_mixed_close(hipStream_t st, const Entry* ents, int n_ent, double* B, const float* adv,
                         const float* d, size_t cells);

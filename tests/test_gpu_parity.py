@@ -202,3 +202,35 @@ def test_full_size_ensemble_first_hour_f64():
         e = rel_l2(got[r], ref[r])
         say(f"  realization {r}: stages {st[r]['stages']} rel-L2 {e:.3e}")
         assert e <= TOL64
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_blocked_tiles_bitwise_equal_unfused(prec):
+    """Every blocked tile shape (temporal blocking in LDS) gives bitwise the
+    same fields as one stage per launch: grid 70 x 150 spans several tiles
+    with ragged tails, realizations with different stage counts end in
+    different groups, and advection increments feed the mixed path."""
+    import paper_2501_06377_amd as sft
+    nt, np_ = 70, 150
+    say(f"case tile invariance precision {prec}")
+    reals = [synth.Realization(nu_km2_s=nu, **synth.dr_mf(amp_mf=a))
+             for nu, a in ((200.0, 10.0), (600.0, 20.0), (1000.0, 15.0))]
+    B0 = np.stack([random_field(nt, np_, 8, 70 + i) for i in range(3)])
+    sched = [("advance", 6.0), ("advance", 13.0)]
+    ref, ens = gpu_run(B0, reals, sched, precision=prec, sts_fuse=1)
+    assert ens.tile_choice(0) == -1
+    i = 0
+    while sft.tile_info(prec, i) is not None:
+        got, e2 = gpu_run(B0, reals, sched, precision=prec, sts_tile=i)
+        assert e2.tile_choice(0) == i
+        same = np.array_equal(got, ref)
+        say(f"  tile {i} {sft.tile_info(prec, i)}: bitwise {same}")
+        assert same, i
+        i += 1
+    assert i >= 3
+    auto, e3 = gpu_run(B0, reals, sched, precision=prec)
+    say(f"  autotuned choice {e3.tile_choice(0)}")
+    assert np.array_equal(auto, ref)
+    if prec == 0:
+        oref, _ = oracle_run(B0, reals, sched)
+        assert rel_l2(ref, oref) <= TOL64
