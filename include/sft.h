@@ -220,6 +220,63 @@ sft_status sft_sync(sft_ctx* ctx);
 sft_status sft_counts(sft_ctx* ctx, int32_t real_id, int64_t* steps, int64_t* stages,
                       int64_t* adv_stages, int64_t* assim);
 
+/* ------------------------------------------------------------------------
+ * Learned surrogate of one 1-hour transport interval (no counterpart in the
+ * paper; its plain solver above is both the fallback and the judge).
+ * Network: five 3x3 convolutions 6 -> 64 -> 64 -> 64 -> 64 -> 1 on the
+ * sphere (longitude wraps; the ghost row beyond a pole is the pole row
+ * shifted by half a turn), ReLU after the first four, input channels
+ * (B/500 G, three per-sample parameter features, cos theta, sin theta),
+ * output y with B_next = B + 500 G * y.  BF16 operands on the matrix cores
+ * with FP32 accumulation, FP32 master weights, MSE loss on
+ * (B_target - B)/500, Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * Parameter vector (FP32): for each layer W[c_out][c_in][3][3] then b[c_out].
+ * ------------------------------------------------------------------------ */
+typedef struct sft_net sft_net;
+
+/* Creates a network for nt x np fields and batches of up to max_batch
+ * samples (device memory ~0.6 GB per sample at 512 x 1024).  Parameters
+ * start at zero (load them with sft_net_set_params).  hip_stream as in
+ * sft_create.  Errors: SFT_ERR_ARG, SFT_ERR_OOM, SFT_ERR_HIP. */
+sft_status sft_net_create(sft_net** net, int32_t ntheta, int32_t nphi, int32_t max_batch,
+                          void* hip_stream);
+sft_status sft_net_param_count(const sft_net* net, int64_t* n);
+/* Copies the FP32 parameter vector in / out (host or device memory); setting
+ * parameters resets the Adam moments. */
+sft_status sft_net_set_params(sft_net* net, const float* params, int32_t on_device);
+sft_status sft_net_get_params(sft_net* net, float* params, int32_t on_device);
+/* Gradient vector of the last training step (same layout as the parameters). */
+sft_status sft_net_get_grads(sft_net* net, float* grads, int32_t on_device);
+/* Forward pass on device arrays: b_in [batch][nt][np] (dtype F64 or F32),
+ * feats [batch][3] FP32, y [batch][nt][np] FP32 (may be NULL). */
+sft_status sft_net_forward(sft_net* net, int32_t batch, const void* b_in, int32_t dtype,
+                           const float* feats, float* y);
+/* Copies the bf16 activations (NHWC, uint16 storage) of the last forward pass:
+ * layer 0 = the 16-channel input, 1..4 = hidden layer outputs (64 channels). */
+sft_status sft_net_get_activation(sft_net* net, int32_t layer, void* out);
+/* One training step on device arrays b_in, b_target [batch][nt][np] (dtype F64
+ * or F32) and feats [batch][3]: forward, loss, backward; with apply = 1 also
+ * the Adam update at learning rate lr.  *loss (may be NULL; waits for the
+ * stream) receives the mean squared error of y against (b_target - b_in)/500. */
+sft_status sft_net_train_step(sft_net* net, int32_t batch, const void* b_in, const void* b_target,
+                              int32_t dtype, const float* feats, float lr, int32_t apply,
+                              double* loss);
+sft_status sft_net_sync(sft_net* net);
+sft_status sft_net_destroy(sft_net* net);
+
+/* Advances the context from its time to t_end with the surrogate for grid
+ * class grid_id (the network must be trained for t_end - t = 1 h and have the
+ * class's resolution); other classes take the plain path.  feats: host
+ * [R][3] features of the class's realizations.  check = 1: the plain solver
+ * also runs, each realization keeps the surrogate field only if its relative
+ * L2 distance (FP64) to the plain field is <= tol, else the plain field (the
+ * fallback); err_out (host [R], may be NULL) receives the distances.
+ * check = 0: the surrogate field is taken unverified.  Counts accepted and
+ * rejected intervals in sft_diag.  Errors: SFT_ERR_ARG, SFT_ERR_SHAPE,
+ * SFT_ERR_STATE, SFT_ERR_HIP. */
+sft_status sft_surrogate_advance(sft_ctx* ctx, int32_t grid_id, sft_net* net, const float* feats,
+                                 double t_end, double tol, int32_t check, double* err_out);
+
 /* Kernel families for sft_get_timing. */
 #define SFT_KFAM_STS_STAGE 0   /* diffusion stages j >= 2 (the hot loop)            */
 #define SFT_KFAM_STS_FIRST 1   /* L(Y0) and the first diffusion stage               */

@@ -176,3 +176,89 @@ def tile_info(precision: int, index: int):
             self.close()
         except Exception:
             pass
+
+
+class Net:
+    """The CNN surrogate network (marshalling to the sft_net_* functions).
+
+    Device arrays are torch CUDA tensors; host arrays numpy."""
+
+    def __init__(self, nt: int, np_: int, max_batch: int, stream=None):
+        self.L = load()
+        self.h = ctypes.c_void_p()
+        check(self.L.sft_net_create(ctypes.byref(self.h), nt, np_, max_batch,
+                                    ctypes.c_void_p(stream or 0)), None, "sft_net_create")
+        n = ctypes.c_int64()
+        check(self.L.sft_net_param_count(self.h, ctypes.byref(n)), None, "sft_net_param_count")
+        self.n = n.value
+        self.nt, self.np, self.max_batch = nt, np_, max_batch
+
+    def set_params(self, params):
+        p, code, dev = _ptr(params)
+        count = params.numel() if hasattr(params, "numel") else params.size
+        if code != _abi.SFT_DTYPE_F32 or count != self.n:
+            raise ValueError(f"expected {self.n} float32 parameters")
+        check(self.L.sft_net_set_params(self.h, p, dev), None, "sft_net_set_params")
+
+    def get_params(self, out=None):
+        out = np.empty(self.n, np.float32) if out is None else out
+        p, _, dev = _ptr(out)
+        check(self.L.sft_net_get_params(self.h, p, dev), None, "sft_net_get_params")
+        return out
+
+    def get_grads(self, out=None):
+        out = np.empty(self.n, np.float32) if out is None else out
+        p, _, dev = _ptr(out)
+        check(self.L.sft_net_get_grads(self.h, p, dev), None, "sft_net_get_grads")
+        return out
+
+    def forward(self, b_in, feats, y=None):
+        p, code, _ = _ptr(b_in)
+        f, _, _ = _ptr(feats)
+        yp = _ptr(y)[0] if y is not None else ctypes.c_void_p(0)
+        check(self.L.sft_net_forward(self.h, b_in.shape[0], p, code, f, yp), None, "sft_net_forward")
+        return y
+
+    def activation(self, layer: int, out):
+        """Copies bf16 activations into a torch CUDA tensor (int16 storage)."""
+        check(self.L.sft_net_get_activation(self.h, layer, ctypes.c_void_p(out.data_ptr())), None,
+              "sft_net_get_activation")
+        return out
+
+    def train_step(self, b_in, b_target, feats, lr: float, apply: bool = True) -> float:
+        p, code, _ = _ptr(b_in)
+        t, tcode, _ = _ptr(b_target)
+        if tcode != code:
+            raise ValueError("b_in and b_target must share dtype")
+        f, _, _ = _ptr(feats)
+        loss = ctypes.c_double()
+        check(self.L.sft_net_train_step(self.h, b_in.shape[0], p, t, code, f, float(lr), int(apply),
+                                        ctypes.byref(loss)), None, "sft_net_train_step")
+        return loss.value
+
+    def sync(self):
+        check(self.L.sft_net_sync(self.h), None, "sft_net_sync")
+
+    def close(self):
+        if self.h:
+            self.L.sft_net_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def surrogate_advance(ens: "Ensemble", gid: int, net: Net, feats: np.ndarray, t_end: float, tol: float,
+                      check_: bool = True):
+    """sft_surrogate_advance; returns the per-realization relative L2 distances."""
+    feats = np.ascontiguousarray(feats, dtype=np.float32)
+    R = ens.grids[gid][3]
+    err = np.zeros(R)
+    check(ens.L.sft_surrogate_advance(ens.ctx, gid, net.h, feats.ctypes.data_as(ctypes.c_void_p),
+                                      float(t_end), float(tol), int(check_),
+                                      err.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+          ens.ctx, "sft_surrogate_advance")
+    return err

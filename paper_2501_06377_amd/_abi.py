@@ -81,6 +81,17 @@ SIGNATURES = {
     "sft_tile_info": (_I, [_I, _I, _PI, _PI, _PI, _PI]),
     "sft_tile_choice": (_I, [_P, _I, _PI]),
     "sft_destroy": (_I, [_P]),
+    "sft_net_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, _P]),
+    "sft_net_param_count": (_I, [_P, _PI64]),
+    "sft_net_set_params": (_I, [_P, _P, _I]),
+    "sft_net_get_params": (_I, [_P, _P, _I]),
+    "sft_net_get_grads": (_I, [_P, _P, _I]),
+    "sft_net_forward": (_I, [_P, _I, _P, _I, _P, _P]),
+    "sft_net_get_activation": (_I, [_P, _I, _P]),
+    "sft_net_train_step": (_I, [_P, _I, _P, _P, _I, _P, ctypes.c_float, _I, ctypes.POINTER(_D)]),
+    "sft_net_sync": (_I, [_P]),
+    "sft_net_destroy": (_I, [_P]),
+    "sft_surrogate_advance": (_I, [_P, _I, _P, _P, _D, _D, _I, ctypes.POINTER(_D)]),
     "sft_status_string": (ctypes.c_char_p, [_I]),
     "sft_last_error": (ctypes.c_char_p, [_P]),
 }

@@ -16,6 +16,15 @@
 #include "../../include/sft.h"
 #include "sft_internal.h"
 
+namespace sft {
+sft_status net_predict(sft_net* net, hipStream_t st, int batch, const double* Bin, const float* feats,
+                       float** y_out);
+void net_dims(const sft_net* net, int* H, int* W, int* maxb);
+void cnn_pred(hipStream_t st, const double* Bin, const float* y, double* pred, size_t n);
+void cnn_check(hipStream_t st, const double* pred, const double* plain, double* part, int nblk, int R,
+               size_t n, double tol, double* err, int* accept, double* B);
+}  // namespace sft
+
 using namespace sft;
 
 namespace {
@@ -73,8 +82,13 @@ struct GridClass {
     bool diag_valid = false;
     int tile = -2;               // blocked tile shape (-1 = unfused, -2 = not chosen yet)
     std::map<uint64_t, Plan*> plans;
+    // surrogate buffers (allocated on first use)
+    double* pred = nullptr;
+    float* sfeat = nullptr;
+    double *spart = nullptr, *serr = nullptr;
+    int* sacc = nullptr;
     // counters since creation
-    std::vector<int64_t> steps, stages, adv_stages, assim;
+    std::vector<int64_t> steps, stages, adv_stages, assim, s_acc, s_rej, s_unchk;
     std::vector<double> dt_last;
     size_t cells() const { return (size_t)nt * np; }
 };
@@ -1037,6 +1051,9 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
     g->stages.assign(R, 0);
     g->adv_stages.assign(R, 0);
     g->assim.assign(R, 0);
+    g->s_acc.assign(R, 0);
+    g->s_rej.assign(R, 0);
+    g->s_unchk.assign(R, 0);
     g->dt_last.assign(R, 0.0);
     return SFT_OK;
 }
@@ -1157,9 +1174,16 @@ sft_status sft_get_states(sft_ctx* c, int32_t gid, void* br, int32_t dtype, int3
     return copy_out(c, br, g->B, (size_t)g->R * g->cells(), dtype, on_device);
 }
 
+static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid);
+
 sft_status sft_advance(sft_ctx* c, double t_end)
 {
     if (!c) return SFT_ERR_ARG;
+    return advance_impl(c, t_end, -1);
+}
+
+static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
+{
     if (!(t_end >= c->t) || !std::isfinite(t_end))
         return fail(c, SFT_ERR_ARG, "t_end %.17g before context time %.17g", t_end, c->t);
     bool any = false;
@@ -1171,8 +1195,9 @@ sft_status sft_advance(sft_ctx* c, double t_end)
     const double len = t_end - c->t;
     if (len == 0.0) return SFT_OK;
     std::vector<Plan*> plans;
-    for (auto* g : c->grids) {
-        if (!g->R) {
+    for (size_t gi = 0; gi < c->grids.size(); ++gi) {
+        GridClass* g = c->grids[gi];
+        if (!g->R || (int)gi == skip_gid) {
             plans.push_back(nullptr);
             continue;
         }
@@ -1195,8 +1220,15 @@ sft_status sft_advance(sft_ctx* c, double t_end)
             if (c->opt.diag_every_call) launch_diag_class(c, g);
         }
     };
+    bool work = false;
+    for (Plan* p : plans) work |= p != nullptr;
+    if (!work) {
+        c->t = t_end;
+        return SFT_OK;
+    }
     if (c->opt.use_graphs && !c->timing) {
-        const uint64_t key = dbits(len) ^ (c->opt.diag_every_call ? 0x5bd1e995ull : 0);
+        const uint64_t key = dbits(len) ^ (c->opt.diag_every_call ? 0x5bd1e995ull : 0) ^
+                             ((uint64_t)(skip_gid + 1) << 52);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             GraphEntry ge;
@@ -1318,8 +1350,72 @@ sft_status sft_diagnostics(sft_ctx* c, int32_t id, sft_diag* out)
     out->bmax = d.bmax;
     out->babs_min = d.babs;
     out->nonfinite = (int32_t)d.nonfinite;
+    out->surr_accept = g->s_acc[r];
+    out->surr_reject = g->s_rej[r];
     if (out->nonfinite) return fail(c, SFT_ERR_NOT_FINITE, "realization %d holds %d non-finite cells", id,
                                     out->nonfinite);
+    return SFT_OK;
+}
+
+sft_status sft_surrogate_advance(sft_ctx* c, int32_t gid, sft_net* net, const float* feats, double t_end,
+                                 double tol, int32_t check, double* err_out)
+{
+    if (!c || !net || !feats || gid < 0 || gid >= (int)c->grids.size()) return SFT_ERR_ARG;
+    GridClass* g = c->grids[gid];
+    if (!g->R) return fail(c, SFT_ERR_STATE, "grid %d has no realizations", gid);
+    int H, W, maxb;
+    net_dims(net, &H, &W, &maxb);
+    if (H != g->nt || W != g->np) return fail(c, SFT_ERR_SHAPE, "network grid %dx%d != class %dx%d", H, W,
+                                              g->nt, g->np);
+    if (!(t_end > c->t)) return fail(c, SFT_ERR_ARG, "t_end must be after the context time");
+    const size_t n = g->cells();
+    if (!g->pred) {
+        TRY(dalloc(c, &g->pred, (size_t)g->R * n));
+        TRY(dalloc(c, &g->sfeat, (size_t)g->R * 3));
+        TRY(dalloc(c, &g->spart, (size_t)g->R * g->red_nblk * 2));
+        TRY(dalloc(c, &g->serr, (size_t)g->R));
+        TRY(dalloc(c, &g->sacc, (size_t)g->R));
+    }
+    HIPCHK(c, hipMemcpyAsync(g->sfeat, feats, (size_t)g->R * 3 * sizeof(float), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->started = true;
+    // surrogate prediction for every realization of the class, before the
+    // plain solver touches the state
+    for (int r0 = 0; r0 < g->R; r0 += maxb) {
+        const int nb = std::min(maxb, g->R - r0);
+        float* y = nullptr;
+        TRY(net_predict(net, c->stream, nb, g->B + (size_t)r0 * n, g->sfeat + (size_t)r0 * 3, &y));
+        cnn_pred(c->stream, g->B + (size_t)r0 * n, y, g->pred + (size_t)r0 * n, (size_t)nb * n);
+    }
+    if (check) {
+        // plain advance of everything, then accept the surrogate where it is
+        // within tol (relative L2) of the plain result
+        TRY(advance_impl(c, t_end, -1));
+        cnn_check(c->stream, g->pred, g->B, g->spart, g->red_nblk, g->R, n, tol, g->serr, g->sacc, g->B);
+        std::vector<int> acc(g->R);
+        std::vector<double> err(g->R);
+        HIPCHK(c, hipMemcpyAsync(acc.data(), g->sacc, g->R * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(err.data(), g->serr, g->R * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int r = 0; r < g->R; ++r) {
+            if (acc[r]) g->s_acc[r] += 1;
+            else g->s_rej[r] += 1;
+            if (err_out) err_out[r] = err[r];
+        }
+    } else {
+        TRY(advance_impl(c, t_end, gid));
+        HIPCHK(c, hipMemcpyAsync(g->B, g->pred, (size_t)g->R * n * sizeof(double), hipMemcpyDeviceToDevice,
+                                 c->stream));
+        for (int r = 0; r < g->R; ++r) {
+            g->s_unchk[r] += 1;
+            if (err_out) err_out[r] = -1.0;
+        }
+        c->t = t_end;
+    }
+    if (c->opt.diag_every_call) launch_diag_class(c, g);
+    else g->diag_valid = false;
+    HIPCHK(c, hipGetLastError());
     return SFT_OK;
 }
 

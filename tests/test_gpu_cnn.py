@@ -1,0 +1,211 @@
+"""CNN surrogate kernels (BF16 MFMA, FP32 accumulate) vs the FP64 oracle.
+
+Each layer is checked on identical operands: the oracle is fed the GPU's own
+bf16 activations of the previous layer and the bf16-rounded weights, so only
+the FP32 accumulation order differs before the final bf16 rounding (at most
+one bf16 ulp, on a small fraction of elements).  Gradients are checked with
+the oracle emulating the same bf16 storage points.  The surrogate advance is
+checked for its fallback (tolerance 0 gives the plain solver's field bit for
+bit) and its accept path.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import rel_l2, say
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def bf16_to_f64(t):
+    """bf16 bits in an int16 tensor -> float64 numpy array."""
+    a = t.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+    return a.view(np.float32).astype(np.float64)
+
+
+def random_params(rng, scale_last=0.3):
+    params = cnn.init_params(6, rng)
+    params[-1][0] = rng.standard_normal(params[-1][0].shape) * scale_last / 24.0
+    for layer in params:
+        layer[1] = rng.standard_normal(layer[1].shape) * 0.05
+    return params
+
+
+def flat(params):
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
+
+
+def unflat(vec, like):
+    out, o = [], 0
+    for w, b in like:
+        nw, nb = w.size, b.size
+        out.append([vec[o:o + nw].reshape(w.shape).astype(np.float64),
+                    vec[o + nw:o + nw + nb].astype(np.float64)])
+        o += nw + nb
+    return out
+
+
+def nchw(a, c=None):
+    x = np.transpose(a, (0, 3, 1, 2))
+    return x[:, :c] if c else x
+
+
+def close_bf16(gpu, ref):
+    """At most one bf16 ulp apart, and identical almost everywhere."""
+    diff = np.abs(gpu - ref)
+    tol = 2.0 ** -7 * np.maximum(np.abs(gpu), np.abs(ref)) + 1e-30
+    frac = float(np.mean(gpu != ref))
+    return bool(np.all(diff <= tol)), frac
+
+
+def setup_net(H, W, batch, seed):
+    torch = torch_cuda()
+    import paper_2501_06377_amd as sft
+    rng = np.random.default_rng(seed)
+    params = random_params(rng)
+    # round the master weights to float32 as the library stores them
+    params = unflat(flat(params), params)
+    net = sft.Net(H, W, batch)
+    net.set_params(flat(params))
+    B = torch.tensor(rng.standard_normal((batch, H, W)) * 200.0, dtype=torch.float64, device="cuda")
+    feats = torch.tensor(rng.uniform(0.2, 1.2, (batch, 3)), dtype=torch.float32, device="cuda")
+    return torch, net, params, B, feats
+
+
+def get_acts(torch, net, batch, H, W):
+    acts = []
+    for layer in range(5):
+        c = 16 if layer == 0 else 64
+        t = torch.empty((batch, H, W, c), dtype=torch.int16, device="cuda")
+        net.activation(layer, t)
+        acts.append(nchw(bf16_to_f64(t)))
+    return acts
+
+
+@pytest.mark.parametrize("H,W", [(20, 40), (13, 64)])
+def test_cnn_forward_layers_match_oracle(H, W):
+    say(f"case cnn forward {H}x{W}")
+    batch = 2
+    torch, net, params, B, feats = setup_net(H, W, batch, 11)
+    y = torch.empty((batch, H, W), dtype=torch.float32, device="cuda")
+    net.forward(B, feats, y)
+    torch.cuda.synchronize()
+    acts = get_acts(torch, net, batch, H, W)
+    x0_ref = cnn.bf16_round(cnn.features(B.cpu().numpy(), H, feats.cpu().numpy().astype(np.float64)))
+    ok, frac = close_bf16(acts[0][:, :6], x0_ref)
+    say(f"  input features: within 1 ulp {ok}, differing {frac:.2e}")
+    assert ok and frac < 1e-3 and np.all(acts[0][:, 6:] == 0)
+    for l in range(1, 5):
+        w, b = params[l - 1]
+        xin = acts[l - 1][:, :6] if l == 1 else acts[l - 1]
+        ref = cnn.bf16_round(np.maximum(cnn.conv3x3(xin, cnn.bf16_round(w), b), 0.0))
+        ok, frac = close_bf16(acts[l], ref)
+        say(f"  layer {l}: within 1 ulp {ok}, differing {frac:.2e}")
+        assert ok and frac < 2e-2, l
+    w5, b5 = params[4]
+    yref = cnn.conv3x3(acts[4], w5, b5)[:, 0]
+    e = float(np.abs(y.cpu().numpy() - yref).max() / np.abs(yref).max())
+    say(f"  output layer: max rel {e:.2e}")
+    assert e < 1e-5
+
+
+def test_cnn_gradients_match_oracle():
+    H, W, batch = 16, 32, 2
+    say(f"case cnn gradients {H}x{W}")
+    torch, net, params, B, feats = setup_net(H, W, batch, 12)
+    rng = np.random.default_rng(13)
+    Bt = B + torch.tensor(rng.standard_normal((batch, H, W)) * 3.0, dtype=torch.float64, device="cuda")
+    loss = net.train_step(B, Bt, feats, lr=0.0, apply=False)
+    g = unflat(net.get_grads(), params)
+    acts = get_acts(torch, net, batch, H, W)
+    w5, b5 = params[4]
+    y = cnn.conv3x3(acts[4], w5, b5)
+    t = ((Bt - B).cpu().numpy() / 500.0)[:, None]
+    n = y.size
+    loss_ref = float(np.mean((y - t) ** 2))
+    assert loss == pytest.approx(loss_ref, rel=1e-4)
+    gy = 2.0 * (y - t) / n
+    ref = [None] * 5
+    gx, gw, gb = cnn.conv3x3_backward(acts[4], w5, gy)
+    ref[4] = (gw, gb)
+    dz = cnn.bf16_round(gx * (acts[4] > 0))
+    for l in range(4, 0, -1):
+        w, _ = params[l - 1]
+        xin = acts[l - 1][:, :6] if l == 1 else acts[l - 1]
+        gx, gw, gb = cnn.conv3x3_backward(xin, cnn.bf16_round(w), dz)
+        ref[l - 1] = (gw, gb)
+        if l > 1:
+            dz = cnn.bf16_round(gx * (acts[l - 1] > 0))
+    for l in range(5):
+        ew = rel_l2(g[l][0], ref[l][0])
+        eb = rel_l2(g[l][1], ref[l][1])
+        say(f"  layer {l + 1}: weight-grad rel-L2 {ew:.2e}, bias-grad rel-L2 {eb:.2e}")
+        assert ew < 3e-3 and eb < 3e-3, l
+
+
+def test_training_reduces_loss():
+    torch = torch_cuda()
+    import paper_2501_06377_amd as sft
+    H, W, batch = 16, 32, 4
+    say("case cnn training smoke")
+    rng = np.random.default_rng(14)
+    params = cnn.init_params(6, rng)
+    net = sft.Net(H, W, batch)
+    net.set_params(flat(params))
+    # targets: a fixed smooth map of the input, so a small net can learn it
+    B = torch.tensor(rng.standard_normal((batch, H, W)) * 100.0, dtype=torch.float32, device="cuda")
+    Bt = B + 0.05 * torch.roll(B, 1, dims=2)
+    feats = torch.full((batch, 3), 0.5, dtype=torch.float32, device="cuda")
+    losses = [net.train_step(B, Bt, feats, lr=1e-3) for _ in range(60)]
+    say(f"  loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+    assert losses[-1] < 0.2 * losses[0]
+
+
+def test_surrogate_fallback_is_plain_bitwise_and_accept_path():
+    torch = torch_cuda()
+    import paper_2501_06377_amd as sft
+    from gpu_helpers import random_field
+    nt, np_ = 32, 64
+    say("case surrogate fallback / accept")
+    reals = [synth.Realization(nu_km2_s=500.0, **synth.dr_mf(amp_mf=15.0)),
+             synth.Realization(nu_km2_s=800.0, **synth.dr_mf(amp_mf=20.0))]
+    B0 = np.stack([random_field(nt, np_, 6, 80 + i) for i in range(2)])
+    feats = np.array([[0.5, 1.0, 0.75], [0.8, 1.0, 1.0]], np.float32)
+    rng = np.random.default_rng(15)
+    params = random_params(rng, scale_last=0.01)
+    net = sft.Net(nt, np_, 2)
+    net.set_params(flat(params))
+
+    plain = sft.Ensemble()
+    g = plain.add_grid(nt, np_, reals)
+    plain.set_states(g, B0)
+    plain.advance(1.0)
+    ref = plain.get_states(g)
+
+    ens = sft.Ensemble()
+    g = ens.add_grid(nt, np_, reals)
+    ens.set_states(g, B0)
+    err = sft.surrogate_advance(ens, g, net, feats, 1.0, 0.0)
+    got = ens.get_states(g)
+    assert np.array_equal(got, ref)
+    assert ens.diagnostics(0)["surr_reject"] == 1 and ens.time() == 1.0
+    say(f"  rejected at tol 0, distances {err}")
+
+    # accept path: the state becomes B + 500 y of the network
+    y = torch.empty((2, nt, np_), dtype=torch.float32, device="cuda")
+    net.forward(torch.tensor(B0, device="cuda"), torch.tensor(feats, device="cuda"), y)
+    pred = B0 + 500.0 * y.cpu().numpy().astype(np.float64)
+    ens2 = sft.Ensemble()
+    g = ens2.add_grid(nt, np_, reals)
+    ens2.set_states(g, B0)
+    err2 = sft.surrogate_advance(ens2, g, net, feats, 1.0, 1e30)
+    assert np.array_equal(ens2.get_states(g), pred)
+    assert np.allclose(err2, [rel_l2(pred[r], ref[r]) for r in range(2)], rtol=1e-10)
+    assert ens2.diagnostics(1)["surr_accept"] == 1
