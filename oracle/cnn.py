@@ -162,6 +162,14 @@ def features(B, nt, feats):
     return x
 
 
+def split_bf16(f: np.ndarray):
+    """A float32 value as a pair of bfloat16 values: hi = bf16(f),
+    lo = bf16(f - hi) (exact difference), so hi + lo carries 16 significant bits."""
+    f32 = np.asarray(f, dtype=np.float32).astype(np.float64)
+    hi = bf16_round(f32)
+    return hi, bf16_round(f32 - hi)
+
+
 def bf16_round(a: np.ndarray) -> np.ndarray:
     """Round to bfloat16 (nearest even) and return as float64."""
     f = np.asarray(a, dtype=np.float32)

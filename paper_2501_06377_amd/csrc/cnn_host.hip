@@ -40,7 +40,8 @@ void cnn_pack_last(hipStream_t st, const float* Wm, float* w5t);
 using namespace sft;
 
 namespace {
-// five 3x3 layers: 6 -> 64 -> 64 -> 64 -> 64 -> 1 (weights W[co][ci][3][3], then bias)
+// five 3x3 layers: 6 -> 64 -> 64 -> 64 -> 64 -> 1 (weights W[co][ci][3][3], then bias);
+// the first layer reads 16 packed input slots (field hi/lo sharing weight 0)
 const int kCin[5] = {6, 64, 64, 64, 64};
 const int kCout[5] = {64, 64, 64, 64, 1};
 const int kWGB = 512;     // weight-gradient partial blocks per tap

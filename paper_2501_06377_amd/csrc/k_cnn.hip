@@ -60,7 +60,11 @@ __device__ __forceinline__ bool sphere_src(int j, int k, int H, int W, int& sj, 
 }
 
 // ------------------------------------------------------------ input features
-// X0[b][j][k][0..15]: B/500, three per-sample features, cos(theta), sin(theta), zeros.
+// X0[b][j][k][0..15]: the field f = B/500 as a pair of bf16 values (hi =
+// bf16(f), lo = bf16(f - hi): 16 significant bits, so that a 1-hour increment
+// of ~1% of B is resolved), three per-sample features, cos(theta),
+// sin(theta), zeros.  The first layer applies the field channel's weight to
+// both hi and lo.
 template <typename TB>
 __global__ void cnn_features_kernel(const TB* __restrict__ Bin, const float* __restrict__ feats,
                                     uint16_t* __restrict__ X0, int H, int W)
@@ -71,14 +75,17 @@ __global__ void cnn_features_kernel(const TB* __restrict__ Bin, const float* __r
          p += (size_t)gridDim.x * blockDim.x) {
         const int j = (int)(p / W);
         const double th = (j + 0.5) * (M_PI / H);
+        const float f = (float)((double)Bin[(size_t)b * n + p] / 500.0);
+        const uint16_t hi = f2bf(f);
         float v[16];
-        v[0] = (float)((double)Bin[(size_t)b * n + p] / 500.0);
-        v[1] = feats[b * 3 + 0];
-        v[2] = feats[b * 3 + 1];
-        v[3] = feats[b * 3 + 2];
-        v[4] = (float)cos(th);
-        v[5] = (float)sin(th);
-        for (int c = 6; c < 16; ++c) v[c] = 0.f;
+        v[0] = bf2f(hi);
+        v[1] = f - bf2f(hi);
+        v[2] = feats[b * 3 + 0];
+        v[3] = feats[b * 3 + 1];
+        v[4] = feats[b * 3 + 2];
+        v[5] = (float)cos(th);
+        v[6] = (float)sin(th);
+        for (int c = 7; c < 16; ++c) v[c] = 0.f;
         uint16_t* o = X0 + ((size_t)b * n + p) * 16;
         for (int c = 0; c < 16; ++c) o[c] = f2bf(v[c]);
     }
@@ -290,18 +297,23 @@ __global__ __launch_bounds__(256) void wgrad_mfma_kernel(const uint16_t* __restr
     }
 }
 
-// grad[co][ci][dy][dx] (master layout, ci < cin_out) = sum over blocks, fixed order.
+// grad[co][mc][dy][dx] (master layout) = sum over blocks, fixed order, of the
+// packed slots feeding master channel mc (two slots for the field channel of
+// the first layer, whose weight is shared by the hi and lo parts).
 __global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nblk, int cin, int cin_out,
                                     float* __restrict__ grad)
 {
-    const int n = 9 * 64 * cin;
+    const int n = 9 * 64 * cin_out;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const int tap = e / (64 * cin), rem = e - tap * 64 * cin;
-        const int co = rem / cin, ci = rem - co * cin;
-        if (ci >= cin_out) continue;
+        const int tap = e / (64 * cin_out), rem = e - tap * 64 * cin_out;
+        const int co = rem / cin_out, mc = rem - co * cin_out;
         float s = 0.f;
-        for (int bk = 0; bk < nblk; ++bk) s += part[((size_t)bk * 9 + tap) * 64 * cin + rem];
-        grad[((size_t)co * cin_out + ci) * 9 + tap] = s;
+        for (int bk = 0; bk < nblk; ++bk) {
+            const float* pb = part + ((size_t)bk * 9 + tap) * 64 * cin + (size_t)co * cin;
+            if (cin == 16) s += mc == 0 ? pb[0] + pb[1] : pb[mc + 1];
+            else s += pb[mc];
+        }
+        grad[((size_t)co * cin_out + mc) * 9 + tap] = s;
     }
 }
 
@@ -469,6 +481,16 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
     }
 }
 
+// Master input channel feeding packed slot ci: identity, except for the
+// first layer (cip = 16), whose slots 0 and 1 (field hi and lo) share master
+// channel 0 and slots 2.. take master channels 1.. .
+__device__ __forceinline__ int master_channel(int ci, int cin, int cip)
+{
+    if (cip != 16) return ci < cin ? ci : -1;
+    if (ci <= 1) return 0;
+    return ci - 1 < cin ? ci - 1 : -1;
+}
+
 // master W[co][ci][dy][dx] -> forward layout wf[tap][co][cip] (zero-padded ci)
 // and (if wd) data-gradient layout wd[tap][ci][co].
 __global__ void pack_weights_kernel(const float* __restrict__ Wm, int cin, int cip,
@@ -478,7 +500,8 @@ __global__ void pack_weights_kernel(const float* __restrict__ Wm, int cin, int c
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
         const int tap = e / (64 * cip), rem = e - tap * 64 * cip;
         const int co = rem / cip, ci = rem - co * cip;
-        const float v = ci < cin ? Wm[((size_t)co * cin + ci) * 9 + tap] : 0.f;
+        const int mc = master_channel(ci, cin, cip);
+        const float v = mc >= 0 ? Wm[((size_t)co * cin + mc) * 9 + tap] : 0.f;
         wf[e] = f2bf(v);
         if (wd && ci < cin) wd[((size_t)tap * cin + ci) * 64 + co] = f2bf(v);
     }

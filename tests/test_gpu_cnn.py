@@ -57,12 +57,18 @@ def nchw(a, c=None):
     return x[:, :c] if c else x
 
 
-def close_bf16(gpu, ref):
-    """At most one bf16 ulp apart, and identical almost everywhere."""
+def close_bf16(gpu, ref, atol=1e-30):
+    """At most one bf16 ulp apart (or atol), and identical almost everywhere."""
     diff = np.abs(gpu - ref)
-    tol = 2.0 ** -7 * np.maximum(np.abs(gpu), np.abs(ref)) + 1e-30
-    frac = float(np.mean(gpu != ref))
+    tol = 2.0 ** -7 * np.maximum(np.abs(gpu), np.abs(ref)) + atol
+    frac = float(np.mean((gpu != ref) & (diff > atol)))
     return bool(np.all(diff <= tol)), frac
+
+
+def x6_from_x0(x0):
+    """The 6-channel network input seen by the first layer: the field as
+    hi + lo (its two bf16 slots share one weight), then the five others."""
+    return np.concatenate([x0[:, 0:1] + x0[:, 1:2], x0[:, 2:7]], axis=1)
 
 
 def setup_net(H, W, batch, seed):
@@ -98,13 +104,16 @@ def test_cnn_forward_layers_match_oracle(H, W):
     net.forward(B, feats, y)
     torch.cuda.synchronize()
     acts = get_acts(torch, net, batch, H, W)
-    x0_ref = cnn.bf16_round(cnn.features(B.cpu().numpy(), H, feats.cpu().numpy().astype(np.float64)))
-    ok, frac = close_bf16(acts[0][:, :6], x0_ref)
+    ref6 = cnn.features(B.cpu().numpy(), H, feats.cpu().numpy().astype(np.float64))
+    hi, lo = cnn.split_bf16(ref6[:, 0])
+    assert np.array_equal(acts[0][:, 0], hi) and np.array_equal(acts[0][:, 1], lo)
+    # cos(theta) of an equator row is ~1e-17 on either side: compare it absolutely
+    ok, frac = close_bf16(acts[0][:, 2:7], cnn.bf16_round(ref6[:, 1:]), atol=1e-12)
     say(f"  input features: within 1 ulp {ok}, differing {frac:.2e}")
-    assert ok and frac < 1e-3 and np.all(acts[0][:, 6:] == 0)
+    assert ok and frac < 1e-3 and np.all(acts[0][:, 7:] == 0)
     for l in range(1, 5):
         w, b = params[l - 1]
-        xin = acts[l - 1][:, :6] if l == 1 else acts[l - 1]
+        xin = x6_from_x0(acts[0]) if l == 1 else acts[l - 1]
         ref = cnn.bf16_round(np.maximum(cnn.conv3x3(xin, cnn.bf16_round(w), b), 0.0))
         ok, frac = close_bf16(acts[l], ref)
         say(f"  layer {l}: within 1 ulp {ok}, differing {frac:.2e}")
@@ -138,7 +147,7 @@ def test_cnn_gradients_match_oracle():
     dz = cnn.bf16_round(gx * (acts[4] > 0))
     for l in range(4, 0, -1):
         w, _ = params[l - 1]
-        xin = acts[l - 1][:, :6] if l == 1 else acts[l - 1]
+        xin = x6_from_x0(acts[0]) if l == 1 else acts[l - 1]
         gx, gw, gb = cnn.conv3x3_backward(xin, cnn.bf16_round(w), dz)
         ref[l - 1] = (gw, gb)
         if l > 1:
