@@ -225,15 +225,18 @@ class Net:
               "sft_net_get_activation")
         return out
 
-    def train_step(self, b_in, b_target, feats, lr: float, apply: bool = True) -> float:
+    def train_step(self, b_in, b_target, feats, lr: float, apply: bool = True,
+                   want_loss: bool = True) -> float:
+        """One training step; returns the loss (and waits for it) if want_loss."""
         p, code, _ = _ptr(b_in)
         t, tcode, _ = _ptr(b_target)
         if tcode != code:
             raise ValueError("b_in and b_target must share dtype")
         f, _, _ = _ptr(feats)
-        loss = ctypes.c_double()
+        loss = ctypes.c_double(float("nan"))
         check(self.L.sft_net_train_step(self.h, b_in.shape[0], p, t, code, f, float(lr), int(apply),
-                                        ctypes.byref(loss)), None, "sft_net_train_step")
+                                        ctypes.byref(loss) if want_loss else None),
+              None, "sft_net_train_step")
         return loss.value
 
     def sync(self):
