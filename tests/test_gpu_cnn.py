@@ -115,7 +115,9 @@ def test_cnn_forward_layers_match_oracle(H, W):
         w, b = params[l - 1]
         xin = x6_from_x0(acts[0]) if l == 1 else acts[l - 1]
         ref = cnn.bf16_round(np.maximum(cnn.conv3x3(xin, cnn.bf16_round(w), b), 0.0))
-        ok, frac = close_bf16(acts[l], ref)
+        # outputs near zero come from cancelling sums: FP32 accumulation error
+        # is relative to the layer's scale there, not to the tiny result
+        ok, frac = close_bf16(acts[l], ref, atol=1e-5 * np.abs(ref).max())
         say(f"  layer {l}: within 1 ulp {ok}, differing {frac:.2e}")
         assert ok and frac < 2e-2, l
     w5, b5 = params[4]
