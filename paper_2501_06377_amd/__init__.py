@@ -160,12 +160,6 @@ class Ensemble:
         return v.value
 
 
-def tile_info(precision: int, index: int):
-    """(tx, ty, k, nthreads) of a blocked tile shape, or None past the table."""
-    v = [ctypes.c_int32() for _ in range(4)]
-    st = load().sft_tile_info(precision, index, *[ctypes.byref(x) for x in v])
-    return tuple(x.value for x in v) if st == _abi.SFT_OK else None
-
     def close(self):
         if self.ctx:
             self.L.sft_destroy(self.ctx)
@@ -176,6 +170,13 @@ def tile_info(precision: int, index: int):
             self.close()
         except Exception:
             pass
+
+
+def tile_info(precision: int, index: int):
+    """(tx, ty, k, nthreads) of a blocked tile shape, or None past the table."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    st = load().sft_tile_info(precision, index, *[ctypes.byref(x) for x in v])
+    return tuple(x.value for x in v) if st == _abi.SFT_OK else None
 
 
 class Net:
