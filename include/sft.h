@@ -227,9 +227,9 @@ sft_status sft_counts(sft_ctx* ctx, int32_t real_id, int64_t* steps, int64_t* st
  * sphere (longitude wraps; the ghost row beyond a pole is the pole row
  * shifted by half a turn), ReLU after the first four, input channels
  * (B/500 G, three per-sample parameter features, cos theta, sin theta),
- * output y with B_next = B + 500 G * y.  BF16 operands on the matrix cores
+ * output y with B_next = B + 5 G * y.  BF16 operands on the matrix cores
  * with FP32 accumulation, FP32 master weights, MSE loss on
- * (B_target - B)/500, Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * (B_target - B)/5 G, Adam (beta1 0.9, beta2 0.999, eps 1e-8).
  * Parameter vector (FP32): for each layer W[c_out][c_in][3][3] then b[c_out].
  * ------------------------------------------------------------------------ */
 typedef struct sft_net sft_net;
@@ -257,7 +257,7 @@ sft_status sft_net_get_activation(sft_net* net, int32_t layer, void* out);
 /* One training step on device arrays b_in, b_target [batch][nt][np] (dtype F64
  * or F32) and feats [batch][3]: forward, loss, backward; with apply = 1 also
  * the Adam update at learning rate lr.  *loss (may be NULL; waits for the
- * stream) receives the mean squared error of y against (b_target - b_in)/500. */
+ * stream) receives the mean squared error of y against (b_target - b_in)/5 G. */
 sft_status sft_net_train_step(sft_net* net, int32_t batch, const void* b_in, const void* b_target,
                               int32_t dtype, const float* feats, float lr, int32_t apply,
                               double* loss);

@@ -3,7 +3,8 @@
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  The paper has no learned
 component; this network follows the workload definition of the surrogate:
 five 3x3 convolution layers (C_in -> 64 -> 64 -> 64 -> 64 -> 1), ReLU after
-the first four, a residual output B_out = B_in + 500 G * y, padding that
+the first four, a residual output B_out = B_in + 5 G * y (about one
+hour's typical change, so y is of order one), padding that
 wraps periodically in longitude and reflects across the pole in colatitude
 (the ghost row above row 0 at column k is row 0 at column k + n_phi/2, and
 likewise below the last row), MSE loss on the scaled increment, and Adam with
@@ -20,7 +21,7 @@ from __future__ import annotations
 import numpy as np
 
 CHANNELS = (64, 64, 64, 64, 1)
-OUT_SCALE = 500.0     # gauss per unit of network output
+OUT_SCALE = 5.0       # gauss per unit of network output
 B_SCALE = 500.0       # gauss per unit of the field input channel
 
 

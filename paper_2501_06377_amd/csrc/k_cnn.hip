@@ -371,7 +371,7 @@ __global__ __launch_bounds__(256) void conv_last_fwd_kernel(const uint16_t* __re
     }
 }
 
-// target t = (B_target - B_in)/500; dy = 2 (y - t)/count; per-block FP64 loss sums
+// target t = (B_target - B_in)/5 G; dy = 2 (y - t)/count; per-block FP64 loss sums
 template <typename TB>
 __global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict__ y,
                                                         const TB* __restrict__ Bin,
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict_
     __shared__ double red[256];
     double s = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-        const float t = (float)(((double)Bt[i] - (double)Bin[i]) / 500.0);
+        const float t = (float)(((double)Bt[i] - (double)Bin[i]) / 5.0);
         const float d = y[i] - t;
         dy[i] = (float)(2.0 * (double)d / count);
         s += (double)d * (double)d;
@@ -534,13 +534,13 @@ __global__ void last_reduce_kernel(const float* __restrict__ part, int nblk, flo
 }
 
 // ----------------------------------------------- surrogate prediction / check
-// pred = B_in + 500 y (FP64)
+// pred = B_in + 5 G y (FP64)
 __global__ void surrogate_pred_kernel(const double* __restrict__ Bin, const float* __restrict__ y,
                                       double* __restrict__ pred, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
-        pred[i] = Bin[i] + 500.0 * (double)y[i];
+        pred[i] = Bin[i] + 5.0 * (double)y[i];
 }
 
 // per-block FP64 sums of (a - b)^2 and b^2 per realization

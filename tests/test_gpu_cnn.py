@@ -138,7 +138,7 @@ def test_cnn_gradients_match_oracle():
     acts = get_acts(torch, net, batch, H, W)
     w5, b5 = params[4]
     y = cnn.conv3x3(acts[4], w5, b5)
-    t = ((Bt - B).cpu().numpy() / 500.0)[:, None]
+    t = ((Bt - B).cpu().numpy() / cnn.OUT_SCALE)[:, None]
     n = y.size
     loss_ref = float(np.mean((y - t) ** 2))
     assert loss == pytest.approx(loss_ref, rel=1e-4)
@@ -209,10 +209,10 @@ def test_surrogate_fallback_is_plain_bitwise_and_accept_path():
     assert ens.diagnostics(0)["surr_reject"] == 1 and ens.time() == 1.0
     say(f"  rejected at tol 0, distances {err}")
 
-    # accept path: the state becomes B + 500 y of the network
+    # accept path: the state becomes B + 5 G y of the network
     y = torch.empty((2, nt, np_), dtype=torch.float32, device="cuda")
     net.forward(torch.tensor(B0, device="cuda"), torch.tensor(feats, device="cuda"), y)
-    pred = B0 + 500.0 * y.cpu().numpy().astype(np.float64)
+    pred = B0 + cnn.OUT_SCALE * y.cpu().numpy().astype(np.float64)
     ens2 = sft.Ensemble()
     g = ens2.add_grid(nt, np_, reals)
     ens2.set_states(g, B0)
