@@ -18,23 +18,21 @@ void cnn_features(hipStream_t st, const void* Bin, int dtype, const float* feats
                   int H, int W);
 void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,
                   uint16_t* out, int batch, int H, int W);
-void cnn_conv_dgrad(hipStream_t st, const uint16_t* dz, const uint16_t* wd, float* dxp, int batch, int H,
-                    int W);
+void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
+                  int batch, int H, int W);
+void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, float* dxp, int batch,
+                    int H, int W);
 void cnn_fold_mask(hipStream_t st, const float* dxp, const uint16_t* act, uint16_t* dz, int batch, int H,
                    int W);
-void cnn_wgrad(hipStream_t st, int cin, int cin_out, const uint16_t* x, const uint16_t* dz, float* part,
-               int nblk, float* grad, int batch, int H, int W);
-void cnn_bgrad(hipStream_t st, const uint16_t* dz, long npix, float* part, int nblk, float* gb);
-void cnn_last_fwd(hipStream_t st, const uint16_t* x4, const float* w5t, const float* b5, float* y, int batch,
-                  int H, int W);
-void cnn_loss_grad(hipStream_t st, const float* y, const void* Bin, const void* Bt, int dtype, float* dy,
+void cnn_wgrad(hipStream_t st, int cin, int cout, int cin_out, int cout_out, const uint16_t* x,
+               const uint16_t* dz, float* part, float* bpart, int nblk, float* grad, float* gbias,
+               int batch, int H, int W);
+void cnn_loss_grad(hipStream_t st, const float* y, const void* Bin, const void* Bt, int dtype, uint16_t* dyb,
                    double* part, int nblk, size_t n);
-void cnn_last_bwd(hipStream_t st, const float* dy, const float* w5t, const uint16_t* x4, uint16_t* dz4,
-                  float* part, int nblk, float* gw5, float* gb5, int batch, int H, int W);
 void cnn_adam(hipStream_t st, float* p, const float* g, float* m, float* v, int n, float lr, float b1,
               float b2, float eps, float c1, float c2);
-void cnn_pack(hipStream_t st, const float* Wm, int cin, int cip, uint16_t* wf, uint16_t* wd);
-void cnn_pack_last(hipStream_t st, const float* Wm, float* w5t);
+void cnn_pack(hipStream_t st, const float* Wm, int cin, int cout, int cip, int nout, int cop, uint16_t* wf,
+              uint16_t* wd);
 }  // namespace sft
 
 using namespace sft;
@@ -56,14 +54,14 @@ struct sft_net {
     int64_t woff[5], boff[5];
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     int step = 0;
-    uint16_t* wf[4] = {};
-    uint16_t* wd[4] = {};
-    float* w5t = nullptr;
+    uint16_t* wf[5] = {};   // forward layouts (layer 5: one 32-wide tile, row 0 real)
+    uint16_t* wd[5] = {};   // data-gradient layouts (layers 2..5)
     uint16_t* X0 = nullptr;
     uint16_t* X[4] = {};
-    float *y = nullptr, *dy = nullptr, *dxp = nullptr;
+    float *y = nullptr, *dxp = nullptr;
+    uint16_t* dyb = nullptr;   // output gradient as 16 bf16 channels (channel 0 real)
     uint16_t* dz[2] = {};
-    float *wpart = nullptr, *bpart = nullptr, *lpart = nullptr;
+    float *wpart = nullptr, *bpart = nullptr;
     double* losspart = nullptr;
     int last_batch = 0;
     std::vector<void*> allocs;
@@ -98,9 +96,9 @@ sft_status nalloc(sft_net* net, T** p, size_t count)
 void pack_all(sft_net* net)
 {
     for (int l = 0; l < 4; ++l)
-        cnn_pack(net->stream, net->p + net->woff[l], kCin[l], l == 0 ? 16 : 64, net->wf[l],
+        cnn_pack(net->stream, net->p + net->woff[l], kCin[l], 64, l == 0 ? 16 : 64, 64, 64, net->wf[l],
                  l == 0 ? nullptr : net->wd[l]);
-    cnn_pack_last(net->stream, net->p + net->woff[4], net->w5t);
+    cnn_pack(net->stream, net->p + net->woff[4], 64, 1, 64, 32, 16, net->wf[4], net->wd[4]);
 }
 
 void forward(sft_net* net, int batch, const void* Bin, int dtype, const float* feats)
@@ -111,7 +109,7 @@ void forward(sft_net* net, int batch, const void* Bin, int dtype, const float* f
     cnn_conv_fwd(st, 16, net->X0, net->wf[0], net->p + net->boff[0], net->X[0], batch, H, W);
     for (int l = 1; l < 4; ++l)
         cnn_conv_fwd(st, 64, net->X[l - 1], net->wf[l], net->p + net->boff[l], net->X[l], batch, H, W);
-    cnn_last_fwd(st, net->X[3], net->w5t, net->p + net->boff[4], net->y, batch, H, W);
+    cnn_conv_out(st, net->X[3], net->wf[4], net->p + net->boff[4], net->y, batch, H, W);
     net->last_batch = batch;
 }
 
@@ -155,17 +153,17 @@ sft_status sft_net_create(sft_net** out, int32_t nt, int32_t np, int32_t max_bat
         A_(nalloc(net, &net->wf[l], (size_t)9 * 64 * (l == 0 ? 16 : 64)));
         if (l) A_(nalloc(net, &net->wd[l], (size_t)9 * 64 * 64));
     }
-    A_(nalloc(net, &net->w5t, 9 * 64));
+    A_(nalloc(net, &net->wf[4], (size_t)9 * 32 * 64));
+    A_(nalloc(net, &net->wd[4], (size_t)9 * 64 * 16));
     A_(nalloc(net, &net->X0, B * plane * 16));
     for (int l = 0; l < 4; ++l) A_(nalloc(net, &net->X[l], B * plane * 64));
     A_(nalloc(net, &net->y, B * plane));
-    A_(nalloc(net, &net->dy, B * plane));
+    A_(nalloc(net, &net->dyb, B * plane * 16));
     A_(nalloc(net, &net->dxp, B * (size_t)(nt + 2) * np * 64));
     A_(nalloc(net, &net->dz[0], B * plane * 64));
     A_(nalloc(net, &net->dz[1], B * plane * 64));
     A_(nalloc(net, &net->wpart, (size_t)kWGB * 9 * 64 * 64));
-    A_(nalloc(net, &net->bpart, (size_t)kRED * 64));
-    A_(nalloc(net, &net->lpart, (size_t)kRED * (9 * 64 + 1)));
+    A_(nalloc(net, &net->bpart, (size_t)kWGB * 64));
     A_(nalloc(net, &net->losspart, (size_t)kRED));
 #undef A_
     if (st != SFT_OK) {
@@ -257,18 +255,21 @@ sft_status sft_net_train_step(sft_net* net, int32_t batch, const void* b_in, con
     const int H = net->H, W = net->W;
     const size_t npx = (size_t)batch * H * W;
     forward(net, batch, b_in, dtype, feats);
-    cnn_loss_grad(st, net->y, b_in, b_target, dtype, net->dy, net->losspart, kRED, npx);
-    // last layer: gradient into the layer-4 output (masked by its ReLU), w5 and b5
-    cnn_last_bwd(st, net->dy, net->w5t, net->X[3], net->dz[0], net->lpart, kRED, net->g + net->woff[4],
-                 net->g + net->boff[4], batch, H, W);
+    cnn_loss_grad(st, net->y, b_in, b_target, dtype, net->dyb, net->losspart, kRED, npx);
+    // output layer: weight/bias gradient, then the gradient into the layer-4
+    // output masked by its ReLU
+    cnn_wgrad(st, 64, 16, 64, 1, net->X[3], net->dyb, net->wpart, net->bpart, kWGB, net->g + net->woff[4],
+              net->g + net->boff[4], batch, H, W);
+    cnn_conv_dgrad(st, 16, net->dyb, net->wd[4], net->dxp, batch, H, W);
+    cnn_fold_mask(st, net->dxp, net->X[3], net->dz[0], batch, H, W);
     int cur = 0;
     for (int l = 3; l >= 0; --l) {
         const uint16_t* xin = l == 0 ? net->X0 : net->X[l - 1];
         const int cin = l == 0 ? 16 : 64;
-        cnn_wgrad(st, cin, kCin[l], xin, net->dz[cur], net->wpart, kWGB, net->g + net->woff[l], batch, H, W);
-        cnn_bgrad(st, net->dz[cur], (long)npx, net->bpart, kRED, net->g + net->boff[l]);
+        cnn_wgrad(st, cin, 64, kCin[l], 64, xin, net->dz[cur], net->wpart, net->bpart, kWGB,
+                  net->g + net->woff[l], net->g + net->boff[l], batch, H, W);
         if (l > 0) {
-            cnn_conv_dgrad(st, net->dz[cur], net->wd[l], net->dxp, batch, H, W);
+            cnn_conv_dgrad(st, 64, net->dz[cur], net->wd[l], net->dxp, batch, H, W);
             cnn_fold_mask(st, net->dxp, net->X[l - 1], net->dz[cur ^ 1], batch, H, W);
             cur ^= 1;
         }

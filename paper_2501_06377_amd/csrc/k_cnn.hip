@@ -92,15 +92,18 @@ __global__ void cnn_features_kernel(const TB* __restrict__ Bin, const float* __r
 }
 
 // ------------------------------------------------------ MFMA convolution
-// MODE 0 (forward):  out[b][j][k][co] = relu(bias[co] + sum_tap sum_ci
-//                    w[tap][co][ci] x[b][pad(j+dy-1, k+dx-1)][ci]), bf16 out.
-// MODE 1 (dgrad):    out[b][q+1][k][ci] = sum_tap sum_co w[tap][ci][co]
-//                    g[b][q-dy+1][k-dx+1][co] for padded rows q in [-1, H]
-//                    (g zero outside [0, H)), FP32 out, H+2 rows.
-// Weight layout: w[tap][n][k] with the K index (input of the GEMM) contiguous.
+// MODE 0 (hidden layer):  out[b][j][k][co] = relu(bias[co] + sum_tap sum_ci
+//                         w[tap][co][ci] x[b][pad(j+dy-1, k+dx-1)][ci]), bf16, 64 channels.
+// MODE 1 (data gradient): out[b][q+1][k][ci] = sum_tap sum_co w[tap][ci][co]
+//                         g[b][q-dy+1][k-dx+1][co] for padded rows q in [-1, H]
+//                         (g zero outside [0, H)), FP32, H+2 rows, 64 channels.
+// MODE 2 (output layer):  y[b][j][k] = bias[0] + sum_tap sum_ci w[tap][0][ci] x[...][ci],
+//                         FP32 (the weight rows 1..31 of the N tile are zero).
+// Weight layout: w[tap][n][k] with the GEMM's K index (input channel) contiguous;
+// NTN = number of 32-wide output tiles (2 for 64 outputs, 1 for the output layer).
 constexpr int CTY = 8, CTX = 32;      // output tile: 8 rows x 32 columns, 2 waves
 
-template <int CIN, int MODE>
+template <int CIN, int MODE, int NTN>
 __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restrict__ x,
                                                         const uint16_t* __restrict__ w,
                                                         const float* __restrict__ bias,
@@ -109,11 +112,12 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
     constexpr int CP = CIN + 8;                 // padded channel stride in LDS
     constexpr int TR = CTY + 2, TC = CTX + 2;   // staged tile with a one-cell halo
     constexpr int NCH = CIN / 16;               // K chunks per tap
+    constexpr int NOUT = NTN * 32;
     __shared__ __attribute__((aligned(16))) uint16_t tile[TR * TC * CP];
 
     const int b = blockIdx.z;
     const int k0 = blockIdx.x * CTX;
-    const int r0 = (MODE == 0 ? 0 : -1) + blockIdx.y * CTY;   // first output row of the tile
+    const int r0 = (MODE == 1 ? -1 : 0) + blockIdx.y * CTY;   // first output row of the tile
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const size_t plane = (size_t)H * W;
     const uint16_t* xb = x + (size_t)b * plane * CIN;
@@ -125,7 +129,7 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
         const int tr = pix / TC, tc = pix - (pix / TC) * TC;
         const int j = r0 - 1 + tr, k = k0 - 1 + tc;
         uint4 val = make_uint4(0, 0, 0, 0);
-        if (MODE == 0) {
+        if (MODE != 1) {
             int sj, sk;
             if (sphere_src(j, k, H, W, sj, sk))
                 val = *(const uint4*)(xb + ((size_t)sj * W + sk) * CIN + cv * 8);
@@ -136,31 +140,31 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
     }
     __syncthreads();
 
-    f32x16 acc[4][2];
+    f32x16 acc[4][NTN];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n)
+        for (int n = 0; n < NTN; ++n)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
 
     const int col = lane & 31, kh = lane >> 5;
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap - (tap / 3) * 3;
-        const int oy = MODE == 0 ? dy : 2 - dy, ox = MODE == 0 ? dx : 2 - dx;
+        const int oy = MODE == 1 ? 2 - dy : dy, ox = MODE == 1 ? 2 - dx : dx;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int kb = ch * 16 + kh * 8;
-            bf16x8 bfr[2];
+            bf16x8 bfr[NTN];
 #pragma unroll
-            for (int n = 0; n < 2; ++n)
-                bfr[n] = *(const bf16x8*)(w + ((size_t)tap * 64 + n * 32 + col) * CIN + kb);
+            for (int n = 0; n < NTN; ++n)
+                bfr[n] = *(const bf16x8*)(w + ((size_t)tap * NOUT + n * 32 + col) * CIN + kb);
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int tr = wv * 4 + m + oy;
                 const bf16x8 a = *(const bf16x8*)(tile + (tr * TC + col + ox) * CP + kb);
 #pragma unroll
-                for (int n = 0; n < 2; ++n)
+                for (int n = 0; n < NTN; ++n)
                     acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[n], acc[m][n], 0, 0, 0);
             }
         }
@@ -170,12 +174,12 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         const int row = r0 + wv * 4 + m;
-        const int rlim = MODE == 0 ? H : H + 1;
-        if (row > rlim - 1 || row < (MODE == 0 ? 0 : -1)) continue;
+        if (MODE == 1 ? (row < -1 || row > H) : (row >= H)) continue;
 #pragma unroll
-        for (int n = 0; n < 2; ++n) {
+        for (int n = 0; n < NTN; ++n) {
             const int c = n * 32 + col;
-            const float bv = MODE == 0 ? bias[c] : 0.f;
+            if (MODE == 2 && c != 0) continue;
+            const float bv = MODE == 1 ? 0.f : bias[c];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int px = 8 * (r >> 2) + 4 * kh + (r & 3);
@@ -185,9 +189,11 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
                     float v = acc[m][n][r] + bv;
                     v = v > 0.f ? v : 0.f;
                     ((uint16_t*)out)[((size_t)b * plane + (size_t)row * W + k) * 64 + c] = f2bf(v);
-                } else {
+                } else if (MODE == 1) {
                     ((float*)out)[((size_t)b * (H + 2) * W + (size_t)(row + 1) * W + k) * 64 + c] =
                         acc[m][n][r];
+                } else {
+                    ((float*)out)[(size_t)b * plane + (size_t)row * W + k] = acc[m][n][r] + bv;
                 }
             }
         }
@@ -209,107 +215,129 @@ __global__ void fold_mask_kernel(const float* __restrict__ dxp, const uint16_t* 
         const int j = (int)(p / W), k = (int)(p - (size_t)j * W);
         const float* g = dxp + (size_t)b * (H + 2) * W * 64;
         float v = g[((size_t)(j + 1) * W + k) * 64 + c];
-        const int ks = (k + W / 2) % W;
-        if (j == 0) v += g[((size_t)0 * W + ks) * 64 + c];
-        if (j == H - 1) v += g[((size_t)(H + 1) * W + ks) * 64 + c];
+        if (j == 0 || j == H - 1) {
+            const int ks = k + W / 2 < W ? k + W / 2 : k - W / 2;
+            if (j == 0) v += g[(size_t)ks * 64 + c];
+            if (j == H - 1) v += g[((size_t)(H + 1) * W + ks) * 64 + c];
+        }
         const uint16_t a = act[(size_t)b * n + e];
         dz[(size_t)b * n + e] = (bf2f(a) > 0.f) ? f2bf(v) : (uint16_t)0;
     }
 }
 
 // ------------------------------------------------------------ weight grad
-// part[blk][tap][co][ci] = sum over the block's pixels p of
-//   x[pad(p + tap)][ci] * dz[p][co]   (FP32, MFMA with pixels as K).
-// Waves: (ci tile, co tile) in {0,1} x {0,1}; CIN = 16 uses ci tile 0 only,
-// zero-extended to 32 rows.
-constexpr int WG_PX = 64;    // pixels (one row segment) per staging step
+// For one row segment of WG_PX output pixels at a time, every tap:
+//   part[blk][tap][co][ci] += sum_p x[pad(p + tap)][ci] * dz[p][co]
+// (MFMA with pixels as K; x staged transposed, once per column shift dx),
+// and bpart[blk][co] += sum_p dz[p][co] (bias gradient).  Wave (ci tile, co
+// tile) accumulates all nine taps, reusing each dz fragment nine times.
+// CIN or COUT of 16 are zero-extended to one 32-row tile.
+constexpr int WG_PX = 64;
 
-template <int CIN>
-__global__ __launch_bounds__(256) void wgrad_mfma_kernel(const uint16_t* __restrict__ x,
-                                                         const uint16_t* __restrict__ dz,
-                                                         float* __restrict__ part, int batch, int H,
-                                                         int W)
+template <int CIN, int COUT>
+__global__ __launch_bounds__(64 * (CIN < 32 ? 1 : CIN / 32) * (COUT < 32 ? 1 : COUT / 32))
+void wgrad_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restrict__ dz,
+                       float* __restrict__ part, float* __restrict__ bpart, int batch, int H, int W)
 {
-    constexpr int CIP = CIN < 32 ? 32 : CIN;    // ci rows held in LDS
-    constexpr int PS = WG_PX + 8;               // pixel stride of a channel row (bf16)
-    __shared__ __attribute__((aligned(16))) uint16_t xs[CIP * PS];
-    __shared__ __attribute__((aligned(16))) uint16_t gs[64 * PS];
+    constexpr int CIP = CIN < 32 ? 32 : CIN, COP = COUT < 32 ? 32 : COUT;
+    constexpr int NCI = CIP / 32, NCO = COP / 32, NT = 64 * NCI * NCO;
+    constexpr int PS = WG_PX + 8;      // pixel stride of one channel row (bf16)
+    __shared__ __attribute__((aligned(16))) uint16_t xs[3 * 3 * CIP * PS];
+    __shared__ __attribute__((aligned(16))) uint16_t gs[COP * PS];
 
-    const int tap = blockIdx.y, dy = tap / 3, dx = tap - (tap / 3) * 3;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int ci_t = wv >> 1, co_t = wv & 1;
+    const int ci_t = wv / NCO, co_t = wv - (wv / NCO) * NCO;
     const int col = lane & 31, kh = lane >> 5;
-    const int segs_per_row = (W + WG_PX - 1) / WG_PX;
-    const long nseg = (long)batch * H * segs_per_row;
+    const int segs = (W + WG_PX - 1) / WG_PX;
+    const long nseg = (long)batch * H * segs;
 
-    if (CIN < 32) {   // zero rows CIN..31 once
-        for (int e = tid; e < (CIP - CIN) * PS; e += 256) xs[CIN * PS + e] = 0;
-    }
-    f32x16 acc;
+    for (int e = tid; e < 3 * 3 * CIP * PS; e += NT) xs[e] = 0;
+    for (int e = tid; e < COP * PS; e += NT) gs[e] = 0;
+    f32x16 acc[9];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
+    float bsum = 0.f;
 
-    for (long sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
-        const int b = (int)(sgi / ((long)H * segs_per_row));
-        const long rem = sgi - (long)b * H * segs_per_row;
-        const int j = (int)(rem / segs_per_row);
-        const int k0 = (int)(rem - (long)j * segs_per_row) * WG_PX;
+    for (long sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+        const int b = (int)(sg / ((long)H * segs));
+        const long rem = sg - (long)b * H * segs;
+        const int j = (int)(rem / segs);
+        const int k0 = (int)(rem - (long)j * segs) * WG_PX;
         __syncthreads();
-        // stage x (shifted by the tap, sphere padding) and dz, transposed to [c][px]
-        for (int v = tid; v < WG_PX * (CIN / 8); v += 256) {
-            const int px = v / (CIN / 8), cv = v - (v / (CIN / 8)) * (CIN / 8);
-            const int k = k0 + px;
-            uint4 val = make_uint4(0, 0, 0, 0);
+        // x rows j-1..j+1, columns k0-1 .. k0+WG_PX: copy dx holds column k0 + px + dx - 1
+        for (int v = tid; v < 3 * (WG_PX + 2) * (CIN / 8); v += NT) {
+            const int cv = v % (CIN / 8), pr = v / (CIN / 8);
+            const int dy = pr / (WG_PX + 2), pc = pr - (pr / (WG_PX + 2)) * (WG_PX + 2);
             int sj, sk;
-            if (k < W && sphere_src(j + dy - 1, k + dx - 1, H, W, sj, sk))
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (sphere_src(j + dy - 1, k0 + pc - 1, H, W, sj, sk))
                 val = *(const uint4*)(x + (((size_t)b * H + sj) * W + sk) * CIN + cv * 8);
             const uint16_t* h = (const uint16_t*)&val;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) xs[(cv * 8 + i) * PS + px] = h[i];
+            for (int dx = 0; dx < 3; ++dx) {
+                const int px = pc - dx;
+                if (px < 0 || px >= WG_PX) continue;
+                uint16_t* dst = xs + ((dx * 3 + dy) * CIP + cv * 8) * PS + px;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) dst[i * PS] = h[i];
+            }
         }
-        for (int v = tid; v < WG_PX * 8; v += 256) {
-            const int px = v >> 3, cv = v & 7;
+        for (int v = tid; v < WG_PX * (COUT / 8); v += NT) {
+            const int cv = v % (COUT / 8), px = v / (COUT / 8);
             const int k = k0 + px;
             uint4 val = make_uint4(0, 0, 0, 0);
-            if (k < W) val = *(const uint4*)(dz + (((size_t)b * H + j) * W + k) * 64 + cv * 8);
+            if (k < W) val = *(const uint4*)(dz + (((size_t)b * H + j) * W + k) * COUT + cv * 8);
             const uint16_t* h = (const uint16_t*)&val;
 #pragma unroll
             for (int i = 0; i < 8; ++i) gs[(cv * 8 + i) * PS + px] = h[i];
         }
         __syncthreads();
-        if (CIN < 32 && ci_t == 1) continue;
+        if (tid < COUT) {
+            float s = 0.f;
+            for (int px = 0; px < WG_PX; ++px) s += bf2f(gs[tid * PS + px]);
+            bsum += s;
+        }
 #pragma unroll
         for (int ks = 0; ks < WG_PX / 16; ++ks) {
             const int pb = ks * 16 + kh * 8;
-            const bf16x8 a = *(const bf16x8*)(xs + (ci_t * 32 + col) * PS + pb);
             const bf16x8 bb = *(const bf16x8*)(gs + (co_t * 32 + col) * PS + pb);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc, 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int dy = t / 3, dx = t - (t / 3) * 3;
+                const bf16x8 a = *(const bf16x8*)(xs + ((dx * 3 + dy) * CIP + ci_t * 32 + col) * PS + pb);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[t], 0, 0, 0);
+            }
         }
     }
-    if (CIN < 32 && ci_t == 1) return;
-    // C[ci][co]: row = ci (8*(r/4) + 4*kh + r%4 within the tile), column = co
-    float* o = part + ((size_t)blockIdx.x * 9 + tap) * 64 * CIN;
+    // C[ci][co] of each tap: row ci = 8*(r/4) + 4*kh + r%4 within the tile, column co
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int ci = ci_t * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-        const int co = co_t * 32 + col;
-        if (ci < CIN) o[co * CIN + ci] = acc[r];
+    for (int t = 0; t < 9; ++t) {
+        float* o = part + ((size_t)blockIdx.x * 9 + t) * COUT * CIN;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int ci = ci_t * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+            const int co = co_t * 32 + col;
+            if (ci < CIN && co < COUT) o[co * CIN + ci] = acc[t][r];
+        }
     }
+    if (tid < COUT) bpart[(size_t)blockIdx.x * COUT + tid] = bsum;
 }
 
-// grad[co][mc][dy][dx] (master layout) = sum over blocks, fixed order, of the
-// packed slots feeding master channel mc (two slots for the field channel of
-// the first layer, whose weight is shared by the hi and lo parts).
-__global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nblk, int cin, int cin_out,
-                                    float* __restrict__ grad)
+// Master-layout gradient grad[co][mc][dy][dx], co < cout_out, summed over the
+// blocks in a fixed order; packed input slots map to master channels as in
+// the first layer's packing (field hi and lo share channel 0).
+__global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nblk, int cin, int cout,
+                                    int cin_out, int cout_out, float* __restrict__ grad)
 {
-    const int n = 9 * 64 * cin_out;
+    const int n = 9 * cout_out * cin_out;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const int tap = e / (64 * cin_out), rem = e - tap * 64 * cin_out;
+        const int tap = e / (cout_out * cin_out), rem = e - tap * cout_out * cin_out;
         const int co = rem / cin_out, mc = rem - co * cin_out;
         float s = 0.f;
         for (int bk = 0; bk < nblk; ++bk) {
-            const float* pb = part + ((size_t)bk * 9 + tap) * 64 * cin + (size_t)co * cin;
+            const float* pb = part + ((size_t)bk * 9 + tap) * cout * cin + (size_t)co * cin;
             if (cin == 16) s += mc == 0 ? pb[0] + pb[1] : pb[mc + 1];
             else s += pb[mc];
         }
@@ -317,65 +345,24 @@ __global__ void wgrad_reduce_kernel(const float* __restrict__ part, int nblk, in
     }
 }
 
-// per-block channel sums of dz (bias gradient), then a fixed-order reduce
-__global__ __launch_bounds__(256) void bgrad_partial_kernel(const uint16_t* __restrict__ dz, long npix,
-                                                            float* __restrict__ part)
-{
-    __shared__ float red[256];
-    const int c = threadIdx.x & 63, sub = threadIdx.x >> 6;
-    float s = 0.f;
-    for (long p = (long)blockIdx.x * 4 + sub; p < npix; p += (long)gridDim.x * 4)
-        s += bf2f(dz[p * 64 + c]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x < 64)
-        part[(size_t)blockIdx.x * 64 + c] = red[c] + red[64 + c] + red[128 + c] + red[192 + c];
-}
-
-__global__ void colsum_reduce_kernel(const float* __restrict__ part, int nblk, int ncol,
+__global__ void colsum_reduce_kernel(const float* __restrict__ part, int nblk, int ncol, int nout,
                                      float* __restrict__ out)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncol) return;
+    if (c >= nout) return;
     float s = 0.f;
     for (int b = 0; b < nblk; ++b) s += part[(size_t)b * ncol + c];
     out[c] = s;
 }
 
-// ------------------------------------------------------ last layer (64 -> 1)
-// y[b][j][k] = bias + sum_tap sum_c w5[tap][c] x4[pad(j+dy-1, k+dx-1)][c]   (VALU, FP32)
-__global__ __launch_bounds__(256) void conv_last_fwd_kernel(const uint16_t* __restrict__ x4,
-                                                            const float* __restrict__ w5,
-                                                            const float* __restrict__ b5,
-                                                            float* __restrict__ y, int H, int W)
-{
-    __shared__ float ws[9 * 64];
-    for (int e = threadIdx.x; e < 9 * 64; e += 256) ws[e] = w5[e];
-    __syncthreads();
-    const int b = blockIdx.y;
-    const size_t n = (size_t)H * W;
-    for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (size_t)gridDim.x * 256) {
-        const int j = (int)(p / W), k = (int)(p - (size_t)j * W);
-        float s = b5[0];
-        for (int tap = 0; tap < 9; ++tap) {
-            int sj, sk;
-            sphere_src(j + tap / 3 - 1, k + tap % 3 - 1, H, W, sj, sk);
-            const uint4* src = (const uint4*)(x4 + (((size_t)b * H + sj) * W + sk) * 64);
-            for (int cv = 0; cv < 8; ++cv) {
-                const uint4 v = src[cv];
-                const uint16_t* h = (const uint16_t*)&v;
-                for (int i = 0; i < 8; ++i) s += ws[tap * 64 + cv * 8 + i] * bf2f(h[i]);
-            }
-        }
-        y[(size_t)b * n + p] = s;
-    }
-}
-
-// target t = (B_target - B_in)/5 G; dy = 2 (y - t)/count; per-block FP64 loss sums
+// target t = (B_target - B_in)/5 G; dy = 2 (y - t)/count, also as the
+// 16-channel bf16 input of the output layer's backward (channel 0 = dy);
+// per-block FP64 loss sums.
 template <typename TB>
 __global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict__ y,
                                                         const TB* __restrict__ Bin,
-                                                        const TB* __restrict__ Bt, float* __restrict__ dy,
+                                                        const TB* __restrict__ Bt,
+                                                        uint16_t* __restrict__ dyb,
                                                         double* __restrict__ part, size_t n, double count)
 {
     __shared__ double red[256];
@@ -383,7 +370,11 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict_
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
         const float t = (float)(((double)Bt[i] - (double)Bin[i]) / 5.0);
         const float d = y[i] - t;
-        dy[i] = (float)(2.0 * (double)d / count);
+        uint4 v = make_uint4(0, 0, 0, 0);
+        v.x = (uint32_t)f2bf((float)(2.0 * (double)d / count));
+        uint4* o = (uint4*)(dyb + i * 16);
+        o[0] = v;
+        o[1] = make_uint4(0, 0, 0, 0);
         s += (double)d * (double)d;
     }
     red[threadIdx.x] = s;
@@ -393,77 +384,6 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict_
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
-// Gradient of the last layer w.r.t. its input, masked by the layer-4 ReLU:
-// dz4[p][c] = (x4[p][c] > 0) * sum over output pixels q that read p through
-// tap t (directly, or through a ghost row across a pole) of w5[t][c] dy[q].
-__global__ __launch_bounds__(256) void conv_last_dgrad_kernel(const float* __restrict__ dy,
-                                                              const float* __restrict__ w5,
-                                                              const uint16_t* __restrict__ x4,
-                                                              uint16_t* __restrict__ dz4, int H, int W)
-{
-    __shared__ float ws[9 * 64];
-    for (int e = threadIdx.x; e < 9 * 64; e += 256) ws[e] = w5[e];
-    __syncthreads();
-    const int b = blockIdx.y;
-    const size_t n = (size_t)H * W;
-    const float* g = dy + (size_t)b * n;
-    for (size_t p = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6); p < n; p += (size_t)gridDim.x * 4) {
-        const int c = threadIdx.x & 63;
-        const int j = (int)(p / W), k = (int)(p - (size_t)j * W);
-        float s = 0.f;
-        for (int tap = 0; tap < 9; ++tap) {
-            const int dyy = tap / 3, dxx = tap % 3;
-            const int qj = j - dyy + 1, qk = wrapk(k - dxx + 1, W);
-            if (qj >= 0 && qj < H) s += ws[tap * 64 + c] * g[(size_t)qj * W + qk];
-        }
-        // ghost paths: output row 0 reads row 0 at k + W/2 through tap dy = 0
-        if (j == 0)
-            for (int dxx = 0; dxx < 3; ++dxx)
-                s += ws[dxx * 64 + c] * g[(size_t)0 * W + wrapk(k + W / 2 - dxx + 1, W)];
-        if (j == H - 1)
-            for (int dxx = 0; dxx < 3; ++dxx)
-                s += ws[(6 + dxx) * 64 + c] * g[(size_t)(H - 1) * W + wrapk(k + W / 2 - dxx + 1, W)];
-        const size_t e = ((size_t)b * n + p) * 64 + c;
-        dz4[e] = bf2f(x4[e]) > 0.f ? f2bf(s) : (uint16_t)0;
-    }
-}
-
-// per-block partials of dw5[tap][c] = sum_p x4[pad(p+tap)][c] dy[p] and db5
-__global__ __launch_bounds__(256) void conv_last_wgrad_kernel(const float* __restrict__ dy,
-                                                              const uint16_t* __restrict__ x4,
-                                                              float* __restrict__ part, int batch,
-                                                              int H, int W)
-{
-    const size_t n = (size_t)H * W;
-    const long tot = (long)batch * n;
-    float acc[3];
-    int idx[3];
-    for (int q = 0; q < 3; ++q) {
-        idx[q] = threadIdx.x + q * 256;
-        acc[q] = 0.f;
-    }
-    float db = 0.f;
-    for (long pp = blockIdx.x; pp < tot; pp += gridDim.x) {
-        const int b = (int)(pp / n);
-        const size_t p = pp - (long)b * n;
-        const int j = (int)(p / W), k = (int)(p - (size_t)j * W);
-        const float g = dy[pp];
-        if (threadIdx.x == 0) db += g;
-        for (int q = 0; q < 3; ++q) {
-            const int e = idx[q];
-            if (e >= 9 * 64) continue;
-            const int tap = e >> 6, c = e & 63;
-            int sj, sk;
-            sphere_src(j + tap / 3 - 1, k + tap % 3 - 1, H, W, sj, sk);
-            acc[q] += bf2f(x4[(((size_t)b * H + sj) * W + sk) * 64 + c]) * g;
-        }
-    }
-    float* o = part + (size_t)blockIdx.x * (9 * 64 + 1);
-    for (int q = 0; q < 3; ++q)
-        if (idx[q] < 9 * 64) o[idx[q]] = acc[q];
-    if (threadIdx.x == 0) o[9 * 64] = db;
 }
 
 // ------------------------------------------------------------ optimizer
@@ -491,45 +411,27 @@ __device__ __forceinline__ int master_channel(int ci, int cin, int cip)
     return ci - 1 < cin ? ci - 1 : -1;
 }
 
-// master W[co][ci][dy][dx] -> forward layout wf[tap][co][cip] (zero-padded ci)
-// and (if wd) data-gradient layout wd[tap][ci][co].
-__global__ void pack_weights_kernel(const float* __restrict__ Wm, int cin, int cip,
-                                    uint16_t* __restrict__ wf, uint16_t* __restrict__ wd)
+// master W[co][ci][dy][dx] (co < cout) -> forward layout wf[tap][nout][cip]
+// (rows co >= cout and slots without a master channel zero) and, if wd, the
+// data-gradient layout wd[tap][ci][cop] (co contiguous, padded to cop).
+__global__ void pack_weights_kernel(const float* __restrict__ Wm, int cin, int cout, int cip, int nout,
+                                    int cop, uint16_t* __restrict__ wf, uint16_t* __restrict__ wd)
 {
-    const int n = 9 * 64 * cip;
+    const int n = 9 * nout * cip;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
-        const int tap = e / (64 * cip), rem = e - tap * 64 * cip;
+        const int tap = e / (nout * cip), rem = e - tap * nout * cip;
         const int co = rem / cip, ci = rem - co * cip;
         const int mc = master_channel(ci, cin, cip);
-        const float v = mc >= 0 ? Wm[((size_t)co * cin + mc) * 9 + tap] : 0.f;
+        const float v = (mc >= 0 && co < cout) ? Wm[((size_t)co * cin + mc) * 9 + tap] : 0.f;
         wf[e] = f2bf(v);
-        if (wd && ci < cin) wd[((size_t)tap * cin + ci) * 64 + co] = f2bf(v);
     }
-}
-
-// last layer master w5[0][c][dy][dx] -> w5t[tap][c] (FP32)
-__global__ void pack_last_kernel(const float* __restrict__ Wm, float* __restrict__ w5t)
-{
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < 9 * 64) {
-        const int tap = e >> 6, c = e & 63;
-        w5t[e] = Wm[c * 9 + tap];
-    }
-}
-
-// last-layer weight gradient: grad[c][tap] (master layout) and bias
-__global__ void last_reduce_kernel(const float* __restrict__ part, int nblk, float* __restrict__ gw,
-                                   float* __restrict__ gb)
-{
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e > 9 * 64) return;
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * (9 * 64 + 1) + e];
-    if (e == 9 * 64) {
-        gb[0] = s;
-    } else {
-        const int tap = e >> 6, c = e & 63;
-        gw[c * 9 + tap] = s;
+    if (!wd) return;
+    const int nd = 9 * cin * cop;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nd; e += gridDim.x * blockDim.x) {
+        const int tap = e / (cin * cop), rem = e - tap * cin * cop;
+        const int ci = rem / cop, co = rem - ci * cop;
+        const float v = co < cout ? Wm[((size_t)co * cin + ci) * 9 + tap] : 0.f;
+        wd[e] = f2bf(v);
     }
 }
 
@@ -622,17 +524,29 @@ void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf
 {
     dim3 g((W + CTX - 1) / CTX, (H + CTY - 1) / CTY, batch);
     if (cin == 16)
-        hipLaunchKernelGGL((conv_mfma_kernel<16, 0>), g, dim3(128), 0, st, x, wf, bias, (void*)out, H, W);
+        hipLaunchKernelGGL((conv_mfma_kernel<16, 0, 2>), g, dim3(128), 0, st, x, wf, bias, (void*)out, H, W);
     else
-        hipLaunchKernelGGL((conv_mfma_kernel<64, 0>), g, dim3(128), 0, st, x, wf, bias, (void*)out, H, W);
+        hipLaunchKernelGGL((conv_mfma_kernel<64, 0, 2>), g, dim3(128), 0, st, x, wf, bias, (void*)out, H, W);
 }
 
-void cnn_conv_dgrad(hipStream_t st, const uint16_t* dz, const uint16_t* wd, float* dxp, int batch, int H,
-                    int W)
+void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
+                  int batch, int H, int W)
+{
+    dim3 g((W + CTX - 1) / CTX, (H + CTY - 1) / CTY, batch);
+    hipLaunchKernelGGL((conv_mfma_kernel<64, 2, 1>), g, dim3(128), 0, st, x4, wf5, b5, (void*)y, H, W);
+}
+
+// cin = channels of the gradient input (64, or 16 for the output layer's dy)
+void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, float* dxp, int batch,
+                    int H, int W)
 {
     dim3 g((W + CTX - 1) / CTX, (H + 2 + CTY - 1) / CTY, batch);
-    hipLaunchKernelGGL((conv_mfma_kernel<64, 1>), g, dim3(128), 0, st, dz, wd, (const float*)nullptr,
-                       (void*)dxp, H, W);
+    if (cin == 16)
+        hipLaunchKernelGGL((conv_mfma_kernel<16, 1, 2>), g, dim3(128), 0, st, dz, wd, (const float*)nullptr,
+                           (void*)dxp, H, W);
+    else
+        hipLaunchKernelGGL((conv_mfma_kernel<64, 1, 2>), g, dim3(128), 0, st, dz, wd, (const float*)nullptr,
+                           (void*)dxp, H, W);
 }
 
 void cnn_fold_mask(hipStream_t st, const float* dxp, const uint16_t* act, uint16_t* dz, int batch, int H,
@@ -642,49 +556,36 @@ void cnn_fold_mask(hipStream_t st, const float* dxp, const uint16_t* act, uint16
     hipLaunchKernelGGL(fold_mask_kernel, g, dim3(256), 0, st, dxp, act, dz, H, W);
 }
 
-void cnn_wgrad(hipStream_t st, int cin, int cin_out, const uint16_t* x, const uint16_t* dz, float* part,
-               int nblk, float* grad, int batch, int H, int W)
+// weight and bias gradient of one layer: x has cin packed channels (16 or 64),
+// dz cout channels (64, or 16 for the output layer's dy); master gradient for
+// cin_out x cout_out channels.
+void cnn_wgrad(hipStream_t st, int cin, int cout, int cin_out, int cout_out, const uint16_t* x,
+               const uint16_t* dz, float* part, float* bpart, int nblk, float* grad, float* gbias,
+               int batch, int H, int W)
 {
-    dim3 g(nblk, 9);
     if (cin == 16)
-        hipLaunchKernelGGL(wgrad_mfma_kernel<16>, g, dim3(256), 0, st, x, dz, part, batch, H, W);
+        hipLaunchKernelGGL((wgrad_mfma_kernel<16, 64>), dim3(nblk), dim3(128), 0, st, x, dz, part, bpart,
+                           batch, H, W);
+    else if (cout == 16)
+        hipLaunchKernelGGL((wgrad_mfma_kernel<64, 16>), dim3(nblk), dim3(128), 0, st, x, dz, part, bpart,
+                           batch, H, W);
     else
-        hipLaunchKernelGGL(wgrad_mfma_kernel<64>, g, dim3(256), 0, st, x, dz, part, batch, H, W);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(gblocks((size_t)9 * 64 * cin, 256, 1024)), dim3(256), 0,
-                       st, part, nblk, cin, cin_out, grad);
+        hipLaunchKernelGGL((wgrad_mfma_kernel<64, 64>), dim3(nblk), dim3(256), 0, st, x, dz, part, bpart,
+                           batch, H, W);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(gblocks((size_t)9 * cout_out * cin_out, 256, 1024)),
+                       dim3(256), 0, st, part, nblk, cin, cout, cin_out, cout_out, grad);
+    hipLaunchKernelGGL(colsum_reduce_kernel, dim3(1), dim3(64), 0, st, bpart, nblk, cout, cout_out, gbias);
 }
 
-void cnn_bgrad(hipStream_t st, const uint16_t* dz, long npix, float* part, int nblk, float* gb)
-{
-    hipLaunchKernelGGL(bgrad_partial_kernel, dim3(nblk), dim3(256), 0, st, dz, npix, part);
-    hipLaunchKernelGGL(colsum_reduce_kernel, dim3(1), dim3(64), 0, st, part, nblk, 64, gb);
-}
-
-void cnn_last_fwd(hipStream_t st, const uint16_t* x4, const float* w5t, const float* b5, float* y, int batch,
-                  int H, int W)
-{
-    dim3 g(gblocks((size_t)H * W, 256, 2048), batch);
-    hipLaunchKernelGGL(conv_last_fwd_kernel, g, dim3(256), 0, st, x4, w5t, b5, y, H, W);
-}
-
-void cnn_loss_grad(hipStream_t st, const float* y, const void* Bin, const void* Bt, int dtype, float* dy,
+void cnn_loss_grad(hipStream_t st, const float* y, const void* Bin, const void* Bt, int dtype, uint16_t* dyb,
                    double* part, int nblk, size_t n)
 {
     if (dtype == 1)
         hipLaunchKernelGGL(loss_grad_kernel<float>, dim3(nblk), dim3(256), 0, st, y, (const float*)Bin,
-                           (const float*)Bt, dy, part, n, (double)n);
+                           (const float*)Bt, dyb, part, n, (double)n);
     else
         hipLaunchKernelGGL(loss_grad_kernel<double>, dim3(nblk), dim3(256), 0, st, y, (const double*)Bin,
-                           (const double*)Bt, dy, part, n, (double)n);
-}
-
-void cnn_last_bwd(hipStream_t st, const float* dy, const float* w5t, const uint16_t* x4, uint16_t* dz4,
-                  float* part, int nblk, float* gw5, float* gb5, int batch, int H, int W)
-{
-    dim3 g(gblocks((size_t)H * W, 4, 4096), batch);
-    hipLaunchKernelGGL(conv_last_dgrad_kernel, g, dim3(256), 0, st, dy, w5t, x4, dz4, H, W);
-    hipLaunchKernelGGL(conv_last_wgrad_kernel, dim3(nblk), dim3(256), 0, st, dy, x4, part, batch, H, W);
-    hipLaunchKernelGGL(last_reduce_kernel, dim3(3), dim3(256), 0, st, part, nblk, gw5, gb5);
+                           (const double*)Bt, dyb, part, n, (double)n);
 }
 
 void cnn_adam(hipStream_t st, float* p, const float* g, float* m, float* v, int n, float lr, float b1,
@@ -694,15 +595,11 @@ void cnn_adam(hipStream_t st, float* p, const float* g, float* m, float* v, int 
                        eps, c1, c2);
 }
 
-void cnn_pack(hipStream_t st, const float* Wm, int cin, int cip, uint16_t* wf, uint16_t* wd)
+void cnn_pack(hipStream_t st, const float* Wm, int cin, int cout, int cip, int nout, int cop, uint16_t* wf,
+              uint16_t* wd)
 {
-    hipLaunchKernelGGL(pack_weights_kernel, dim3(gblocks((size_t)9 * 64 * cip, 256, 1024)), dim3(256), 0, st,
-                       Wm, cin, cip, wf, wd);
-}
-
-void cnn_pack_last(hipStream_t st, const float* Wm, float* w5t)
-{
-    hipLaunchKernelGGL(pack_last_kernel, dim3(3), dim3(256), 0, st, Wm, w5t);
+    hipLaunchKernelGGL(pack_weights_kernel, dim3(gblocks((size_t)9 * nout * cip, 256, 1024)), dim3(256), 0,
+                       st, Wm, cin, cout, cip, nout, cop, wf, wd);
 }
 
 void cnn_pred(hipStream_t st, const double* Bin, const float* y, double* pred, size_t n)

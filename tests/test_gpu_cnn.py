@@ -121,7 +121,7 @@ def test_cnn_forward_layers_match_oracle(H, W):
         say(f"  layer {l}: within 1 ulp {ok}, differing {frac:.2e}")
         assert ok and frac < 2e-2, l
     w5, b5 = params[4]
-    yref = cnn.conv3x3(acts[4], w5, b5)[:, 0]
+    yref = cnn.conv3x3(acts[4], cnn.bf16_round(w5), b5)[:, 0]
     e = float(np.abs(y.cpu().numpy() - yref).max() / np.abs(yref).max())
     say(f"  output layer: max rel {e:.2e}")
     assert e < 1e-5
@@ -137,14 +137,15 @@ def test_cnn_gradients_match_oracle():
     g = unflat(net.get_grads(), params)
     acts = get_acts(torch, net, batch, H, W)
     w5, b5 = params[4]
-    y = cnn.conv3x3(acts[4], w5, b5)
+    y = cnn.conv3x3(acts[4], cnn.bf16_round(w5), b5)
     t = ((Bt - B).cpu().numpy() / cnn.OUT_SCALE)[:, None]
     n = y.size
     loss_ref = float(np.mean((y - t) ** 2))
     assert loss == pytest.approx(loss_ref, rel=1e-4)
-    gy = 2.0 * (y - t) / n
+    # the output gradient is stored as bf16 for the matrix cores
+    gy = cnn.bf16_round(2.0 * (y - t) / n)
     ref = [None] * 5
-    gx, gw, gb = cnn.conv3x3_backward(acts[4], w5, gy)
+    gx, gw, gb = cnn.conv3x3_backward(acts[4], cnn.bf16_round(w5), gy)
     ref[4] = (gw, gb)
     dz = cnn.bf16_round(gx * (acts[4] > 0))
     for l in range(4, 0, -1):
