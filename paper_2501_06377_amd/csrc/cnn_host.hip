@@ -20,10 +20,8 @@ void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf
                   uint16_t* out, int batch, int H, int W);
 void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
                   int batch, int H, int W);
-void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, float* dxp, int batch,
-                    int H, int W);
-void cnn_fold_mask(hipStream_t st, const float* dxp, const uint16_t* act, uint16_t* dz, int batch, int H,
-                   int W);
+void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, const uint16_t* act,
+                    uint16_t* dx, float* edge, int batch, int H, int W);
 void cnn_wgrad(hipStream_t st, int cin, int cout, int cin_out, int cout_out, const uint16_t* x,
                const uint16_t* dz, float* part, float* bpart, int nblk, float* grad, float* gbias,
                int batch, int H, int W);
@@ -42,7 +40,7 @@ namespace {
 // the first layer reads 16 packed input slots (field hi/lo sharing weight 0)
 const int kCin[5] = {6, 64, 64, 64, 64};
 const int kCout[5] = {64, 64, 64, 64, 1};
-const int kWGB = 512;     // weight-gradient partial blocks per tap
+const int kWGB = 256;     // weight-gradient blocks (one per compute unit), each with its own partial
 const int kRED = 1024;    // reduction blocks
 }  // namespace
 
@@ -58,7 +56,7 @@ struct sft_net {
     uint16_t* wd[5] = {};   // data-gradient layouts (layers 2..5)
     uint16_t* X0 = nullptr;
     uint16_t* X[4] = {};
-    float *y = nullptr, *dxp = nullptr;
+    float *y = nullptr, *dxp = nullptr;   // dxp: pole-row edge scratch [B][4][np][64]
     uint16_t* dyb = nullptr;   // output gradient as 16 bf16 channels (channel 0 real)
     uint16_t* dz[2] = {};
     float *wpart = nullptr, *bpart = nullptr;
@@ -159,7 +157,7 @@ sft_status sft_net_create(sft_net** out, int32_t nt, int32_t np, int32_t max_bat
     for (int l = 0; l < 4; ++l) A_(nalloc(net, &net->X[l], B * plane * 64));
     A_(nalloc(net, &net->y, B * plane));
     A_(nalloc(net, &net->dyb, B * plane * 16));
-    A_(nalloc(net, &net->dxp, B * (size_t)(nt + 2) * np * 64));
+    A_(nalloc(net, &net->dxp, B * (size_t)4 * np * 64));
     A_(nalloc(net, &net->dz[0], B * plane * 64));
     A_(nalloc(net, &net->dz[1], B * plane * 64));
     A_(nalloc(net, &net->wpart, (size_t)kWGB * 9 * 64 * 64));
@@ -260,8 +258,7 @@ sft_status sft_net_train_step(sft_net* net, int32_t batch, const void* b_in, con
     // output masked by its ReLU
     cnn_wgrad(st, 64, 16, 64, 1, net->X[3], net->dyb, net->wpart, net->bpart, kWGB, net->g + net->woff[4],
               net->g + net->boff[4], batch, H, W);
-    cnn_conv_dgrad(st, 16, net->dyb, net->wd[4], net->dxp, batch, H, W);
-    cnn_fold_mask(st, net->dxp, net->X[3], net->dz[0], batch, H, W);
+    cnn_conv_dgrad(st, 16, net->dyb, net->wd[4], net->X[3], net->dz[0], net->dxp, batch, H, W);
     int cur = 0;
     for (int l = 3; l >= 0; --l) {
         const uint16_t* xin = l == 0 ? net->X0 : net->X[l - 1];
@@ -269,8 +266,8 @@ sft_status sft_net_train_step(sft_net* net, int32_t batch, const void* b_in, con
         cnn_wgrad(st, cin, 64, kCin[l], 64, xin, net->dz[cur], net->wpart, net->bpart, kWGB,
                   net->g + net->woff[l], net->g + net->boff[l], batch, H, W);
         if (l > 0) {
-            cnn_conv_dgrad(st, 64, net->dz[cur], net->wd[l], net->dxp, batch, H, W);
-            cnn_fold_mask(st, net->dxp, net->X[l - 1], net->dz[cur ^ 1], batch, H, W);
+            cnn_conv_dgrad(st, 64, net->dz[cur], net->wd[l], net->X[l - 1], net->dz[cur ^ 1], net->dxp, batch,
+                           H, W);
             cur ^= 1;
         }
     }

@@ -107,7 +107,9 @@ template <int CIN, int MODE, int NTN>
 __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restrict__ x,
                                                         const uint16_t* __restrict__ w,
                                                         const float* __restrict__ bias,
-                                                        void* __restrict__ out, int H, int W)
+                                                        void* __restrict__ out, int H, int W,
+                                                        const uint16_t* __restrict__ act,
+                                                        float* __restrict__ edge)
 {
     constexpr int CP = CIN + 8;                 // padded channel stride in LDS
     constexpr int TR = CTY + 2, TC = CTX + 2;   // staged tile with a one-cell halo
@@ -190,8 +192,17 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
                     v = v > 0.f ? v : 0.f;
                     ((uint16_t*)out)[((size_t)b * plane + (size_t)row * W + k) * 64 + c] = f2bf(v);
                 } else if (MODE == 1) {
-                    ((float*)out)[((size_t)b * (H + 2) * W + (size_t)(row + 1) * W + k) * 64 + c] =
-                        acc[m][n][r];
+                    // rows 1..H-2: masked bf16 gradient of the layer input;
+                    // rows -1, 0, H-1, H (pole rows and their ghosts) go to
+                    // the edge buffer and are folded by edge_fold_kernel
+                    const float v = acc[m][n][r];
+                    if (row >= 1 && row <= H - 2) {
+                        const size_t e = ((size_t)b * plane + (size_t)row * W + k) * 64 + c;
+                        ((uint16_t*)out)[e] = bf2f(act[e]) > 0.f ? f2bf(v) : (uint16_t)0;
+                    } else {
+                        const int er = row <= 0 ? row + 1 : row - H + 4;
+                        edge[(((size_t)b * 4 + er) * W + k) * 64 + c] = v;
+                    }
                 } else {
                     ((float*)out)[(size_t)b * plane + (size_t)row * W + k] = acc[m][n][r] + bv;
                 }
@@ -200,28 +211,28 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
     }
 }
 
-// dZ[b][j][k][c] = (dXp[j+1] + ghost fold) * (act[b][j][k][c] > 0), bf16.
-// The ghost row above row 0 (padded row 0) read row 0 at column k + W/2, so
-// its gradient folds back there; likewise the ghost row below the last row.
-__global__ void fold_mask_kernel(const float* __restrict__ dxp, const uint16_t* __restrict__ act,
+// Pole rows of the input gradient: edge rows (-1, 0, H-1, H) -> rows 0 and
+// H-1, adding the ghost row's gradient at the half-turn column (the ghost
+// row above row 0 read row 0 at column k + W/2, likewise below the last row),
+// then the ReLU mask of the layer input; bf16.
+__global__ void edge_fold_kernel(const float* __restrict__ edge, const uint16_t* __restrict__ act,
                                  uint16_t* __restrict__ dz, int H, int W)
 {
     const int b = blockIdx.y;
-    const size_t n = (size_t)H * W * 64;
+    const size_t n = (size_t)2 * W * 64;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (size_t)gridDim.x * blockDim.x) {
         const int c = (int)(e & 63);
         const size_t p = e >> 6;
-        const int j = (int)(p / W), k = (int)(p - (size_t)j * W);
-        const float* g = dxp + (size_t)b * (H + 2) * W * 64;
-        float v = g[((size_t)(j + 1) * W + k) * 64 + c];
-        if (j == 0 || j == H - 1) {
-            const int ks = k + W / 2 < W ? k + W / 2 : k - W / 2;
-            if (j == 0) v += g[(size_t)ks * 64 + c];
-            if (j == H - 1) v += g[((size_t)(H + 1) * W + ks) * 64 + c];
-        }
-        const uint16_t a = act[(size_t)b * n + e];
-        dz[(size_t)b * n + e] = (bf2f(a) > 0.f) ? f2bf(v) : (uint16_t)0;
+        const int side = (int)(p / W), k = (int)(p - (size_t)side * W);
+        const int ks = k + W / 2 < W ? k + W / 2 : k - W / 2;
+        const float* g = edge + (size_t)b * 4 * W * 64;
+        // side 0: row 0 = edge 1 + ghost edge 0; side 1: row H-1 = edge 2 + ghost edge 3
+        const float v = side == 0 ? g[((size_t)1 * W + k) * 64 + c] + g[((size_t)0 * W + ks) * 64 + c]
+                                  : g[((size_t)2 * W + k) * 64 + c] + g[((size_t)3 * W + ks) * 64 + c];
+        const int j = side == 0 ? 0 : H - 1;
+        const size_t o = ((size_t)b * H * W + (size_t)j * W + k) * 64 + c;
+        dz[o] = bf2f(act[o]) > 0.f ? f2bf(v) : (uint16_t)0;
     }
 }
 
@@ -266,10 +277,12 @@ void wgrad_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restric
         const int j = (int)(rem / segs);
         const int k0 = (int)(rem - (long)j * segs) * WG_PX;
         __syncthreads();
-        // x rows j-1..j+1, columns k0-1 .. k0+WG_PX: copy dx holds column k0 + px + dx - 1
+        // x rows j-1..j+1, columns k0-1 .. k0+WG_PX: copy dx holds column
+        // k0 + px + dx - 1.  Consecutive lanes take consecutive columns, so the
+        // transposed 2-byte LDS writes of a wave land in consecutive banks.
         for (int v = tid; v < 3 * (WG_PX + 2) * (CIN / 8); v += NT) {
-            const int cv = v % (CIN / 8), pr = v / (CIN / 8);
-            const int dy = pr / (WG_PX + 2), pc = pr - (pr / (WG_PX + 2)) * (WG_PX + 2);
+            const int pc = v % (WG_PX + 2), rest = v / (WG_PX + 2);
+            const int dy = rest % 3, cv = rest / 3;
             int sj, sk;
             uint4 val = make_uint4(0, 0, 0, 0);
             if (sphere_src(j + dy - 1, k0 + pc - 1, H, W, sj, sk))
@@ -285,7 +298,7 @@ void wgrad_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restric
             }
         }
         for (int v = tid; v < WG_PX * (COUT / 8); v += NT) {
-            const int cv = v % (COUT / 8), px = v / (COUT / 8);
+            const int px = v % WG_PX, cv = v / WG_PX;
             const int k = k0 + px;
             uint4 val = make_uint4(0, 0, 0, 0);
             if (k < W) val = *(const uint4*)(dz + (((size_t)b * H + j) * W + k) * COUT + cv * 8);
@@ -524,36 +537,37 @@ void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf
 {
     dim3 g((W + CTX - 1) / CTX, (H + CTY - 1) / CTY, batch);
     if (cin == 16)
-        hipLaunchKernelGGL((conv_mfma_kernel<16, 0, 2>), g, dim3(128), 0, st, x, wf, bias, (void*)out, H, W);
+        hipLaunchKernelGGL((conv_mfma_kernel<16, 0, 2>), g, dim3(128), 0, st, x, wf, bias, (void*)out, H, W,
+                           (const uint16_t*)nullptr, (float*)nullptr);
     else
-        hipLaunchKernelGGL((conv_mfma_kernel<64, 0, 2>), g, dim3(128), 0, st, x, wf, bias, (void*)out, H, W);
+        hipLaunchKernelGGL((conv_mfma_kernel<64, 0, 2>), g, dim3(128), 0, st, x, wf, bias, (void*)out, H, W,
+                           (const uint16_t*)nullptr, (float*)nullptr);
 }
 
 void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
                   int batch, int H, int W)
 {
     dim3 g((W + CTX - 1) / CTX, (H + CTY - 1) / CTY, batch);
-    hipLaunchKernelGGL((conv_mfma_kernel<64, 2, 1>), g, dim3(128), 0, st, x4, wf5, b5, (void*)y, H, W);
+    hipLaunchKernelGGL((conv_mfma_kernel<64, 2, 1>), g, dim3(128), 0, st, x4, wf5, b5, (void*)y, H, W,
+                       (const uint16_t*)nullptr, (float*)nullptr);
 }
 
-// cin = channels of the gradient input (64, or 16 for the output layer's dy)
-void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, float* dxp, int batch,
-                    int H, int W)
+// Gradient of a layer's input, masked by that input's ReLU, as bf16:
+// cin = channels of the gradient input (64, or 16 for the output layer's dy),
+// act = the layer input (post-ReLU activation), edge = FP32 scratch of
+// batch x 4 x W x 64.
+void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, const uint16_t* act,
+                    uint16_t* dx, float* edge, int batch, int H, int W)
 {
     dim3 g((W + CTX - 1) / CTX, (H + 2 + CTY - 1) / CTY, batch);
     if (cin == 16)
         hipLaunchKernelGGL((conv_mfma_kernel<16, 1, 2>), g, dim3(128), 0, st, dz, wd, (const float*)nullptr,
-                           (void*)dxp, H, W);
+                           (void*)dx, H, W, act, edge);
     else
         hipLaunchKernelGGL((conv_mfma_kernel<64, 1, 2>), g, dim3(128), 0, st, dz, wd, (const float*)nullptr,
-                           (void*)dxp, H, W);
-}
-
-void cnn_fold_mask(hipStream_t st, const float* dxp, const uint16_t* act, uint16_t* dz, int batch, int H,
-                   int W)
-{
-    dim3 g(gblocks((size_t)H * W * 64, 256, 4096), batch);
-    hipLaunchKernelGGL(fold_mask_kernel, g, dim3(256), 0, st, dxp, act, dz, H, W);
+                           (void*)dx, H, W, act, edge);
+    dim3 ge(gblocks((size_t)2 * W * 64, 256, 1024), batch);
+    hipLaunchKernelGGL(edge_fold_kernel, ge, dim3(256), 0, st, edge, act, dx, H, W);
 }
 
 // weight and bias gradient of one layer: x has cin packed channels (16 or 64),
