@@ -200,7 +200,7 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
                         const size_t e = ((size_t)b * plane + (size_t)row * W + k) * 64 + c;
                         ((uint16_t*)out)[e] = bf2f(act[e]) > 0.f ? f2bf(v) : (uint16_t)0;
                     } else {
-                        const int er = row <= 0 ? row + 1 : row - H + 4;
+                        const int er = row <= 0 ? row + 1 : row - H + 3;   // -1,0 -> 0,1; H-1,H -> 2,3
                         edge[(((size_t)b * 4 + er) * W + k) * 64 + c] = v;
                     }
                 } else {
