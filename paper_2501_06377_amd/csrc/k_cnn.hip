@@ -94,9 +94,11 @@ __global__ void cnn_features_kernel(const TB* __restrict__ Bin, const float* __r
 // ------------------------------------------------------ MFMA convolution
 // MODE 0 (hidden layer):  out[b][j][k][co] = relu(bias[co] + sum_tap sum_ci
 //                         w[tap][co][ci] x[b][pad(j+dy-1, k+dx-1)][ci]), bf16, 64 channels.
-// MODE 1 (data gradient): out[b][q+1][k][ci] = sum_tap sum_co w[tap][ci][co]
+// MODE 1 (data gradient): G[q][k][ci] = sum_tap sum_co w[tap][ci][co]
 //                         g[b][q-dy+1][k-dx+1][co] for padded rows q in [-1, H]
-//                         (g zero outside [0, H)), FP32, H+2 rows, 64 channels.
+//                         (g zero outside [0, H)); rows 1..H-2 are written as
+//                         bf16 masked by act > 0, rows -1, 0, H-1, H as FP32
+//                         to the edge buffer [b][4][W][64].
 // MODE 2 (output layer):  y[b][j][k] = bias[0] + sum_tap sum_ci w[tap][0][ci] x[...][ci],
 //                         FP32 (the weight rows 1..31 of the N tile are zero).
 // Weight layout: w[tap][n][k] with the GEMM's K index (input channel) contiguous;
@@ -115,7 +117,11 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
     constexpr int TR = CTY + 2, TC = CTX + 2;   // staged tile with a one-cell halo
     constexpr int NCH = CIN / 16;               // K chunks per tap
     constexpr int NOUT = NTN * 32;
-    __shared__ __attribute__((aligned(16))) uint16_t tile[TR * TC * CP];
+    // the input tile; MODE 0/1 reuse it for the bf16 output tile (channel
+    // stride CTS), written back as 16-byte vectors
+    constexpr int CTS = 64 + 8;
+    constexpr int TILE_E = TR * TC * CP, OUT_E = MODE == 2 ? 0 : CTY * CTX * CTS;
+    __shared__ __attribute__((aligned(16))) uint16_t tile[TILE_E > OUT_E ? TILE_E : OUT_E];
 
     const int b = blockIdx.z;
     const int k0 = blockIdx.x * CTX;
@@ -173,41 +179,61 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
     }
 
     // epilogue: C row = pixel column within the tile row, C column = channel
+    if (MODE == 2) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int row = r0 + wv * 4 + m;
+            if (row >= H || col != 0) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int k = k0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                if (k < W) ((float*)out)[(size_t)b * plane + (size_t)row * W + k] = acc[m][0][r] + bias[0];
+            }
+        }
+        return;
+    }
+    __syncthreads();   // every wave is done reading the input tile
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        const int row = r0 + wv * 4 + m;
-        if (MODE == 1 ? (row < -1 || row > H) : (row >= H)) continue;
+        const int rl = wv * 4 + m, row = r0 + rl;
 #pragma unroll
         for (int n = 0; n < NTN; ++n) {
             const int c = n * 32 + col;
-            if (MODE == 2 && c != 0) continue;
             const float bv = MODE == 1 ? 0.f : bias[c];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int px = 8 * (r >> 2) + 4 * kh + (r & 3);
-                const int k = k0 + px;
-                if (k >= W) continue;
-                if (MODE == 0) {
-                    float v = acc[m][n][r] + bv;
-                    v = v > 0.f ? v : 0.f;
-                    ((uint16_t*)out)[((size_t)b * plane + (size_t)row * W + k) * 64 + c] = f2bf(v);
-                } else if (MODE == 1) {
-                    // rows 1..H-2: masked bf16 gradient of the layer input;
-                    // rows -1, 0, H-1, H (pole rows and their ghosts) go to
-                    // the edge buffer and are folded by edge_fold_kernel
-                    const float v = acc[m][n][r];
-                    if (row >= 1 && row <= H - 2) {
-                        const size_t e = ((size_t)b * plane + (size_t)row * W + k) * 64 + c;
-                        ((uint16_t*)out)[e] = bf2f(act[e]) > 0.f ? f2bf(v) : (uint16_t)0;
-                    } else {
-                        const int er = row <= 0 ? row + 1 : row - H + 3;   // -1,0 -> 0,1; H-1,H -> 2,3
-                        edge[(((size_t)b * 4 + er) * W + k) * 64 + c] = v;
-                    }
-                } else {
-                    ((float*)out)[(size_t)b * plane + (size_t)row * W + k] = acc[m][n][r] + bv;
+                float v = acc[m][n][r] + bv;
+                if (MODE == 0) v = v > 0.f ? v : 0.f;
+                tile[(rl * CTX + px) * CTS + c] = f2bf(v);
+                // data gradient of the pole rows and their ghost rows (-1, 0,
+                // H-1, H): FP32 to the edge buffer, folded by edge_fold_kernel
+                if (MODE == 1 && (row <= 0 || row >= H - 1) && row >= -1 && row <= H && k0 + px < W) {
+                    const int er = row <= 0 ? row + 1 : row - H + 3;   // -1,0 -> 0,1; H-1,H -> 2,3
+                    edge[(((size_t)b * 4 + er) * W + k0 + px) * 64 + c] = v;
                 }
             }
         }
+    }
+    __syncthreads();
+    // MODE 0: rows < H; MODE 1: interior rows 1..H-2, masked by the ReLU of
+    // the layer input (act > 0)
+    for (int v = tid; v < CTY * CTX * 8; v += 128) {
+        const int cv = v & 7, pix = v >> 3;
+        const int rl = pix / CTX, px = pix - (pix / CTX) * CTX;
+        const int row = r0 + rl, k = k0 + px;
+        if (k >= W || (MODE == 0 ? row >= H : (row < 1 || row > H - 2))) continue;
+        uint4 val = *(const uint4*)(tile + pix * CTS + cv * 8);
+        const size_t o = ((size_t)b * plane + (size_t)row * W + k) * 64 + cv * 8;
+        if (MODE == 1) {
+            const uint4 a = *(const uint4*)(act + o);
+            uint16_t* h = (uint16_t*)&val;
+            const uint16_t* ha = (const uint16_t*)&a;
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (!(bf2f(ha[i]) > 0.f)) h[i] = 0;
+        }
+        *(uint4*)((uint16_t*)out + o) = val;
     }
 }
 
