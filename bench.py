@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", action="store_true", help="replay captured graphs (no per-kernel timing)")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surr-batch", type=int, default=64)
     return ap.parse_args()
 
 
@@ -84,6 +86,88 @@ def cpu_baseline(w, f0, obs_first, max_seconds):
             "sample": f"first {hours} h of the ensemble workload, all {len(reals)} realizations "
                       f"({el:.1f} s of CPU work, FP64 C oracle, OpenMP over rows)",
             "sim_days_per_s": hours / 24.0 / el}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def surrogate_bench(sft, torch, batch, n_real=16, hours=3, tol=1e-3):
+    """The learned surrogate at 512 x 1024: BF16-MFMA inference throughput of
+    a batch, then plain and surrogate intervals on the same realizations
+    (drawn from the surrogate's training distribution: no assimilation),
+    with the acceptance rate of the checked surrogate at tol."""
+    from paper_2501_06377_amd import surrogate as S
+    nt, np_ = 512, 1024
+    params, wname = S.load_weights(nt, np_)
+    reals, feats = S.sample_realizations(n_real, 2)
+    f0 = S.initial_fields(nt, np_, n_real, 2)
+    reps = (batch + n_real - 1) // n_real
+    net = sft.Net(nt, np_, batch)
+    net.set_params(params)
+    B = torch.tensor(np.concatenate([f0] * reps)[:batch], dtype=torch.float64, device="cuda")
+    F = torch.tensor(np.concatenate([feats] * reps)[:batch], device="cuda")
+    y = torch.empty((batch, nt, np_), dtype=torch.float32, device="cuda")
+    net.forward(B, F, y)
+    net.sync()
+    iters = 5
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        net.forward(B, F, y)
+    net.sync()
+    ms = (time.perf_counter() - t0) / iters * 1e3
+    flop = S.FLOP_PER_PIXEL * nt * np_ * batch
+    tflops = flop / (ms * 1e-3) / 1e12
+    net.close()
+    del B, F, y
+    log(f"surrogate inference: batch {batch} in {ms:.2f} ms ({tflops:.1f} TFLOP/s)")
+
+    net = sft.Net(nt, np_, n_real)
+    net.set_params(params)
+    ens = sft.Ensemble()
+    gid = ens.add_grid(nt, np_, reals)
+    ens.set_states(gid, f0)
+    ens.advance(1.0)
+    ens.sync()
+    t0 = time.perf_counter()
+    ens.advance(2.0)
+    ens.sync()
+    plain = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    sft.surrogate_advance(ens, gid, net, feats, 3.0, tol, check_=False)
+    ens.sync()
+    unchecked = (time.perf_counter() - t0) * 1e3
+    # checked intervals from a plain state
+    ens.set_states(gid, f0)
+    ens.set_time(0.0)
+    errs, ident = [], []
+    prev = f0
+    checked = 0.0
+    for h in range(1, hours + 1):
+        t0 = time.perf_counter()
+        e = sft.surrogate_advance(ens, gid, net, feats, float(h), tol)
+        ens.sync()
+        checked += (time.perf_counter() - t0) * 1e3
+        cur = ens.get_states(gid)
+        ident += list(np.linalg.norm((cur - prev).reshape(n_real, -1), axis=1) /
+                      np.linalg.norm(cur.reshape(n_real, -1), axis=1))
+        errs += e.tolist()
+        prev = cur
+    acc = sum(ens.diagnostics(r)["surr_accept"] for r in range(n_real))
+    rej = sum(ens.diagnostics(r)["surr_reject"] for r in range(n_real))
+    net.close()
+    ens.close()
+    errs = np.array(errs)
+    return {"weights": wname, "grid": f"{nt}x{np_}",
+            "inference": {"batch": batch, "ms_per_batch": ms, "flop_per_batch": flop, "TFLOP_s": tflops,
+                          "peak_TFLOP_s": 2500.0, "mfma_frac": tflops / 2500.0, "dtype": "bf16 (fp32 acc)"},
+            "ms_per_realization_interval": {"plain_f64": plain / n_real, "surrogate_unchecked": unchecked / n_real,
+                                            "surrogate_checked": checked / hours / n_real},
+            "speedup_unchecked_vs_plain": plain / unchecked,
+            "tol_rel_l2": tol, "checked_intervals": int(errs.size), "accept_rate": acc / max(acc + rej, 1),
+            "err_median": float(np.median(errs)), "err_max": float(errs.max()),
+            "identity_err_median": float(np.median(ident)),
+            "gain_over_identity": float(np.median(ident) / max(np.median(errs), 1e-300))}
 
 
 def traffic_from_profiles(kernel_file):
@@ -170,12 +254,21 @@ def main():
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "avg_launch_us": f["ms"] / max(f["launches"], 1) * 1e3,
                            "alg_bytes_per_launch": f["bytes"] / max(f["launches"], 1),
-                           "launches": f["launches"]}
+                           "launches": f["launches"],
+                           # bytes a fused multi-stage launch must move at least
+                           # (one read of its inputs, one write of its outputs)
+                           "min_hbm_GB_s": f["min_bytes"] / (f["ms"] * 1e-3) / 1e9,
+                           "min_hbm_frac": f["min_bytes"] / (f["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
         out["kernels"] = {k: {"ms": v["ms"], "launches": v["launches"],
                               "GB_s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
                           for k, v in fams.items() if v["launches"]}
         out["kernel_time_frac"] = sum(v["ms"] for v in fams.values()) * 1e-3 / wall
     out["final_diag_r0"] = {k: diag[k] for k in ("phi_pos", "phi_neg", "dax", "bmin", "bmax")}
+    ens.close()
+    del obs_d, init_d
+    log(f"ensemble: {wall:.2f} s for {K} intervals")
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_bench(sft, torch, args.surr_batch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, f0, obs[:24], args.cpu_seconds)
     print(json.dumps(out), flush=True)

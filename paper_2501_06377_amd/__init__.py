@@ -159,7 +159,6 @@ class Ensemble:
         self._chk(self.L.sft_tile_choice(self.ctx, gid, ctypes.byref(v)), "sft_tile_choice")
         return v.value
 
-
     def close(self):
         if self.ctx:
             self.L.sft_destroy(self.ctx)

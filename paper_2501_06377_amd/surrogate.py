@@ -179,6 +179,19 @@ def run_train(a):
     print(json.dumps({"train": {k: v for k, v in info.items() if k != "loss_history"}, "eval": ev}))
 
 
+def weights_path(nt: int, np_: int) -> str:
+    return os.path.join(WEIGHTS, f"surrogate_{nt}x{np_}.npy")
+
+
+def load_weights(nt: int, np_: int):
+    """(parameters, description): the trained weights shipped with the
+    package for this grid, else the untrained identity-map initialisation."""
+    path = weights_path(nt, np_)
+    if os.path.exists(path):
+        return np.load(path).astype(np.float32), os.path.relpath(path, ROOT)
+    return init_params(7), "untrained (identity-map initialisation)"
+
+
 def init_params(seed: int) -> np.ndarray:
     """He-normal initial weights in the library's parameter layout (last
     layer zero: the untrained surrogate is the identity map)."""
