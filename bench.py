@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--graphs", action="store_true", help="replay captured graphs (no per-kernel timing)")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surr-batch", type=int, default=64)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -170,18 +172,34 @@ def surrogate_bench(sft, torch, batch, n_real=16, hours=3, tol=1e-3):
             "gain_over_identity": float(np.median(ident) / max(np.median(errs), 1e-300))}
 
 
-def traffic_from_profiles(kernel_file):
-    """HBM traffic per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source (else None)."""
+def copy_probe(mib):
+    """A plain device-to-device copy of known size, five times: the reference
+    for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}))
+
+
+def traffic_from_profiles(family):
+    """HBM bytes per launch of a kernel family from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_2501_06377_amd", "csrc", kernel_file), "rb").read()
-    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+    rec = json.load(open(path)).get(family)
+    if not rec:
         return None
-    return rec.get("bytes_per_launch")
+    for f, h in rec["sources_sha256"].items():
+        src = open(os.path.join(ROOT, "paper_2501_06377_amd", "csrc", f), "rb").read()
+        if hashlib.sha256(src).hexdigest() != h:
+            return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def main():
@@ -190,6 +208,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(realizations would shard across GPUs, see DESIGN.md)"}))
         sys.exit(2)
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
+        return
     import torch
 
     import paper_2501_06377_amd as sft
@@ -249,7 +270,7 @@ def main():
         dom = max(fams, key=lambda k: fams[k]["ms"])
         f = fams[dom]
         achieved = f["bytes"] / (f["ms"] * 1e-3) / 1e9
-        traffic = traffic_from_profiles("k_diffusion.hip") if dom.startswith("sts") else None
+        traffic = traffic_from_profiles(dom)
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "avg_launch_us": f["ms"] / max(f["launches"], 1) * 1e3,

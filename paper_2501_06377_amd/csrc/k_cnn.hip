@@ -96,9 +96,13 @@ __global__ void cnn_features_kernel(const TB* __restrict__ Bin, const float* __r
 //                         w[tap][co][ci] x[b][pad(j+dy-1, k+dx-1)][ci]), bf16, 64 channels.
 // MODE 1 (data gradient): G[q][k][ci] = sum_tap sum_co w[tap][ci][co]
 //                         g[b][q-dy+1][k-dx+1][co] for padded rows q in [-1, H]
-//                         (g zero outside [0, H)); rows 1..H-2 are written as
-//                         bf16 masked by act > 0, rows -1, 0, H-1, H as FP32
-//                         to the edge buffer [b][4][W][64].
+//                         (computed as a forward correlation with the
+//                         tap-reversed weights of the wd layout)
+//                         (g zero outside [0, H)); interior rows 1..H-2,
+//                         written as bf16 masked by act > 0.
+// MODE 3 (data gradient, pole rows): G of rows -1, 0 (blockIdx.y = 0) and
+//                         H-1, H (blockIdx.y = 1) as FP32 to the edge buffer
+//                         [b][4][W][64], for edge_fold_kernel.
 // MODE 2 (output layer):  y[b][j][k] = bias[0] + sum_tap sum_ci w[tap][0][ci] x[...][ci],
 //                         FP32 (the weight rows 1..31 of the N tile are zero).
 // Weight layout: w[tap][n][k] with the GEMM's K index (input channel) contiguous;
@@ -120,12 +124,15 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
     // the input tile; MODE 0/1 reuse it for the bf16 output tile (channel
     // stride CTS), written back as 16-byte vectors
     constexpr int CTS = 64 + 8;
-    constexpr int TILE_E = TR * TC * CP, OUT_E = MODE == 2 ? 0 : CTY * CTX * CTS;
+    constexpr int TILE_E = TR * TC * CP, OUT_E = MODE >= 2 ? 0 : CTY * CTX * CTS;
+    constexpr bool DGRAD = MODE == 1 || MODE == 3;
     __shared__ __attribute__((aligned(16))) uint16_t tile[TILE_E > OUT_E ? TILE_E : OUT_E];
 
     const int b = blockIdx.z;
     const int k0 = blockIdx.x * CTX;
-    const int r0 = (MODE == 1 ? -1 : 0) + blockIdx.y * CTY;   // first output row of the tile
+    // first output row of the tile
+    const int r0 = MODE == 1 ? 1 + blockIdx.y * CTY : MODE == 3 ? (blockIdx.y == 0 ? -1 : H - 1)
+                                                                : blockIdx.y * CTY;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const size_t plane = (size_t)H * W;
     const uint16_t* xb = x + (size_t)b * plane * CIN;
@@ -137,7 +144,7 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
         const int tr = pix / TC, tc = pix - (pix / TC) * TC;
         const int j = r0 - 1 + tr, k = k0 - 1 + tc;
         uint4 val = make_uint4(0, 0, 0, 0);
-        if (MODE != 1) {
+        if (!DGRAD) {
             int sj, sk;
             if (sphere_src(j, k, H, W, sj, sk))
                 val = *(const uint4*)(xb + ((size_t)sj * W + sk) * CIN + cv * 8);
@@ -157,23 +164,37 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
             for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
 
     const int col = lane & 31, kh = lane >> 5;
+    // weight fragments come from global memory (L2-resident: every block
+    // reads the same layer); the next tap's fragments are loaded while the
+    // current tap's MFMAs run
+    const uint16_t* wl = w + (size_t)col * CIN + kh * 8;
+    bf16x8 wb[2][NCH][NTN];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int n = 0; n < NTN; ++n) wb[0][ch][n] = *(const bf16x8*)(wl + (size_t)n * 32 * CIN + ch * 16);
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap - (tap / 3) * 3;
-        const int oy = MODE == 1 ? 2 - dy : dy, ox = MODE == 1 ? 2 - dx : dx;
+        const int cur = tap & 1;
+        if (tap + 1 < 9) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                for (int n = 0; n < NTN; ++n)
+                    wb[cur ^ 1][ch][n] =
+                        *(const bf16x8*)(wl + ((size_t)(tap + 1) * NOUT + n * 32) * CIN + ch * 16);
+        }
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int kb = ch * 16 + kh * 8;
-            bf16x8 bfr[NTN];
-#pragma unroll
-            for (int n = 0; n < NTN; ++n)
-                bfr[n] = *(const bf16x8*)(w + ((size_t)tap * NOUT + n * 32 + col) * CIN + kb);
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const int tr = wv * 4 + m + oy;
-                const bf16x8 a = *(const bf16x8*)(tile + (tr * TC + col + ox) * CP + kb);
+                const int tr = wv * 4 + m + dy;
+                const bf16x8 a = *(const bf16x8*)(tile + (tr * TC + col + dx) * CP + kb);
 #pragma unroll
                 for (int n = 0; n < NTN; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[n], acc[m][n], 0, 0, 0);
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, wb[cur][ch][n], acc[m][n], 0, 0, 0);
             }
         }
     }
@@ -192,6 +213,22 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
         }
         return;
     }
+    if (MODE == 3) {
+        // rows r0, r0 + 1 (wave 0, m = 0, 1) -> edge rows 0, 1 or 2, 3
+        if (wv != 0) return;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int er = (blockIdx.y == 0 ? 0 : 2) + m;
+#pragma unroll
+            for (int n = 0; n < NTN; ++n)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int k = k0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                    if (k < W) edge[(((size_t)b * 4 + er) * W + k) * 64 + n * 32 + col] = acc[m][n][r];
+                }
+        }
+        return;
+    }
     __syncthreads();   // every wave is done reading the input tile
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -206,12 +243,6 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
                 float v = acc[m][n][r] + bv;
                 if (MODE == 0) v = v > 0.f ? v : 0.f;
                 tile[(rl * CTX + px) * CTS + c] = f2bf(v);
-                // data gradient of the pole rows and their ghost rows (-1, 0,
-                // H-1, H): FP32 to the edge buffer, folded by edge_fold_kernel
-                if (MODE == 1 && (row <= 0 || row >= H - 1) && row >= -1 && row <= H && k0 + px < W) {
-                    const int er = row <= 0 ? row + 1 : row - H + 3;   // -1,0 -> 0,1; H-1,H -> 2,3
-                    edge[(((size_t)b * 4 + er) * W + k0 + px) * 64 + c] = v;
-                }
             }
         }
     }
@@ -452,7 +483,10 @@ __device__ __forceinline__ int master_channel(int ci, int cin, int cip)
 
 // master W[co][ci][dy][dx] (co < cout) -> forward layout wf[tap][nout][cip]
 // (rows co >= cout and slots without a master channel zero) and, if wd, the
-// data-gradient layout wd[tap][ci][cop] (co contiguous, padded to cop).
+// data-gradient layout wd[tap][ci][cop] (co contiguous, padded to cop) with
+// the taps reversed (wd tap t holds master tap 8 - t), so that the data
+// gradient is the same correlation over the padded neighbourhood as the
+// forward pass.
 __global__ void pack_weights_kernel(const float* __restrict__ Wm, int cin, int cout, int cip, int nout,
                                     int cop, uint16_t* __restrict__ wf, uint16_t* __restrict__ wd)
 {
@@ -469,7 +503,7 @@ __global__ void pack_weights_kernel(const float* __restrict__ Wm, int cin, int c
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nd; e += gridDim.x * blockDim.x) {
         const int tap = e / (cin * cop), rem = e - tap * cin * cop;
         const int ci = rem / cop, co = rem - ci * cop;
-        const float v = co < cout ? Wm[((size_t)co * cin + ci) * 9 + tap] : 0.f;
+        const float v = co < cout ? Wm[((size_t)co * cin + ci) * 9 + (8 - tap)] : 0.f;
         wd[e] = f2bf(v);
     }
 }
@@ -585,13 +619,18 @@ void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const
 void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, const uint16_t* act,
                     uint16_t* dx, float* edge, int batch, int H, int W)
 {
-    dim3 g((W + CTX - 1) / CTX, (H + 2 + CTY - 1) / CTY, batch);
-    if (cin == 16)
+    dim3 g((W + CTX - 1) / CTX, (H - 2 + CTY - 1) / CTY, batch), ge2((W + CTX - 1) / CTX, 2, batch);
+    if (cin == 16) {
         hipLaunchKernelGGL((conv_mfma_kernel<16, 1, 2>), g, dim3(128), 0, st, dz, wd, (const float*)nullptr,
                            (void*)dx, H, W, act, edge);
-    else
+        hipLaunchKernelGGL((conv_mfma_kernel<16, 3, 2>), ge2, dim3(128), 0, st, dz, wd, (const float*)nullptr,
+                           (void*)dx, H, W, act, edge);
+    } else {
         hipLaunchKernelGGL((conv_mfma_kernel<64, 1, 2>), g, dim3(128), 0, st, dz, wd, (const float*)nullptr,
                            (void*)dx, H, W, act, edge);
+        hipLaunchKernelGGL((conv_mfma_kernel<64, 3, 2>), ge2, dim3(128), 0, st, dz, wd, (const float*)nullptr,
+                           (void*)dx, H, W, act, edge);
+    }
     dim3 ge(gblocks((size_t)2 * W * 64, 256, 1024), batch);
     hipLaunchKernelGGL(edge_fold_kernel, ge, dim3(256), 0, st, edge, act, dx, H, W);
 }
