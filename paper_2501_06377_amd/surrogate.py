@@ -80,7 +80,12 @@ def generate(nt, np_, n_traj, hours, sub=0, n_pairs=200, log=print):
     return snaps, feats, reals
 
 
-def train(net, snaps, feats, epochs=2, batch=16, lr=1e-3, lr_min=1e-5, log=print, log_every=200):
+def train(net, snaps, feats, epochs=2, batch=16, lr=1e-3, lr_min=1e-5, log=print, log_every=200,
+          seconds=0.0, save=None, save_every=120.0):
+    """Adam with a cosine learning-rate schedule over shuffled (trajectory,
+    hour) pairs.  With seconds > 0 the number of steps is set from the
+    measured step time so that training ends after about that long (epochs
+    is then ignored); save(params) is called every save_every seconds."""
     import torch
     n_traj, hp1 = snaps.shape[0], snaps.shape[1]
     pairs = np.array([(t, h) for t in range(n_traj) for h in range(hp1 - 1)], dtype=np.int64)
@@ -90,26 +95,40 @@ def train(net, snaps, feats, epochs=2, batch=16, lr=1e-3, lr_min=1e-5, log=print
     total = epochs * steps_per_epoch
     step = 0
     t0 = time.perf_counter()
+    last_save = t0
     hist = []
-    for ep in range(epochs):
-        order = order_rng.permutation(len(pairs))
-        for i in range(steps_per_epoch):
-            sel = pairs[order[i * batch:(i + 1) * batch]]
-            ti = torch.tensor(sel[:, 0], device="cuda")
-            hi = torch.tensor(sel[:, 1], device="cuda")
-            b_in = snaps[ti, hi].contiguous()
-            b_out = snaps[ti, hi + 1].contiguous()
-            f = fdev[ti].contiguous()
-            cur_lr = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step / max(total, 1)))
-            want = (step % log_every == 0) or step == total - 1
-            loss = net.train_step(b_in, b_out, f, cur_lr, want_loss=want)
-            if want:
-                el = time.perf_counter() - t0
-                log(f"epoch {ep} step {step}/{total} loss {loss:.4e} lr {cur_lr:.2e} ({el:.1f} s)")
-                hist.append((step, loss))
-            step += 1
+    order = order_rng.permutation(len(pairs))
+    i = 0
+    while step < total:
+        if i == steps_per_epoch:
+            order = order_rng.permutation(len(pairs))
+            i = 0
+        sel = pairs[order[i * batch:(i + 1) * batch]]
+        i += 1
+        ti = torch.tensor(sel[:, 0], device="cuda")
+        hi = torch.tensor(sel[:, 1], device="cuda")
+        b_in = snaps[ti, hi].contiguous()
+        b_out = snaps[ti, hi + 1].contiguous()
+        f = fdev[ti].contiguous()
+        cur_lr = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * step / max(total, 1)))
+        want = (step % log_every == 0) or step == total - 1
+        loss = net.train_step(b_in, b_out, f, cur_lr, want_loss=want)
+        if seconds > 0 and step == 20:
+            torch.cuda.synchronize()
+            per = (time.perf_counter() - t0) / 21
+            total = max(int(seconds / per), 21)
+            log(f"step time {per * 1e3:.1f} ms -> {total} steps ({total * batch / len(pairs):.2f} epochs)")
+        if want:
+            el = time.perf_counter() - t0
+            log(f"step {step}/{total} loss {loss:.4e} lr {cur_lr:.2e} ({el:.1f} s)")
+            hist.append((step, loss))
+        if save and time.perf_counter() - last_save > save_every:
+            save(net.get_params())
+            last_save = time.perf_counter()
+        step += 1
     torch.cuda.synchronize()
-    return {"steps": total, "seconds": time.perf_counter() - t0, "loss_history": hist}
+    return {"steps": total, "seconds": time.perf_counter() - t0, "loss_history": hist,
+            "epochs": total * batch / len(pairs)}
 
 
 def evaluate(net_params, nt, np_, n_real, hours, sub, tol=1e-3, log=print):
@@ -161,6 +180,8 @@ def main(argv=None):
     t.add_argument("--out", required=True)
     t.add_argument("--eval-real", type=int, default=4)
     t.add_argument("--eval-hours", type=int, default=24)
+    t.add_argument("--minutes", type=float, default=0.0, help="train for about this long (sets the steps)")
+    t.add_argument("--lr-min", type=float, default=1e-5)
     return ap.parse_args(argv)
 
 
@@ -171,7 +192,8 @@ def run_train(a):
         net.set_params(np.load(a.init).astype(np.float32))
     else:
         net.set_params(init_params(7))
-    info = train(net, snaps, feats, a.epochs, a.batch, a.lr)
+    info = train(net, snaps, feats, a.epochs, a.batch, a.lr, a.lr_min, seconds=60.0 * a.minutes,
+                 save=lambda p: np.save(a.out, p))
     params = net.get_params()
     np.save(a.out, params)
     del snaps
