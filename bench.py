@@ -41,8 +41,13 @@ METRIC = "realization-cell-updates/s + sim-days/s at 1 GPU; surrogate vs plain @
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=655)
+    ap.add_argument("--steps", type=int, default=None, help="1-hour intervals (default: 655 for the "
+                    "ensemble workload, 24 for the others)")
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=("ensemble", "precision", "batching"), default="ensemble",
+                    help="ensemble: 8 x 512x1024 FP64 with hourly assimilation (the headline); "
+                         "precision: 32 x 1024x2048 FP32-mixed with hourly assimilation; "
+                         "batching: 96 realizations in three size classes, FP32-mixed, graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", action="store_true", help="replay captured graphs (no per-kernel timing)")
@@ -60,34 +65,43 @@ def make_obs(f0, hours, dtype=np.float64):
     return np.stack(maps)
 
 
-def cpu_baseline(w, f0, obs_first, max_seconds):
-    """FP64 oracle on the first hours of the workload (all realizations)."""
+def cpu_baseline(nt, np_, reals, f0, obs_first, max_seconds):
+    """FP64 oracle on the first realization-hours of a workload class (hour
+    by hour, all realizations of an hour in turn), stopped after about
+    max_seconds of CPU work."""
     import math
 
     import oracle
-    nt, np_, reals = w.classes[0]
     B = [f0.copy() for _ in reals]
     updates = 0
+    done = 0
     t0 = time.perf_counter()
-    hours = 0
-    while True:
-        h = hours + 1
-        b0, l0 = synth.observer(float(h))
-        mu = oracle.mu_disk(nt, np_, math.radians(b0), math.radians(l0))
+    h = 0
+    el = 0.0
+    while el < max_seconds:
+        h += 1
+        if obs_first is not None:
+            if h > len(obs_first):
+                break
+            b0, l0 = synth.observer(float(h))
+            mu = oracle.mu_disk(nt, np_, math.radians(b0), math.radians(l0))
         for r, real in enumerate(reals):
-            B[r], st = oracle.advance(B[r], real.flow, real.nu_km2_s, float(hours), float(h))
-            F = oracle.weight_from_mu(mu, real.alpha_mu, real.mu_lim, math.radians(real.lat_lim_deg))
-            B[r] = oracle.assimilate(B[r], obs_first[hours], F, real.flux_balance)
-            updates += nt * np_ * (st["stages"] + 4 * st["steps"] + 1)
-        hours = h
-        el = time.perf_counter() - t0
-        if el >= max_seconds or hours >= len(obs_first):
-            break
+            B[r], st = oracle.advance(B[r], real.flow, real.nu_km2_s, float(h - 1), float(h))
+            n = st["stages"] + 4 * st["steps"]
+            if obs_first is not None:
+                F = oracle.weight_from_mu(mu, real.alpha_mu, real.mu_lim, math.radians(real.lat_lim_deg))
+                B[r] = oracle.assimilate(B[r], obs_first[h - 1], F, real.flux_balance)
+                n += 1
+            updates += nt * np_ * n
+            done += 1
+            el = time.perf_counter() - t0
+            if el >= max_seconds:
+                break
     return {"value": updates / el, "unit": "realization-cell-updates/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"first {hours} h of the ensemble workload, all {len(reals)} realizations "
-                      f"({el:.1f} s of CPU work, FP64 C oracle, OpenMP over rows)",
-            "sim_days_per_s": hours / 24.0 / el}
+            "sample": f"first {done} realization-hours ({nt}x{np_}, hour by hour over {len(reals)} "
+                      f"realizations; {el:.1f} s of CPU work, FP64 C oracle, OpenMP over rows)",
+            "sim_days_per_s": done / len(reals) / 24.0 / el}
 
 
 def log(msg):
@@ -215,34 +229,50 @@ def main():
 
     import paper_2501_06377_amd as sft
 
-    w = synth.config2()
-    nt, np_, reals = w.classes[0]
-    R = len(reals)
-    K, W = args.steps, args.warmup
-    f0 = synth.bipolar_field(nt, np_, synth.bipolar_pairs(w.n_pairs))
-    obs = make_obs(f0, range(1, max(K, W) + 1))
+    w = {"ensemble": synth.config2, "precision": synth.config3, "batching": synth.config4}[args.workload]()
+    K = args.steps if args.steps is not None else (655 if args.workload == "ensemble" else 24)
+    W = args.warmup
+    prec = 0 if w.precision == "f64" else 1
+    graphs = args.graphs or args.workload == "batching"
+    assim = w.assim_every_h > 0
     dev = torch.device("cuda:0")
-    obs_d = torch.from_numpy(obs).to(dev)
-    init_d = torch.from_numpy(np.ascontiguousarray(np.broadcast_to(f0, (R, nt, np_)))).to(dev)
+    ens = sft.Ensemble(precision=prec, use_graphs=1 if graphs else 0)
+    gids, inits, obs_d, f0s, obs0 = [], [], [], [], None
+    for ci, (nt, np_, reals) in enumerate(w.classes):
+        f0 = synth.bipolar_field(nt, np_, synth.bipolar_pairs(w.n_pairs, ci))
+        f0s.append(f0)
+        if assim:
+            obs = make_obs(f0, range(1, max(K, W) + 1))
+            if ci == 0:
+                obs0 = obs[:24]
+            obs_d.append(torch.from_numpy(obs).to(dev))
+            del obs
+        inits.append(torch.from_numpy(np.ascontiguousarray(np.broadcast_to(f0, (len(reals), nt, np_)))).to(dev))
+        gids.append(ens.add_grid(nt, np_, reals))
+    R = w.n_real
     torch.cuda.synchronize()
-
-    ens = sft.Ensemble(use_graphs=1 if args.graphs else 0)
-    gid = ens.add_grid(nt, np_, reals)
+    log(f"{w.name}: inputs resident, {K} timed intervals")
 
     def run(n_steps):
         for h in range(1, n_steps + 1):
             ens.advance(float(h))
-            b0, l0 = synth.observer(float(h))
-            ens.assimilate(gid, obs_d[h - 1], None, sft.SFT_WEIGHT_DISK, b0, l0)
+            if assim:
+                b0, l0 = synth.observer(float(h))
+                for g, o in zip(gids, obs_d):
+                    ens.assimilate(g, o[h - 1], None, sft.SFT_WEIGHT_DISK, b0, l0)
 
-    ens.set_states(gid, init_d)
+    def reset():
+        for g, x in zip(gids, inits):
+            ens.set_states(g, x)
+        ens.set_time(0.0)
+
+    reset()
     run(W)
     ens.sync()
     # timed region starts from the initial state at t = 0
-    ens.set_states(gid, init_d)
-    ens.set_time(0.0)
+    reset()
     c0 = [ens.counts(r) for r in range(R)]
-    ens.set_timing(not args.graphs)
+    ens.set_timing(not graphs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run(K)
@@ -250,20 +280,22 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     c1 = [ens.counts(r) for r in range(R)]
-    fams = ens.timing() if not args.graphs else {}
+    fams = ens.timing() if not graphs else {}
 
-    cells = nt * np_
-    updates = sum(cells * ((b["stages"] - a["stages"]) + (b["adv_stages"] - a["adv_stages"]) +
-                           (b["assim"] - a["assim"])) for a, b in zip(c0, c1))
+    cells = [nt * np_ for nt, np_, reals in w.classes for _ in reals]
+    updates = sum(n * ((b["stages"] - a["stages"]) + (b["adv_stages"] - a["adv_stages"]) +
+                       (b["assim"] - a["assim"])) for n, a, b in zip(cells, c0, c1))
     value = updates / wall
     diag = ens.diagnostics(0)
     out = {
         "metric": METRIC, "value": value, "unit": "realization-cell-updates/s", "n_gpus": 1,
         "steps": K, "warmup": W, "ms_per_step": wall / K * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": w.name, "grid": f"{nt}x{np_}", "realizations": R,
-                   "step": "1 h interval: advection + RKG2 diffusion + mu^4 assimilation + diagnostics",
-                   "simulated_hours": K, "graphs": bool(args.graphs)},
+        "scaling": "weak", "vs_baseline": None, "dtype": w.precision, "data": "synthetic",
+        "config": {"workload": w.name, "grid": [f"{nt}x{np_}x{len(r)}" for nt, np_, r in w.classes],
+                   "realizations": R,
+                   "step": "1 h interval: advection + RKG2 diffusion" +
+                           (" + mu^4 assimilation" if assim else "") + " + diagnostics",
+                   "simulated_hours": K, "graphs": bool(graphs)},
         "sim_days_per_s": K / 24.0 / wall,
     }
     if fams:
@@ -285,13 +317,17 @@ def main():
                           for k, v in fams.items() if v["launches"]}
         out["kernel_time_frac"] = sum(v["ms"] for v in fams.values()) * 1e-3 / wall
     out["final_diag_r0"] = {k: diag[k] for k in ("phi_pos", "phi_neg", "dax", "bmin", "bmax")}
+    if w.precision == "f32":
+        out["state_dtype"] = "f64 (state, flux and weight reductions)"
     ens.close()
-    del obs_d, init_d
-    log(f"ensemble: {wall:.2f} s for {K} intervals")
-    if not args.no_surrogate:
+    del obs_d, inits
+    log(f"{w.name}: {wall:.2f} s for {K} intervals")
+    if not args.no_surrogate and args.workload == "ensemble":
         out["surrogate"] = surrogate_bench(sft, torch, args.surr_batch)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, f0, obs[:24], args.cpu_seconds)
+        nt, np_, reals = w.classes[-1]
+        out["cpu_baseline"] = cpu_baseline(nt, np_, reals, f0s[-1], obs0 if len(w.classes) == 1 else None,
+                                           args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

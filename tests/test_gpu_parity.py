@@ -234,3 +234,72 @@ def test_blocked_tiles_bitwise_equal_unfused(prec):
     if prec == 0:
         oref, _ = oracle_run(B0, reals, sched)
         assert rel_l2(ref, oref) <= TOL64
+
+
+def run_classes(classes, fields, hours, **optkw):
+    """All size classes in one context (one plan / graph per interval)."""
+    import paper_2501_06377_amd as sft
+    ens = sft.Ensemble(**optkw)
+    gids = []
+    for (nt, np_, reals), B0 in zip(classes, fields):
+        g = ens.add_grid(nt, np_, reals)
+        ens.set_states(g, B0)
+        gids.append(g)
+    for h in hours:
+        ens.advance(float(h))
+    return [ens.get_states(g) for g in gids], ens
+
+
+@pytest.mark.parametrize("prec,graphs", [(0, 0), (0, 1), (1, 1)])
+def test_uneven_classes_in_one_context(prec, graphs):
+    """Three grid classes of uneven sizes advanced together (per-realization
+    dt and stage counts, one graph per interval), each realization against
+    the oracle."""
+    say(f"case uneven classes precision {prec} graphs {graphs}")
+    classes = [(24, 48, reals_mix(2)), (40, 80, reals_mix(3)), (64, 128, reals_mix(2, nu=(900.0, 300.0)))]
+    fields = [np.stack([random_field(nt, np_, 6, 90 + 10 * c + i) for i in range(len(rs))])
+              for c, (nt, np_, rs) in enumerate(classes)]
+    hours = [1.0, 2.0, 3.5]
+    got, ens = run_classes(classes, fields, hours, precision=prec, use_graphs=graphs)
+    tol = TOL64 if prec == 0 else TOL32
+    for c, ((nt, np_, rs), B0) in enumerate(zip(classes, fields)):
+        ref, _ = oracle_run(B0, rs, [("advance", h) for h in hours])
+        for r in range(len(rs)):
+            e = rel_l2(got[c][r], ref[r])
+            say(f"  class {nt}x{np_} realization {r}: rel-L2 {e:.3e}")
+            assert e <= tol
+
+
+def test_full_size_mixed_precision_first_hour():
+    """The precision workload's grid (1024 x 2048, FP32 stencils with FP64
+    state and reductions): two of its realizations, first hour plus one
+    mu^4 assimilation, against the FP64 oracle."""
+    w = synth.config3(n=2)
+    nt, np_, reals = w.classes[0]
+    say(f"case {w.name}: first hour, 2 realizations")
+    f0 = random_field(nt, np_, w.n_pairs)
+    B0 = np.stack([f0] * len(reals))
+    b0, l0 = synth.observer(1.0)
+    sched = [("advance", 1.0), ("assim", synth.observation(f0, 1.0, 1), 2, None, b0, l0)]
+    ref, st = oracle_run(B0, reals, sched)
+    got, _ = gpu_run(B0, reals, sched, precision=1)
+    for r in range(len(reals)):
+        e = rel_l2(got[r], ref[r])
+        say(f"  realization {r}: stages {st[r]['stages']} rel-L2 {e:.3e} "
+            f"max-abs {np.abs(got[r] - ref[r]).max():.3e} G")
+        assert e <= TOL32
+
+
+def test_full_size_uneven_batch_first_hour():
+    """The batching workload's three size classes (256x512, 512x1024,
+    1024x2048; one realization each here) in one graph-captured context,
+    FP32 stencils, first hour, against the FP64 oracle."""
+    w = synth.config4(n_each=1)
+    say(f"case {w.name}: first hour, one realization per class")
+    fields = [random_field(nt, np_, w.n_pairs, 7)[None].copy() for nt, np_, _ in w.classes]
+    got, _ = run_classes(w.classes, fields, [1.0], precision=1, use_graphs=1)
+    for c, ((nt, np_, rs), B0) in enumerate(zip(w.classes, fields)):
+        ref, st = oracle_run(B0, rs, [("advance", 1.0)])
+        e = rel_l2(got[c][0], ref[0])
+        say(f"  class {nt}x{np_}: stages {st[0]['stages']} rel-L2 {e:.3e}")
+        assert e <= TOL32
