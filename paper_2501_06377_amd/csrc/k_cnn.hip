@@ -164,37 +164,22 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
             for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
 
     const int col = lane & 31, kh = lane >> 5;
-    // weight fragments come from global memory (L2-resident: every block
-    // reads the same layer); the next tap's fragments are loaded while the
-    // current tap's MFMAs run
-    const uint16_t* wl = w + (size_t)col * CIN + kh * 8;
-    bf16x8 wb[2][NCH][NTN];
-#pragma unroll
-    for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-        for (int n = 0; n < NTN; ++n) wb[0][ch][n] = *(const bf16x8*)(wl + (size_t)n * 32 * CIN + ch * 16);
-#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap - (tap / 3) * 3;
-        const int cur = tap & 1;
-        if (tap + 1 < 9) {
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch)
-#pragma unroll
-                for (int n = 0; n < NTN; ++n)
-                    wb[cur ^ 1][ch][n] =
-                        *(const bf16x8*)(wl + ((size_t)(tap + 1) * NOUT + n * 32) * CIN + ch * 16);
-        }
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int kb = ch * 16 + kh * 8;
+            bf16x8 bfr[NTN];
+#pragma unroll
+            for (int n = 0; n < NTN; ++n)
+                bfr[n] = *(const bf16x8*)(w + ((size_t)tap * NOUT + n * 32 + col) * CIN + kb);
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int tr = wv * 4 + m + dy;
                 const bf16x8 a = *(const bf16x8*)(tile + (tr * TC + col + dx) * CP + kb);
 #pragma unroll
                 for (int n = 0; n < NTN; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, wb[cur][ch][n], acc[m][n], 0, 0, 0);
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[n], acc[m][n], 0, 0, 0);
             }
         }
     }
