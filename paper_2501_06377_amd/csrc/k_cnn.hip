@@ -279,13 +279,17 @@ __global__ void edge_fold_kernel(const float* __restrict__ edge, const uint16_t*
 }
 
 // ------------------------------------------------------------ weight grad
-// For one row segment of WG_PX output pixels at a time, every tap:
-//   part[blk][tap][co][ci] += sum_p x[pad(p + tap)][ci] * dz[p][co]
-// (MFMA with pixels as K; x staged transposed, once per column shift dx),
-// and bpart[blk][co] += sum_p dz[p][co] (bias gradient).  Wave (ci tile, co
-// tile) accumulates all nine taps, reusing each dz fragment nine times.
-// CIN or COUT of 16 are zero-extended to one 32-row tile.
-constexpr int WG_PX = 64;
+// One work item = a column segment of WG_PX output pixels over WG_RB
+// consecutive rows of one sample.  For every row j of it and every tap:
+//   part[blk][tap][co][ci] += sum_p x[pad(j + dy - 1, p + dx - 1)][ci] * dz[j][p][co]
+// (MFMA with pixels as K), and bpart[blk][co] += sum_p dz[j][p][co] (bias
+// gradient).  The input rows j-1, j, j+1 live in a three-slot ring in LDS,
+// stored transposed (pixels contiguous) once per column shift dx, so each
+// input row is staged once per work item; the next row's global loads are
+// in flight while the current row's MFMAs run.  Wave (ci tile, co tile)
+// accumulates all nine taps.  CIN or COUT of 16 are zero-extended to one
+// 32-row tile.
+constexpr int WG_PX = 64, WG_RB = 16;
 
 template <int CIN, int COUT>
 __global__ __launch_bounds__(64 * (CIN < 32 ? 1 : CIN / 32) * (COUT < 32 ? 1 : COUT / 32))
@@ -295,14 +299,16 @@ void wgrad_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restric
     constexpr int CIP = CIN < 32 ? 32 : CIN, COP = COUT < 32 ? 32 : COUT;
     constexpr int NCI = CIP / 32, NCO = COP / 32, NT = 64 * NCI * NCO;
     constexpr int PS = WG_PX + 8;      // pixel stride of one channel row (bf16)
-    __shared__ __attribute__((aligned(16))) uint16_t xs[3 * 3 * CIP * PS];
-    __shared__ __attribute__((aligned(16))) uint16_t gs[COP * PS];
+    constexpr int XV = (WG_PX + 2) * (CIN / 8), XPT = (XV + NT - 1) / NT;   // x row: 16-byte vectors
+    constexpr int GV = WG_PX * (COUT / 8), GPT = (GV + NT - 1) / NT;        // dz row
+    __shared__ __attribute__((aligned(16))) uint16_t xs[3 * 3 * CIP * PS];  // [slot][dx][ci][px]
+    __shared__ __attribute__((aligned(16))) uint16_t gs[COP * PS];          // [co][px]
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int ci_t = wv / NCO, co_t = wv - (wv / NCO) * NCO;
     const int col = lane & 31, kh = lane >> 5;
-    const int segs = (W + WG_PX - 1) / WG_PX;
-    const long nseg = (long)batch * H * segs;
+    const int segs = (W + WG_PX - 1) / WG_PX, rch = (H + WG_RB - 1) / WG_RB;
+    const long nwork = (long)batch * rch * segs;
 
     for (int e = tid; e < 3 * 3 * CIP * PS; e += NT) xs[e] = 0;
     for (int e = tid; e < COP * PS; e += NT) gs[e] = 0;
@@ -313,56 +319,99 @@ void wgrad_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restric
         for (int r = 0; r < 16; ++r) acc[t][r] = 0.f;
     float bsum = 0.f;
 
-    for (long sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
-        const int b = (int)(sg / ((long)H * segs));
-        const long rem = sg - (long)b * H * segs;
-        const int j = (int)(rem / segs);
-        const int k0 = (int)(rem - (long)j * segs) * WG_PX;
-        __syncthreads();
-        // x rows j-1..j+1, columns k0-1 .. k0+WG_PX: copy dx holds column
-        // k0 + px + dx - 1.  Consecutive lanes take consecutive columns, so the
-        // transposed 2-byte LDS writes of a wave land in consecutive banks.
-        for (int v = tid; v < 3 * (WG_PX + 2) * (CIN / 8); v += NT) {
-            const int pc = v % (WG_PX + 2), rest = v / (WG_PX + 2);
-            const int dy = rest % 3, cv = rest / 3;
+    uint4 xr[XPT], gr[GPT];
+    // x row j (padded coordinates), columns k0-1 .. k0+WG_PX -> registers
+    auto load_x = [&](int b, int j, int k0) {
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            const int v = tid + i * NT;
+            const int pc = v % (WG_PX + 2), cv = v / (WG_PX + 2);
             int sj, sk;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (sphere_src(j + dy - 1, k0 + pc - 1, H, W, sj, sk))
-                val = *(const uint4*)(x + (((size_t)b * H + sj) * W + sk) * CIN + cv * 8);
-            const uint16_t* h = (const uint16_t*)&val;
+            xr[i] = make_uint4(0, 0, 0, 0);
+            if (v < XV && sphere_src(j, k0 + pc - 1, H, W, sj, sk))
+                xr[i] = *(const uint4*)(x + (((size_t)b * H + sj) * W + sk) * CIN + cv * 8);
+        }
+    };
+    // registers -> ring slot, copy dx holding column k0 + px + dx - 1;
+    // consecutive lanes take consecutive columns (conflict-free 2-byte writes)
+    auto store_x = [&](int slot) {
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) {
+            const int v = tid + i * NT;
+            if (v >= XV) continue;
+            const int pc = v % (WG_PX + 2), cv = v / (WG_PX + 2);
+            const uint16_t* h = (const uint16_t*)&xr[i];
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
                 const int px = pc - dx;
                 if (px < 0 || px >= WG_PX) continue;
-                uint16_t* dst = xs + ((dx * 3 + dy) * CIP + cv * 8) * PS + px;
+                uint16_t* dst = xs + ((slot * 3 + dx) * CIP + cv * 8) * PS + px;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) dst[i * PS] = h[i];
+                for (int e = 0; e < 8; ++e) dst[e * PS] = h[e];
             }
         }
-        for (int v = tid; v < WG_PX * (COUT / 8); v += NT) {
+    };
+    auto load_g = [&](int b, int j, int k0) {
+#pragma unroll
+        for (int i = 0; i < GPT; ++i) {
+            const int v = tid + i * NT;
             const int px = v % WG_PX, cv = v / WG_PX;
-            const int k = k0 + px;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if (k < W) val = *(const uint4*)(dz + (((size_t)b * H + j) * W + k) * COUT + cv * 8);
-            const uint16_t* h = (const uint16_t*)&val;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) gs[(cv * 8 + i) * PS + px] = h[i];
+            gr[i] = make_uint4(0, 0, 0, 0);
+            if (v < GV && k0 + px < W)
+                gr[i] = *(const uint4*)(dz + (((size_t)b * H + j) * W + k0 + px) * COUT + cv * 8);
         }
-        __syncthreads();
-        if (tid < COUT) {
-            float s = 0.f;
-            for (int px = 0; px < WG_PX; ++px) s += bf2f(gs[tid * PS + px]);
-            bsum += s;
+    };
+    auto store_g = [&]() {
+#pragma unroll
+        for (int i = 0; i < GPT; ++i) {
+            const int v = tid + i * NT;
+            if (v >= GV) continue;
+            const int px = v % WG_PX, cv = v / WG_PX;
+            const uint16_t* h = (const uint16_t*)&gr[i];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) gs[(cv * 8 + e) * PS + px] = h[e];
         }
+    };
+
+    for (long wk = blockIdx.x; wk < nwork; wk += gridDim.x) {
+        const int b = (int)(wk / ((long)rch * segs));
+        const long rem = wk - (long)b * rch * segs;
+        const int rc = (int)(rem / segs);
+        const int k0 = (int)(rem - (long)rc * segs) * WG_PX;
+        const int j0 = rc * WG_RB, j1 = j0 + WG_RB < H ? j0 + WG_RB : H;
+        __syncthreads();   // the previous work item is done with the ring
+        load_x(b, j0 - 1, k0);
+        store_x((j0 + 2) % 3);
+        load_x(b, j0, k0);
+        store_x(j0 % 3);
+        load_x(b, j0 + 1, k0);
+        load_g(b, j0, k0);
+        for (int j = j0; j < j1; ++j) {
+            __syncthreads();   // the MFMAs of row j-1 are done with slot (j+1)%3 and gs
+            store_x((j + 1) % 3);
+            store_g();
+            __syncthreads();
+            if (j + 1 < j1) {
+                load_x(b, j + 2, k0);
+                load_g(b, j + 1, k0);
+            }
+            if (tid < COUT) {
+                float sb = 0.f;
+                for (int px = 0; px < WG_PX; ++px) sb += bf2f(gs[tid * PS + px]);
+                bsum += sb;
+            }
 #pragma unroll
-        for (int ks = 0; ks < WG_PX / 16; ++ks) {
-            const int pb = ks * 16 + kh * 8;
-            const bf16x8 bb = *(const bf16x8*)(gs + (co_t * 32 + col) * PS + pb);
+            for (int ks = 0; ks < WG_PX / 16; ++ks) {
+                const int pb = ks * 16 + kh * 8;
+                const bf16x8 bb = *(const bf16x8*)(gs + (co_t * 32 + col) * PS + pb);
 #pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int dy = t / 3, dx = t - (t / 3) * 3;
-                const bf16x8 a = *(const bf16x8*)(xs + ((dx * 3 + dy) * CIP + ci_t * 32 + col) * PS + pb);
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[t], 0, 0, 0);
+                for (int t = 0; t < 9; ++t) {
+                    const int dy = t / 3, dx = t - (t / 3) * 3;
+                    const int slot = (j + dy + 2) % 3;   // row j + dy - 1
+                    const bf16x8 a =
+                        *(const bf16x8*)(xs + ((slot * 3 + dx) * CIP + ci_t * 32 + col) * PS + pb);
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bb, acc[t], 0, 0, 0);
+                }
             }
         }
     }
@@ -378,6 +427,56 @@ void wgrad_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restric
         }
     }
     if (tid < COUT) bpart[(size_t)blockIdx.x * COUT + tid] = bsum;
+}
+
+// Weight and bias gradient of the output layer (one output channel), a
+// plain reduction over pixels on the vector units:
+//   part[blk][tap][ci] = sum_{j,k} g[j][k] x[pad(j + dy - 1, k + dx - 1)][ci],
+//   bpart[blk] = sum g,
+// g = channel 0 of the 16-channel bf16 output gradient.  Thread: channels
+// 2c, 2c+1 (c = tid % 32) and every 8th pixel of a row (phase tid / 32);
+// rows are distributed over the blocks, partials folded in LDS.
+__global__ __launch_bounds__(256) void wgrad_out_kernel(const uint16_t* __restrict__ x,
+                                                        const uint16_t* __restrict__ dyb,
+                                                        float* __restrict__ part, float* __restrict__ bpart,
+                                                        int batch, int H, int W)
+{
+    __shared__ float red[8][9 * 64 + 1];
+    const int tid = threadIdx.x, c2 = tid & 31, ph = tid >> 5;
+    float acc[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t][0] = acc[t][1] = 0.f;
+    float bs = 0.f;
+    const long nrow = (long)batch * H;
+    for (long rw = blockIdx.x; rw < nrow; rw += gridDim.x) {
+        const int b = (int)(rw / H), j = (int)(rw - (long)b * H);
+        for (int k = ph; k < W; k += 8) {
+            const float g = bf2f(dyb[(((size_t)b * H + j) * W + k) * 16]);
+            bs += g;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int dy = t / 3, dx = t - (t / 3) * 3;
+                int sj, sk;
+                if (!sphere_src(j + dy - 1, k + dx - 1, H, W, sj, sk)) continue;
+                const uint32_t v = *(const uint32_t*)(x + (((size_t)b * H + sj) * W + sk) * 64 + 2 * c2);
+                acc[t][0] += g * bf2f((uint16_t)(v & 0xFFFFu));
+                acc[t][1] += g * bf2f((uint16_t)(v >> 16));
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        red[ph][t * 64 + 2 * c2] = acc[t][0];
+        red[ph][t * 64 + 2 * c2 + 1] = acc[t][1];
+    }
+    if (c2 == 0) red[ph][9 * 64] = bs;
+    __syncthreads();
+    for (int e = tid; e < 9 * 64 + 1; e += 256) {
+        float s = 0.f;
+        for (int q = 0; q < 8; ++q) s += red[q][e];
+        if (e < 9 * 64) part[(size_t)blockIdx.x * 9 * 64 + e] = s;
+        else bpart[blockIdx.x] = s;
+    }
 }
 
 // Master-layout gradient grad[co][mc][dy][dx], co < cout_out, summed over the
@@ -627,18 +726,23 @@ void cnn_wgrad(hipStream_t st, int cin, int cout, int cin_out, int cout_out, con
                const uint16_t* dz, float* part, float* bpart, int nblk, float* grad, float* gbias,
                int batch, int H, int W)
 {
-    if (cin == 16)
+    int pc = cout;   // output channels of the partial layout
+    if (cin == 16) {
         hipLaunchKernelGGL((wgrad_mfma_kernel<16, 64>), dim3(nblk), dim3(128), 0, st, x, dz, part, bpart,
                            batch, H, W);
-    else if (cout == 16)
-        hipLaunchKernelGGL((wgrad_mfma_kernel<64, 16>), dim3(nblk), dim3(128), 0, st, x, dz, part, bpart,
-                           batch, H, W);
-    else
+    } else if (cout == 16) {
+        // the output layer: only channel 0 of its gradient input is live;
+        // 4 nblk blocks of 9 x 64 partials fit the buffers sized for nblk x 9 x 64 x 64
+        nblk *= 4;
+        hipLaunchKernelGGL(wgrad_out_kernel, dim3(nblk), dim3(256), 0, st, x, dz, part, bpart, batch, H, W);
+        pc = 1;
+    } else {
         hipLaunchKernelGGL((wgrad_mfma_kernel<64, 64>), dim3(nblk), dim3(256), 0, st, x, dz, part, bpart,
                            batch, H, W);
+    }
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(gblocks((size_t)9 * cout_out * cin_out, 256, 1024)),
-                       dim3(256), 0, st, part, nblk, cin, cout, cin_out, cout_out, grad);
-    hipLaunchKernelGGL(colsum_reduce_kernel, dim3(1), dim3(64), 0, st, bpart, nblk, cout, cout_out, gbias);
+                       dim3(256), 0, st, part, nblk, cin, pc, cin_out, cout_out, grad);
+    hipLaunchKernelGGL(colsum_reduce_kernel, dim3(1), dim3(64), 0, st, bpart, nblk, pc, cout_out, gbias);
 }
 
 void cnn_loss_grad(hipStream_t st, const float* y, const void* Bin, const void* Bt, int dtype, uint16_t* dyb,
