@@ -145,17 +145,151 @@ __global__ __launch_bounds__(NT) void diff_fused_kernel(
     }
 }
 
+// ------------------------------------------------------------ strip variant
+// The same K-stage blocking with a different owner map: lane = column of a
+// 64-column staged region (TX = 64 - 2K output columns), wave w = a strip of
+// RPT consecutive rows (TY = NW * RPT - 2K output rows).  A cell's west and
+// east neighbours come from the adjacent lanes through whole-wave DPP shifts,
+// north and south from the lane's own registers; only the two end rows of
+// each strip are exchanged through LDS (double-buffered by stage parity, one
+// barrier per stage).  Row coefficients are wave-uniform (scalar loads).
+// Ring cells (lane 0 and 63, the first and last staged row) are never
+// updated, exactly as in the tiled variant, so both give identical results.
+__device__ __forceinline__ double lane_west(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_east(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_west(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_east(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+
+template <bool MIXED, int K, int RPT, int NW>
+__global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
+    const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs, int j0,
+    const DiffRow<typename FT<MIXED>::T>* __restrict__ drow,
+    const typename FT<MIXED>::T* __restrict__ in1, const typename FT<MIXED>::T* __restrict__ in2,
+    const double* __restrict__ y0, const typename FT<MIXED>::T* __restrict__ ly0,
+    typename FT<MIXED>::T* __restrict__ out1, typename FT<MIXED>::T* __restrict__ out2,
+    double* __restrict__ B, const float* __restrict__ adv, int nt, int np)
+{
+    using T = typename FT<MIXED>::T;
+    constexpr int LX = 64, TX = LX - 2 * K, LY = NW * RPT, TY = LY - 2 * K;
+    __shared__ T xch[2][2][NW][64];   // [stage parity][top, bottom row][wave][lane]
+
+    const Entry e = ents[blockIdx.z];
+    const int kk = min(K, e.s - j0 + 1);
+    const bool fin = (j0 + kk - 1 == e.s);
+    const size_t base = (size_t)e.r * nt * np;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int k0 = blockIdx.x * TX, jt0 = blockIdx.y * TY;
+    const int jw = jt0 - K + w * RPT;   // global row of the strip's first cell
+    int kc = (k0 - K + lane) % np;
+    if (kc < 0) kc += np;
+    const bool colact = lane >= 1 && lane <= LX - 2;
+    const bool has_in2 = in2 != nullptr;
+    const DiffRow<T>* dr = drow + (size_t)e.r * nt;
+
+    T ycur[RPT], ym2[RPT], lyr[RPT];
+    double y0r[MIXED ? 1 : RPT];
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const int j = jw + m;
+        T a = T(0), b = T(0), l = T(0);
+        double z = 0.0;
+        if (j >= 0 && j < nt) {
+            const size_t i = base + (size_t)j * np + kc;
+            a = in1[i];
+            if (has_in2) b = in2[i];
+            l = ly0[i];
+            if constexpr (!MIXED) z = y0[i];
+        }
+        ycur[m] = a;
+        ym2[m] = b;
+        lyr[m] = l;
+        if constexpr (!MIXED) y0r[m] = z;
+    }
+
+    for (int i = 0; i < kk; ++i) {
+        const StageCoef c = coefs[e.coef_off + j0 + i];
+        const bool h2 = has_in2 || i > 0;
+        const int q = i & 1;
+        xch[q][0][w][lane] = ycur[0];
+        xch[q][1][w][lane] = ycur[RPT - 1];
+        __syncthreads();
+        const T north = w > 0 ? xch[q][1][w - 1][lane] : T(0);
+        const T south = w < NW - 1 ? xch[q][0][w + 1][lane] : T(0);
+        T prev = north;   // this stage's input value of the row above
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int j = jw + m, ly = w * RPT + m;
+            const T cur = ycur[m];
+            const T sv = m < RPT - 1 ? ycur[m + 1] : south;
+            const T wv = lane_west(cur), ev = lane_east(cur);
+            if (ly >= 1 && ly <= LY - 2 && j >= 0 && j < nt) {
+                const DiffRow<T> d = dr[j];
+                const T L = L5<T>(d, wv, prev, cur, sv, ev);
+                T v;
+                if constexpr (MIXED) v = sts_mixed(c, cur, ym2[m], h2, L, lyr[m]);
+                else v = sts_f64(c, cur, ym2[m], y0r[m], L, lyr[m]);
+                if (colact) {
+                    ym2[m] = cur;
+                    ycur[m] = v;
+                }
+            }
+            prev = cur;
+        }
+    }
+
+    const int k = k0 + lane - K;
+    if (lane < K || lane >= K + TX || k >= np) return;
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const int ly = w * RPT + m, j = jw + m;
+        if (ly < K || ly >= K + TY || j >= nt) continue;
+        const size_t gi = base + (size_t)j * np + k;
+        if (fin) {
+            if constexpr (MIXED) {
+                double yv = B[gi];
+                if (e.pad) yv += (double)adv[gi];
+                B[gi] = yv + (double)ycur[m];
+            } else {
+                B[gi] = ycur[m];
+            }
+        } else {
+            out1[gi] = ycur[m];
+            out2[gi] = ym2[m];
+        }
+    }
+}
+
 // ------------------------------------------------------------ configurations
 struct FusedCfg {
     int tx, ty, k, nt;
 };
 
+// tiled shapes first, then the strip variant (tx = 64 - 2K, ty = waves x rows - 2K)
 static const FusedCfg kCfg64[] = {
-    {64, 16, 4, 256}, {64, 32, 8, 256}, {128, 16, 4, 256}, {32, 32, 4, 256}, {64, 32, 6, 256}};
+    {64, 16, 4, 256}, {64, 32, 8, 256}, {128, 16, 4, 256}, {32, 32, 4, 256}, {64, 32, 6, 256},
+    {48, 48, 8, 256}, {48, 112, 8, 512}, {52, 116, 6, 512}, {48, 48, 8, 512}};
 static const FusedCfg kCfg32[] = {
-    {64, 16, 4, 256}, {64, 32, 8, 256}, {128, 32, 8, 256}, {128, 16, 8, 256}, {64, 64, 8, 512}};
+    {64, 16, 4, 256}, {64, 32, 8, 256}, {128, 32, 8, 256}, {128, 16, 8, 256}, {64, 64, 8, 512},
+    {48, 48, 8, 256}, {48, 112, 8, 512}, {48, 112, 8, 256}, {52, 116, 6, 512}};
 
-int fused_config_count(bool mixed) { return mixed ? 5 : 5; }
+int fused_config_count(bool mixed) { return mixed ? 9 : 9; }
 
 int fused_config_k(bool mixed, int cfg) { return mixed ? kCfg32[cfg].k : kCfg64[cfg].k; }
 
@@ -181,6 +315,20 @@ static void launch_one(hipStream_t st, const Entry* ents, int n_act, const Stage
                        (T*)out1, (T*)out2, B, adv, nt, np);
 }
 
+template <bool MIXED, int K, int RPT, int NW>
+static void launch_strip(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs, int j0,
+                         const void* drow, const void* in1, const void* in2, const double* y0,
+                         const void* ly0, void* out1, void* out2, double* B, const float* adv, int nt,
+                         int np)
+{
+    using T = typename FT<MIXED>::T;
+    constexpr int TX = 64 - 2 * K, TY = NW * RPT - 2 * K;
+    dim3 grid((np + TX - 1) / TX, (nt + TY - 1) / TY, n_act);
+    hipLaunchKernelGGL((diff_strip_kernel<MIXED, K, RPT, NW>), grid, dim3(64 * NW), 0, st, ents, coefs, j0,
+                       (const DiffRow<T>*)drow, (const T*)in1, (const T*)in2, y0, (const T*)ly0,
+                       (T*)out1, (T*)out2, B, adv, nt, np);
+}
+
 void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, int n_act,
                        const StageCoef* coefs, int j0, const void* drow, const void* in1,
                        const void* in2, const double* y0, const void* ly0, void* out1, void* out2,
@@ -188,13 +336,19 @@ void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, i
 {
 #define L1(M, a, b, c, d) \
     launch_one<M, a, b, c, d>(st, ents, n_act, coefs, j0, drow, in1, in2, y0, ly0, out1, out2, B, adv, nt, np)
+#define S1(M, k, r, w) \
+    launch_strip<M, k, r, w>(st, ents, n_act, coefs, j0, drow, in1, in2, y0, ly0, out1, out2, B, adv, nt, np)
     if (!mixed) {
         switch (cfg) {
         case 0: L1(false, 64, 16, 4, 256); break;
         case 1: L1(false, 64, 32, 8, 256); break;
         case 2: L1(false, 128, 16, 4, 256); break;
         case 3: L1(false, 32, 32, 4, 256); break;
-        default: L1(false, 64, 32, 6, 256); break;
+        case 4: L1(false, 64, 32, 6, 256); break;
+        case 5: S1(false, 8, 16, 4); break;
+        case 6: S1(false, 8, 16, 8); break;
+        case 7: S1(false, 6, 16, 8); break;
+        default: S1(false, 8, 8, 8); break;
         }
     } else {
         switch (cfg) {
@@ -202,10 +356,15 @@ void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, i
         case 1: L1(true, 64, 32, 8, 256); break;
         case 2: L1(true, 128, 32, 8, 256); break;
         case 3: L1(true, 128, 16, 8, 256); break;
-        default: L1(true, 64, 64, 8, 512); break;
+        case 4: L1(true, 64, 64, 8, 512); break;
+        case 5: S1(true, 8, 16, 4); break;
+        case 6: S1(true, 8, 16, 8); break;
+        case 7: S1(true, 8, 32, 4); break;
+        default: S1(true, 6, 16, 8); break;
         }
     }
 #undef L1
+#undef S1
 }
 
 }  // namespace sft
