@@ -281,6 +281,11 @@ def main():
     wall = time.perf_counter() - t0
     c1 = [ens.counts(r) for r in range(R)]
     fams = ens.timing() if not graphs else {}
+    tiles = []
+    for g in gids:
+        ti = ens.tile_choice(g)
+        desc = sft.tile_info(prec, ti) if ti >= 0 else None
+        tiles.append({"index": ti, "shape_tx_ty_k_threads": desc})
 
     cells = [nt * np_ for nt, np_, reals in w.classes for _ in reals]
     updates = sum(n * ((b["stages"] - a["stages"]) + (b["adv_stages"] - a["adv_stages"]) +
@@ -295,7 +300,7 @@ def main():
                    "realizations": R,
                    "step": "1 h interval: advection + RKG2 diffusion" +
                            (" + mu^4 assimilation" if assim else "") + " + diagnostics",
-                   "simulated_hours": K, "graphs": bool(graphs)},
+                   "simulated_hours": K, "graphs": bool(graphs), "sts_tiles": tiles},
         "sim_days_per_s": K / 24.0 / wall,
     }
     if fams:

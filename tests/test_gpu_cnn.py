@@ -221,3 +221,55 @@ def test_surrogate_fallback_is_plain_bitwise_and_accept_path():
     assert np.array_equal(ens2.get_states(g), pred)
     assert np.allclose(err2, [rel_l2(pred[r], ref[r]) for r in range(2)], rtol=1e-10)
     assert ens2.diagnostics(1)["surr_accept"] == 1
+
+
+def test_trained_surrogate_gain():
+    """The shipped trained network on held-out realizations of its training
+    distribution (512 x 1024, no assimilation): its one-hour prediction is
+    checked against the plain solver every interval.  It must beat the
+    method without it (the identity map, i.e. no transport) by a clear
+    factor, every accepted interval must be within the tolerance, and every
+    rejected one must leave the plain solver's field."""
+    import os
+    import paper_2501_06377_amd as sft
+    from paper_2501_06377_amd import surrogate as S
+    nt, np_ = 512, 1024
+    path = S.weights_path(nt, np_)
+    assert os.path.exists(path), "trained weights are shipped with the package"
+    params = np.load(path).astype(np.float32)
+    n, hours, tol = 4, 3, 1e-3
+    reals, feats = S.sample_realizations(n, 7)
+    f0 = S.initial_fields(nt, np_, n, 7)
+    say(f"case trained surrogate gain: {n} held-out realizations x {hours} h")
+    net = sft.Net(nt, np_, n)
+    net.set_params(params)
+    ens = sft.Ensemble()
+    g = ens.add_grid(nt, np_, reals)
+    ens.set_states(g, f0)
+    plain = sft.Ensemble()
+    gp = plain.add_grid(nt, np_, reals)
+    plain.set_states(gp, f0)
+    prev = f0
+    errs, ident = [], []
+    for h in range(1, hours + 1):
+        # both start the interval from the same state
+        plain.set_states(gp, prev)
+        plain.set_time(h - 1.0)
+        plain.advance(float(h))
+        ref = plain.get_states(gp)
+        e = sft.surrogate_advance(ens, g, net, feats, float(h), tol)
+        got = ens.get_states(g)
+        for r in range(n):
+            if e[r] <= tol:
+                assert rel_l2(got[r], ref[r]) <= tol
+            else:
+                assert np.array_equal(got[r], ref[r])
+            ident.append(rel_l2(prev[r], ref[r]))
+        errs += e.tolist()
+        prev = got
+    errs, ident = np.array(errs), np.array(ident)
+    acc = float(np.mean(errs <= tol))
+    gain = float(np.median(ident) / np.median(errs))
+    say(f"  surrogate rel-L2 median {np.median(errs):.3e} (max {errs.max():.3e}), identity median "
+        f"{np.median(ident):.3e}, gain {gain:.1f}x, accepted {acc:.0%} at {tol}")
+    assert gain > 5.0 and acc >= 0.5
