@@ -103,10 +103,8 @@ __global__ void cnn_features_kernel(const TB* __restrict__ Bin, const float* __r
 // MODE 3 (data gradient, pole rows): G of rows -1, 0 (blockIdx.y = 0) and
 //                         H-1, H (blockIdx.y = 1) as FP32 to the edge buffer
 //                         [b][4][W][64], for edge_fold_kernel.
-// MODE 2 (output layer):  y[b][j][k] = bias[0] + sum_tap sum_ci w[tap][0][ci] x[...][ci],
-//                         FP32 (the weight rows 1..31 of the N tile are zero).
 // Weight layout: w[tap][n][k] with the GEMM's K index (input channel) contiguous;
-// NTN = number of 32-wide output tiles (2 for 64 outputs, 1 for the output layer).
+// NTN = number of 32-wide output tiles.
 constexpr int CTY = 8, CTX = 32;      // output tile: 8 rows x 32 columns, 2 waves
 
 template <int CIN, int MODE, int NTN>
@@ -124,7 +122,7 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
     // the input tile; MODE 0/1 reuse it for the bf16 output tile (channel
     // stride CTS), written back as 16-byte vectors
     constexpr int CTS = 64 + 8;
-    constexpr int TILE_E = TR * TC * CP, OUT_E = MODE >= 2 ? 0 : CTY * CTX * CTS;
+    constexpr int TILE_E = TR * TC * CP, OUT_E = MODE == 3 ? 0 : CTY * CTX * CTS;
     constexpr bool DGRAD = MODE == 1 || MODE == 3;
     __shared__ __attribute__((aligned(16))) uint16_t tile[TILE_E > OUT_E ? TILE_E : OUT_E];
 
@@ -185,19 +183,6 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
     }
 
     // epilogue: C row = pixel column within the tile row, C column = channel
-    if (MODE == 2) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int row = r0 + wv * 4 + m;
-            if (row >= H || col != 0) continue;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int k = k0 + 8 * (r >> 2) + 4 * kh + (r & 3);
-                if (k < W) ((float*)out)[(size_t)b * plane + (size_t)row * W + k] = acc[m][0][r] + bias[0];
-            }
-        }
-        return;
-    }
     if (MODE == 3) {
         // rows r0, r0 + 1 (wave 0, m = 0, 1) -> edge rows 0, 1 or 2, 3
         if (wv != 0) return;
@@ -251,6 +236,52 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
         }
         *(uint4*)((uint16_t*)out + o) = val;
     }
+}
+
+// Output layer (one channel) on the vector units:
+//   y[b][j][k] = bias + sum_tap sum_ci w[tap][ci] x[pad(j + dy - 1, k + dx - 1)][ci]
+// with the bf16 weights of the packed layout (row 0 of wf[tap][32][64]) and
+// FP32 accumulation.  A block stages OTY rows x OTX columns plus a one-cell
+// spherical halo of the 64-channel input in LDS (pixel stride 72 bf16, so the
+// 16-byte reads of consecutive pixels fall in different banks); one thread
+// per output pixel; the weights are uniform (scalar loads).
+constexpr int OTY = 4, OTX = 64;
+
+__global__ __launch_bounds__(OTY * OTX) void conv_out_kernel(const uint16_t* __restrict__ x,
+                                                             const uint16_t* __restrict__ wf,
+                                                             const float* __restrict__ bias,
+                                                             float* __restrict__ y, int H, int W)
+{
+    constexpr int CP = 72, TR = OTY + 2, TC = OTX + 2, NT = OTY * OTX;
+    __shared__ __attribute__((aligned(16))) uint16_t tile[TR * TC * CP];
+    const int b = blockIdx.z, k0 = blockIdx.x * OTX, r0 = blockIdx.y * OTY;
+    const int tid = threadIdx.x;
+    for (int v = tid; v < TR * TC * 8; v += NT) {
+        const int pix = v >> 3, cv = v & 7;
+        const int tr = pix / TC, tc = pix - (pix / TC) * TC;
+        int sj, sk;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if (sphere_src(r0 - 1 + tr, k0 - 1 + tc, H, W, sj, sk))
+            val = *(const uint4*)(x + (((size_t)b * H + sj) * W + sk) * 64 + cv * 8);
+        *(uint4*)(tile + pix * CP + cv * 8) = val;
+    }
+    __syncthreads();
+    const int ty = tid / OTX, tx = tid - (tid / OTX) * OTX;
+    float acc = bias[0];
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3, dx = tap - (tap / 3) * 3;
+        const uint16_t* src = tile + ((ty + dy) * TC + tx + dx) * CP;
+        const uint16_t* wt = wf + (size_t)tap * 32 * 64;
+#pragma unroll
+        for (int cv = 0; cv < 8; ++cv) {
+            const uint4 v = *(const uint4*)(src + cv * 8);
+            const uint16_t* h = (const uint16_t*)&v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc += bf2f(h[e]) * bf2f(wt[cv * 8 + e]);
+        }
+    }
+    const int j = r0 + ty, k = k0 + tx;
+    if (j < H && k < W) y[((size_t)b * H + j) * W + k] = acc;
 }
 
 // Pole rows of the input gradient: edge rows (-1, 0, H-1, H) -> rows 0 and
@@ -691,9 +722,8 @@ void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf
 void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
                   int batch, int H, int W)
 {
-    dim3 g((W + CTX - 1) / CTX, (H + CTY - 1) / CTY, batch);
-    hipLaunchKernelGGL((conv_mfma_kernel<64, 2, 1>), g, dim3(128), 0, st, x4, wf5, b5, (void*)y, H, W,
-                       (const uint16_t*)nullptr, (float*)nullptr);
+    dim3 g((W + OTX - 1) / OTX, (H + OTY - 1) / OTY, batch);
+    hipLaunchKernelGGL(conv_out_kernel, g, dim3(OTY * OTX), 0, st, x4, wf5, b5, y, H, W);
 }
 
 // Gradient of a layer's input, masked by that input's ReLU, as bf16:

@@ -153,8 +153,6 @@ __global__ __launch_bounds__(NT) void diff_fused_kernel(
 // north and south from the lane's own registers; only the two end rows of
 // each strip are exchanged through LDS (double-buffered by stage parity, one
 // barrier per stage).  Row coefficients are wave-uniform (scalar loads).
-// Ring cells (lane 0 and 63, the first and last staged row) are never
-// updated, exactly as in the tiled variant, so both give identical results.
 __device__ __forceinline__ double lane_west(double v)
 {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
@@ -199,11 +197,12 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     const int jw = jt0 - K + w * RPT;   // global row of the strip's first cell
     int kc = (k0 - K + lane) % np;
     if (kc < 0) kc += np;
-    const bool colact = lane >= 1 && lane <= LX - 2;
     const bool has_in2 = in2 != nullptr;
     const DiffRow<T>* dr = drow + (size_t)e.r * nt;
 
-    T ycur[RPT], ym2[RPT], lyr[RPT];
+    // ya / yb alternate as (current, previous); rows beyond the poles stay
+    // zero (they only meet the pole rows' zero coefficient)
+    T ya[RPT], yb[RPT], lyr[RPT];
     double y0r[MIXED ? 1 : RPT];
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
@@ -217,42 +216,45 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
             l = ly0[i];
             if constexpr (!MIXED) z = y0[i];
         }
-        ycur[m] = a;
-        ym2[m] = b;
+        ya[m] = a;
+        yb[m] = b;
         lyr[m] = l;
         if constexpr (!MIXED) y0r[m] = z;
     }
 
-    for (int i = 0; i < kk; ++i) {
+    // One stage: cur holds the stage input, prv the stage before it and
+    // receives the result.  Every staged cell in range is updated, the outer
+    // ring included (its neighbours outside the region read as zero): the
+    // error this starts moves inwards one cell per stage, and the output
+    // region lies K cells inside the ring, as in the tiled variant.
+    auto stage = [&](int i, T (&cur)[RPT], T (&prv)[RPT]) {
         const StageCoef c = coefs[e.coef_off + j0 + i];
         const bool h2 = has_in2 || i > 0;
         const int q = i & 1;
-        xch[q][0][w][lane] = ycur[0];
-        xch[q][1][w][lane] = ycur[RPT - 1];
+        xch[q][0][w][lane] = cur[0];
+        xch[q][1][w][lane] = cur[RPT - 1];
         __syncthreads();
         const T north = w > 0 ? xch[q][1][w - 1][lane] : T(0);
         const T south = w < NW - 1 ? xch[q][0][w + 1][lane] : T(0);
-        T prev = north;   // this stage's input value of the row above
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const int j = jw + m, ly = w * RPT + m;
-            const T cur = ycur[m];
-            const T sv = m < RPT - 1 ? ycur[m + 1] : south;
-            const T wv = lane_west(cur), ev = lane_east(cur);
-            if (ly >= 1 && ly <= LY - 2 && j >= 0 && j < nt) {
-                const DiffRow<T> d = dr[j];
-                const T L = L5<T>(d, wv, prev, cur, sv, ev);
-                T v;
-                if constexpr (MIXED) v = sts_mixed(c, cur, ym2[m], h2, L, lyr[m]);
-                else v = sts_f64(c, cur, ym2[m], y0r[m], L, lyr[m]);
-                if (colact) {
-                    ym2[m] = cur;
-                    ycur[m] = v;
-                }
+            const int j = jw + m;
+            const T wv = lane_west(cur[m]), ev = lane_east(cur[m]);
+            if (j >= 0 && j < nt) {
+                const T L = L5<T>(dr[j], wv, m > 0 ? cur[m - 1] : north, cur[m],
+                                  m < RPT - 1 ? cur[m + 1] : south, ev);
+                if constexpr (MIXED) prv[m] = sts_mixed(c, cur[m], prv[m], h2, L, lyr[m]);
+                else prv[m] = sts_f64(c, cur[m], prv[m], y0r[m], L, lyr[m]);
             }
-            prev = cur;
         }
+    };
+    int i = 0;
+    for (; i + 1 < kk; i += 2) {
+        stage(i, ya, yb);
+        stage(i + 1, yb, ya);
     }
+    const bool odd = i < kk;
+    if (odd) stage(i, ya, yb);
 
     const int k = k0 + lane - K;
     if (lane < K || lane >= K + TX || k >= np) return;
@@ -260,18 +262,19 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     for (int m = 0; m < RPT; ++m) {
         const int ly = w * RPT + m, j = jw + m;
         if (ly < K || ly >= K + TY || j >= nt) continue;
+        const T last = odd ? yb[m] : ya[m], before = odd ? ya[m] : yb[m];
         const size_t gi = base + (size_t)j * np + k;
         if (fin) {
             if constexpr (MIXED) {
                 double yv = B[gi];
                 if (e.pad) yv += (double)adv[gi];
-                B[gi] = yv + (double)ycur[m];
+                B[gi] = yv + (double)last;
             } else {
-                B[gi] = ycur[m];
+                B[gi] = last;
             }
         } else {
-            out1[gi] = ycur[m];
-            out2[gi] = ym2[m];
+            out1[gi] = last;
+            out2[gi] = before;
         }
     }
 }
