@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", action="store_true", help="replay captured graphs (no per-kernel timing)")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--sts-tile", type=int, default=-1, help="blocked STS shape (-1: autotuned)")
     ap.add_argument("--surr-batch", type=int, default=64)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
@@ -236,7 +237,7 @@ def main():
     graphs = args.graphs or args.workload == "batching"
     assim = w.assim_every_h > 0
     dev = torch.device("cuda:0")
-    ens = sft.Ensemble(precision=prec, use_graphs=1 if graphs else 0)
+    ens = sft.Ensemble(precision=prec, use_graphs=1 if graphs else 0, sts_tile=args.sts_tile)
     gids, inits, obs_d, f0s, obs0 = [], [], [], [], None
     for ci, (nt, np_, reals) in enumerate(w.classes):
         f0 = synth.bipolar_field(nt, np_, synth.bipolar_pairs(w.n_pairs, ci))
