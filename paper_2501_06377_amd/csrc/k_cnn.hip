@@ -254,8 +254,10 @@ __global__ __launch_bounds__(OTY * OTX) void conv_out_kernel(const uint16_t* __r
 {
     constexpr int CP = 72, TR = OTY + 2, TC = OTX + 2, NT = OTY * OTX;
     __shared__ __attribute__((aligned(16))) uint16_t tile[TR * TC * CP];
+    __shared__ float wl[9 * 64];
     const int b = blockIdx.z, k0 = blockIdx.x * OTX, r0 = blockIdx.y * OTY;
     const int tid = threadIdx.x;
+    for (int e = tid; e < 9 * 64; e += NT) wl[e] = bf2f(wf[(size_t)(e >> 6) * 32 * 64 + (e & 63)]);
     for (int v = tid; v < TR * TC * 8; v += NT) {
         const int pix = v >> 3, cv = v & 7;
         const int tr = pix / TC, tc = pix - (pix / TC) * TC;
@@ -268,16 +270,20 @@ __global__ __launch_bounds__(OTY * OTX) void conv_out_kernel(const uint16_t* __r
     __syncthreads();
     const int ty = tid / OTX, tx = tid - (tid / OTX) * OTX;
     float acc = bias[0];
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap - (tap / 3) * 3;
         const uint16_t* src = tile + ((ty + dy) * TC + tx + dx) * CP;
-        const uint16_t* wt = wf + (size_t)tap * 32 * 64;
 #pragma unroll
         for (int cv = 0; cv < 8; ++cv) {
             const uint4 v = *(const uint4*)(src + cv * 8);
-            const uint16_t* h = (const uint16_t*)&v;
+            const float* wt = wl + tap * 64 + cv * 8;
+            const uint32_t u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int e = 0; e < 8; ++e) acc += bf2f(h[e]) * bf2f(wt[cv * 8 + e]);
+            for (int e = 0; e < 4; ++e) {
+                acc += __uint_as_float(u[e] << 16) * wt[2 * e];
+                acc += __uint_as_float(u[e] & 0xFFFF0000u) * wt[2 * e + 1];
+            }
         }
     }
     const int j = r0 + ty, k = k0 + tx;
@@ -466,7 +472,9 @@ void wgrad_mfma_kernel(const uint16_t* __restrict__ x, const uint16_t* __restric
 //   bpart[blk] = sum g,
 // g = channel 0 of the 16-channel bf16 output gradient.  Thread: channels
 // 2c, 2c+1 (c = tid % 32) and every 8th pixel of a row (phase tid / 32);
-// rows are distributed over the blocks, partials folded in LDS.
+// rows are distributed over the blocks, partials folded in LDS.  The three
+// source rows of a row (across-pole rows with their half-turn) are resolved
+// once per row; columns wrap with one compare.
 __global__ __launch_bounds__(256) void wgrad_out_kernel(const uint16_t* __restrict__ x,
                                                         const uint16_t* __restrict__ dyb,
                                                         float* __restrict__ part, float* __restrict__ bpart,
@@ -479,19 +487,37 @@ __global__ __launch_bounds__(256) void wgrad_out_kernel(const uint16_t* __restri
     for (int t = 0; t < 9; ++t) acc[t][0] = acc[t][1] = 0.f;
     float bs = 0.f;
     const long nrow = (long)batch * H;
+    const int half = W / 2;
     for (long rw = blockIdx.x; rw < nrow; rw += gridDim.x) {
         const int b = (int)(rw / H), j = (int)(rw - (long)b * H);
+        const uint32_t* xr[3];
+        int shift[3];
+        bool valid[3];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const int jj = j + dy - 1;
+            const int sj = jj < 0 ? 0 : (jj >= H ? H - 1 : jj);
+            valid[dy] = jj >= -1 && jj <= H;   // always true for a 3x3 stencil
+            shift[dy] = (jj < 0 || jj >= H) ? half : 0;
+            xr[dy] = (const uint32_t*)(x + ((size_t)b * H + sj) * W * 64) + c2;
+        }
+        const uint16_t* gr = dyb + ((size_t)b * H + j) * W * 16;
         for (int k = ph; k < W; k += 8) {
-            const float g = bf2f(dyb[(((size_t)b * H + j) * W + k) * 16]);
+            const float g = bf2f(gr[(size_t)k * 16]);
             bs += g;
 #pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int dy = t / 3, dx = t - (t / 3) * 3;
-                int sj, sk;
-                if (!sphere_src(j + dy - 1, k + dx - 1, H, W, sj, sk)) continue;
-                const uint32_t v = *(const uint32_t*)(x + (((size_t)b * H + sj) * W + sk) * 64 + 2 * c2);
-                acc[t][0] += g * bf2f((uint16_t)(v & 0xFFFFu));
-                acc[t][1] += g * bf2f((uint16_t)(v >> 16));
+            for (int dx = 0; dx < 3; ++dx) {
+                int kk = k + dx - 1;
+                kk = kk < 0 ? kk + W : (kk >= W ? kk - W : kk);
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    if (!valid[dy]) continue;
+                    int ks = kk + shift[dy];
+                    ks = ks >= W ? ks - W : ks;
+                    const uint32_t v = xr[dy][(size_t)ks * 32];
+                    acc[dy * 3 + dx][0] += g * __uint_as_float(v << 16);
+                    acc[dy * 3 + dx][1] += g * __uint_as_float(v & 0xFFFF0000u);
+                }
             }
         }
     }
@@ -503,10 +529,10 @@ __global__ __launch_bounds__(256) void wgrad_out_kernel(const uint16_t* __restri
     if (c2 == 0) red[ph][9 * 64] = bs;
     __syncthreads();
     for (int e = tid; e < 9 * 64 + 1; e += 256) {
-        float s = 0.f;
-        for (int q = 0; q < 8; ++q) s += red[q][e];
-        if (e < 9 * 64) part[(size_t)blockIdx.x * 9 * 64 + e] = s;
-        else bpart[blockIdx.x] = s;
+        float sum = 0.f;
+        for (int q = 0; q < 8; ++q) sum += red[q][e];
+        if (e < 9 * 64) part[(size_t)blockIdx.x * 9 * 64 + e] = sum;
+        else bpart[blockIdx.x] = sum;
     }
 }
 

@@ -1,10 +1,11 @@
 """GPU (HIP library through its C ABI) vs FP64 CPU oracle, element by element.
 
-FP64 path: the kernels evaluate the paper's formulas in the oracle's order
-without FMA contraction, so fields agree to the last bit except where a
-reduction order differs (flux-balance sums, device cosine of the observer
-geometry); the bar is rel-L2 <= 1e-12 (stated in the tests), and the
-measured error is printed.  FP32 mixed path: rel-L2 <= 1e-5.
+FP64 path: the kernels evaluate the paper's formulas in the oracle's order;
+the diffusion stages use fused multiply-adds where the oracle rounds each
+product, and reduction orders differ (flux-balance sums, device cosine of
+the observer geometry), so fields agree to rounding level.  The bar is
+rel-L2 <= 1e-12 (stated in the tests), and the measured error is printed.
+FP32 mixed path: rel-L2 <= 1e-5.
 """
 import math
 
@@ -75,7 +76,8 @@ def test_config1_plain_f64():
     od = oracle.diagnostics(ref[0])
     for k in ("phi_pos", "phi_neg", "h1", "h2", "dax"):
         assert d[k] == pytest.approx(od[k], rel=1e-11, abs=1e-9 * abs(od["phi_pos"])), k
-    assert d["bmin"] == od["bmin"] and d["bmax"] == od["bmax"]
+    assert d["bmin"] == pytest.approx(od["bmin"], rel=TOL64)
+    assert d["bmax"] == pytest.approx(od["bmax"], rel=TOL64)
 
 
 @pytest.mark.parametrize("kind", [0, 1, 2])
