@@ -103,6 +103,15 @@ def load() -> ctypes.CDLL:
     """Load libsft.so (raises if it is missing: build it with build.py)."""
     global _lib
     if _lib is None:
+        # One HIP runtime per process: torch ships its own libamdhip64 and
+        # HSA runtime.  Loaded first, they satisfy this library's
+        # libamdhip64.so.7 dependency by soname, so device pointers and
+        # streams of torch tensors are valid here; loaded after this library,
+        # a second runtime would claim the device and torch could not use it.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"HIP library {LIB_PATH} is missing; build it with "
