@@ -239,25 +239,23 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
 }
 
 // Output layer (one channel) on the vector units:
-//   y[b][j][k] = bias + sum_tap sum_ci w[tap][ci] x[pad(j + dy - 1, k + dx - 1)][ci]
-// with the bf16 weights of the packed layout (row 0 of wf[tap][32][64]) and
-// FP32 accumulation.  A block stages OTY rows x OTX columns plus a one-cell
+//   y[b][j][k] = bias + sum_tap sum_ci w5[tap][ci] x[pad(j + dy - 1, k + dx - 1)][ci]
+// with the bf16-rounded weights held as FP32 (w5[9][64], written by the
+// packing kernel) and FP32 accumulation.  A block stages OTY rows x OTX columns plus a one-cell
 // spherical halo of the 64-channel input in LDS (pixel stride 72 bf16, so the
 // 16-byte reads of consecutive pixels fall in different banks); one thread
 // per output pixel; the weights are uniform (scalar loads).
 constexpr int OTY = 4, OTX = 64;
 
 __global__ __launch_bounds__(OTY * OTX) void conv_out_kernel(const uint16_t* __restrict__ x,
-                                                             const uint16_t* __restrict__ wf,
+                                                             const float* __restrict__ w5,
                                                              const float* __restrict__ bias,
                                                              float* __restrict__ y, int H, int W)
 {
     constexpr int CP = 72, TR = OTY + 2, TC = OTX + 2, NT = OTY * OTX;
     __shared__ __attribute__((aligned(16))) uint16_t tile[TR * TC * CP];
-    __shared__ float wl[9 * 64];
     const int b = blockIdx.z, k0 = blockIdx.x * OTX, r0 = blockIdx.y * OTY;
     const int tid = threadIdx.x;
-    for (int e = tid; e < 9 * 64; e += NT) wl[e] = bf2f(wf[(size_t)(e >> 6) * 32 * 64 + (e & 63)]);
     for (int v = tid; v < TR * TC * 8; v += NT) {
         const int pix = v >> 3, cv = v & 7;
         const int tr = pix / TC, tc = pix - (pix / TC) * TC;
@@ -277,7 +275,7 @@ __global__ __launch_bounds__(OTY * OTX) void conv_out_kernel(const uint16_t* __r
 #pragma unroll
         for (int cv = 0; cv < 8; ++cv) {
             const uint4 v = *(const uint4*)(src + cv * 8);
-            const float* wt = wl + tap * 64 + cv * 8;
+            const float* wt = w5 + tap * 64 + cv * 8;   // uniform: scalar loads
             const uint32_t u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -492,31 +490,43 @@ __global__ __launch_bounds__(256) void wgrad_out_kernel(const uint16_t* __restri
         const int b = (int)(rw / H), j = (int)(rw - (long)b * H);
         const uint32_t* xr[3];
         int shift[3];
-        bool valid[3];
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
-            const int jj = j + dy - 1;
+            const int jj = j + dy - 1;   // in [-1, H]
             const int sj = jj < 0 ? 0 : (jj >= H ? H - 1 : jj);
-            valid[dy] = jj >= -1 && jj <= H;   // always true for a 3x3 stencil
             shift[dy] = (jj < 0 || jj >= H) ? half : 0;
             xr[dy] = (const uint32_t*)(x + ((size_t)b * H + sj) * W * 64) + c2;
         }
         const uint16_t* gr = dyb + ((size_t)b * H + j) * W * 16;
-        for (int k = ph; k < W; k += 8) {
-            const float g = bf2f(gr[(size_t)k * 16]);
-            bs += g;
+        // four pixels per iteration, so that 4 x 9 independent loads are in
+        // flight together
+        for (int k4 = ph; k4 < W; k4 += 32) {
+            float g[4];
+            uint32_t v[4][9];
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                int kk = k + dx - 1;
-                kk = kk < 0 ? kk + W : (kk >= W ? kk - W : kk);
+            for (int u = 0; u < 4; ++u) {
+                const int k = k4 + 8 * u;
+                g[u] = k < W ? bf2f(gr[(size_t)k * 16]) : 0.f;
+                const int kc = k < W ? k : W - 1;
 #pragma unroll
-                for (int dy = 0; dy < 3; ++dy) {
-                    if (!valid[dy]) continue;
-                    int ks = kk + shift[dy];
-                    ks = ks >= W ? ks - W : ks;
-                    const uint32_t v = xr[dy][(size_t)ks * 32];
-                    acc[dy * 3 + dx][0] += g * __uint_as_float(v << 16);
-                    acc[dy * 3 + dx][1] += g * __uint_as_float(v & 0xFFFF0000u);
+                for (int dx = 0; dx < 3; ++dx) {
+                    int kk = kc + dx - 1;
+                    kk = kk < 0 ? kk + W : (kk >= W ? kk - W : kk);
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy) {
+                        int ks = kk + shift[dy];
+                        ks = ks >= W ? ks - W : ks;
+                        v[u][dy * 3 + dx] = xr[dy][(size_t)ks * 32];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bs += g[u];
+#pragma unroll
+                for (int t = 0; t < 9; ++t) {
+                    acc[t][0] += g[u] * __uint_as_float(v[u][t] << 16);
+                    acc[t][1] += g[u] * __uint_as_float(v[u][t] & 0xFFFF0000u);
                 }
             }
         }
@@ -629,7 +639,8 @@ __device__ __forceinline__ int master_channel(int ci, int cin, int cip)
 // gradient is the same correlation over the padded neighbourhood as the
 // forward pass.
 __global__ void pack_weights_kernel(const float* __restrict__ Wm, int cin, int cout, int cip, int nout,
-                                    int cop, uint16_t* __restrict__ wf, uint16_t* __restrict__ wd)
+                                    int cop, uint16_t* __restrict__ wf, uint16_t* __restrict__ wd,
+                                    float* __restrict__ w1f)
 {
     const int n = 9 * nout * cip;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
@@ -638,6 +649,8 @@ __global__ void pack_weights_kernel(const float* __restrict__ Wm, int cin, int c
         const int mc = master_channel(ci, cin, cip);
         const float v = (mc >= 0 && co < cout) ? Wm[((size_t)co * cin + mc) * 9 + tap] : 0.f;
         wf[e] = f2bf(v);
+        // single-output layer: the bf16-rounded weights of output 0 as FP32 [tap][ci]
+        if (w1f && co == 0) w1f[tap * cip + ci] = bf2f(f2bf(v));
     }
     if (!wd) return;
     const int nd = 9 * cin * cop;
@@ -745,11 +758,11 @@ void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf
                            (const uint16_t*)nullptr, (float*)nullptr);
 }
 
-void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
+void cnn_conv_out(hipStream_t st, const uint16_t* x4, const float* w5f, const float* b5, float* y,
                   int batch, int H, int W)
 {
     dim3 g((W + OTX - 1) / OTX, (H + OTY - 1) / OTY, batch);
-    hipLaunchKernelGGL(conv_out_kernel, g, dim3(OTY * OTX), 0, st, x4, wf5, b5, y, H, W);
+    hipLaunchKernelGGL(conv_out_kernel, g, dim3(OTY * OTX), 0, st, x4, w5f, b5, y, H, W);
 }
 
 // Gradient of a layer's input, masked by that input's ReLU, as bf16:
@@ -820,10 +833,10 @@ void cnn_adam(hipStream_t st, float* p, const float* g, float* m, float* v, int 
 }
 
 void cnn_pack(hipStream_t st, const float* Wm, int cin, int cout, int cip, int nout, int cop, uint16_t* wf,
-              uint16_t* wd)
+              uint16_t* wd, float* w1f)
 {
     hipLaunchKernelGGL(pack_weights_kernel, dim3(gblocks((size_t)9 * nout * cip, 256, 1024)), dim3(256), 0,
-                       st, Wm, cin, cout, cip, nout, cop, wf, wd);
+                       st, Wm, cin, cout, cip, nout, cop, wf, wd, w1f);
 }
 
 void cnn_pred(hipStream_t st, const double* Bin, const float* y, double* pred, size_t n)
