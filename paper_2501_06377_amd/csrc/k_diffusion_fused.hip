@@ -146,13 +146,14 @@ __global__ __launch_bounds__(NT) void diff_fused_kernel(
 }
 
 // ------------------------------------------------------------ strip variant
-// The same K-stage blocking with a different owner map: lane = column of a
-// 64-column staged region (TX = 64 - 2K output columns), wave w = a strip of
-// RPT consecutive rows (TY = NW * RPT - 2K output rows).  A cell's west and
-// east neighbours come from the adjacent lanes through whole-wave DPP shifts,
-// north and south from the lane's own registers; only the two end rows of
-// each strip are exchanged through LDS (double-buffered by stage parity, one
-// barrier per stage).  Row coefficients are wave-uniform (scalar loads).
+// The same K-stage blocking with a different owner map: lane = CPL adjacent
+// columns of a 64 * CPL-column staged region (TX = 64 CPL - 2K output
+// columns), wave w = a strip of RPT consecutive rows (TY = NW * RPT - 2K
+// output rows).  A lane's outer west and east neighbours come from the
+// adjacent lanes through whole-wave DPP shifts, the others and north / south
+// from the lane's own registers; only the two end rows of each strip are
+// exchanged through LDS (double-buffered by stage parity, one barrier per
+// stage).  Row coefficients are wave-uniform (scalar loads).
 __device__ __forceinline__ double lane_west(double v)
 {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
@@ -174,7 +175,7 @@ __device__ __forceinline__ float lane_east(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
 }
 
-template <bool MIXED, int K, int RPT, int NW>
+template <bool MIXED, int K, int RPT, int NW, int CPL>
 __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs, int j0,
     const DiffRow<typename FT<MIXED>::T>* __restrict__ drow,
@@ -184,8 +185,8 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     double* __restrict__ B, const float* __restrict__ adv, int nt, int np)
 {
     using T = typename FT<MIXED>::T;
-    constexpr int LX = 64, TX = LX - 2 * K, LY = NW * RPT, TY = LY - 2 * K;
-    __shared__ T xch[2][2][NW][64];   // [stage parity][top, bottom row][wave][lane]
+    constexpr int LX = 64 * CPL, TX = LX - 2 * K, LY = NW * RPT, TY = LY - 2 * K;
+    __shared__ T xch[2][2][NW][LX];   // [stage parity][top, bottom row][wave][column]
 
     const Entry e = ents[blockIdx.z];
     const int kk = min(K, e.s - j0 + 1);
@@ -195,31 +196,38 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int k0 = blockIdx.x * TX, jt0 = blockIdx.y * TY;
     const int jw = jt0 - K + w * RPT;   // global row of the strip's first cell
-    int kc = (k0 - K + lane) % np;
-    if (kc < 0) kc += np;
+    int kc[CPL];                        // global columns of the lane's cells
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        int k = (k0 - K + lane * CPL + c) % np;
+        kc[c] = k < 0 ? k + np : k;
+    }
     const bool has_in2 = in2 != nullptr;
     const DiffRow<T>* dr = drow + (size_t)e.r * nt;
 
     // ya / yb alternate as (current, previous); rows beyond the poles stay
     // zero (they only meet the pole rows' zero coefficient)
-    T ya[RPT], yb[RPT], lyr[RPT];
-    double y0r[MIXED ? 1 : RPT];
+    T ya[RPT][CPL], yb[RPT][CPL], lyr[RPT][CPL];
+    double y0r[MIXED ? 1 : RPT][MIXED ? 1 : CPL];
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
         const int j = jw + m;
-        T a = T(0), b = T(0), l = T(0);
-        double z = 0.0;
-        if (j >= 0 && j < nt) {
-            const size_t i = base + (size_t)j * np + kc;
-            a = in1[i];
-            if (has_in2) b = in2[i];
-            l = ly0[i];
-            if constexpr (!MIXED) z = y0[i];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            T a = T(0), b = T(0), l = T(0);
+            double z = 0.0;
+            if (j >= 0 && j < nt) {
+                const size_t i = base + (size_t)j * np + kc[c];
+                a = in1[i];
+                if (has_in2) b = in2[i];
+                l = ly0[i];
+                if constexpr (!MIXED) z = y0[i];
+            }
+            ya[m][c] = a;
+            yb[m][c] = b;
+            lyr[m][c] = l;
+            if constexpr (!MIXED) y0r[m][c] = z;
         }
-        ya[m] = a;
-        yb[m] = b;
-        lyr[m] = l;
-        if constexpr (!MIXED) y0r[m] = z;
     }
 
     // One stage: cur holds the stage input, prv the stage before it and
@@ -227,24 +235,37 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     // ring included (its neighbours outside the region read as zero): the
     // error this starts moves inwards one cell per stage, and the output
     // region lies K cells inside the ring, as in the tiled variant.
-    auto stage = [&](int i, T (&cur)[RPT], T (&prv)[RPT]) {
-        const StageCoef c = coefs[e.coef_off + j0 + i];
+    auto stage = [&](int i, T (&cur)[RPT][CPL], T (&prv)[RPT][CPL]) {
+        const StageCoef cf = coefs[e.coef_off + j0 + i];
         const bool h2 = has_in2 || i > 0;
         const int q = i & 1;
-        xch[q][0][w][lane] = cur[0];
-        xch[q][1][w][lane] = cur[RPT - 1];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            xch[q][0][w][lane * CPL + c] = cur[0][c];
+            xch[q][1][w][lane * CPL + c] = cur[RPT - 1][c];
+        }
         __syncthreads();
-        const T north = w > 0 ? xch[q][1][w - 1][lane] : T(0);
-        const T south = w < NW - 1 ? xch[q][0][w + 1][lane] : T(0);
+        T north[CPL], south[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            north[c] = w > 0 ? xch[q][1][w - 1][lane * CPL + c] : T(0);
+            south[c] = w < NW - 1 ? xch[q][0][w + 1][lane * CPL + c] : T(0);
+        }
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             const int j = jw + m;
-            const T wv = lane_west(cur[m]), ev = lane_east(cur[m]);
+            const T wl = lane_west(cur[m][CPL - 1]), el = lane_east(cur[m][0]);
             if (j >= 0 && j < nt) {
-                const T L = L5<T>(dr[j], wv, m > 0 ? cur[m - 1] : north, cur[m],
-                                  m < RPT - 1 ? cur[m + 1] : south, ev);
-                if constexpr (MIXED) prv[m] = sts_mixed(c, cur[m], prv[m], h2, L, lyr[m]);
-                else prv[m] = sts_f64(c, cur[m], prv[m], y0r[m], L, lyr[m]);
+                const DiffRow<T> d = dr[j];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const T wv = c > 0 ? cur[m][c - 1] : wl;
+                    const T ev = c < CPL - 1 ? cur[m][c + 1] : el;
+                    const T L = L5<T>(d, wv, m > 0 ? cur[m - 1][c] : north[c], cur[m][c],
+                                      m < RPT - 1 ? cur[m + 1][c] : south[c], ev);
+                    if constexpr (MIXED) prv[m][c] = sts_mixed(cf, cur[m][c], prv[m][c], h2, L, lyr[m][c]);
+                    else prv[m][c] = sts_f64(cf, cur[m][c], prv[m][c], y0r[m][c], L, lyr[m][c]);
+                }
             }
         }
     };
@@ -256,25 +277,28 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     const bool odd = i < kk;
     if (odd) stage(i, ya, yb);
 
-    const int k = k0 + lane - K;
-    if (lane < K || lane >= K + TX || k >= np) return;
 #pragma unroll
-    for (int m = 0; m < RPT; ++m) {
-        const int ly = w * RPT + m, j = jw + m;
-        if (ly < K || ly >= K + TY || j >= nt) continue;
-        const T last = odd ? yb[m] : ya[m], before = odd ? ya[m] : yb[m];
-        const size_t gi = base + (size_t)j * np + k;
-        if (fin) {
-            if constexpr (MIXED) {
-                double yv = B[gi];
-                if (e.pad) yv += (double)adv[gi];
-                B[gi] = yv + (double)last;
+    for (int c = 0; c < CPL; ++c) {
+        const int lx = lane * CPL + c, k = k0 + lx - K;
+        if (lx < K || lx >= K + TX || k >= np) continue;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const int ly = w * RPT + m, j = jw + m;
+            if (ly < K || ly >= K + TY || j >= nt) continue;
+            const T last = odd ? yb[m][c] : ya[m][c], before = odd ? ya[m][c] : yb[m][c];
+            const size_t gi = base + (size_t)j * np + k;
+            if (fin) {
+                if constexpr (MIXED) {
+                    double yv = B[gi];
+                    if (e.pad) yv += (double)adv[gi];
+                    B[gi] = yv + (double)last;
+                } else {
+                    B[gi] = last;
+                }
             } else {
-                B[gi] = last;
+                out1[gi] = last;
+                out2[gi] = before;
             }
-        } else {
-            out1[gi] = last;
-            out2[gi] = before;
         }
     }
 }
@@ -284,15 +308,18 @@ struct FusedCfg {
     int tx, ty, k, nt;
 };
 
-// tiled shapes first, then the strip variant (tx = 64 - 2K, ty = waves x rows - 2K)
+// tiled shapes first, then the strip variant (tx = 64 x columns per lane - 2K,
+// ty = waves x rows per wave - 2K)
 static const FusedCfg kCfg64[] = {
     {64, 16, 4, 256}, {64, 32, 8, 256}, {128, 16, 4, 256}, {32, 32, 4, 256}, {64, 32, 6, 256},
-    {48, 48, 8, 256}, {48, 112, 8, 512}, {52, 116, 6, 512}, {48, 48, 8, 512}};
+    {48, 48, 8, 256}, {48, 112, 8, 512}, {52, 116, 6, 512}, {48, 48, 8, 512},
+    {112, 48, 8, 512}, {116, 52, 6, 512}, {112, 80, 8, 512}};
 static const FusedCfg kCfg32[] = {
     {64, 16, 4, 256}, {64, 32, 8, 256}, {128, 32, 8, 256}, {128, 16, 8, 256}, {64, 64, 8, 512},
-    {48, 48, 8, 256}, {48, 112, 8, 512}, {48, 112, 8, 256}, {52, 116, 6, 512}};
+    {48, 48, 8, 256}, {48, 112, 8, 512}, {48, 112, 8, 256}, {52, 116, 6, 512},
+    {112, 48, 8, 512}, {112, 112, 8, 512}, {112, 112, 8, 256}};
 
-int fused_config_count(bool mixed) { return mixed ? 9 : 9; }
+int fused_config_count(bool mixed) { return mixed ? 12 : 12; }
 
 int fused_config_k(bool mixed, int cfg) { return mixed ? kCfg32[cfg].k : kCfg64[cfg].k; }
 
@@ -318,16 +345,16 @@ static void launch_one(hipStream_t st, const Entry* ents, int n_act, const Stage
                        (T*)out1, (T*)out2, B, adv, nt, np);
 }
 
-template <bool MIXED, int K, int RPT, int NW>
+template <bool MIXED, int K, int RPT, int NW, int CPL>
 static void launch_strip(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs, int j0,
                          const void* drow, const void* in1, const void* in2, const double* y0,
                          const void* ly0, void* out1, void* out2, double* B, const float* adv, int nt,
                          int np)
 {
     using T = typename FT<MIXED>::T;
-    constexpr int TX = 64 - 2 * K, TY = NW * RPT - 2 * K;
+    constexpr int TX = 64 * CPL - 2 * K, TY = NW * RPT - 2 * K;
     dim3 grid((np + TX - 1) / TX, (nt + TY - 1) / TY, n_act);
-    hipLaunchKernelGGL((diff_strip_kernel<MIXED, K, RPT, NW>), grid, dim3(64 * NW), 0, st, ents, coefs, j0,
+    hipLaunchKernelGGL((diff_strip_kernel<MIXED, K, RPT, NW, CPL>), grid, dim3(64 * NW), 0, st, ents, coefs, j0,
                        (const DiffRow<T>*)drow, (const T*)in1, (const T*)in2, y0, (const T*)ly0,
                        (T*)out1, (T*)out2, B, adv, nt, np);
 }
@@ -339,8 +366,8 @@ void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, i
 {
 #define L1(M, a, b, c, d) \
     launch_one<M, a, b, c, d>(st, ents, n_act, coefs, j0, drow, in1, in2, y0, ly0, out1, out2, B, adv, nt, np)
-#define S1(M, k, r, w) \
-    launch_strip<M, k, r, w>(st, ents, n_act, coefs, j0, drow, in1, in2, y0, ly0, out1, out2, B, adv, nt, np)
+#define S1(M, k, r, w, c) \
+    launch_strip<M, k, r, w, c>(st, ents, n_act, coefs, j0, drow, in1, in2, y0, ly0, out1, out2, B, adv, nt, np)
     if (!mixed) {
         switch (cfg) {
         case 0: L1(false, 64, 16, 4, 256); break;
@@ -348,10 +375,13 @@ void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, i
         case 2: L1(false, 128, 16, 4, 256); break;
         case 3: L1(false, 32, 32, 4, 256); break;
         case 4: L1(false, 64, 32, 6, 256); break;
-        case 5: S1(false, 8, 16, 4); break;
-        case 6: S1(false, 8, 16, 8); break;
-        case 7: S1(false, 6, 16, 8); break;
-        default: S1(false, 8, 8, 8); break;
+        case 5: S1(false, 8, 16, 4, 1); break;
+        case 6: S1(false, 8, 16, 8, 1); break;
+        case 7: S1(false, 6, 16, 8, 1); break;
+        case 8: S1(false, 8, 8, 8, 1); break;
+        case 9: S1(false, 8, 8, 8, 2); break;
+        case 10: S1(false, 6, 8, 8, 2); break;
+        default: S1(false, 8, 12, 8, 2); break;
         }
     } else {
         switch (cfg) {
@@ -360,10 +390,13 @@ void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, i
         case 2: L1(true, 128, 32, 8, 256); break;
         case 3: L1(true, 128, 16, 8, 256); break;
         case 4: L1(true, 64, 64, 8, 512); break;
-        case 5: S1(true, 8, 16, 4); break;
-        case 6: S1(true, 8, 16, 8); break;
-        case 7: S1(true, 8, 32, 4); break;
-        default: S1(true, 6, 16, 8); break;
+        case 5: S1(true, 8, 16, 4, 1); break;
+        case 6: S1(true, 8, 16, 8, 1); break;
+        case 7: S1(true, 8, 32, 4, 1); break;
+        case 8: S1(true, 6, 16, 8, 1); break;
+        case 9: S1(true, 8, 8, 8, 2); break;
+        case 10: S1(true, 8, 16, 8, 2); break;
+        default: S1(true, 8, 32, 4, 2); break;
         }
     }
 #undef L1

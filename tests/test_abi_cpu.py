@@ -71,3 +71,21 @@ def test_struct_layouts_match_header(tmp_path):
         want.append(ctypes.sizeof(cls))
         want += [getattr(cls, f).offset for f in fs]
     assert got == want
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """Loading the library before torch must not map a second HIP runtime:
+    torch's device pointers and streams are only valid in its own runtime."""
+    import subprocess
+    import sys
+    code = (
+        "import paper_2501_06377_amd._abi as a\n"
+        "a.load()\n"
+        "import torch\n"
+        "maps = open('/proc/self/maps').read().splitlines()\n"
+        "libs = sorted({l.split()[-1] for l in maps if 'libamdhip64' in l})\n"
+        "print(len(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         cwd=__import__("os").path.dirname(__import__("os").path.dirname(__file__)))
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
