@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sft_internal.h"
 
 namespace sft {
@@ -235,6 +237,170 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
                 if (!(bf2f(ha[i]) > 0.f)) h[i] = 0;
         }
         *(uint4*)((uint16_t*)out + o) = val;
+    }
+}
+
+// ------------------------------------------- persistent MFMA convolution
+// The 64-output convolutions of the forward pass (MODE 0: bias + ReLU) and of
+// the data gradient (MODE 1: interior rows 1..H-2, ReLU mask of the layer
+// input), as implicit GEMMs on v_mfma_f32_32x32x16_bf16 with every operand in
+// LDS.  One 256-thread block per compute unit keeps all nine taps' weights
+// resident (9 x 64 x CIN bf16) and walks output tiles of PTY x PTX pixels;
+// while a tile's MFMAs run, the next tile (with its one-cell halo) is already
+// being loaded into registers, and goes to LDS once the tile's epilogue is
+// done.  Wave w computes rows PMR w .. PMR w + PMR - 1 of the tile for all
+// 64 outputs.
+// LDS rows are stored in 16-byte chunks permuted by an XOR with the row
+// (pixel) index, so the fragment reads of 8 consecutive lanes hit distinct
+// banks without padding.
+constexpr int PTY = 8, PTX = 32, PMR = PTY / 4;   // tile rows, columns; rows per wave
+
+template <int CIN>
+__device__ __forceinline__ int chunk_swz(int row, int q)
+{
+    return q ^ (row & (CIN / 8 - 1));
+}
+
+template <int CIN, int MODE>
+__global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __restrict__ x,
+                                                           const uint16_t* __restrict__ w,
+                                                           const float* __restrict__ bias,
+                                                           uint16_t* __restrict__ out, int batch, int H, int W,
+                                                           const uint16_t* __restrict__ act)
+{
+    constexpr int NQ = CIN / 8;                   // 16-byte chunks per pixel / weight row
+    constexpr int NCH = CIN / 16;                 // K chunks per tap
+    constexpr int TR = PTY + 2, TC = PTX + 2;
+    constexpr int CTS = 64 + 8;                   // channel stride of the staged output tile
+    constexpr int TILE_E = TR * TC * CIN, OUT_E = PTY * PTX * CTS;
+    constexpr int BUF_E = TILE_E > OUT_E ? TILE_E : OUT_E;
+    constexpr int WE = 9 * 64 * CIN;
+    constexpr int NV = TR * TC * NQ, VPT = (NV + 255) / 256;
+    __shared__ __attribute__((aligned(16))) uint16_t wl[WE];
+    __shared__ __attribute__((aligned(16))) uint16_t buf[BUF_E];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int col = lane & 31, kh = lane >> 5;
+
+    for (int v = tid; v < 9 * 64 * NQ; v += 256) {
+        const int row = v / NQ, q = v - (v / NQ) * NQ;   // row = tap * 64 + output channel
+        *(uint4*)(wl + (size_t)row * CIN + chunk_swz<CIN>(row, q) * 8) = *(const uint4*)(w + (size_t)v * 8);
+    }
+
+    const int out_rows = MODE == 1 ? H - 2 : H, r_base = MODE == 1 ? 1 : 0;
+    const int tiles_x = (W + PTX - 1) / PTX, tiles_y = (out_rows + PTY - 1) / PTY;
+    const long ntiles = (long)batch * tiles_y * tiles_x;
+    const size_t plane = (size_t)H * W;
+
+    uint4 pre[VPT];
+    auto load_tile = [&](long t) {
+        const int b = (int)(t / ((long)tiles_y * tiles_x));
+        const int rem = (int)(t - (long)b * tiles_y * tiles_x);
+        const int r0 = r_base + (rem / tiles_x) * PTY, k0 = (rem - (rem / tiles_x) * tiles_x) * PTX;
+        const uint16_t* xb = x + (size_t)b * plane * CIN;
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int v = tid + i * 256;
+            pre[i] = make_uint4(0, 0, 0, 0);
+            if (v < NV) {
+                const int pix = v / NQ, q = v - (v / NQ) * NQ;
+                const int tr = pix / TC, tc = pix - (pix / TC) * TC;
+                const int j = r0 - 1 + tr, k = k0 - 1 + tc;
+                if (MODE == 0) {
+                    int sj, sk;
+                    if (sphere_src(j, k, H, W, sj, sk))
+                        pre[i] = *(const uint4*)(xb + ((size_t)sj * W + sk) * CIN + q * 8);
+                } else if (j >= 0 && j < H) {
+                    pre[i] = *(const uint4*)(xb + ((size_t)j * W + wrapk(k, W)) * CIN + q * 8);
+                }
+            }
+        }
+    };
+
+    long t = blockIdx.x;
+    if (t < ntiles) load_tile(t);
+    for (; t < ntiles; t += gridDim.x) {
+        const int b = (int)(t / ((long)tiles_y * tiles_x));
+        const int rem = (int)(t - (long)b * tiles_y * tiles_x);
+        const int r0 = r_base + (rem / tiles_x) * PTY, k0 = (rem - (rem / tiles_x) * tiles_x) * PTX;
+        __syncthreads();   // the previous tile's epilogue is done with buf
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int v = tid + i * 256;
+            if (v < NV) {
+                const int pix = v / NQ, q = v - (v / NQ) * NQ;
+                *(uint4*)(buf + (size_t)pix * CIN + chunk_swz<CIN>(pix, q) * 8) = pre[i];
+            }
+        }
+        __syncthreads();
+        if (t + gridDim.x < ntiles) load_tile(t + gridDim.x);
+
+        f32x16 acc[PMR][2];
+#pragma unroll
+        for (int m = 0; m < PMR; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
+#pragma unroll 1
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap - (tap / 3) * 3;
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const int q = ch * 2 + kh;
+                bf16x8 bfr[2];
+#pragma unroll
+                for (int n = 0; n < 2; ++n) {
+                    const int row = tap * 64 + n * 32 + col;
+                    bfr[n] = *(const bf16x8*)(wl + (size_t)row * CIN + chunk_swz<CIN>(row, q) * 8);
+                }
+#pragma unroll
+                for (int m = 0; m < PMR; ++m) {
+                    const int pix = (wv * PMR + m + dy) * TC + col + dx;
+                    const bf16x8 a = *(const bf16x8*)(buf + (size_t)pix * CIN + chunk_swz<CIN>(pix, q) * 8);
+#pragma unroll
+                    for (int n = 0; n < 2; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[n], acc[m][n], 0, 0, 0);
+                }
+            }
+        }
+
+        // epilogue through LDS: C row = pixel column within the tile row, C column = channel
+        __syncthreads();   // every wave is done reading the input tile
+#pragma unroll
+        for (int m = 0; m < PMR; ++m) {
+            const int rl = wv * PMR + m;
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                const int c = n * 32 + col;
+                const float bv = MODE == 1 ? 0.f : bias[c];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int px = 8 * (r >> 2) + 4 * kh + (r & 3);
+                    float v = acc[m][n][r] + bv;
+                    if (MODE == 0) v = v > 0.f ? v : 0.f;
+                    buf[(rl * PTX + px) * CTS + c] = f2bf(v);
+                }
+            }
+        }
+        __syncthreads();
+        for (int v = tid; v < PTY * PTX * 8; v += 256) {
+            const int cv = v & 7, pix = v >> 3;
+            const int rl = pix / PTX, px = pix - (pix / PTX) * PTX;
+            const int row = r0 + rl, k = k0 + px;
+            if (k >= W || row >= r_base + out_rows) continue;
+            uint4 val = *(const uint4*)(buf + pix * CTS + cv * 8);
+            const size_t o = ((size_t)b * plane + (size_t)row * W + k) * 64 + cv * 8;
+            if (MODE == 1) {
+                const uint4 a = *(const uint4*)(act + o);
+                uint16_t* h = (uint16_t*)&val;
+                const uint16_t* ha = (const uint16_t*)&a;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (!(bf2f(ha[i]) > 0.f)) h[i] = 0;
+            }
+            *(uint4*)(out + o) = val;
+        }
     }
 }
 
@@ -746,16 +912,29 @@ void cnn_features(hipStream_t st, const void* Bin, int dtype, const float* feats
                            H, W);
 }
 
+static int persist_blocks()
+{
+    static int n = 0;
+    if (!n) {
+        int dev = 0, cus = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        n = cus > 0 ? cus : 256;
+    }
+    return n;
+}
+
 void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,
                   uint16_t* out, int batch, int H, int W)
 {
-    dim3 g((W + CTX - 1) / CTX, (H + CTY - 1) / CTY, batch);
+    const long tiles = (long)batch * ((H + PTY - 1) / PTY) * ((W + PTX - 1) / PTX);
+    const int nb = (int)std::min<long>(tiles, persist_blocks());
     if (cin == 16)
-        hipLaunchKernelGGL((conv_mfma_kernel<16, 0, 2>), g, dim3(128), 0, st, x, wf, bias, (void*)out, H, W,
-                           (const uint16_t*)nullptr, (float*)nullptr);
+        hipLaunchKernelGGL((conv_persist_kernel<16, 0>), dim3(nb), dim3(256), 0, st, x, wf, bias, out, batch, H,
+                           W, (const uint16_t*)nullptr);
     else
-        hipLaunchKernelGGL((conv_mfma_kernel<64, 0, 2>), g, dim3(128), 0, st, x, wf, bias, (void*)out, H, W,
-                           (const uint16_t*)nullptr, (float*)nullptr);
+        hipLaunchKernelGGL((conv_persist_kernel<64, 0>), dim3(nb), dim3(256), 0, st, x, wf, bias, out, batch, H,
+                           W, (const uint16_t*)nullptr);
 }
 
 void cnn_conv_out(hipStream_t st, const uint16_t* x4, const float* w5f, const float* b5, float* y,
@@ -772,15 +951,17 @@ void cnn_conv_out(hipStream_t st, const uint16_t* x4, const float* w5f, const fl
 void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, const uint16_t* act,
                     uint16_t* dx, float* edge, int batch, int H, int W)
 {
-    dim3 g((W + CTX - 1) / CTX, (H - 2 + CTY - 1) / CTY, batch), ge2((W + CTX - 1) / CTX, 2, batch);
+    const long tiles = (long)batch * ((H - 2 + PTY - 1) / PTY) * ((W + PTX - 1) / PTX);
+    const int nb = (int)std::min<long>(tiles, persist_blocks());
+    dim3 ge2((W + CTX - 1) / CTX, 2, batch);
     if (cin == 16) {
-        hipLaunchKernelGGL((conv_mfma_kernel<16, 1, 2>), g, dim3(128), 0, st, dz, wd, (const float*)nullptr,
-                           (void*)dx, H, W, act, edge);
+        hipLaunchKernelGGL((conv_persist_kernel<16, 1>), dim3(nb), dim3(256), 0, st, dz, wd, (const float*)nullptr,
+                           dx, batch, H, W, act);
         hipLaunchKernelGGL((conv_mfma_kernel<16, 3, 2>), ge2, dim3(128), 0, st, dz, wd, (const float*)nullptr,
                            (void*)dx, H, W, act, edge);
     } else {
-        hipLaunchKernelGGL((conv_mfma_kernel<64, 1, 2>), g, dim3(128), 0, st, dz, wd, (const float*)nullptr,
-                           (void*)dx, H, W, act, edge);
+        hipLaunchKernelGGL((conv_persist_kernel<64, 1>), dim3(nb), dim3(256), 0, st, dz, wd, (const float*)nullptr,
+                           dx, batch, H, W, act);
         hipLaunchKernelGGL((conv_mfma_kernel<64, 3, 2>), ge2, dim3(128), 0, st, dz, wd, (const float*)nullptr,
                            (void*)dx, H, W, act, edge);
     }
