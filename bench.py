@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--sts-tile", type=int, default=-1, help="blocked STS shape (-1: autotuned)")
     ap.add_argument("--surr-batch", type=int, default=64)
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="only the surrogate measurement (inference batch, plain vs surrogate intervals)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -200,15 +202,16 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}))
 
 
-def traffic_from_profiles(family):
+def traffic_from_profiles(family, tile_index):
     """HBM bytes per launch of a kernel family from the committed rocprofv3
-    counter summary, if it was taken on the current kernel sources (else None)."""
+    counter summary, if it was taken on the same kernel (tile shape) and the
+    current kernel sources (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(family)
-    if not rec:
+    if not rec or rec.get("tile_index") != tile_index:
         return None
     for f, h in rec["sources_sha256"].items():
         src = open(os.path.join(ROOT, "paper_2501_06377_amd", "csrc", f), "rb").read()
@@ -230,6 +233,9 @@ def main():
 
     import paper_2501_06377_amd as sft
 
+    if args.surrogate_only:
+        print(json.dumps({"surrogate": surrogate_bench(sft, torch, args.surr_batch)}), flush=True)
+        return
     w = {"ensemble": synth.config2, "precision": synth.config3, "batching": synth.config4}[args.workload]()
     K = args.steps if args.steps is not None else (655 if args.workload == "ensemble" else 24)
     W = args.warmup
@@ -308,7 +314,7 @@ def main():
         dom = max(fams, key=lambda k: fams[k]["ms"])
         f = fams[dom]
         achieved = f["bytes"] / (f["ms"] * 1e-3) / 1e9
-        traffic = traffic_from_profiles(dom)
+        traffic = traffic_from_profiles(dom, tiles[0]["index"]) if len(tiles) == 1 else None
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "avg_launch_us": f["ms"] / max(f["launches"], 1) * 1e3,

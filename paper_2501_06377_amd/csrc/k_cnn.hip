@@ -342,26 +342,34 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
             for (int n = 0; n < 2; ++n)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
+        // per column shift dx and K chunk: the wave's PMR + 2 input rows are
+        // read once and shared by the three row shifts dy (row m + dy)
 #pragma unroll 1
-        for (int tap = 0; tap < 9; ++tap) {
-            const int dy = tap / 3, dx = tap - (tap / 3) * 3;
+        for (int dx = 0; dx < 3; ++dx) {
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 const int q = ch * 2 + kh;
-                bf16x8 bfr[2];
+                bf16x8 bfr[3][2], afr[PMR + 2];
 #pragma unroll
-                for (int n = 0; n < 2; ++n) {
-                    const int row = tap * 64 + n * 32 + col;
-                    bfr[n] = *(const bf16x8*)(wl + (size_t)row * CIN + chunk_swz<CIN>(row, q) * 8);
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int n = 0; n < 2; ++n) {
+                        const int row = (dy * 3 + dx) * 64 + n * 32 + col;
+                        bfr[dy][n] = *(const bf16x8*)(wl + (size_t)row * CIN + chunk_swz<CIN>(row, q) * 8);
+                    }
+#pragma unroll
+                for (int rr = 0; rr < PMR + 2; ++rr) {
+                    const int pix = (wv * PMR + rr) * TC + col + dx;
+                    afr[rr] = *(const bf16x8*)(buf + (size_t)pix * CIN + chunk_swz<CIN>(pix, q) * 8);
                 }
 #pragma unroll
-                for (int m = 0; m < PMR; ++m) {
-                    const int pix = (wv * PMR + m + dy) * TC + col + dx;
-                    const bf16x8 a = *(const bf16x8*)(buf + (size_t)pix * CIN + chunk_swz<CIN>(pix, q) * 8);
+                for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                    for (int n = 0; n < 2; ++n)
-                        acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[n], acc[m][n], 0, 0, 0);
-                }
+                    for (int m = 0; m < PMR; ++m)
+#pragma unroll
+                        for (int n = 0; n < 2; ++n)
+                            acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[m + dy], bfr[dy][n], acc[m][n],
+                                                                                0, 0, 0);
             }
         }
 
