@@ -18,7 +18,7 @@ void cnn_features(hipStream_t st, const void* Bin, int dtype, const float* feats
                   int H, int W);
 void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,
                   uint16_t* out, int batch, int H, int W);
-void cnn_conv_out(hipStream_t st, const uint16_t* x4, const float* w5f, const float* b5, float* y,
+void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
                   int batch, int H, int W);
 void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, const uint16_t* act,
                     uint16_t* dx, float* edge, int batch, int H, int W);
@@ -30,7 +30,7 @@ void cnn_loss_grad(hipStream_t st, const float* y, const void* Bin, const void* 
 void cnn_adam(hipStream_t st, float* p, const float* g, float* m, float* v, int n, float lr, float b1,
               float b2, float eps, float c1, float c2);
 void cnn_pack(hipStream_t st, const float* Wm, int cin, int cout, int cip, int nout, int cop, uint16_t* wf,
-              uint16_t* wd, float* w1f);
+              uint16_t* wd);
 }  // namespace sft
 
 using namespace sft;
@@ -54,7 +54,6 @@ struct sft_net {
     int step = 0;
     uint16_t* wf[5] = {};   // forward layouts (layer 5: one 32-wide tile, row 0 real)
     uint16_t* wd[5] = {};   // data-gradient layouts (layers 2..5)
-    float* w5f = nullptr;   // output layer's bf16-rounded weights as FP32 [tap][64]
     uint16_t* X0 = nullptr;
     uint16_t* X[4] = {};
     float *y = nullptr, *dxp = nullptr;   // dxp: pole-row edge scratch [B][4][np][64]
@@ -96,8 +95,8 @@ void pack_all(sft_net* net)
 {
     for (int l = 0; l < 4; ++l)
         cnn_pack(net->stream, net->p + net->woff[l], kCin[l], 64, l == 0 ? 16 : 64, 64, 64, net->wf[l],
-                 l == 0 ? nullptr : net->wd[l], nullptr);
-    cnn_pack(net->stream, net->p + net->woff[4], 64, 1, 64, 32, 16, net->wf[4], net->wd[4], net->w5f);
+                 l == 0 ? nullptr : net->wd[l]);
+    cnn_pack(net->stream, net->p + net->woff[4], 64, 1, 64, 32, 16, net->wf[4], net->wd[4]);
 }
 
 void forward(sft_net* net, int batch, const void* Bin, int dtype, const float* feats)
@@ -108,7 +107,7 @@ void forward(sft_net* net, int batch, const void* Bin, int dtype, const float* f
     cnn_conv_fwd(st, 16, net->X0, net->wf[0], net->p + net->boff[0], net->X[0], batch, H, W);
     for (int l = 1; l < 4; ++l)
         cnn_conv_fwd(st, 64, net->X[l - 1], net->wf[l], net->p + net->boff[l], net->X[l], batch, H, W);
-    cnn_conv_out(st, net->X[3], net->w5f, net->p + net->boff[4], net->y, batch, H, W);
+    cnn_conv_out(st, net->X[3], net->wf[4], net->p + net->boff[4], net->y, batch, H, W);
     net->last_batch = batch;
 }
 
@@ -153,7 +152,6 @@ sft_status sft_net_create(sft_net** out, int32_t nt, int32_t np, int32_t max_bat
         if (l) A_(nalloc(net, &net->wd[l], (size_t)9 * 64 * 64));
     }
     A_(nalloc(net, &net->wf[4], (size_t)9 * 32 * 64));
-    A_(nalloc(net, &net->w5f, (size_t)9 * 64));
     A_(nalloc(net, &net->wd[4], (size_t)9 * 64 * 16));
     A_(nalloc(net, &net->X0, B * plane * 16));
     for (int l = 0; l < 4; ++l) A_(nalloc(net, &net->X[l], B * plane * 64));

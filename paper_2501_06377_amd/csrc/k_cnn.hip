@@ -412,54 +412,73 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
     }
 }
 
-// Output layer (one channel) on the vector units:
-//   y[b][j][k] = bias + sum_tap sum_ci w5[tap][ci] x[pad(j + dy - 1, k + dx - 1)][ci]
-// with the bf16-rounded weights held as FP32 (w5[9][64], written by the
-// packing kernel) and FP32 accumulation.  A block stages OTY rows x OTX columns plus a one-cell
-// spherical halo of the 64-channel input in LDS (pixel stride 72 bf16, so the
-// 16-byte reads of consecutive pixels fall in different banks); one thread
-// per output pixel; the weights are uniform (scalar loads).
-constexpr int OTY = 4, OTX = 64;
+// Output layer (one channel) on the matrix cores, with the nine taps as the
+// GEMM's N dimension:
+//   Z[p][t] = sum_ci x[p][ci] w[t][ci]      (MFMA: M = 32 pixels, N = 32 >= 9 taps, K = 64)
+//   y[j][k] = bias + sum_t Z[(j + dy - 1, k + dx - 1)][t]
+// A block produces an OTY x OTX output tile: Z is computed for the tile and
+// its one-cell spherical halo, (OTY + 2) x (OTX + 2) pixels, with the A
+// fragments read straight from global memory, kept in LDS as FP32 (the nine
+// useful columns), and gathered per output pixel.  w = the packed bf16
+// layout wf[tap][32][64] (row 0 holds the output channel).
+constexpr int OTY = 8, OTX = 64;
 
-__global__ __launch_bounds__(OTY * OTX) void conv_out_kernel(const uint16_t* __restrict__ x,
-                                                             const float* __restrict__ w5,
-                                                             const float* __restrict__ bias,
-                                                             float* __restrict__ y, int H, int W)
+__global__ __launch_bounds__(256) void conv_out_kernel(const uint16_t* __restrict__ x,
+                                                       const uint16_t* __restrict__ wf,
+                                                       const float* __restrict__ bias,
+                                                       float* __restrict__ y, int H, int W)
 {
-    constexpr int CP = 72, TR = OTY + 2, TC = OTX + 2, NT = OTY * OTX;
-    __shared__ __attribute__((aligned(16))) uint16_t tile[TR * TC * CP];
+    constexpr int ZR = OTY + 2, ZC = OTX + 2, NZ = ZR * ZC, NG = (NZ + 31) / 32;
+    __shared__ float zs[NZ * 9];
     const int b = blockIdx.z, k0 = blockIdx.x * OTX, r0 = blockIdx.y * OTY;
-    const int tid = threadIdx.x;
-    for (int v = tid; v < TR * TC * 8; v += NT) {
-        const int pix = v >> 3, cv = v & 7;
-        const int tr = pix / TC, tc = pix - (pix / TC) * TC;
-        int sj, sk;
-        uint4 val = make_uint4(0, 0, 0, 0);
-        if (sphere_src(r0 - 1 + tr, k0 - 1 + tc, H, W, sj, sk))
-            val = *(const uint4*)(x + (((size_t)b * H + sj) * W + sk) * 64 + cv * 8);
-        *(uint4*)(tile + pix * CP + cv * 8) = val;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int col = lane & 31, kh = lane >> 5;
+    const uint16_t* xb = x + (size_t)b * H * W * 64;
+
+    // B fragments (taps as columns): column col = tap (zero beyond 8), rows = K chunk
+    bf16x8 bfr[4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        bfr[ch] = bf16x8{};
+        if (col < 9) bfr[ch] = *(const bf16x8*)(wf + (size_t)col * 32 * 64 + ch * 16 + kh * 8);
     }
-    __syncthreads();
-    const int ty = tid / OTX, tx = tid - (tid / OTX) * OTX;
-    float acc = bias[0];
+    for (int g = wv; g < NG; g += 4) {
+        const int zi = g * 32 + col;   // this lane's pixel of the group (A row)
+        bf16x8 afr[4];
+        int sj = 0, sk = 0;
+        const bool ok = zi < NZ && sphere_src(r0 - 1 + zi / ZC, k0 - 1 + zi % ZC, H, W, sj, sk);
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3, dx = tap - (tap / 3) * 3;
-        const uint16_t* src = tile + ((ty + dy) * TC + tx + dx) * CP;
+        for (int ch = 0; ch < 4; ++ch) {
+            afr[ch] = bf16x8{};
+            if (ok) afr[ch] = *(const bf16x8*)(xb + ((size_t)sj * W + sk) * 64 + ch * 16 + kh * 8);
+        }
+        f32x16 acc;
 #pragma unroll
-        for (int cv = 0; cv < 8; ++cv) {
-            const uint4 v = *(const uint4*)(src + cv * 8);
-            const float* wt = w5 + tap * 64 + cv * 8;   // uniform: scalar loads
-            const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+        for (int r = 0; r < 16; ++r) acc[r] = 0.f;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                acc += __uint_as_float(u[e] << 16) * wt[2 * e];
-                acc += __uint_as_float(u[e] & 0xFFFF0000u) * wt[2 * e + 1];
+        for (int ch = 0; ch < 4; ++ch) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[ch], bfr[ch], acc, 0, 0, 0);
+        // C register r: pixel 8(r/4) + 4 kh + r%4 of the group, column = tap
+        if (col < 9) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int z = g * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                if (z < NZ) zs[z * 9 + col] = acc[r];
             }
         }
     }
-    const int j = r0 + ty, k = k0 + tx;
-    if (j < H && k < W) y[((size_t)b * H + j) * W + k] = acc;
+    __syncthreads();
+    for (int o = tid; o < OTY * OTX; o += 256) {
+        const int ty = o / OTX, tx = o - (o / OTX) * OTX;
+        const int j = r0 + ty, k = k0 + tx;
+        if (j >= H || k >= W) continue;
+        float acc = bias[0];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3, dx = t - (t / 3) * 3;
+            acc += zs[((ty + dy) * ZC + tx + dx) * 9 + t];
+        }
+        y[((size_t)b * H + j) * W + k] = acc;
+    }
 }
 
 // Pole rows of the input gradient: edge rows (-1, 0, H-1, H) -> rows 0 and
@@ -813,8 +832,7 @@ __device__ __forceinline__ int master_channel(int ci, int cin, int cip)
 // gradient is the same correlation over the padded neighbourhood as the
 // forward pass.
 __global__ void pack_weights_kernel(const float* __restrict__ Wm, int cin, int cout, int cip, int nout,
-                                    int cop, uint16_t* __restrict__ wf, uint16_t* __restrict__ wd,
-                                    float* __restrict__ w1f)
+                                    int cop, uint16_t* __restrict__ wf, uint16_t* __restrict__ wd)
 {
     const int n = 9 * nout * cip;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
@@ -823,8 +841,6 @@ __global__ void pack_weights_kernel(const float* __restrict__ Wm, int cin, int c
         const int mc = master_channel(ci, cin, cip);
         const float v = (mc >= 0 && co < cout) ? Wm[((size_t)co * cin + mc) * 9 + tap] : 0.f;
         wf[e] = f2bf(v);
-        // single-output layer: the bf16-rounded weights of output 0 as FP32 [tap][ci]
-        if (w1f && co == 0) w1f[tap * cip + ci] = bf2f(f2bf(v));
     }
     if (!wd) return;
     const int nd = 9 * cin * cop;
@@ -945,11 +961,11 @@ void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf
                            W, (const uint16_t*)nullptr);
 }
 
-void cnn_conv_out(hipStream_t st, const uint16_t* x4, const float* w5f, const float* b5, float* y,
+void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
                   int batch, int H, int W)
 {
     dim3 g((W + OTX - 1) / OTX, (H + OTY - 1) / OTY, batch);
-    hipLaunchKernelGGL(conv_out_kernel, g, dim3(OTY * OTX), 0, st, x4, w5f, b5, y, H, W);
+    hipLaunchKernelGGL(conv_out_kernel, g, dim3(256), 0, st, x4, wf5, b5, y, H, W);
 }
 
 // Gradient of a layer's input, masked by that input's ReLU, as bf16:
@@ -1022,10 +1038,10 @@ void cnn_adam(hipStream_t st, float* p, const float* g, float* m, float* v, int 
 }
 
 void cnn_pack(hipStream_t st, const float* Wm, int cin, int cout, int cip, int nout, int cop, uint16_t* wf,
-              uint16_t* wd, float* w1f)
+              uint16_t* wd)
 {
     hipLaunchKernelGGL(pack_weights_kernel, dim3(gblocks((size_t)9 * nout * cip, 256, 1024)), dim3(256), 0,
-                       st, Wm, cin, cout, cip, nout, cop, wf, wd, w1f);
+                       st, Wm, cin, cout, cip, nout, cop, wf, wd);
 }
 
 void cnn_pred(hipStream_t st, const double* Bin, const float* y, double* pred, size_t n)
