@@ -245,10 +245,9 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
 // the data gradient (MODE 1: interior rows 1..H-2, ReLU mask of the layer
 // input), as implicit GEMMs on v_mfma_f32_32x32x16_bf16 with every operand in
 // LDS.  One 256-thread block per compute unit keeps all nine taps' weights
-// resident (9 x 64 x CIN bf16) and walks output tiles of PTY x PTX pixels;
-// while a tile's MFMAs run, the next tile (with its one-cell halo) is already
-// being loaded into registers, and goes to LDS once the tile's epilogue is
-// done.  Wave w computes rows PMR w .. PMR w + PMR - 1 of the tile for all
+// resident (9 x 64 x CIN bf16) and walks output tiles of PTY x PTX pixels
+// (with their one-cell halo); a tile's input is loaded into registers two
+// tiles ahead and goes to LDS once the previous tile's epilogue is done.  Wave w computes rows PMR w .. PMR w + PMR - 1 of the tile for all
 // 64 outputs.
 // LDS rows are stored in 16-byte chunks permuted by an XOR with the row
 // (pixel) index, so the fragment reads of 8 consecutive lanes hit distinct
@@ -292,8 +291,9 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
     const long ntiles = (long)batch * tiles_y * tiles_x;
     const size_t plane = (size_t)H * W;
 
-    uint4 pre[VPT];
-    auto load_tile = [&](long t) {
+    // registers for two tiles in flight ahead of the one being computed
+    uint4 pra[VPT], prb[VPT];
+    auto load_tile = [&](long t, uint4 (&pre)[VPT]) {
         const int b = (int)(t / ((long)tiles_y * tiles_x));
         const int rem = (int)(t - (long)b * tiles_y * tiles_x);
         const int r0 = r_base + (rem / tiles_x) * PTY, k0 = (rem - (rem / tiles_x) * tiles_x) * PTX;
@@ -317,9 +317,9 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
         }
     };
 
-    long t = blockIdx.x;
-    if (t < ntiles) load_tile(t);
-    for (; t < ntiles; t += gridDim.x) {
+    // one tile: staged registers -> LDS, refill them with the tile two
+    // steps ahead, MFMAs, epilogue
+    auto tile_step = [&](long t, uint4 (&pre)[VPT]) {
         const int b = (int)(t / ((long)tiles_y * tiles_x));
         const int rem = (int)(t - (long)b * tiles_y * tiles_x);
         const int r0 = r_base + (rem / tiles_x) * PTY, k0 = (rem - (rem / tiles_x) * tiles_x) * PTX;
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
             }
         }
         __syncthreads();
-        if (t + gridDim.x < ntiles) load_tile(t + gridDim.x);
+        if (t + 2 * (long)gridDim.x < ntiles) load_tile(t + 2 * (long)gridDim.x, pre);
 
         f32x16 acc[PMR][2];
 #pragma unroll
@@ -409,6 +409,15 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
             }
             *(uint4*)(out + o) = val;
         }
+    };
+
+    const long G = gridDim.x;
+    long t = blockIdx.x;
+    if (t < ntiles) load_tile(t, pra);
+    if (t + G < ntiles) load_tile(t + G, prb);
+    for (; t < ntiles; t += 2 * G) {
+        tile_step(t, pra);
+        if (t + G < ntiles) tile_step(t + G, prb);
     }
 }
 
@@ -952,7 +961,8 @@ void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf
                   uint16_t* out, int batch, int H, int W)
 {
     const long tiles = (long)batch * ((H + PTY - 1) / PTY) * ((W + PTX - 1) / PTX);
-    const int nb = (int)std::min<long>(tiles, persist_blocks());
+    // the 16-channel layer's weights and tile need 55 KB of LDS: two blocks per compute unit
+    const int nb = (int)std::min<long>(tiles, (cin == 16 ? 2 : 1) * persist_blocks());
     if (cin == 16)
         hipLaunchKernelGGL((conv_persist_kernel<16, 0>), dim3(nb), dim3(256), 0, st, x, wf, bias, out, batch, H,
                            W, (const uint16_t*)nullptr);
@@ -976,7 +986,7 @@ void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t*
                     uint16_t* dx, float* edge, int batch, int H, int W)
 {
     const long tiles = (long)batch * ((H - 2 + PTY - 1) / PTY) * ((W + PTX - 1) / PTX);
-    const int nb = (int)std::min<long>(tiles, persist_blocks());
+    const int nb = (int)std::min<long>(tiles, (cin == 16 ? 2 : 1) * persist_blocks());
     dim3 ge2((W + CTX - 1) / CTX, 2, batch);
     if (cin == 16) {
         hipLaunchKernelGGL((conv_persist_kernel<16, 1>), dim3(nb), dim3(256), 0, st, dz, wd, (const float*)nullptr,
