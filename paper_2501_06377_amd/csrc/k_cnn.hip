@@ -244,15 +244,24 @@ __global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restri
 // The 64-output convolutions of the forward pass (MODE 0: bias + ReLU) and of
 // the data gradient (MODE 1: interior rows 1..H-2, ReLU mask of the layer
 // input), as implicit GEMMs on v_mfma_f32_32x32x16_bf16 with every operand in
-// LDS.  One 256-thread block per compute unit keeps all nine taps' weights
-// resident (9 x 64 x CIN bf16) and walks output tiles of PTY x PTX pixels
-// (with their one-cell halo); a tile's input is loaded into registers two
-// tiles ahead and goes to LDS once the previous tile's epilogue is done.  Wave w computes rows PMR w .. PMR w + PMR - 1 of the tile for all
-// 64 outputs.
-// LDS rows are stored in 16-byte chunks permuted by an XOR with the row
-// (pixel) index, so the fragment reads of 8 consecutive lanes hit distinct
-// banks without padding.
-constexpr int PTY = 8, PTX = 32, PMR = PTY / 4;   // tile rows, columns; rows per wave
+// LDS.  A 256-thread block keeps all nine taps' weights resident
+// (9 x 64 x CIN bf16) and walks output tiles of PTY x PTX pixels (with their
+// one-cell halo); a tile's input is loaded into registers DEPTH tiles ahead
+// and goes to LDS once the previous tile's epilogue is done.  Wave w computes
+// rows PMR w .. PMR w + PMR - 1 of the tile, every 32-pixel column group,
+// all 64 outputs: per column shift dx and K chunk it reads the three row
+// shifts' weight fragments and its PMR + 2 input rows once and issues
+// 3 x PMR x (PTX / 32) x 2 MFMAs.  LDS rows are stored in 16-byte chunks
+// permuted by an XOR with the row (pixel) index, so the fragment reads of 8
+// consecutive lanes hit distinct banks without padding.
+constexpr int PTY = 8, PMR = PTY / 4;   // tile rows; rows per wave
+
+template <int CIN>
+struct PersistShape {
+    static constexpr int PTX = CIN == 64 ? 64 : 32;   // tile columns (LDS: 158 KB / 55 KB per block)
+    static constexpr int DEPTH = CIN == 64 ? 1 : 2;   // tiles in flight in registers
+    static constexpr int BLOCKS_PER_CU = CIN == 64 ? 1 : 2;
+};
 
 template <int CIN>
 __device__ __forceinline__ int chunk_swz(int row, int q)
@@ -267,6 +276,8 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
                                                            uint16_t* __restrict__ out, int batch, int H, int W,
                                                            const uint16_t* __restrict__ act)
 {
+    constexpr int PTX = PersistShape<CIN>::PTX, DEPTH = PersistShape<CIN>::DEPTH;
+    constexpr int NCG = PTX / 32;                 // 32-pixel column groups
     constexpr int NQ = CIN / 8;                   // 16-byte chunks per pixel / weight row
     constexpr int NCH = CIN / 16;                 // K chunks per tap
     constexpr int TR = PTY + 2, TC = PTX + 2;
@@ -291,9 +302,8 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
     const long ntiles = (long)batch * tiles_y * tiles_x;
     const size_t plane = (size_t)H * W;
 
-    // registers for two tiles in flight ahead of the one being computed
-    uint4 pra[VPT], prb[VPT];
-    auto load_tile = [&](long t, uint4 (&pre)[VPT]) {
+    uint4 pra[VPT], prb[DEPTH > 1 ? VPT : 1];
+    auto load_tile = [&](long t, auto& pre) {
         const int b = (int)(t / ((long)tiles_y * tiles_x));
         const int rem = (int)(t - (long)b * tiles_y * tiles_x);
         const int r0 = r_base + (rem / tiles_x) * PTY, k0 = (rem - (rem / tiles_x) * tiles_x) * PTX;
@@ -317,9 +327,10 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
         }
     };
 
-    // one tile: staged registers -> LDS, refill them with the tile two
+    const long G = gridDim.x;
+    // one tile: staged registers -> LDS, refill them with the tile DEPTH
     // steps ahead, MFMAs, epilogue
-    auto tile_step = [&](long t, uint4 (&pre)[VPT]) {
+    auto tile_step = [&](long t, auto& pre) {
         const int b = (int)(t / ((long)tiles_y * tiles_x));
         const int rem = (int)(t - (long)b * tiles_y * tiles_x);
         const int r0 = r_base + (rem / tiles_x) * PTY, k0 = (rem - (rem / tiles_x) * tiles_x) * PTX;
@@ -333,23 +344,23 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
             }
         }
         __syncthreads();
-        if (t + 2 * (long)gridDim.x < ntiles) load_tile(t + 2 * (long)gridDim.x, pre);
+        if (t + DEPTH * G < ntiles) load_tile(t + DEPTH * G, pre);
 
-        f32x16 acc[PMR][2];
+        f32x16 acc[PMR][NCG][2];
 #pragma unroll
         for (int m = 0; m < PMR; ++m)
 #pragma unroll
-            for (int n = 0; n < 2; ++n)
+            for (int g = 0; g < NCG; ++g)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
-        // per column shift dx and K chunk: the wave's PMR + 2 input rows are
-        // read once and shared by the three row shifts dy (row m + dy)
+                for (int n = 0; n < 2; ++n)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[m][g][n][r] = 0.f;
 #pragma unroll 1
         for (int dx = 0; dx < 3; ++dx) {
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 const int q = ch * 2 + kh;
-                bf16x8 bfr[3][2], afr[PMR + 2];
+                bf16x8 bfr[3][2], afr[NCG][PMR + 2];
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
@@ -358,38 +369,44 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
                         bfr[dy][n] = *(const bf16x8*)(wl + (size_t)row * CIN + chunk_swz<CIN>(row, q) * 8);
                     }
 #pragma unroll
-                for (int rr = 0; rr < PMR + 2; ++rr) {
-                    const int pix = (wv * PMR + rr) * TC + col + dx;
-                    afr[rr] = *(const bf16x8*)(buf + (size_t)pix * CIN + chunk_swz<CIN>(pix, q) * 8);
-                }
+                for (int g = 0; g < NCG; ++g)
+#pragma unroll
+                    for (int rr = 0; rr < PMR + 2; ++rr) {
+                        const int pix = (wv * PMR + rr) * TC + g * 32 + col + dx;
+                        afr[g][rr] = *(const bf16x8*)(buf + (size_t)pix * CIN + chunk_swz<CIN>(pix, q) * 8);
+                    }
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
                     for (int m = 0; m < PMR; ++m)
 #pragma unroll
-                        for (int n = 0; n < 2; ++n)
-                            acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[m + dy], bfr[dy][n], acc[m][n],
-                                                                                0, 0, 0);
+                        for (int g = 0; g < NCG; ++g)
+#pragma unroll
+                            for (int n = 0; n < 2; ++n)
+                                acc[m][g][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[g][m + dy], bfr[dy][n],
+                                                                                       acc[m][g][n], 0, 0, 0);
             }
         }
 
-        // epilogue through LDS: C row = pixel column within the tile row, C column = channel
+        // epilogue through LDS: C row = pixel column within the group, C column = channel
         __syncthreads();   // every wave is done reading the input tile
 #pragma unroll
         for (int m = 0; m < PMR; ++m) {
             const int rl = wv * PMR + m;
 #pragma unroll
-            for (int n = 0; n < 2; ++n) {
-                const int c = n * 32 + col;
-                const float bv = MODE == 1 ? 0.f : bias[c];
+            for (int g = 0; g < NCG; ++g)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int px = 8 * (r >> 2) + 4 * kh + (r & 3);
-                    float v = acc[m][n][r] + bv;
-                    if (MODE == 0) v = v > 0.f ? v : 0.f;
-                    buf[(rl * PTX + px) * CTS + c] = f2bf(v);
+                for (int n = 0; n < 2; ++n) {
+                    const int c = n * 32 + col;
+                    const float bv = MODE == 1 ? 0.f : bias[c];
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int px = g * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                        float v = acc[m][g][n][r] + bv;
+                        if (MODE == 0) v = v > 0.f ? v : 0.f;
+                        buf[(rl * PTX + px) * CTS + c] = f2bf(v);
+                    }
                 }
-            }
         }
         __syncthreads();
         for (int v = tid; v < PTY * PTX * 8; v += 256) {
@@ -411,13 +428,16 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
         }
     };
 
-    const long G = gridDim.x;
     long t = blockIdx.x;
     if (t < ntiles) load_tile(t, pra);
-    if (t + G < ntiles) load_tile(t + G, prb);
-    for (; t < ntiles; t += 2 * G) {
-        tile_step(t, pra);
-        if (t + G < ntiles) tile_step(t + G, prb);
+    if constexpr (DEPTH > 1) {
+        if (t + G < ntiles) load_tile(t + G, prb);
+        for (; t < ntiles; t += 2 * G) {
+            tile_step(t, pra);
+            if (t + G < ntiles) tile_step(t + G, prb);
+        }
+    } else {
+        for (; t < ntiles; t += G) tile_step(t, pra);
     }
 }
 
@@ -957,18 +977,23 @@ static int persist_blocks()
     return n;
 }
 
+template <int CIN, int MODE>
+static void launch_persist(hipStream_t st, const uint16_t* x, const uint16_t* w, const float* bias,
+                           uint16_t* out, int batch, int H, int W, const uint16_t* act)
+{
+    constexpr int PTX = PersistShape<CIN>::PTX;
+    const int rows = MODE == 1 ? H - 2 : H;
+    const long tiles = (long)batch * ((rows + PTY - 1) / PTY) * ((W + PTX - 1) / PTX);
+    const int nb = (int)std::min<long>(tiles, (long)PersistShape<CIN>::BLOCKS_PER_CU * persist_blocks());
+    hipLaunchKernelGGL((conv_persist_kernel<CIN, MODE>), dim3(nb), dim3(256), 0, st, x, w, bias, out, batch, H,
+                       W, act);
+}
+
 void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,
                   uint16_t* out, int batch, int H, int W)
 {
-    const long tiles = (long)batch * ((H + PTY - 1) / PTY) * ((W + PTX - 1) / PTX);
-    // the 16-channel layer's weights and tile need 55 KB of LDS: two blocks per compute unit
-    const int nb = (int)std::min<long>(tiles, (cin == 16 ? 2 : 1) * persist_blocks());
-    if (cin == 16)
-        hipLaunchKernelGGL((conv_persist_kernel<16, 0>), dim3(nb), dim3(256), 0, st, x, wf, bias, out, batch, H,
-                           W, (const uint16_t*)nullptr);
-    else
-        hipLaunchKernelGGL((conv_persist_kernel<64, 0>), dim3(nb), dim3(256), 0, st, x, wf, bias, out, batch, H,
-                           W, (const uint16_t*)nullptr);
+    if (cin == 16) launch_persist<16, 0>(st, x, wf, bias, out, batch, H, W, nullptr);
+    else launch_persist<64, 0>(st, x, wf, bias, out, batch, H, W, nullptr);
 }
 
 void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
@@ -985,17 +1010,13 @@ void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const
 void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, const uint16_t* act,
                     uint16_t* dx, float* edge, int batch, int H, int W)
 {
-    const long tiles = (long)batch * ((H - 2 + PTY - 1) / PTY) * ((W + PTX - 1) / PTX);
-    const int nb = (int)std::min<long>(tiles, (cin == 16 ? 2 : 1) * persist_blocks());
     dim3 ge2((W + CTX - 1) / CTX, 2, batch);
     if (cin == 16) {
-        hipLaunchKernelGGL((conv_persist_kernel<16, 1>), dim3(nb), dim3(256), 0, st, dz, wd, (const float*)nullptr,
-                           dx, batch, H, W, act);
+        launch_persist<16, 1>(st, dz, wd, nullptr, dx, batch, H, W, act);
         hipLaunchKernelGGL((conv_mfma_kernel<16, 3, 2>), ge2, dim3(128), 0, st, dz, wd, (const float*)nullptr,
                            (void*)dx, H, W, act, edge);
     } else {
-        hipLaunchKernelGGL((conv_persist_kernel<64, 1>), dim3(nb), dim3(256), 0, st, dz, wd, (const float*)nullptr,
-                           dx, batch, H, W, act);
+        launch_persist<64, 1>(st, dz, wd, nullptr, dx, batch, H, W, act);
         hipLaunchKernelGGL((conv_mfma_kernel<64, 3, 2>), ge2, dim3(128), 0, st, dz, wd, (const float*)nullptr,
                            (void*)dx, H, W, act, edge);
     }
