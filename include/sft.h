@@ -7,8 +7,8 @@
  *   - advection by differential rotation and meridional flow
  *     (eq. advection, eq. dr, eq. mf; WENO3-CS(h) fluxes of App. B with the
  *     upwind pole rows and finite-volume pole closure of App. A;
- *     SSPRK(4,3) or forward-Euler time stepping, Sec. "Advection temporal
- *     schemes"),
+ *     SSPRK(4,3), SSPRK(3,3) or forward-Euler time stepping, Sec.
+ *     "Advection temporal schemes"),
  *   - surface diffusion (eq. diffusion, eq. diffusion_matrix) advanced by
  *     super time stepping (RKG2(3/2) default, RKL2, or forward Euler,
  *     Sec. "Diffusion temporal schemes"),
@@ -71,6 +71,7 @@ typedef int32_t sft_status;
 /* advection time scheme */
 #define SFT_SSPRK43 0
 #define SFT_FE 1
+#define SFT_SSPRK33 2
 /* diffusion time scheme */
 #define SFT_RKG2 0
 #define SFT_RKL2 1
@@ -86,7 +87,7 @@ typedef int32_t sft_status;
 typedef struct {
     int32_t precision;    /* SFT_FP64 (default) or SFT_FP32_MIXED                          */
     int32_t adv_scheme;   /* SFT_WENO3CSH (default) or SFT_UPWIND                          */
-    int32_t adv_time;     /* SFT_SSPRK43 (default) or SFT_FE                               */
+    int32_t adv_time;     /* SFT_SSPRK43 (default), SFT_FE or SFT_SSPRK33                  */
     int32_t diff_time;    /* SFT_RKG2 (default), SFT_RKL2 or SFT_DIFF_FE                   */
     double cfl_safety;    /* safety factor on the flow CFL limit (default 0.9)             */
     double dt_max;        /* upper bound on a step, hours; 0 = none (default)              */

@@ -17,7 +17,7 @@ SFT_ERR_ARG, SFT_ERR_SHAPE, SFT_ERR_OOM, SFT_ERR_HIP = -1, -2, -3, -4
 SFT_ERR_NOT_FINITE, SFT_ERR_STATE, SFT_ERR_UNSUPPORTED = -5, -6, -7
 SFT_FP64, SFT_FP32_MIXED = 0, 1
 SFT_WENO3CSH, SFT_UPWIND = 0, 1
-SFT_SSPRK43, SFT_FE = 0, 1
+SFT_SSPRK43, SFT_FE, SFT_SSPRK33 = 0, 1, 2
 SFT_RKG2, SFT_RKL2, SFT_DIFF_FE = 0, 1, 2
 SFT_DTYPE_F64, SFT_DTYPE_F32 = 0, 1
 SFT_WEIGHT_F, SFT_WEIGHT_MU, SFT_WEIGHT_DISK = 0, 1, 2

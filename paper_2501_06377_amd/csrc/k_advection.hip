@@ -168,6 +168,12 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
             T d;
             if (time_scheme == 1) {
                 d = -(dt * op);
+            } else if (time_scheme == 2) {
+                // SSPRK(3,3) in increments of fn: d1 = -dt A, d2 = d1/4 - (dt/4) A,
+                // d3 = 2 d2/3 - (2 dt/3) A
+                if (stage == 0) d = -(dt * op);
+                else if (stage == 1) d = T(0.25) * fin[i] - (T(0.25) * dt) * op;
+                else d = (T(2) / T(3)) * fin[i] - ((T(2) / T(3)) * dt) * op;
             } else if (stage == 0) {
                 d = -(hdt * op);
             } else if (stage == 1) {
@@ -184,6 +190,12 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
             T v;
             if (time_scheme == 1) {
                 v = cur - dt * op;
+            } else if (time_scheme == 2) {
+                // SSPRK(3,3): f1 = fn - dt A(fn), f2 = 3/4 fn + 1/4 f1 - 1/4 dt A(f1),
+                // fn+1 = 1/3 fn + 2/3 f2 - 2/3 dt A(f2)
+                if (stage == 0) v = cur - dt * op;
+                else if (stage == 1) v = 0.75 * (T)fn[i] + 0.25 * cur - 0.25 * dt * op;
+                else v = (T(1) / T(3)) * (T)fn[i] + (T(2) / T(3)) * cur - (T(2) / T(3)) * dt * op;
             } else if (stage == 2) {
                 v = (T(2) / T(3)) * (T)fn[i] + (T(1) / T(3)) * cur - ((T(1) / T(6)) * dt) * op;
             } else {

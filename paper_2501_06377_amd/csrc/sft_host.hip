@@ -397,7 +397,7 @@ sft_status build_plan(sft_ctx* c, GridClass* g, double len, Plan** out)
     std::vector<Entry> ents;
     std::vector<StageCoef> coefs;
     std::vector<StageCoef> tmp;
-    const int adv_nst = o.adv_time == SFT_SSPRK43 ? 4 : 1;
+    const int adv_nst = o.adv_time == SFT_SSPRK43 ? 4 : (o.adv_time == SFT_SSPRK33 ? 3 : 1);
     for (size_t i = 0; i < max_steps; ++i) {
         // advection phase
         Phase pa{0, (int)ents.size(), 0, 0, {}};
@@ -703,7 +703,7 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p)
     const double cells = (double)g->cells();
     const double dth = M_PI / nt, dph = 2.0 * M_PI / np;
     const int upwind = o.adv_scheme == SFT_UPWIND;
-    const int ts = o.adv_time == SFT_SSPRK43 ? 0 : 1;
+    const int ts = o.adv_time == SFT_SSPRK43 ? 0 : (o.adv_time == SFT_SSPRK33 ? 2 : 1);
     for (const Phase& ph : p->phases) {
         const Entry* E = p->d_ents + ph.ent_off;
         const double ne = (double)ph.n_ent;
@@ -712,22 +712,23 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p)
                 Geom<double> geo{g->sf64, g->denth64, g->denph64};
                 WenoConst<double> wt = weno_const(dth), wp = weno_const(dph);
                 double *B = g->B, *W1 = g->W[0], *W2 = g->W[1];
+                // SSPRK(4,3): B -> W1 -> W2 -> W1 -> B; SSPRK(3,3): B -> W1 -> W2 -> B
                 const double* fin[4] = {B, W1, W2, W1};
-                double* fout[4] = {W1, W2, W1, B};
-                const int nst = ts == 1 ? 1 : 4;
+                double* fout[4] = {W1, W2, ts == 2 ? B : W1, B};
+                const int nst = ts == 1 ? 1 : (ts == 2 ? 3 : 4);
                 for (int k = 0; k < nst; ++k) {
                     tbeg(c);
                     launch_adv_stage_f64(st, E, ph.n_ent, k, ts, upwind, g->adv64, geo, wt, wp, B, fin[k],
                                          fout[k], nt, np);
-                    tend(c, SFT_KFAM_ADV_STAGE, (k == 2 ? 24.0 : 16.0) * cells * ne);
+                    tend(c, SFT_KFAM_ADV_STAGE, (k == 2 || (ts == 2 && k == 1) ? 24.0 : 16.0) * cells * ne);
                 }
             } else {
                 Geom<float> geo{g->sf32, g->denth32, g->denph32};
                 WenoConst<float> wt = weno_const_f(dth), wp = weno_const_f(dph);
                 float *A0 = g->A[0], *A1 = g->A[1], *A2 = g->A[2];
                 const float* din[4] = {nullptr, A1, A2, A1};
-                float* dout[4] = {ts == 1 ? A0 : A1, A2, A1, A0};
-                const int nst = ts == 1 ? 1 : 4;
+                float* dout[4] = {ts == 1 ? A0 : A1, A2, ts == 2 ? A0 : A1, A0};
+                const int nst = ts == 1 ? 1 : (ts == 2 ? 3 : 4);
                 for (int k = 0; k < nst; ++k) {
                     tbeg(c);
                     launch_adv_stage_mixed(st, E, ph.n_ent, k, ts, upwind, g->adv32, geo, wt, wp, g->B,
@@ -868,7 +869,7 @@ sft_status sft_create(sft_ctx** ctx, const sft_options* opt, void* hip_stream)
     else sft_options_default(&o);
     if (o.precision != SFT_FP64 && o.precision != SFT_FP32_MIXED) return SFT_ERR_ARG;
     if (o.adv_scheme != SFT_WENO3CSH && o.adv_scheme != SFT_UPWIND) return SFT_ERR_ARG;
-    if (o.adv_time != SFT_SSPRK43 && o.adv_time != SFT_FE) return SFT_ERR_ARG;
+    if (o.adv_time != SFT_SSPRK43 && o.adv_time != SFT_FE && o.adv_time != SFT_SSPRK33) return SFT_ERR_ARG;
     if (o.diff_time != SFT_RKG2 && o.diff_time != SFT_RKL2 && o.diff_time != SFT_DIFF_FE)
         return SFT_ERR_ARG;
     if (!(o.cfl_safety > 0.0 && o.cfl_safety <= 1.0) || o.dt_max < 0.0 || o.ptl_dt < 0.0)

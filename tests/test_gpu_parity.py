@@ -104,7 +104,7 @@ def test_assimilation_f64(kind, balance):
 
 
 @pytest.mark.parametrize("opts", [
-    {"adv_time": 1}, {"diff_time": 1}, {"diff_time": 2, "dt_max": 0.05}, {"ptl_dt": 0.3},
+    {"adv_time": 1}, {"adv_time": 2}, {"diff_time": 1}, {"diff_time": 2, "dt_max": 0.05}, {"ptl_dt": 0.3},
     {"dt_max": 0.7, "cfl_safety": 0.5}])
 def test_scheme_options_f64(opts):
     nt, np_ = 24, 48
@@ -122,9 +122,10 @@ def test_scheme_options_f64(opts):
     assert e <= TOL64
 
 
-def test_mixed_precision_matches_oracle():
+@pytest.mark.parametrize("adv_time", [0, 2])
+def test_mixed_precision_matches_oracle(adv_time):
     nt, np_ = 64, 128
-    say("case fp32 mixed 64x128, 24 h with hourly assimilation")
+    say(f"case fp32 mixed 64x128, 24 h with hourly assimilation, advection scheme {adv_time}")
     reals = reals_mix(4)
     B0 = np.stack([random_field(nt, np_, 12, 30 + i) for i in range(4)])
     sched = []
@@ -132,8 +133,8 @@ def test_mixed_precision_matches_oracle():
         sched.append(("advance", float(h)))
         b0, l0 = synth.observer(h)
         sched.append(("assim", synth.observation(B0[0], h, h), 2, None, b0, l0))
-    ref, _ = oracle_run(B0, reals, sched)
-    got, _ = gpu_run(B0, reals, sched, precision=1)
+    ref, _ = oracle_run(B0, reals, sched, {"adv_time": adv_time})
+    got, _ = gpu_run(B0, reals, sched, precision=1, adv_time=adv_time)
     for r in range(4):
         e = rel_l2(got[r], ref[r])
         say(f"  realization {r}: rel-L2 {e:.3e}  max-abs {np.abs(got[r] - ref[r]).max():.3e} G")
