@@ -211,10 +211,11 @@ def hh(X, Y):
 
 
 def advance(B, prm, nu_km2_s, t0, t_end, adv_scheme=WENO3CSH, adv_time=SSPRK43,
-            diff_scheme=RKG2, safety=0.9, dt_max=0.0, eps_mode=0.0, ptl_dt=0.0):
-    """Advance one realization from t0 to t_end (hours).  Returns (B, stats)."""
+            diff_scheme=RKG2, safety=0.9, dt_max=0.0, eps_mode=0.0, ptl_dt=0.0, strang=0):
+    """Advance one realization from t0 to t_end (hours), operator split with
+    or without Strang splitting.  Returns (B, stats)."""
     B = _f64(B).copy()
-    opts = np.array([adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt],
+    opts = np.array([adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang],
                     dtype=np.float64)
     stats = np.zeros(3)
     lib().or_advance(B.shape[0], B.shape[1], _p(B), _p(_f64(prm)), float(nu_km2_s), float(t0),

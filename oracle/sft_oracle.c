@@ -713,14 +713,18 @@ double or_hh(long n, const double *X, const double *Y)
 }
 
 /* ------------------------------------------------------------- time loop */
-/* Sec. "Time steps" and "Operator splitting" (no Strang): each step takes
+/* Sec. "Time steps" and "Operator splitting": each step takes
  * dt = min(time left in the interval, safety * CFL limit, dt_max), then
- * B* = A(B, dt), B** = D(B*, dt); the source term is absent.  Reading: the
- * time left is measured from the start of the interval (elapsed time is
- * accumulated from zero, the interval length is t_end - t0), and a step that
- * would leave less than 1e-10 h before t_end is stretched to land on t_end.
+ * without Strang splitting (eq. num_opsplit_nostrang) B* = A(B, dt),
+ * B** = D(B*, dt); with Strang splitting (eq. num_opsplit_strang)
+ * B* = A(B, dt/2), B** = D(B*, dt), B*** = A(B**, dt/2), and the CFL limit of
+ * the step doubles because each advection advance is dt/2.  The source term
+ * is absent.  Reading: the time left is measured from the start of the
+ * interval (elapsed time is accumulated from zero, the interval length is
+ * t_end - t0), and a step that would leave less than 1e-10 h before t_end is
+ * stretched to land on t_end.
  * prm = {d0, d2, d4, m1, m3, m5} (m/s), nu_km2_s scalar diffusivity.
- * opts = {adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt}
+ * opts = {adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang}
  * stats = {steps, diffusion stages, last dt}.  Returns 0. */
 int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, double t0,
                double t_end, const double *opts, double *stats)
@@ -730,6 +734,7 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
     double nu = nu_km2_s * k2;
     int adv_scheme = (int)opts[0], adv_time = (int)opts[1], dscheme = (int)opts[2];
     double safety = opts[3], dt_max = opts[4], eps_mode = opts[5], ptl_dt = opts[6];
+    int strang = (int)opts[7];
     double *vph = (double *)malloc(sizeof(double) * nt);
     double *vth = (double *)malloc(sizeof(double) * (nt + 1));
     or_flows(nt, prm, vph, vth);
@@ -737,6 +742,7 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
     for (int j = 0; j < nt; ++j) has_flow |= vph[j] != 0.0;
     for (int f = 0; f <= nt; ++f) has_flow |= vth[f] != 0.0;
     double cfl = or_cfl_dt(nt, np, vph, vth, adv_time);
+    if (strang) cfl *= 2.0;
     double len = t_end - t0;
     double el = 0.0;
     long steps = 0, stages = 0;
@@ -751,8 +757,14 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
             dt = rem;
             final = 1;
         }
-        if (has_flow) or_adv_step(nt, np, B, vph, vth, dt, adv_scheme, adv_time, eps_mode);
-        stages += or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
+        if (strang) {
+            if (has_flow) or_adv_step(nt, np, B, vph, vth, 0.5 * dt, adv_scheme, adv_time, eps_mode);
+            stages += or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
+            if (has_flow) or_adv_step(nt, np, B, vph, vth, 0.5 * dt, adv_scheme, adv_time, eps_mode);
+        } else {
+            if (has_flow) or_adv_step(nt, np, B, vph, vth, dt, adv_scheme, adv_time, eps_mode);
+            stages += or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
+        }
         el = final ? len : el + dt;
         last = dt;
         ++steps;

@@ -15,6 +15,7 @@ import scipy.linalg as sla
 import scipy.special as sps
 
 import oracle
+import synth
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.txt")
 
@@ -515,3 +516,43 @@ def test_meridional_divergence_converges():
     assert e_max[-1] < 1e-3
     assert order(e_max, ns)[-1] > 0.9, e_max
     assert order(e_l1, ns)[-1] > 0.9, e_l1
+
+
+def test_strang_splitting_is_second_order():
+    """Eq. num_opsplit_strang vs eq. num_opsplit_nostrang on a linear problem
+    (upwind advection, diffusion) whose exact solution is the matrix
+    exponential of the summed operators: with fixed steps, the plain split
+    converges at first order and the Strang split at second order; with the
+    CFL-limited step, the Strang step is twice as long."""
+    import scipy.linalg as sl
+    nt, np_ = 12, 24
+    r = synth.Realization(nu_km2_s=2000.0, **synth.dr_mf(om2=-40.0, om4=-30.0, amp_mf=300.0))
+    vph, vth = oracle.flows(nt, r.flow)
+    nu = r.nu_km2_s * oracle.units()[1]
+    n = nt * np_
+    MA, MD = np.zeros((n, n)), np.zeros((n, n))
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        MA[:, i] = oracle.adv_operator(e.reshape(nt, np_), vph, vth, oracle.UPWIND).ravel()
+        MD[:, i] = oracle.diff_operator(e.reshape(nt, np_), nu).ravel()
+    B0 = np.random.default_rng(1).standard_normal((nt, np_))
+    T = 4.0
+    exact = (sl.expm(T * (MD - MA)) @ B0.ravel()).reshape(nt, np_)
+    order = {}
+    for strang in (0, 1):
+        errs = []
+        for N in (16, 32, 64):
+            B, _ = oracle.advance(B0, r.flow, r.nu_km2_s, 0.0, T, adv_scheme=oracle.UPWIND, dt_max=T / N,
+                                  strang=strang)
+            errs.append(np.linalg.norm(B - exact) / np.linalg.norm(exact))
+        order[strang] = np.log2(errs[-2] / errs[-1])
+    assert 0.9 < order[0] < 1.2, order
+    assert 1.8 < order[1] < 2.3, order
+    # CFL-limited steps: the Strang step (two half advections) is twice as long
+    cfl = oracle.cfl_dt(nt, np_, vph, vth, oracle.SSPRK43)
+    T2 = 40.0
+    _, s0 = oracle.advance(B0, r.flow, r.nu_km2_s, 0.0, T2, adv_scheme=oracle.UPWIND)
+    _, s1 = oracle.advance(B0, r.flow, r.nu_km2_s, 0.0, T2, adv_scheme=oracle.UPWIND, strang=1)
+    assert s0["steps"] == int(np.ceil(T2 / (0.9 * cfl) - 1e-9))
+    assert s1["steps"] == int(np.ceil(T2 / (2 * 0.9 * cfl) - 1e-9))
