@@ -15,8 +15,9 @@
  *   - data assimilation (eq. data_assim, eq. data_assim_f, with the optional
  *     flux balance of eqs. data_assim_deltab / fluxbal),
  *   - FP64 analysis reductions (Sec. "Analysis").
- * Steps are operator split without Strang splitting (eq.
- * num_opsplit_nostrang); assimilation happens at the end of an advance.
+ * Steps are operator split without (eq. num_opsplit_nostrang, the default)
+ * or with Strang splitting (eq. num_opsplit_strang); assimilation happens at
+ * the end of an advance.
  *
  * Grid: uniform cell-centred finite-volume grid of the unit sphere, nt rows
  * in colatitude (theta_j = (j+1/2) pi/nt) and np periodic columns in
@@ -99,7 +100,11 @@ typedef struct {
     int32_t diag_every_call; /* 1 (default) = refresh diagnostics after advance/assimilate */
     int32_t sts_tile;     /* -1 (default) = autotune; >= 0 forces a blocked tile shape
                              (index into the library's table; see sft_tile_info)      */
-    int32_t reserved[6];
+    int32_t strang;       /* 0 (default) = eq. num_opsplit_nostrang; 1 = Strang splitting
+                             (eq. num_opsplit_strang): advection over dt/2, diffusion
+                             over dt, advection over dt/2, with the CFL limit of the
+                             step doubled                                               */
+    int32_t reserved[5];
 } sft_options;
 
 /* Per-realization parameters (Sec. "Multiple Realizations"). */
@@ -176,7 +181,9 @@ sft_status sft_get_states(sft_ctx* ctx, int32_t grid_id, void* br_out, int32_t d
  * landing exactly on t_end (Sec. "Time steps": each realization takes steps
  * dt = min(t_end - t, cfl_safety * flow CFL limit, dt_max); a step that would
  * leave less than 1e-10 h is stretched to t_end).  Each step applies
- * advection then diffusion (eq. num_opsplit_nostrang).  Stream-ordered; does
+ * advection then diffusion (eq. num_opsplit_nostrang), or with opt.strang
+ * half an advection, the diffusion and the other half (eq.
+ * num_opsplit_strang, CFL limit doubled).  Stream-ordered; does
  * not wait for the GPU.  Errors: SFT_ERR_ARG (t_end < t), SFT_ERR_STATE (no
  * realizations), SFT_ERR_HIP. */
 sft_status sft_advance(sft_ctx* ctx, double t_end_hours);

@@ -32,7 +32,7 @@ class sft_options(ctypes.Structure):
                 ("cfl_safety", ctypes.c_double), ("dt_max", ctypes.c_double),
                 ("ptl_dt", ctypes.c_double), ("use_graphs", ctypes.c_int32),
                 ("sts_fuse", ctypes.c_int32), ("diag_every_call", ctypes.c_int32),
-                ("sts_tile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("sts_tile", ctypes.c_int32), ("strang", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class sft_params(ctypes.Structure):

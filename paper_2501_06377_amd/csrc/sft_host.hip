@@ -390,20 +390,25 @@ sft_status build_plan(sft_ctx* c, GridClass* g, double len, Plan** out)
     p->dt_last.assign(g->R, 0.0);
     std::vector<std::vector<double>> seq(g->R);
     size_t max_steps = 0;
+    // Strang splitting: each advection advance is half a step, so the CFL
+    // limit of the step doubles
+    const bool strang = o.strang != 0;
     for (int r = 0; r < g->R; ++r) {
-        step_sequence(len, o.cfl_safety * g->cfl[r], o.dt_max, seq[r]);
+        step_sequence(len, (strang ? 2.0 : 1.0) * o.cfl_safety * g->cfl[r], o.dt_max, seq[r]);
         max_steps = std::max(max_steps, seq[r].size());
     }
     std::vector<Entry> ents;
     std::vector<StageCoef> coefs;
     std::vector<StageCoef> tmp;
     const int adv_nst = o.adv_time == SFT_SSPRK43 ? 4 : (o.adv_time == SFT_SSPRK33 ? 3 : 1);
-    for (size_t i = 0; i < max_steps; ++i) {
-        // advection phase
+    const double adv_frac = strang ? 0.5 : 1.0;
+    // one advection advance of adv_frac * dt for every realization with flow
+    // that takes step i (FP64 forward Euler: copy the result back to B)
+    auto advection_phase = [&](size_t i) {
         Phase pa{0, (int)ents.size(), 0, 0, {}};
         for (int r = 0; r < g->R; ++r) {
             if (i >= seq[r].size() || !g->has_flow[r]) continue;
-            Entry e{r, 0, 0, 0, seq[r][i]};
+            Entry e{r, 0, 0, 0, adv_frac * seq[r][i]};
             ents.push_back(e);
             p->adv_stages[r] += adv_nst;
         }
@@ -415,6 +420,10 @@ sft_status build_plan(sft_ctx* c, GridClass* g, double len, Plan** out)
                 p->phases.push_back(pc);
             }
         }
+    };
+    for (size_t i = 0; i < max_steps; ++i) {
+        // advection (eq. num_opsplit_nostrang), or its first half (eq. num_opsplit_strang)
+        advection_phase(i);
         // diffusion calls (several when the PTL hook splits the step)
         int ncall_max = 0;
         std::vector<int> ncall(g->R, 0);
@@ -470,6 +479,20 @@ sft_status build_plan(sft_ctx* c, GridClass* g, double len, Plan** out)
             }
             pcl.n_ent = (int)ents.size() - pcl.ent_off;
             if (pcl.n_ent) p->phases.push_back(pcl);
+        }
+        if (strang) {
+            // second half advection after the diffusion; in the mixed path its
+            // increment is folded into B by a close phase
+            advection_phase(i);
+            if (mixed) {
+                Phase pcl{5, (int)ents.size(), 0, 0, {}};
+                for (int r = 0; r < g->R; ++r) {
+                    if (i >= seq[r].size() || !g->has_flow[r]) continue;
+                    ents.push_back(Entry{r, 0, 0, 1, adv_frac * seq[r][i]});
+                }
+                pcl.n_ent = (int)ents.size() - pcl.ent_off;
+                if (pcl.n_ent) p->phases.push_back(pcl);
+            }
         }
         for (int r = 0; r < g->R; ++r)
             if (i < seq[r].size()) {
@@ -870,6 +893,7 @@ sft_status sft_create(sft_ctx** ctx, const sft_options* opt, void* hip_stream)
     if (o.precision != SFT_FP64 && o.precision != SFT_FP32_MIXED) return SFT_ERR_ARG;
     if (o.adv_scheme != SFT_WENO3CSH && o.adv_scheme != SFT_UPWIND) return SFT_ERR_ARG;
     if (o.adv_time != SFT_SSPRK43 && o.adv_time != SFT_FE && o.adv_time != SFT_SSPRK33) return SFT_ERR_ARG;
+    if (o.strang != 0 && o.strang != 1) return SFT_ERR_ARG;
     if (o.diff_time != SFT_RKG2 && o.diff_time != SFT_RKL2 && o.diff_time != SFT_DIFF_FE)
         return SFT_ERR_ARG;
     if (!(o.cfl_safety > 0.0 && o.cfl_safety <= 1.0) || o.dt_max < 0.0 || o.ptl_dt < 0.0)

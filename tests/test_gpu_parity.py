@@ -105,7 +105,7 @@ def test_assimilation_f64(kind, balance):
 
 @pytest.mark.parametrize("opts", [
     {"adv_time": 1}, {"adv_time": 2}, {"diff_time": 1}, {"diff_time": 2, "dt_max": 0.05}, {"ptl_dt": 0.3},
-    {"dt_max": 0.7, "cfl_safety": 0.5}])
+    {"dt_max": 0.7, "cfl_safety": 0.5}, {"strang": 1}, {"strang": 1, "adv_time": 1}])
 def test_scheme_options_f64(opts):
     nt, np_ = 24, 48
     say(f"case options {opts}")
@@ -114,7 +114,7 @@ def test_scheme_options_f64(opts):
     sched = [("advance", 1.0), ("advance", 2.3)]
     okw = {"adv_time": opts.get("adv_time", 0), "diff_scheme": opts.get("diff_time", 0),
            "dt_max": opts.get("dt_max", 0.0), "ptl_dt": opts.get("ptl_dt", 0.0),
-           "safety": opts.get("cfl_safety", 0.9)}
+           "safety": opts.get("cfl_safety", 0.9), "strang": opts.get("strang", 0)}
     ref, _ = oracle_run(B0, reals, sched, okw)
     got, _ = gpu_run(B0, reals, sched, **opts)
     e = rel_l2(got, ref)
@@ -122,10 +122,10 @@ def test_scheme_options_f64(opts):
     assert e <= TOL64
 
 
-@pytest.mark.parametrize("adv_time", [0, 2])
-def test_mixed_precision_matches_oracle(adv_time):
+@pytest.mark.parametrize("adv_time,strang", [(0, 0), (2, 0), (0, 1)])
+def test_mixed_precision_matches_oracle(adv_time, strang):
     nt, np_ = 64, 128
-    say(f"case fp32 mixed 64x128, 24 h with hourly assimilation, advection scheme {adv_time}")
+    say(f"case fp32 mixed 64x128, 24 h with hourly assimilation, advection scheme {adv_time}, strang {strang}")
     reals = reals_mix(4)
     B0 = np.stack([random_field(nt, np_, 12, 30 + i) for i in range(4)])
     sched = []
@@ -133,8 +133,8 @@ def test_mixed_precision_matches_oracle(adv_time):
         sched.append(("advance", float(h)))
         b0, l0 = synth.observer(h)
         sched.append(("assim", synth.observation(B0[0], h, h), 2, None, b0, l0))
-    ref, _ = oracle_run(B0, reals, sched, {"adv_time": adv_time})
-    got, _ = gpu_run(B0, reals, sched, precision=1, adv_time=adv_time)
+    ref, _ = oracle_run(B0, reals, sched, {"adv_time": adv_time, "strang": strang})
+    got, _ = gpu_run(B0, reals, sched, precision=1, adv_time=adv_time, strang=strang)
     for r in range(4):
         e = rel_l2(got[r], ref[r])
         say(f"  realization {r}: rel-L2 {e:.3e}  max-abs {np.abs(got[r] - ref[r]).max():.3e} G")
@@ -306,3 +306,26 @@ def test_full_size_uneven_batch_first_hour():
         e = rel_l2(got[c][0], ref[0])
         say(f"  class {nt}x{np_}: stages {st[0]['stages']} rel-L2 {e:.3e}")
         assert e <= TOL32
+
+
+def test_strang_step_count_and_counters():
+    """With Strang splitting the CFL-limited step is twice as long (half as
+    many steps and diffusion calls) and each step runs two advection advances;
+    the fields match the oracle's Strang sequence."""
+    nt, np_ = 48, 96
+    say("case strang counters")
+    reals = reals_mix(2)
+    B0 = np.stack([random_field(nt, np_, 6, 110 + i) for i in range(2)])
+    sched = [("advance", 12.0)]
+    plain, e0 = gpu_run(B0, reals, sched)
+    got, e1 = gpu_run(B0, reals, sched, strang=1)
+    ref, st = oracle_run(B0, reals, sched, {"strang": 1})
+    for r in range(2):
+        c0, c1 = e0.counts(r), e1.counts(r)
+        say(f"  realization {r}: steps {c0['steps']} -> {c1['steps']}, adv stages {c0['adv_stages']} -> "
+            f"{c1['adv_stages']}, rel-L2 vs oracle {rel_l2(got[r], ref[r]):.3e}")
+        assert c1["steps"] == st[r]["steps"]
+        assert c1["steps"] <= (c0["steps"] + 1) // 2 + 1
+        assert c1["adv_stages"] == 2 * 4 * c1["steps"]
+        assert rel_l2(got[r], ref[r]) <= TOL64
+
