@@ -30,12 +30,13 @@ __device__ __forceinline__ T L5(const DiffRow<T>& d, T w, T n, T c, T s, T e)
     return v;
 }
 
-// FP64 stage: Y_j = mu Y_{j-1} + nu Y_{j-2} + cy0 Y0 + cL L + cLY0 L(Y0).
+// FP64 stage: Y_j = nu Y_{j-2} + mu Y_{j-1} + cy0 Y0 + cL L + cLY0 L(Y0)
+// (the Y_{j-2} term first: its register, dead afterwards, takes the result).
 __device__ __forceinline__ double sts_f64(const StageCoef& c, double ym1, double ym2, double y0,
                                           double L, double ly0)
 {
-    double v = c.mu * ym1;
-    v = __builtin_fma(c.nu, ym2, v);
+    double v = c.nu * ym2;
+    v = __builtin_fma(c.mu, ym1, v);
     v = __builtin_fma(c.cy0, y0, v);
     v = __builtin_fma(c.cL, L, v);
     v = __builtin_fma(c.cLY0, ly0, v);

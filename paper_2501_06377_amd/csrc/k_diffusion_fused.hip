@@ -154,25 +154,27 @@ __global__ __launch_bounds__(NT) void diff_fused_kernel(
 // from the lane's own registers; only the two end rows of each strip are
 // exchanged through LDS (double-buffered by stage parity, one barrier per
 // stage).  Row coefficients are wave-uniform (scalar loads).
+// Value of lane l - 1 (west) / l + 1 (east) of the wave, 0 past its ends
+// (bound_ctrl: a lane whose source is out of range reads zero).
 __device__ __forceinline__ double lane_west(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double lane_east(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ float lane_west(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float lane_east(float v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xF, 0xF, true));
 }
 
 template <bool MIXED, int K, int RPT, int NW, int CPL>
@@ -205,8 +207,8 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     const bool has_in2 = in2 != nullptr;
     const DiffRow<T>* dr = drow + (size_t)e.r * nt;
 
-    // ya / yb alternate as (current, previous); rows beyond the poles stay
-    // zero (they only meet the pole rows' zero coefficient)
+    // ya / yb alternate as (current, previous); rows beyond the poles start
+    // at zero
     T ya[RPT][CPL], yb[RPT][CPL], lyr[RPT][CPL];
     double y0r[MIXED ? 1 : RPT][MIXED ? 1 : CPL];
 #pragma unroll
@@ -251,21 +253,23 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
             north[c] = w > 0 ? xch[q][1][w - 1][lane * CPL + c] : T(0);
             south[c] = w < NW - 1 ? xch[q][0][w + 1][lane * CPL + c] : T(0);
         }
+        // Rows beyond a pole (only in strips that reach it) are updated too,
+        // with the pole row's coefficients: they start at zero, stay finite,
+        // are never written out, and the pole row meets them only through its
+        // zero pole-face coefficient.  No per-row branch, so the row
+        // coefficients (wave-uniform scalar loads) can be issued early.
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const int j = jw + m;
+            const DiffRow<T> d = dr[min(max(jw + m, 0), nt - 1)];
             const T wl = lane_west(cur[m][CPL - 1]), el = lane_east(cur[m][0]);
-            if (j >= 0 && j < nt) {
-                const DiffRow<T> d = dr[j];
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    const T wv = c > 0 ? cur[m][c - 1] : wl;
-                    const T ev = c < CPL - 1 ? cur[m][c + 1] : el;
-                    const T L = L5<T>(d, wv, m > 0 ? cur[m - 1][c] : north[c], cur[m][c],
-                                      m < RPT - 1 ? cur[m + 1][c] : south[c], ev);
-                    if constexpr (MIXED) prv[m][c] = sts_mixed(cf, cur[m][c], prv[m][c], h2, L, lyr[m][c]);
-                    else prv[m][c] = sts_f64(cf, cur[m][c], prv[m][c], y0r[m][c], L, lyr[m][c]);
-                }
+            for (int c = 0; c < CPL; ++c) {
+                const T wv = c > 0 ? cur[m][c - 1] : wl;
+                const T ev = c < CPL - 1 ? cur[m][c + 1] : el;
+                const T L = L5<T>(d, wv, m > 0 ? cur[m - 1][c] : north[c], cur[m][c],
+                                  m < RPT - 1 ? cur[m + 1][c] : south[c], ev);
+                if constexpr (MIXED) prv[m][c] = sts_mixed(cf, cur[m][c], prv[m][c], h2, L, lyr[m][c]);
+                else prv[m][c] = sts_f64(cf, cur[m][c], prv[m][c], y0r[m][c], L, lyr[m][c]);
             }
         }
     };
