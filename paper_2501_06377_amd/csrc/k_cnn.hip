@@ -93,150 +93,68 @@ __global__ void cnn_features_kernel(const TB* __restrict__ Bin, const float* __r
     }
 }
 
-// ------------------------------------------------------ MFMA convolution
-// MODE 0 (hidden layer):  out[b][j][k][co] = relu(bias[co] + sum_tap sum_ci
-//                         w[tap][co][ci] x[b][pad(j+dy-1, k+dx-1)][ci]), bf16, 64 channels.
-// MODE 1 (data gradient): G[q][k][ci] = sum_tap sum_co w[tap][ci][co]
-//                         g[b][q-dy+1][k-dx+1][co] for padded rows q in [-1, H]
-//                         (computed as a forward correlation with the
-//                         tap-reversed weights of the wd layout)
-//                         (g zero outside [0, H)); interior rows 1..H-2,
-//                         written as bf16 masked by act > 0.
-// MODE 3 (data gradient, pole rows): G of rows -1, 0 (blockIdx.y = 0) and
-//                         H-1, H (blockIdx.y = 1) as FP32 to the edge buffer
-//                         [b][4][W][64], for edge_fold_kernel.
-// Weight layout: w[tap][n][k] with the GEMM's K index (input channel) contiguous;
-// NTN = number of 32-wide output tiles.
-constexpr int CTY = 8, CTX = 32;      // output tile: 8 rows x 32 columns, 2 waves
-
-template <int CIN, int MODE, int NTN>
-__global__ __launch_bounds__(128) void conv_mfma_kernel(const uint16_t* __restrict__ x,
+// --------------------------------------------- pole rows of the data gradient
+// Data gradient of the pole rows and their across-pole ghost rows (padded
+// rows -1, 0 for blockIdx.y = 0; H-1, H for blockIdx.y = 1) as FP32 into the
+// edge buffer [b][4][W][64], for edge_fold_kernel: the same correlation as
+// conv_persist_kernel's MODE 1 (tap-reversed weights w[tap][ci][co], gradient
+// zero outside rows [0, H)).  One wave computes 2 rows x 32 columns x 64
+// outputs on the matrix cores.
+template <int CIN>
+__global__ __launch_bounds__(64) void pole_dgrad_kernel(const uint16_t* __restrict__ g,
                                                         const uint16_t* __restrict__ w,
-                                                        const float* __restrict__ bias,
-                                                        void* __restrict__ out, int H, int W,
-                                                        const uint16_t* __restrict__ act,
-                                                        float* __restrict__ edge)
+                                                        float* __restrict__ edge, int H, int W)
 {
-    constexpr int CP = CIN + 8;                 // padded channel stride in LDS
-    constexpr int TR = CTY + 2, TC = CTX + 2;   // staged tile with a one-cell halo
-    constexpr int NCH = CIN / 16;               // K chunks per tap
-    constexpr int NOUT = NTN * 32;
-    // the input tile; MODE 0/1 reuse it for the bf16 output tile (channel
-    // stride CTS), written back as 16-byte vectors
-    constexpr int CTS = 64 + 8;
-    constexpr int TILE_E = TR * TC * CP, OUT_E = MODE == 3 ? 0 : CTY * CTX * CTS;
-    constexpr bool DGRAD = MODE == 1 || MODE == 3;
-    __shared__ __attribute__((aligned(16))) uint16_t tile[TILE_E > OUT_E ? TILE_E : OUT_E];
-
-    const int b = blockIdx.z;
-    const int k0 = blockIdx.x * CTX;
-    // first output row of the tile
-    const int r0 = MODE == 1 ? 1 + blockIdx.y * CTY : MODE == 3 ? (blockIdx.y == 0 ? -1 : H - 1)
-                                                                : blockIdx.y * CTY;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const size_t plane = (size_t)H * W;
-    const uint16_t* xb = x + (size_t)b * plane * CIN;
-
-    // stage rows r0-1 .. r0+CTY, columns k0-1 .. k0+CTX (16-byte chunks)
-    constexpr int VPP = CIN / 8;                 // 16-byte vectors per pixel
-    for (int v = tid; v < TR * TC * VPP; v += 128) {
+    constexpr int CP = CIN + 8, TR = 4, TC = 34, NCH = CIN / 16, VPP = CIN / 8;
+    __shared__ __attribute__((aligned(16))) uint16_t tile[TR * TC * CP];
+    const int b = blockIdx.z, k0 = blockIdx.x * 32;
+    const int r0 = blockIdx.y == 0 ? -1 : H - 1;   // first of the two output rows
+    const int lane = threadIdx.x, col = lane & 31, kh = lane >> 5;
+    const uint16_t* gb = g + (size_t)b * H * W * CIN;
+    for (int v = lane; v < TR * TC * VPP; v += 64) {
         const int pix = v / VPP, cv = v - (v / VPP) * VPP;
         const int tr = pix / TC, tc = pix - (pix / TC) * TC;
-        const int j = r0 - 1 + tr, k = k0 - 1 + tc;
+        const int j = r0 - 1 + tr;
         uint4 val = make_uint4(0, 0, 0, 0);
-        if (!DGRAD) {
-            int sj, sk;
-            if (sphere_src(j, k, H, W, sj, sk))
-                val = *(const uint4*)(xb + ((size_t)sj * W + sk) * CIN + cv * 8);
-        } else {
-            if (j >= 0 && j < H) val = *(const uint4*)(xb + ((size_t)j * W + wrapk(k, W)) * CIN + cv * 8);
-        }
-        *(uint4*)(tile + (tr * TC + tc) * CP + cv * 8) = val;
+        if (j >= 0 && j < H) val = *(const uint4*)(gb + ((size_t)j * W + wrapk(k0 - 1 + tc, W)) * CIN + cv * 8);
+        *(uint4*)(tile + pix * CP + cv * 8) = val;
     }
     __syncthreads();
-
-    f32x16 acc[4][NTN];
+    f32x16 acc[2][2];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < NTN; ++n)
+        for (int n = 0; n < 2; ++n)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[m][n][r] = 0.f;
-
-    const int col = lane & 31, kh = lane >> 5;
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap - (tap / 3) * 3;
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
             const int kb = ch * 16 + kh * 8;
-            bf16x8 bfr[NTN];
+            bf16x8 bfr[2];
 #pragma unroll
-            for (int n = 0; n < NTN; ++n)
-                bfr[n] = *(const bf16x8*)(w + ((size_t)tap * NOUT + n * 32 + col) * CIN + kb);
+            for (int n = 0; n < 2; ++n) bfr[n] = *(const bf16x8*)(w + ((size_t)tap * 64 + n * 32 + col) * CIN + kb);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int tr = wv * 4 + m + dy;
-                const bf16x8 a = *(const bf16x8*)(tile + (tr * TC + col + dx) * CP + kb);
+            for (int m = 0; m < 2; ++m) {
+                const bf16x8 a = *(const bf16x8*)(tile + ((m + dy) * TC + col + dx) * CP + kb);
 #pragma unroll
-                for (int n = 0; n < NTN; ++n)
+                for (int n = 0; n < 2; ++n)
                     acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bfr[n], acc[m][n], 0, 0, 0);
             }
         }
     }
-
-    // epilogue: C row = pixel column within the tile row, C column = channel
-    if (MODE == 3) {
-        // rows r0, r0 + 1 (wave 0, m = 0, 1) -> edge rows 0, 1 or 2, 3
-        if (wv != 0) return;
+    // C register r: pixel column 8(r/4) + 4 kh + r%4, channel n * 32 + col
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            const int er = (blockIdx.y == 0 ? 0 : 2) + m;
+    for (int m = 0; m < 2; ++m) {
+        const int er = (blockIdx.y == 0 ? 0 : 2) + m;
 #pragma unroll
-            for (int n = 0; n < NTN; ++n)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int k = k0 + 8 * (r >> 2) + 4 * kh + (r & 3);
-                    if (k < W) edge[(((size_t)b * 4 + er) * W + k) * 64 + n * 32 + col] = acc[m][n][r];
-                }
-        }
-        return;
-    }
-    __syncthreads();   // every wave is done reading the input tile
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int rl = wv * 4 + m, row = r0 + rl;
-#pragma unroll
-        for (int n = 0; n < NTN; ++n) {
-            const int c = n * 32 + col;
-            const float bv = MODE == 1 ? 0.f : bias[c];
+        for (int n = 0; n < 2; ++n)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int px = 8 * (r >> 2) + 4 * kh + (r & 3);
-                float v = acc[m][n][r] + bv;
-                if (MODE == 0) v = v > 0.f ? v : 0.f;
-                tile[(rl * CTX + px) * CTS + c] = f2bf(v);
+                const int k = k0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                if (k < W) edge[(((size_t)b * 4 + er) * W + k) * 64 + n * 32 + col] = acc[m][n][r];
             }
-        }
-    }
-    __syncthreads();
-    // MODE 0: rows < H; MODE 1: interior rows 1..H-2, masked by the ReLU of
-    // the layer input (act > 0)
-    for (int v = tid; v < CTY * CTX * 8; v += 128) {
-        const int cv = v & 7, pix = v >> 3;
-        const int rl = pix / CTX, px = pix - (pix / CTX) * CTX;
-        const int row = r0 + rl, k = k0 + px;
-        if (k >= W || (MODE == 0 ? row >= H : (row < 1 || row > H - 2))) continue;
-        uint4 val = *(const uint4*)(tile + pix * CTS + cv * 8);
-        const size_t o = ((size_t)b * plane + (size_t)row * W + k) * 64 + cv * 8;
-        if (MODE == 1) {
-            const uint4 a = *(const uint4*)(act + o);
-            uint16_t* h = (uint16_t*)&val;
-            const uint16_t* ha = (const uint16_t*)&a;
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (!(bf2f(ha[i]) > 0.f)) h[i] = 0;
-        }
-        *(uint4*)((uint16_t*)out + o) = val;
     }
 }
 
@@ -1010,15 +928,13 @@ void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const
 void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, const uint16_t* act,
                     uint16_t* dx, float* edge, int batch, int H, int W)
 {
-    dim3 ge2((W + CTX - 1) / CTX, 2, batch);
+    dim3 ge2((W + 31) / 32, 2, batch);
     if (cin == 16) {
         launch_persist<16, 1>(st, dz, wd, nullptr, dx, batch, H, W, act);
-        hipLaunchKernelGGL((conv_mfma_kernel<16, 3, 2>), ge2, dim3(128), 0, st, dz, wd, (const float*)nullptr,
-                           (void*)dx, H, W, act, edge);
+        hipLaunchKernelGGL(pole_dgrad_kernel<16>, ge2, dim3(64), 0, st, dz, wd, edge, H, W);
     } else {
         launch_persist<64, 1>(st, dz, wd, nullptr, dx, batch, H, W, act);
-        hipLaunchKernelGGL((conv_mfma_kernel<64, 3, 2>), ge2, dim3(128), 0, st, dz, wd, (const float*)nullptr,
-                           (void*)dx, H, W, act, edge);
+        hipLaunchKernelGGL(pole_dgrad_kernel<64>, ge2, dim3(64), 0, st, dz, wd, edge, H, W);
     }
     dim3 ge(gblocks((size_t)2 * W * 64, 256, 1024), batch);
     hipLaunchKernelGGL(edge_fold_kernel, ge, dim3(256), 0, st, edge, act, dx, H, W);
