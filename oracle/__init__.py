@@ -58,6 +58,7 @@ def lib():
             "or_cfl_dt": (d, [i, i, P, P, i]),
             "or_line_flux": (None, [i, i, P, P, P, i, d, P]),
             "or_adv_operator": (None, [i, i, P, P, P, i, d, P]),
+            "or_adv_operator_att": (None, [i, i, P, P, P, i, d, P, d, P]),
             "or_adv_step": (None, [i, i, P, P, P, d, i, i, d]),
             "or_diff_coefs": (None, [i, i, d, P, P, P, P]),
             "or_diff_operator": (None, [i, i, d, P, P]),
@@ -125,11 +126,15 @@ def line_flux(B, dx, v, periodic, scheme=WENO3CSH, eps_mode=0.0):
     return F
 
 
-def adv_operator(B, vph, vth, scheme=WENO3CSH, eps_mode=0.0):
+def adv_operator(B, vph, vth, scheme=WENO3CSH, eps_mode=0.0, Batt=None, b0=0.0):
+    """Flux divergence of eq. advection; with b0 > 0 the face velocities are
+    attenuated (eq. flow_attenuation) by the field Batt."""
     B = _f64(B)
     out = np.empty_like(B)
     nt, np_ = B.shape
-    lib().or_adv_operator(nt, np_, _p(B), _p(_f64(vph)), _p(_f64(vth)), scheme, eps_mode, _p(out))
+    att = _p(_f64(Batt)) if Batt is not None else None
+    lib().or_adv_operator_att(nt, np_, _p(B), _p(_f64(vph)), _p(_f64(vth)), scheme, eps_mode, att,
+                              float(b0), _p(out))
     return out
 
 
@@ -211,11 +216,12 @@ def hh(X, Y):
 
 
 def advance(B, prm, nu_km2_s, t0, t_end, adv_scheme=WENO3CSH, adv_time=SSPRK43,
-            diff_scheme=RKG2, safety=0.9, dt_max=0.0, eps_mode=0.0, ptl_dt=0.0, strang=0):
+            diff_scheme=RKG2, safety=0.9, dt_max=0.0, eps_mode=0.0, ptl_dt=0.0, strang=0, att_b0=0.0):
     """Advance one realization from t0 to t_end (hours), operator split with
-    or without Strang splitting.  Returns (B, stats)."""
+    or without Strang splitting, optionally with flow attenuation (att_b0 in
+    gauss).  Returns (B, stats)."""
     B = _f64(B).copy()
-    opts = np.array([adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang],
+    opts = np.array([adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang, att_b0],
                     dtype=np.float64)
     stats = np.zeros(3)
     lib().or_advance(B.shape[0], B.shape[1], _p(B), _p(_f64(prm)), float(nu_km2_s), float(t0),

@@ -269,8 +269,29 @@ void or_line_flux(int n, int periodic, const double *B, const double *dx, const 
 /* Spherical advection divergence (Sec. "Advection spatial schemes"):
  * [div(B v)]_jk = (s_{j+1/2} F^th_{j+1/2} - s_{j-1/2} F^th_{j-1/2}) / (s_j dth)
  *               + (F^ph_{k+1/2} - F^ph_{k-1/2}) / (s_j dph). */
+/* Flow attenuation (eq. flow_attenuation): a face velocity is multiplied by
+ * 1 - tanh(|B|/b0) with |B| read as the mean of |Batt| over the face's two
+ * cells; Batt is the field at the start of the advection advance.  Batt =
+ * NULL or b0 <= 0: no attenuation. */
+static double att_factor(const double *Batt, double b0, size_t i0, size_t i1)
+{
+    if (!Batt || !(b0 > 0.0)) return 1.0;
+    return 1.0 - tanh(0.5 * (fabs(Batt[i0]) + fabs(Batt[i1])) / b0);
+}
+
+void or_adv_operator_att(int nt, int np, const double *B, const double *vph_row,
+                         const double *vth_face, int scheme, double eps_mode, const double *Batt,
+                         double b0, double *out);
+
 void or_adv_operator(int nt, int np, const double *B, const double *vph_row,
                      const double *vth_face, int scheme, double eps_mode, double *out)
+{
+    or_adv_operator_att(nt, np, B, vph_row, vth_face, scheme, eps_mode, NULL, 0.0, out);
+}
+
+void or_adv_operator_att(int nt, int np, const double *B, const double *vph_row,
+                         const double *vth_face, int scheme, double eps_mode, const double *Batt,
+                         double b0, double *out)
 {
     or_geom g;
     geom_init(&g, nt, np);
@@ -285,7 +306,11 @@ void or_adv_operator(int nt, int np, const double *B, const double *vph_row,
         #pragma omp for schedule(static)
         for (int j = 0; j < nt; ++j) {
             for (int k = 0; k < np; ++k) dxp[k] = g.dph;
-            for (int k = 0; k <= np; ++k) vp[k] = vph_row[j];
+            /* face k lies between cells k-1 and k (periodic) */
+            for (int k = 0; k < np; ++k)
+                vp[k] = vph_row[j] * att_factor(Batt, b0, (size_t)j * np + (k + np - 1) % np,
+                                                (size_t)j * np + k);
+            vp[np] = vp[0];
             or_line_flux(np, 1, B + (size_t)j * np, dxp, vp, scheme, eps_mode,
                          Fph + (size_t)j * (np + 1));
         }
@@ -298,18 +323,25 @@ void or_adv_operator(int nt, int np, const double *B, const double *vph_row,
         double *dxt = (double *)malloc(sizeof(double) * nt);
         double *col = (double *)malloc(sizeof(double) * nt);
         double *Fc = (double *)malloc(sizeof(double) * (nt + 1));
+        double *vt = (double *)malloc(sizeof(double) * (nt + 1));
         #pragma omp for schedule(static)
         for (int k = 0; k < np; ++k) {
             for (int j = 0; j < nt; ++j) {
                 dxt[j] = g.dth;
                 col[j] = B[(size_t)j * np + k];
             }
-            or_line_flux(nt, 0, col, dxt, vth_face, scheme, eps_mode, Fc);
+            /* face f lies between rows f-1 and f; the pole faces carry v = 0 */
+            vt[0] = vth_face[0];
+            vt[nt] = vth_face[nt];
+            for (int f = 1; f < nt; ++f)
+                vt[f] = vth_face[f] * att_factor(Batt, b0, (size_t)(f - 1) * np + k, (size_t)f * np + k);
+            or_line_flux(nt, 0, col, dxt, vt, scheme, eps_mode, Fc);
             for (int f = 0; f <= nt; ++f) Fth[(size_t)f * np + k] = Fc[f];
         }
         free(dxt);
         free(col);
         free(Fc);
+        free(vt);
     }
     #pragma omp parallel for schedule(static)
     for (int j = 0; j < nt; ++j) {
@@ -335,8 +367,19 @@ void or_adv_operator(int nt, int np, const double *B, const double *vph_row,
  *   f1 = fn - dt A(fn); f2 = 3/4 fn + 1/4 f1 - dt/4 A(f1);
  *   fn+1 = 1/3 fn + 2/3 f2 - 2/3 dt A(f2)
  * A is the divergence operator above; B is updated in place. */
+void or_adv_step_att(int nt, int np, double *B, const double *vph_row, const double *vth_face,
+                     double dt, int scheme, int time_scheme, double eps_mode, double b0);
+
 void or_adv_step(int nt, int np, double *B, const double *vph_row, const double *vth_face,
                  double dt, int scheme, int time_scheme, double eps_mode)
+{
+    or_adv_step_att(nt, np, B, vph_row, vth_face, dt, scheme, time_scheme, eps_mode, 0.0);
+}
+
+/* The same with flow attenuation b0 (gauss, <= 0: none), its factors taken
+ * from the field at the start of the advance (fn) for every stage. */
+void or_adv_step_att(int nt, int np, double *B, const double *vph_row, const double *vth_face,
+                     double dt, int scheme, int time_scheme, double eps_mode, double b0)
 {
     size_t n = (size_t)nt * np;
     double *fn = (double *)malloc(sizeof(double) * n);
@@ -345,25 +388,25 @@ void or_adv_step(int nt, int np, double *B, const double *vph_row, const double 
     double *op = (double *)malloc(sizeof(double) * n);
     memcpy(fn, B, sizeof(double) * n);
     if (time_scheme == 1) {
-        or_adv_operator(nt, np, fn, vph_row, vth_face, scheme, eps_mode, op);
+        or_adv_operator_att(nt, np, fn, vph_row, vth_face, scheme, eps_mode, fn, b0, op);
         for (size_t i = 0; i < n; ++i) B[i] = fn[i] - dt * op[i];
     } else if (time_scheme == 2) {
-        or_adv_operator(nt, np, fn, vph_row, vth_face, scheme, eps_mode, op);
+        or_adv_operator_att(nt, np, fn, vph_row, vth_face, scheme, eps_mode, fn, b0, op);
         for (size_t i = 0; i < n; ++i) fa[i] = fn[i] - dt * op[i];
-        or_adv_operator(nt, np, fa, vph_row, vth_face, scheme, eps_mode, op);
+        or_adv_operator_att(nt, np, fa, vph_row, vth_face, scheme, eps_mode, fn, b0, op);
         for (size_t i = 0; i < n; ++i) fb[i] = 0.75 * fn[i] + 0.25 * fa[i] - 0.25 * dt * op[i];
-        or_adv_operator(nt, np, fb, vph_row, vth_face, scheme, eps_mode, op);
+        or_adv_operator_att(nt, np, fb, vph_row, vth_face, scheme, eps_mode, fn, b0, op);
         for (size_t i = 0; i < n; ++i)
             B[i] = (1.0 / 3.0) * fn[i] + (2.0 / 3.0) * fb[i] - (2.0 / 3.0) * dt * op[i];
     } else {
-        or_adv_operator(nt, np, fn, vph_row, vth_face, scheme, eps_mode, op);
+        or_adv_operator_att(nt, np, fn, vph_row, vth_face, scheme, eps_mode, fn, b0, op);
         for (size_t i = 0; i < n; ++i) fa[i] = fn[i] - 0.5 * dt * op[i];          /* f1 */
-        or_adv_operator(nt, np, fa, vph_row, vth_face, scheme, eps_mode, op);
+        or_adv_operator_att(nt, np, fa, vph_row, vth_face, scheme, eps_mode, fn, b0, op);
         for (size_t i = 0; i < n; ++i) fb[i] = fa[i] - 0.5 * dt * op[i];          /* f2 */
-        or_adv_operator(nt, np, fb, vph_row, vth_face, scheme, eps_mode, op);
+        or_adv_operator_att(nt, np, fb, vph_row, vth_face, scheme, eps_mode, fn, b0, op);
         for (size_t i = 0; i < n; ++i)
             fa[i] = (2.0 / 3.0) * fn[i] + (1.0 / 3.0) * fb[i] - (1.0 / 6.0) * dt * op[i]; /* f3 */
-        or_adv_operator(nt, np, fa, vph_row, vth_face, scheme, eps_mode, op);
+        or_adv_operator_att(nt, np, fa, vph_row, vth_face, scheme, eps_mode, fn, b0, op);
         for (size_t i = 0; i < n; ++i) B[i] = fa[i] - 0.5 * dt * op[i];
     }
     free(fn);
@@ -724,7 +767,9 @@ double or_hh(long n, const double *X, const double *Y)
  * t_end - t0), and a step that would leave less than 1e-10 h before t_end is
  * stretched to land on t_end.
  * prm = {d0, d2, d4, m1, m3, m5} (m/s), nu_km2_s scalar diffusivity.
- * opts = {adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang}
+ * opts = {adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang, att_b0}
+ * (att_b0: flow attenuation saturation, gauss, 0 = none; the CFL limit is
+ * that of the unattenuated flow, an upper bound of the attenuated speeds)
  * stats = {steps, diffusion stages, last dt}.  Returns 0. */
 int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, double t0,
                double t_end, const double *opts, double *stats)
@@ -735,6 +780,7 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
     int adv_scheme = (int)opts[0], adv_time = (int)opts[1], dscheme = (int)opts[2];
     double safety = opts[3], dt_max = opts[4], eps_mode = opts[5], ptl_dt = opts[6];
     int strang = (int)opts[7];
+    double att_b0 = opts[8];
     double *vph = (double *)malloc(sizeof(double) * nt);
     double *vth = (double *)malloc(sizeof(double) * (nt + 1));
     or_flows(nt, prm, vph, vth);
@@ -758,11 +804,11 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
             final = 1;
         }
         if (strang) {
-            if (has_flow) or_adv_step(nt, np, B, vph, vth, 0.5 * dt, adv_scheme, adv_time, eps_mode);
+            if (has_flow) or_adv_step_att(nt, np, B, vph, vth, 0.5 * dt, adv_scheme, adv_time, eps_mode, att_b0);
             stages += or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
-            if (has_flow) or_adv_step(nt, np, B, vph, vth, 0.5 * dt, adv_scheme, adv_time, eps_mode);
+            if (has_flow) or_adv_step_att(nt, np, B, vph, vth, 0.5 * dt, adv_scheme, adv_time, eps_mode, att_b0);
         } else {
-            if (has_flow) or_adv_step(nt, np, B, vph, vth, dt, adv_scheme, adv_time, eps_mode);
+            if (has_flow) or_adv_step_att(nt, np, B, vph, vth, dt, adv_scheme, adv_time, eps_mode, att_b0);
             stages += or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
         }
         el = final ? len : el + dt;

@@ -556,3 +556,83 @@ def test_strang_splitting_is_second_order():
     _, s1 = oracle.advance(B0, r.flow, r.nu_km2_s, 0.0, T2, adv_scheme=oracle.UPWIND, strang=1)
     assert s0["steps"] == int(np.ceil(T2 / (0.9 * cfl) - 1e-9))
     assert s1["steps"] == int(np.ceil(T2 / (2 * 0.9 * cfl) - 1e-9))
+
+
+def _att_setup(nt=24, np_=48, seed=3):
+    r = synth.Realization(nu_km2_s=0.0, **synth.dr_mf(amp_mf=15.0))
+    vph, vth = oracle.flows(nt, r.flow)
+    g = np.random.default_rng(seed)
+    return r, vph, vth, g
+
+
+def test_flow_attenuation_limits_and_scaling():
+    """Eq. flow_attenuation: b0 -> infinity leaves the operator unchanged; a
+    field of uniform magnitude c attenuates every face by 1 - tanh(c/b0), so
+    with upwind fluxes (linear in the velocity) the operator scales by it."""
+    nt, np_ = 24, 48
+    r, vph, vth, g = _att_setup(nt, np_)
+    B = g.standard_normal((nt, np_)) * 100
+    for scheme in (oracle.WENO3CSH, oracle.UPWIND):
+        A0 = oracle.adv_operator(B, vph, vth, scheme)
+        assert np.array_equal(oracle.adv_operator(B, vph, vth, scheme, Batt=B, b0=1e300), A0)
+    S = np.sign(g.standard_normal((nt, np_))) * 300.0
+    f = 1.0 - math.tanh(300.0 / 500.0)
+    Au = oracle.adv_operator(S, vph, vth, oracle.UPWIND)
+    Aa = oracle.adv_operator(S, vph, vth, oracle.UPWIND, Batt=S, b0=500.0)
+    assert np.abs(Aa - f * Au).max() <= 1e-14 * np.abs(Au).max()
+
+
+def test_flow_attenuation_face_reading():
+    """Each face velocity is scaled by 1 - tanh(mean(|B| of its two cells)/b0)
+    of the attenuating field (not of the advected one): with a meridional
+    flow only, and an attenuating field whose magnitude is constant along
+    rows, the operator equals the plain one with the theta-face velocities
+    scaled row by row; with a zonal flow only and a magnitude constant along
+    columns, the phi sweep equals the line flux with the phi-face velocities
+    scaled column by column."""
+    nt, np_, b0 = 24, 48, 400.0
+    r, vph, vth, g = _att_setup(nt, np_)
+    B = g.standard_normal((nt, np_)) * 100
+    mag_r = g.uniform(0, 900, nt)
+    Batt = mag_r[:, None] * np.sign(g.standard_normal((nt, np_)))
+    ft = np.ones(nt + 1)
+    ft[1:nt] = 1.0 - np.tanh(0.5 * (mag_r[:-1] + mag_r[1:]) / b0)
+    zero = np.zeros(nt)
+    for scheme in (oracle.WENO3CSH, oracle.UPWIND):
+        got = oracle.adv_operator(B, zero, vth, scheme, Batt=Batt, b0=b0)
+        ref = oracle.adv_operator(B, zero, vth * ft, scheme)
+        assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+    mag_c = g.uniform(0, 900, np_)
+    Batt = mag_c[None, :] * np.sign(g.standard_normal((nt, np_)))
+    fp = 1.0 - np.tanh(0.5 * (np.roll(mag_c, 1) + mag_c) / b0)   # face k between cells k-1, k
+    dph = 2 * math.pi / np_
+    th = (np.arange(nt) + 0.5) * math.pi / nt
+    got = oracle.adv_operator(B, vph, np.zeros(nt + 1), oracle.WENO3CSH, Batt=Batt, b0=b0)
+    for j in (0, 5, nt // 2):
+        v = np.append(vph[j] * fp, vph[j] * fp[0])
+        F = oracle.line_flux(B[j], np.full(np_, dph), v, True)
+        ref = (F[1:np_ + 1] - F[:np_]) / (math.sin(th[j]) * dph)
+        assert np.abs(got[j] - ref).max() <= 1e-13 * np.abs(ref).max(), j
+
+
+def test_flow_attenuation_conserves_and_holds_factors_over_a_step():
+    """The attenuated flux divergence still conserves sum(B w); one advection
+    advance takes its attenuation from the field at its start for every
+    stage (SSPRK(4,3) composed from the operator with that fixed field)."""
+    nt, np_, b0 = 24, 48, 250.0
+    r, vph, vth, g = _att_setup(nt, np_)
+    B0 = g.standard_normal((nt, np_)) * 200
+    w = oracle.cell_weights(nt, np_)
+    A = oracle.adv_operator(B0, vph, vth, Batt=B0, b0=b0)
+    assert abs((A * w[:, None]).sum()) <= 1e-13 * (np.abs(A) * w[:, None]).sum()
+    dt = 0.3
+    op = lambda f: oracle.adv_operator(f, vph, vth, Batt=B0, b0=b0)
+    f1 = B0 - 0.5 * dt * op(B0)
+    f2 = f1 - 0.5 * dt * op(f1)
+    f3 = (2.0 / 3.0) * B0 + (1.0 / 3.0) * f2 - (1.0 / 6.0) * dt * op(f2)
+    ref = f3 - 0.5 * dt * op(f3)
+    got, st = oracle.advance(B0, r.flow, 0.0, 0.0, dt, att_b0=b0)
+    assert st["steps"] == 1
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    plain, _ = oracle.advance(B0, r.flow, 0.0, 0.0, dt)
+    assert np.abs(got - plain).max() > 1e-6 * np.abs(B0).max()
