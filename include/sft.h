@@ -116,7 +116,13 @@ typedef struct {
     double mu_lim;        /* mu limit of eq. data_assim_f                                */
     double lat_lim_deg;   /* latitude limit of eq. data_assim_f, degrees                 */
     int32_t flux_balance; /* 1 = balance the assimilation increment (eq. fluxbal)        */
-    int32_t reserved[3];
+    int32_t reserved;
+    double att_b0;        /* flow attenuation (eq. flow_attenuation): saturation field B0
+                             in gauss, 0 = no attenuation, else > 0.  Each advection
+                             advance scales every face velocity by 1 - tanh(m / B0), m
+                             the mean of |B| over the face's two cells of the field at
+                             the start of the advance; the step length keeps the
+                             unattenuated flow's CFL limit (the factor is <= 1)        */
 } sft_params;
 
 /* Analysis record of one realization (Sec. "Analysis"); FP64 reductions. */

@@ -34,6 +34,7 @@ def make_params(r) -> _abi.sft_params:
     for name in ("nu_km2_s", "d0", "d2", "d4", "m1", "m3", "m5", "alpha_mu", "mu_lim", "lat_lim_deg"):
         setattr(p, name, float(getattr(r, name)))
     p.flux_balance = int(getattr(r, "flux_balance", 0))
+    p.att_b0 = float(getattr(r, "att_b0", 0.0))
     return p
 
 

@@ -13,7 +13,16 @@
 // The FP64 kernel evaluates the paper's formulas in their printed order with
 // no FMA contraction (the library is built with -ffp-contract=off), so its
 // results match a plain serial evaluation of the same formulas to the bit.
+//
+// Flow attenuation (eq. flow_attenuation): the face velocities of one
+// advection advance are scaled by 1 - tanh(m/B0), m the mean of |B| over the
+// face's two cells of the field at the start of the advance.  att_faces_kernel
+// writes them once per advance (one phi-face and one theta-face value per
+// cell); the ATT variant of the stage kernel stages them with a 4-face halo
+// and builds the per-cell LLF split factors in LDS (alpha = max |v| over the
+// faces i-2 .. i+3 of each cell, as for the static flow).
 #include "sft_internal.h"
+#include "adv_att.h"
 
 namespace sft {
 
@@ -68,19 +77,40 @@ __device__ __forceinline__ T upwind_face(T v, T bl, T br)
     return v * T(0.5) * ((one - uw) * br + (one + uw) * bl);
 }
 
+// LDS of the attenuated-flow variant: phi faces k0-4 .. k0+ATX+4 of the tile
+// rows, theta faces j0-4 .. j0+ATY+4 of the tile columns, and per-cell LLF
+// split factors of the staged cells.
+constexpr int AVW = ATX + 9;
+constexpr int AVH = ATY + 9;
+template <typename T, bool ATT>
+struct AttLds {
+};
+template <typename T>
+struct AttLds<T, true> {
+    T vp[ATY][AVW];
+    T vt[AVH][ATX];
+    T cpM[ATY][AW], cpP[ATY][AW];
+    T ctM[AHT][ATX], ctP[AHT][ATX];
+};
+
 // MIXED = false: T = double, stage values read from fin (FP64 fields).
 // MIXED = true : T = float, stage value = (float)(fn + din) (din absent at
 //                stage 0), increments written to dout.
-template <typename T, bool MIXED>
+// ATT = true   : face velocities from vphf / vthf ([R][nt][np] each: phi face
+//                k of row j lies between cells k-1 and k; theta face j lies
+//                between rows j-1 and j) instead of the per-row constants.
+template <typename T, bool MIXED, bool ATT>
 __global__ __launch_bounds__(256) void adv_stage_kernel(
     const Entry* __restrict__ ents, int stage, int time_scheme, int upwind,
     const AdvRow<T>* __restrict__ rows, Geom<T> g, WenoConst<T> wth, WenoConst<T> wph,
-    const double* __restrict__ fn, const T* __restrict__ fin, T* __restrict__ fout, int nt, int np)
+    const double* __restrict__ fn, const T* __restrict__ fin, T* __restrict__ fout,
+    const T* __restrict__ vphf, const T* __restrict__ vthf, int nt, int np)
 {
     __shared__ T tile[AHT][AW];
     __shared__ T fph[ATY][ATX + 1];
     __shared__ T fth[ATY + 1][ATX];
     __shared__ T cthM[AHT], cthP[AHT];
+    __shared__ AttLds<T, ATT> al;
 
     const Entry e = ents[blockIdx.z];
     const size_t base = (size_t)e.r * nt * np;
@@ -105,7 +135,25 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
         }
         tile[tj][tk] = v;
     }
-    if (tid < AHT) {
+    if constexpr (ATT) {
+        for (int idx = tid; idx < ATY * AVW; idx += 256) {
+            const int tj = idx / AVW, q = idx - (idx / AVW) * AVW;
+            const int j = j0 + tj;
+            T v = T(0);
+            if (j < nt) v = vphf[base + (size_t)j * np + wrap_col(k0 - 4 + q, np)];
+            al.vp[tj][q] = v;
+        }
+        // faces outside 0..nt take no part in any window; the pole faces
+        // keep the static flow's value
+        for (int idx = tid; idx < AVH * ATX; idx += 256) {
+            const int q = idx / ATX, c = idx - (idx / ATX) * ATX;
+            const int f = j0 - 4 + q;
+            T v = T(0);
+            if (f == 0 || f == nt) v = rw[f].vth;
+            else if (f > 0 && f < nt) v = vthf[base + (size_t)f * np + wrap_col(k0 + c, np)];
+            al.vt[q][c] = v;
+        }
+    } else if (tid < AHT) {
         const int j = j0 + tid - AH;
         T m = T(0), p = T(0);
         if (j >= 0 && j < nt) {
@@ -116,6 +164,27 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
         cthP[tid] = p;
     }
     __syncthreads();
+    if constexpr (ATT) {
+        // staged cell k0+tk-2 of tile row tj: faces (cell-2) .. (cell+3) are
+        // vp[tj][tk .. tk+5]; its own left and right faces are tk+2, tk+3
+        for (int idx = tid; idx < ATY * AW; idx += 256) {
+            const int tj = idx / AW, tk = idx - (idx / AW) * AW;
+            const T* v = &al.vp[tj][tk];
+            T a = T(0);
+            for (int m = 0; m < 6; ++m) a = fmax(a, fabs(v[m]));
+            al.cpM[tj][tk] = T(0.5) * (v[2] + a);
+            al.cpP[tj][tk] = T(0.5) * (v[3] - a);
+        }
+        // staged row j0+tr-2: faces (row-2) .. (row+3) are vt[tr .. tr+5]
+        for (int idx = tid; idx < AHT * ATX; idx += 256) {
+            const int tr = idx / ATX, c = idx - (idx / ATX) * ATX;
+            T a = T(0);
+            for (int m = 0; m < 6; ++m) a = fmax(a, fabs(al.vt[tr + m][c]));
+            al.ctM[tr][c] = T(0.5) * (al.vt[tr + 2][c] + a);
+            al.ctP[tr][c] = T(0.5) * (al.vt[tr + 3][c] - a);
+        }
+        __syncthreads();
+    }
 
     // phi faces: face fk of tile row tj lies between cells k0+fk-1 and k0+fk
     for (int idx = tid; idx < ATY * (ATX + 1); idx += 256) {
@@ -123,13 +192,24 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
         const int j = j0 + tj;
         T F = T(0);
         if (j < nt) {
-            const AdvRow<T> a = rw[j];
             const T* t = &tile[tj + AH][fk];   // t[0..3] = cells fk-2 .. fk+1
-            if (upwind) {
-                F = upwind_face(a.vph, t[1], t[2]);
+            if constexpr (ATT) {
+                const T* m = &al.cpM[tj][fk];
+                const T* p = &al.cpP[tj][fk];
+                if (upwind) {
+                    F = upwind_face(al.vp[tj][fk + 4], t[1], t[2]);
+                } else {
+                    F = weno_face(t[0] * m[0], t[1] * m[1], t[2] * m[2], t[1] * p[1], t[2] * p[2],
+                                  t[3] * p[3], wph);
+                }
             } else {
-                F = weno_face(t[0] * a.cphM, t[1] * a.cphM, t[2] * a.cphM, t[1] * a.cphP,
-                              t[2] * a.cphP, t[3] * a.cphP, wph);
+                const AdvRow<T> a = rw[j];
+                if (upwind) {
+                    F = upwind_face(a.vph, t[1], t[2]);
+                } else {
+                    F = weno_face(t[0] * a.cphM, t[1] * a.cphM, t[2] * a.cphM, t[1] * a.cphP,
+                                  t[2] * a.cphP, t[3] * a.cphP, wph);
+                }
             }
         }
         fph[tj][fk] = F;
@@ -143,11 +223,18 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
             const int tc = c + AH;
             const T bm1 = tile[fj + 1][tc], b0 = tile[fj + 2][tc];   // rows f-1, f
             if (upwind || f == 1 || f == nt - 1) {
-                F = upwind_face(rw[f].vth, bm1, b0);
+                if constexpr (ATT) F = upwind_face(al.vt[fj + 4][c], bm1, b0);
+                else F = upwind_face(rw[f].vth, bm1, b0);
             } else {
                 const T bm2 = tile[fj][tc], bp1 = tile[fj + 3][tc];  // rows f-2, f+1
-                F = weno_face(bm2 * cthM[fj], bm1 * cthM[fj + 1], b0 * cthM[fj + 2],
-                              bm1 * cthP[fj + 1], b0 * cthP[fj + 2], bp1 * cthP[fj + 3], wth);
+                if constexpr (ATT) {
+                    F = weno_face(bm2 * al.ctM[fj][c], bm1 * al.ctM[fj + 1][c], b0 * al.ctM[fj + 2][c],
+                                  bm1 * al.ctP[fj + 1][c], b0 * al.ctP[fj + 2][c],
+                                  bp1 * al.ctP[fj + 3][c], wth);
+                } else {
+                    F = weno_face(bm2 * cthM[fj], bm1 * cthM[fj + 1], b0 * cthM[fj + 2],
+                                  bm1 * cthP[fj + 1], b0 * cthP[fj + 2], bp1 * cthP[fj + 3], wth);
+                }
             }
         }
         fth[fj][c] = F;
@@ -215,14 +302,44 @@ __global__ void copy_entries_kernel(const Entry* __restrict__ ents, const double
         dst[base + i] = src[base + i];
 }
 
+// Attenuated face velocities of one advance for every entry: one thread per
+// cell writes the phi face on its left and the theta face above it (row 0:
+// the pole face, unattenuated).  Realizations with B0 <= 0 get factor 1.
+template <typename T>
+__global__ __launch_bounds__(256) void att_faces_kernel(const Entry* __restrict__ ents,
+                                                        const AdvRow<double>* __restrict__ rows,
+                                                        const double* __restrict__ b0s,
+                                                        const double* __restrict__ fn,
+                                                        T* __restrict__ vphf, T* __restrict__ vthf,
+                                                        int nt, int np)
+{
+    const Entry e = ents[blockIdx.z];
+    const int j = blockIdx.y;
+    const double b0 = b0s[e.r];
+    const AdvRow<double> a = rows[(size_t)e.r * (nt + 1) + j];
+    const size_t row = ((size_t)e.r * nt + j) * np;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < np; k += gridDim.x * 256) {
+        const double b = fabs(fn[row + k]);
+        double fp = 1.0, ft = 1.0;
+        if (b0 > 0.0) {
+            const double bl = fabs(fn[row + (k == 0 ? np - 1 : k - 1)]);
+            fp = 1.0 - tanh(0.5 * (bl + b) / b0);
+            if (j > 0) ft = 1.0 - tanh(0.5 * (fabs(fn[row - np + k]) + b) / b0);
+        }
+        vphf[row + k] = (T)(a.vph * fp);
+        vthf[row + k] = (T)(a.vth * ft);
+    }
+}
+
 void launch_adv_stage_f64(hipStream_t st, const Entry* ents, int n_ent, int stage, int time_scheme,
                           int upwind, const AdvRow<double>* rows, Geom<double> g,
                           WenoConst<double> wth, WenoConst<double> wph, const double* fn,
                           const double* fin, double* fout, int nt, int np)
 {
     dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
-    hipLaunchKernelGGL((adv_stage_kernel<double, false>), grid, dim3(256), 0, st, ents, stage,
-                       time_scheme, upwind, rows, g, wth, wph, fn, fin, fout, nt, np);
+    hipLaunchKernelGGL((adv_stage_kernel<double, false, false>), grid, dim3(256), 0, st, ents, stage,
+                       time_scheme, upwind, rows, g, wth, wph, fn, fin, fout, nullptr, nullptr, nt,
+                       np);
 }
 
 void launch_adv_stage_mixed(hipStream_t st, const Entry* ents, int n_ent, int stage, int time_scheme,
@@ -231,8 +348,48 @@ void launch_adv_stage_mixed(hipStream_t st, const Entry* ents, int n_ent, int st
                             const float* din, float* dout, int nt, int np)
 {
     dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
-    hipLaunchKernelGGL((adv_stage_kernel<float, true>), grid, dim3(256), 0, st, ents, stage,
-                       time_scheme, upwind, rows, g, wth, wph, fn, din, dout, nt, np);
+    hipLaunchKernelGGL((adv_stage_kernel<float, true, false>), grid, dim3(256), 0, st, ents, stage,
+                       time_scheme, upwind, rows, g, wth, wph, fn, din, dout, nullptr, nullptr, nt, np);
+}
+
+void launch_att_faces_f64(hipStream_t st, const Entry* ents, int n_ent, const AdvRow<double>* rows,
+                          const double* b0s, const double* fn, double* vphf, double* vthf, int nt,
+                          int np)
+{
+    dim3 grid((np + 255) / 256, nt, n_ent);
+    hipLaunchKernelGGL((att_faces_kernel<double>), grid, dim3(256), 0, st, ents, rows, b0s, fn, vphf,
+                       vthf, nt, np);
+}
+
+void launch_att_faces_f32(hipStream_t st, const Entry* ents, int n_ent, const AdvRow<double>* rows,
+                          const double* b0s, const double* fn, float* vphf, float* vthf, int nt,
+                          int np)
+{
+    dim3 grid((np + 255) / 256, nt, n_ent);
+    hipLaunchKernelGGL((att_faces_kernel<float>), grid, dim3(256), 0, st, ents, rows, b0s, fn, vphf,
+                       vthf, nt, np);
+}
+
+void launch_adv_stage_att_f64(hipStream_t st, const Entry* ents, int n_ent, int stage,
+                              int time_scheme, int upwind, const AdvRow<double>* rows,
+                              Geom<double> g, WenoConst<double> wth, WenoConst<double> wph,
+                              const double* fn, const double* fin, double* fout, const double* vphf,
+                              const double* vthf, int nt, int np)
+{
+    dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
+    hipLaunchKernelGGL((adv_stage_kernel<double, false, true>), grid, dim3(256), 0, st, ents, stage,
+                       time_scheme, upwind, rows, g, wth, wph, fn, fin, fout, vphf, vthf, nt, np);
+}
+
+void launch_adv_stage_att_mixed(hipStream_t st, const Entry* ents, int n_ent, int stage,
+                                int time_scheme, int upwind, const AdvRow<float>* rows,
+                                Geom<float> g, WenoConst<float> wth, WenoConst<float> wph,
+                                double* fn, const float* din, float* dout, const float* vphf,
+                                const float* vthf, int nt, int np)
+{
+    dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
+    hipLaunchKernelGGL((adv_stage_kernel<float, true, true>), grid, dim3(256), 0, st, ents, stage,
+                       time_scheme, upwind, rows, g, wth, wph, fn, din, dout, vphf, vthf, nt, np);
 }
 
 void launch_copy_f64(hipStream_t st, const Entry* ents, int n_ent, const double* src, double* dst,

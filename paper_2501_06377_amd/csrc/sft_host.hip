@@ -15,6 +15,7 @@
 
 #include "../../include/sft.h"
 #include "sft_internal.h"
+#include "adv_att.h"
 
 namespace sft {
 sft_status net_predict(sft_net* net, hipStream_t st, int batch, const double* Bin, const float* feats,
@@ -68,6 +69,12 @@ struct GridClass {
     double* dB = nullptr;   // FP64 assimilation increment (mixed precision only)
     AdvRow<double>* adv64 = nullptr;
     AdvRow<float>* adv32 = nullptr;
+    // flow attenuation (allocated when some realization has B0 > 0): B0 per
+    // realization and the face velocities of the advance in progress
+    bool att = false;
+    double* att_b0 = nullptr;
+    double* vf64[2] = {nullptr, nullptr};
+    float* vf32[2] = {nullptr, nullptr};
     DiffRow<double>* dr64 = nullptr;
     DiffRow<float>* dr32 = nullptr;
     double *sf64 = nullptr, *denth64 = nullptr, *denph64 = nullptr;
@@ -739,11 +746,23 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p)
                 const double* fin[4] = {B, W1, W2, W1};
                 double* fout[4] = {W1, W2, ts == 2 ? B : W1, B};
                 const int nst = ts == 1 ? 1 : (ts == 2 ? 3 : 4);
+                if (g->att) {
+                    // attenuated face velocities from the state at the start of the advance
+                    tbeg(c);
+                    launch_att_faces_f64(st, E, ph.n_ent, g->adv64, g->att_b0, B, g->vf64[0], g->vf64[1],
+                                         nt, np);
+                    tend(c, SFT_KFAM_OTHER, 24.0 * cells * ne);
+                }
                 for (int k = 0; k < nst; ++k) {
                     tbeg(c);
-                    launch_adv_stage_f64(st, E, ph.n_ent, k, ts, upwind, g->adv64, geo, wt, wp, B, fin[k],
-                                         fout[k], nt, np);
-                    tend(c, SFT_KFAM_ADV_STAGE, (k == 2 || (ts == 2 && k == 1) ? 24.0 : 16.0) * cells * ne);
+                    if (g->att)
+                        launch_adv_stage_att_f64(st, E, ph.n_ent, k, ts, upwind, g->adv64, geo, wt, wp, B,
+                                                 fin[k], fout[k], g->vf64[0], g->vf64[1], nt, np);
+                    else
+                        launch_adv_stage_f64(st, E, ph.n_ent, k, ts, upwind, g->adv64, geo, wt, wp, B,
+                                             fin[k], fout[k], nt, np);
+                    tend(c, SFT_KFAM_ADV_STAGE,
+                         ((k == 2 || (ts == 2 && k == 1) ? 24.0 : 16.0) + (g->att ? 16.0 : 0.0)) * cells * ne);
                 }
             } else {
                 Geom<float> geo{g->sf32, g->denth32, g->denph32};
@@ -752,11 +771,21 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p)
                 const float* din[4] = {nullptr, A1, A2, A1};
                 float* dout[4] = {ts == 1 ? A0 : A1, A2, ts == 2 ? A0 : A1, A0};
                 const int nst = ts == 1 ? 1 : (ts == 2 ? 3 : 4);
+                if (g->att) {
+                    tbeg(c);
+                    launch_att_faces_f32(st, E, ph.n_ent, g->adv64, g->att_b0, g->B, g->vf32[0], g->vf32[1],
+                                         nt, np);
+                    tend(c, SFT_KFAM_OTHER, 16.0 * cells * ne);
+                }
                 for (int k = 0; k < nst; ++k) {
                     tbeg(c);
-                    launch_adv_stage_mixed(st, E, ph.n_ent, k, ts, upwind, g->adv32, geo, wt, wp, g->B,
-                                           din[k], dout[k], nt, np);
-                    tend(c, SFT_KFAM_ADV_STAGE, (k == 0 ? 12.0 : 16.0) * cells * ne);
+                    if (g->att)
+                        launch_adv_stage_att_mixed(st, E, ph.n_ent, k, ts, upwind, g->adv32, geo, wt, wp, g->B,
+                                                   din[k], dout[k], g->vf32[0], g->vf32[1], nt, np);
+                    else
+                        launch_adv_stage_mixed(st, E, ph.n_ent, k, ts, upwind, g->adv32, geo, wt, wp, g->B,
+                                               din[k], dout[k], nt, np);
+                    tend(c, SFT_KFAM_ADV_STAGE, ((k == 0 ? 12.0 : 16.0) + (g->att ? 8.0 : 0.0)) * cells * ne);
                 }
             }
         } else if (ph.kind == 1) {
@@ -1020,6 +1049,19 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
     TRY(upload(c, g->dr32, d32));
     TRY(dalloc(c, &g->ar, ar.size()));
     TRY(upload(c, g->ar, ar));
+    std::vector<double> b0(R);
+    for (int r = 0; r < R; ++r) {
+        b0[r] = g->prm[r].att_b0;
+        g->att |= b0[r] > 0.0;
+    }
+    if (g->att) {
+        TRY(dalloc(c, &g->att_b0, b0.size()));
+        TRY(upload(c, g->att_b0, b0));
+        for (int i = 0; i < 2; ++i) {
+            if (!mixed) TRY(dalloc(c, &g->vf64[i], n));
+            else TRY(dalloc(c, &g->vf32[i], n));
+        }
+    }
     // geometry
     const double dth = M_PI / nt, dph = 2.0 * M_PI / np;
     std::vector<double> sf(nt + 1), dthv(nt), dphv(nt), st(nt), ct(nt), lat(nt), w(nt), sp(np), cp(np);
@@ -1099,7 +1141,7 @@ sft_status sft_add_realizations(sft_ctx* c, int32_t grid_id, int32_t n, const sf
     for (int i = 0; i < n; ++i) {
         const sft_params& p = prm[i];
         if (!(p.nu_km2_s >= 0.0) || !std::isfinite(p.nu_km2_s) || !(p.alpha_mu > 0.0) ||
-            !(p.lat_lim_deg >= 0.0))
+            !(p.lat_lim_deg >= 0.0) || !(p.att_b0 >= 0.0) || !std::isfinite(p.att_b0))
             return fail(c, SFT_ERR_ARG, "realization %d: invalid parameters", i);
     }
     // ids are consecutive over grid classes in creation order

@@ -134,6 +134,7 @@ class Realization:
     mu_lim: float = 0.0
     lat_lim_deg: float = 90.0
     flux_balance: int = 0
+    att_b0: float = 0.0        # flow attenuation saturation field, gauss (0 = off)
 
     @property
     def flow(self):

@@ -48,7 +48,8 @@ def oracle_run(B0, reals, schedule, opts=None):
         st = {"steps": 0, "stages": 0}
         for ev in schedule:
             if ev[0] == "advance":
-                B, s = oracle.advance(B, real.flow, real.nu_km2_s, t, ev[1], **opts)
+                B, s = oracle.advance(B, real.flow, real.nu_km2_s, t, ev[1],
+                                      att_b0=getattr(real, "att_b0", 0.0), **opts)
                 st["steps"] += s["steps"]
                 st["stages"] += s["stages"]
                 t = ev[1]
