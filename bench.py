@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", action="store_true", help="replay captured graphs (no per-kernel timing)")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--att-b0", type=float, default=0.0,
+                    help="flow attenuation saturation field B0 in gauss for every realization (0: off)")
     ap.add_argument("--sts-tile", type=int, default=-1, help="blocked STS shape (-1: autotuned)")
     ap.add_argument("--surr-batch", type=int, default=64)
     ap.add_argument("--surrogate-only", action="store_true",
@@ -89,7 +91,8 @@ def cpu_baseline(nt, np_, reals, f0, obs_first, max_seconds):
             b0, l0 = synth.observer(float(h))
             mu = oracle.mu_disk(nt, np_, math.radians(b0), math.radians(l0))
         for r, real in enumerate(reals):
-            B[r], st = oracle.advance(B[r], real.flow, real.nu_km2_s, float(h - 1), float(h))
+            B[r], st = oracle.advance(B[r], real.flow, real.nu_km2_s, float(h - 1), float(h),
+                                      att_b0=real.att_b0)
             n = st["stages"] + 4 * st["steps"]
             if obs_first is not None:
                 F = oracle.weight_from_mu(mu, real.alpha_mu, real.mu_lim, math.radians(real.lat_lim_deg))
@@ -238,6 +241,11 @@ def main():
         return
     w = {"ensemble": synth.config2, "precision": synth.config3, "batching": synth.config4}[args.workload]()
     K = args.steps if args.steps is not None else (655 if args.workload == "ensemble" else 24)
+    if args.att_b0 > 0.0:
+        for _, _, reals in w.classes:
+            for r in reals:
+                r.att_b0 = args.att_b0
+        w.name += f"+attenuation-B0-{args.att_b0:g}G"
     W = args.warmup
     prec = 0 if w.precision == "f64" else 1
     graphs = args.graphs or args.workload == "batching"
@@ -305,7 +313,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": w.precision, "data": "synthetic",
         "config": {"workload": w.name, "grid": [f"{nt}x{np_}x{len(r)}" for nt, np_, r in w.classes],
                    "realizations": R,
-                   "step": "1 h interval: advection + RKG2 diffusion" +
+                   "step": "1 h interval: advection" +
+                           (f" (flow attenuation, B0 = {args.att_b0:g} G)" if args.att_b0 > 0.0 else "") +
+                           " + RKG2 diffusion" +
                            (" + mu^4 assimilation" if assim else "") + " + diagnostics",
                    "simulated_hours": K, "graphs": bool(graphs), "sts_tiles": tiles},
         "sim_days_per_s": K / 24.0 / wall,
