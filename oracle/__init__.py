@@ -50,6 +50,7 @@ def lib():
         L = ctypes.CDLL(_LIB)
         P = ctypes.POINTER(ctypes.c_double)
         i, d, l = ctypes.c_int, ctypes.c_double, ctypes.c_long
+        U32P = ctypes.POINTER(ctypes.c_uint32)
         sig = {
             "or_units": (None, [P, P]),
             "or_num_threads": (i, []),
@@ -72,6 +73,10 @@ def lib():
             "or_diagnostics": (None, [i, i, P, P]),
             "or_hh": (d, [l, P, P]),
             "or_advance": (i, [i, i, P, P, d, d, d, P, P]),
+            "or_philox4x32_10": (None, [U32P, U32P, U32P]),
+            "or_rfe_normals": (None, [l, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64, P]),
+            "or_rfe_map": (None, [i, i, i, d, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64, i, P]),
+            "or_rfe_interval": (ctypes.c_int64, [d, d]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -216,14 +221,48 @@ def hh(X, Y):
 
 
 def advance(B, prm, nu_km2_s, t0, t_end, adv_scheme=WENO3CSH, adv_time=SSPRK43,
-            diff_scheme=RKG2, safety=0.9, dt_max=0.0, eps_mode=0.0, ptl_dt=0.0, strang=0, att_b0=0.0):
+            diff_scheme=RKG2, safety=0.9, dt_max=0.0, eps_mode=0.0, ptl_dt=0.0, strang=0, att_b0=0.0,
+            rfe_model=0, rfe_phi_hr=0.0, rfe_tau=0.0, rfe_seed=0, rfe_id=0):
     """Advance one realization from t0 to t_end (hours), operator split with
     or without Strang splitting, optionally with flow attenuation (att_b0 in
-    gauss).  Returns (B, stats)."""
+    gauss) and random flux emergence (model 1 / 2, phi_hr Mx per hour,
+    lifetime rfe_tau hours, 0 = infinite; maps keyed by seed and id).
+    Returns (B, stats)."""
     B = _f64(B).copy()
-    opts = np.array([adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang, att_b0],
-                    dtype=np.float64)
+    opts = np.array([adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang, att_b0,
+                     rfe_model, rfe_phi_hr, rfe_tau, rfe_seed, rfe_id], dtype=np.float64)
     stats = np.zeros(3)
     lib().or_advance(B.shape[0], B.shape[1], _p(B), _p(_f64(prm)), float(nu_km2_s), float(t0),
                      float(t_end), _p(opts), _p(stats))
     return B, {"steps": int(stats[0]), "stages": int(stats[1]), "dt_last": float(stats[2])}
+
+
+# ------------------------------------------------- random flux emergence
+def philox4x32_10(ctr, key):
+    """Philox4x32 with 10 rounds (Salmon et al., SC 2011): 4 counter words,
+    2 key words -> 4 output words."""
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().or_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def rfe_normals(n, seed, rid, k):
+    """Standard normal draws of source map k (n even)."""
+    Y = np.empty(n)
+    lib().or_rfe_normals(int(n), int(seed) & 0xFFFFFFFF, int(rid) & 0xFFFFFFFF, int(k), _p(Y))
+    return Y
+
+
+def rfe_map(nt, np_, model, phi_hr, seed, rid, k, balance=True):
+    """Source map k (gauss per hour) of eq. rfe_m1 (model 1) or rfe_m2 (model 2),
+    flux balanced as eq. fluxbal when balance is true."""
+    S = np.empty((nt, np_))
+    lib().or_rfe_map(nt, np_, int(model), float(phi_hr), int(seed) & 0xFFFFFFFF, int(rid) & 0xFFFFFFFF,
+                     int(k), int(bool(balance)), _p(S))
+    return S
+
+
+def rfe_interval(t, tau):
+    return int(lib().or_rfe_interval(float(t), float(tau)))

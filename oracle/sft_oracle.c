@@ -704,6 +704,140 @@ void or_assimilate(int nt, int np, double *B, const double *data, const double *
     free(w);
 }
 
+/* ---------------------------------------------------- random flux emergence */
+/* Counter-based generator for the random draws of Sec. "Flux emergence": the
+ * Philox4x32 generator with 10 rounds (Salmon, Moraes, Dror and Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC 2011), restated from that
+ * publication.  A round multiplies counter words 0 and 2 by two fixed odd
+ * constants; the new words are (high half of the second product) ^ word 1 ^
+ * key 0, its low half, (high half of the first product) ^ word 3 ^ key 1 and
+ * its low half.  The key grows by two Weyl constants before every round but
+ * the first. */
+void or_philox4x32_10(const uint32_t *ctr, const uint32_t *key, uint32_t *out)
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * x0;
+        uint64_t p1 = (uint64_t)M1 * x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0;
+        x1 = y1;
+        x2 = y2;
+        x3 = y3;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+/* Standard normal draws Y_i (Sec. "Flux emergence") of source map k of the
+ * realization with key (seed, id): cells 2i and 2i+1 take the Box-Muller
+ * pair (Box and Muller 1958) r cos(2 pi u2), r sin(2 pi u2), r =
+ * sqrt(-2 ln u1), of the generator's output at counter (i, k low word,
+ * k high word, 0); u1 comes from output words (0, 1) and u2 from (2, 3),
+ * each as (top 53 bits of the 64-bit word + 1/2) / 2^53, inside (0, 1).
+ * n must be even. */
+void or_rfe_normals(long n, uint32_t seed, uint32_t id, int64_t k, double *Y)
+{
+    const uint32_t key[2] = {seed, id};
+    #pragma omp parallel for schedule(static)
+    for (long i = 0; i < n / 2; ++i) {
+        uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(uint64_t)k, (uint32_t)((uint64_t)k >> 32), 0u};
+        uint32_t x[4];
+        or_philox4x32_10(ctr, key, x);
+        uint64_t a = ((uint64_t)x[0] << 32) | x[1];
+        uint64_t b = ((uint64_t)x[2] << 32) | x[3];
+        double u1 = ((double)(a >> 11) + 0.5) * 0x1p-53;
+        double u2 = ((double)(b >> 11) + 0.5) * 0x1p-53;
+        double r = sqrt(-2.0 * log(u1));
+        double t = 2.0 * M_PI * u2;
+        Y[2 * i] = r * cos(t);
+        Y[2 * i + 1] = r * sin(t);
+    }
+}
+
+/* One random-flux source map S in gauss per hour (Sec. "Flux emergence"),
+ * phi_hr the total unsigned flux per hour in Mx:
+ *   model 1 (eq. rfe_m1): S_jk = phi_hr / (dA_j N_cells) sqrt(pi/2) Y_jk,
+ *                         dA_j = R^2 sin(theta_j) dth dph, N_cells = nt np;
+ *   model 2 (eq. rfe_m2): S = phi_hr / (4 pi R^2) sqrt(pi/2) Y;
+ * R = 6.96e10 cm (Sec. "Units").  With balance != 0 the map is then flux
+ * balanced as eq. fluxbal: positive values divided by, negative values
+ * multiplied by sqrt(|Phi+ / Phi-|), Phi+- the surface integrals (sums of
+ * S w_j) of the positive and negative parts; no change when either is 0. */
+void or_rfe_map(int nt, int np, int model, double phi_hr, uint32_t seed, uint32_t id, int64_t k,
+                int balance, double *S)
+{
+    const double R = OR_RSUN_M * 100.0;
+    const double dth = M_PI / nt, dph = 2.0 * M_PI / np;
+    const size_t n = (size_t)nt * np;
+    or_rfe_normals((long)n, seed, id, k, S);
+    for (int j = 0; j < nt; ++j) {
+        double c;
+        if (model == 1) {
+            double dA = R * R * sin((j + 0.5) * dth) * dth * dph;
+            c = phi_hr / (dA * (double)n) * sqrt(M_PI / 2.0);
+        } else {
+            c = phi_hr / (4.0 * M_PI * R * R) * sqrt(M_PI / 2.0);
+        }
+        for (int q = 0; q < np; ++q) S[(size_t)j * np + q] = c * S[(size_t)j * np + q];
+    }
+    if (!balance) return;
+    double *w = (double *)malloc(sizeof(double) * nt);
+    or_cell_weights(nt, np, w);
+    double pp = 0.0, pm = 0.0;
+    for (int j = 0; j < nt; ++j) {
+        for (int q = 0; q < np; ++q) {
+            double v = S[(size_t)j * np + q];
+            if (v > 0.0) pp += v * w[j];
+            else if (v < 0.0) pm += v * w[j];
+        }
+    }
+    if (pp != 0.0 && pm != 0.0) {
+        double r = sqrt(fabs(pp / pm));
+        for (size_t i = 0; i < n; ++i) S[i] = S[i] > 0.0 ? S[i] / r : S[i] * r;
+    }
+    free(w);
+}
+
+/* Index k of the source-map interval [k tau, (k+1) tau) holding time t (a
+ * time within 1e-10 h below a boundary counts as on it). */
+int64_t or_rfe_interval(double t, double tau)
+{
+    int64_t k = (int64_t)floor(t / tau);
+    if ((double)(k + 1) * tau - t < 1e-10) k += 1;
+    if (t < (double)k * tau - 1e-10) k -= 1;
+    return k;
+}
+
+/* Source sub-advance of length h from time ta (eqs. num_opsplit_nostrang /
+ * num_opsplit_strang with eq. rfe_s): S(t) = (1 - a(t)) S_k + a(t) S_k+1,
+ * a(t) = (t - k tau) / tau, is linear in t on the interval, so its integral
+ * over [ta, ta + h] is h S(ta + h/2), added to B.  tau <= 0 (infinite
+ * lifetime): S = S_k. */
+static void rfe_apply(size_t n, double *B, const double *Sk, const double *Sk1, int64_t k, double tau,
+                      double ta, double h)
+{
+    if (tau <= 0.0) {
+        for (size_t i = 0; i < n; ++i) B[i] = B[i] + h * Sk[i];
+        return;
+    }
+    double tm = ta + 0.5 * h;
+    double a = (tm - (double)k * tau) / tau;
+    for (size_t i = 0; i < n; ++i) B[i] = B[i] + h * ((1.0 - a) * Sk[i] + a * Sk1[i]);
+}
+
 /* ------------------------------------------------------------ diagnostics */
 /* Sec. "Analysis": out = {Phi+, Phi-, net, h1, h2, D, min, max, min|B|}
  *   Phi+- = sum of B w over B > 0 / B < 0, net = their sum,
@@ -761,15 +895,21 @@ double or_hh(long n, const double *X, const double *Y)
  * without Strang splitting (eq. num_opsplit_nostrang) B* = A(B, dt),
  * B** = D(B*, dt); with Strang splitting (eq. num_opsplit_strang)
  * B* = A(B, dt/2), B** = D(B*, dt), B*** = A(B**, dt/2), and the CFL limit of
- * the step doubles because each advection advance is dt/2.  The source term
- * is absent.  Reading: the time left is measured from the start of the
- * interval (elapsed time is accumulated from zero, the interval length is
- * t_end - t0), and a step that would leave less than 1e-10 h before t_end is
- * stretched to land on t_end.
+ * the step doubles because each advection advance is dt/2.  With random flux
+ * emergence the source sub-advances close the step (B^{n+1} = S(B**, dt)) or,
+ * under Strang splitting, open and close it over dt/2 each; each integrates
+ * the interpolated source of eq. rfe_s exactly.  Reading: the time left is
+ * measured from the start of the segment (elapsed time is accumulated from
+ * zero, the segment length is its end minus its start), and a step that would
+ * leave less than 1e-10 h before the segment's end is stretched to land on it.
  * prm = {d0, d2, d4, m1, m3, m5} (m/s), nu_km2_s scalar diffusivity.
- * opts = {adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang, att_b0}
+ * opts = {adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang, att_b0,
+ *         rfe_model, rfe_phi_hr, rfe_tau, rfe_seed, rfe_id}
  * (att_b0: flow attenuation saturation, gauss, 0 = none; the CFL limit is
- * that of the unattenuated flow, an upper bound of the attenuated speeds)
+ * that of the unattenuated flow, an upper bound of the attenuated speeds;
+ * rfe_model 0 = no source, 1 / 2 = eq. rfe_m1 / rfe_m2 maps of phi_hr Mx per
+ * hour, lifetime rfe_tau hours (<= 0: infinite, one map), maps keyed by
+ * (rfe_seed, rfe_id) and their index k, map k belonging to time k tau).
  * stats = {steps, diffusion stages, last dt}.  Returns 0. */
 int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, double t0,
                double t_end, const double *opts, double *stats)
@@ -781,6 +921,10 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
     double safety = opts[3], dt_max = opts[4], eps_mode = opts[5], ptl_dt = opts[6];
     int strang = (int)opts[7];
     double att_b0 = opts[8];
+    int rfe = (int)opts[9];
+    double rfe_phi = opts[10], tau = opts[11];
+    uint32_t seed = (uint32_t)opts[12], rid = (uint32_t)opts[13];
+    size_t n = (size_t)nt * np;
     double *vph = (double *)malloc(sizeof(double) * nt);
     double *vth = (double *)malloc(sizeof(double) * (nt + 1));
     or_flows(nt, prm, vph, vth);
@@ -789,35 +933,68 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
     for (int f = 0; f <= nt; ++f) has_flow |= vth[f] != 0.0;
     double cfl = or_cfl_dt(nt, np, vph, vth, adv_time);
     if (strang) cfl *= 2.0;
-    double len = t_end - t0;
-    double el = 0.0;
+    /* source maps S_k and S_k+1 of the current interval (Sec. "Flux emergence") */
+    double *Sk = NULL, *Sk1 = NULL;
+    int64_t have = -1;
+    if (rfe) {
+        Sk = (double *)malloc(sizeof(double) * n);
+        Sk1 = (double *)malloc(sizeof(double) * n);
+    }
     long steps = 0, stages = 0;
     double last = 0.0;
-    while (el < len) {
-        double rem = len - el;
-        double dt = rem;
-        if (safety * cfl < dt) dt = safety * cfl;
-        if (dt_max > 0.0 && dt_max < dt) dt = dt_max;
-        int final = 0;
-        if (rem - dt < 1e-10) {
-            dt = rem;
-            final = 1;
+    /* Sec. "Time steps": with random flux emergence of finite lifetime tau,
+     * steps also land on the map times k tau, so the advance splits into
+     * segments at those times; each segment takes the greedy step rule. */
+    double a = t0;
+    for (;;) {
+        double b = t_end;
+        int64_t k = 0;
+        if (rfe && tau > 0.0) {
+            k = or_rfe_interval(a, tau);
+            double nb = (double)(k + 1) * tau;
+            if (nb < t_end - 1e-10) b = nb;
         }
-        if (strang) {
-            if (has_flow) or_adv_step_att(nt, np, B, vph, vth, 0.5 * dt, adv_scheme, adv_time, eps_mode, att_b0);
-            stages += or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
-            if (has_flow) or_adv_step_att(nt, np, B, vph, vth, 0.5 * dt, adv_scheme, adv_time, eps_mode, att_b0);
-        } else {
-            if (has_flow) or_adv_step_att(nt, np, B, vph, vth, dt, adv_scheme, adv_time, eps_mode, att_b0);
-            stages += or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
+        if (rfe && k != have) {
+            or_rfe_map(nt, np, rfe, rfe_phi, seed, rid, k, 1, Sk);
+            if (tau > 0.0) or_rfe_map(nt, np, rfe, rfe_phi, seed, rid, k + 1, 1, Sk1);
+            have = k;
         }
-        el = final ? len : el + dt;
-        last = dt;
-        ++steps;
+        double len = b - a;
+        double el = 0.0;
+        while (el < len) {
+            double rem = len - el;
+            double dt = rem;
+            if (safety * cfl < dt) dt = safety * cfl;
+            if (dt_max > 0.0 && dt_max < dt) dt = dt_max;
+            int final = 0;
+            if (rem - dt < 1e-10) {
+                dt = rem;
+                final = 1;
+            }
+            double ta = a + el;
+            if (strang) {
+                if (rfe) rfe_apply(n, B, Sk, Sk1, k, tau, ta, 0.5 * dt);
+                if (has_flow) or_adv_step_att(nt, np, B, vph, vth, 0.5 * dt, adv_scheme, adv_time, eps_mode, att_b0);
+                stages += or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
+                if (has_flow) or_adv_step_att(nt, np, B, vph, vth, 0.5 * dt, adv_scheme, adv_time, eps_mode, att_b0);
+                if (rfe) rfe_apply(n, B, Sk, Sk1, k, tau, ta + 0.5 * dt, 0.5 * dt);
+            } else {
+                if (has_flow) or_adv_step_att(nt, np, B, vph, vth, dt, adv_scheme, adv_time, eps_mode, att_b0);
+                stages += or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
+                if (rfe) rfe_apply(n, B, Sk, Sk1, k, tau, ta, dt);
+            }
+            el = final ? len : el + dt;
+            last = dt;
+            ++steps;
+        }
+        if (b == t_end) break;
+        a = b;
     }
     stats[0] = (double)steps;
     stats[1] = (double)stages;
     stats[2] = last;
+    free(Sk);
+    free(Sk1);
     free(vph);
     free(vth);
     return 0;
