@@ -104,7 +104,15 @@ typedef struct {
                              (eq. num_opsplit_strang): advection over dt/2, diffusion
                              over dt, advection over dt/2, with the CFL limit of the
                              step doubled                                               */
-    int32_t reserved[5];
+    int32_t rfe_model;    /* random flux emergence (Sec. "Flux emergence"): 0 (default) = none,
+                             1 = eq. rfe_m1 maps (unsigned flux per cell), 2 = eq. rfe_m2
+                             maps (unsigned flux per unit area)                         */
+    uint32_t rfe_seed;    /* key word 0 of every source map's generator; key word 1 is
+                             the realization id                                         */
+    int32_t reserved;
+    double rfe_phi_hr;    /* total unsigned flux per hour of a source map, Mx (> 0 when
+                             rfe_model != 0)                                            */
+    double rfe_lifetime_h;/* time between source maps tau, hours; 0 = infinite (one map) */
 } sft_options;
 
 /* Per-realization parameters (Sec. "Multiple Realizations"). */
@@ -189,7 +197,20 @@ sft_status sft_get_states(sft_ctx* ctx, int32_t grid_id, void* br_out, int32_t d
  * leave less than 1e-10 h is stretched to t_end).  Each step applies
  * advection then diffusion (eq. num_opsplit_nostrang), or with opt.strang
  * half an advection, the diffusion and the other half (eq.
- * num_opsplit_strang, CFL limit doubled).  Stream-ordered; does
+ * num_opsplit_strang, CFL limit doubled).
+ * With opt.rfe_model != 0 (random flux emergence, Sec. "Flux emergence"):
+ * source map k of realization id belongs to time k tau (tau =
+ * opt.rfe_lifetime_h; with tau = 0 only map 0 exists); its standard normal
+ * draws come from the Philox4x32-10 generator (Salmon et al. 2011) at counter
+ * (cell pair index, k low word, k high word, 0) and key (opt.rfe_seed, id) by
+ * the Box-Muller transform, scaled by eq. rfe_m1 or rfe_m2 and flux balanced
+ * (eq. fluxbal), so a map is a pure function of (seed, id, k).  Steps also
+ * land on the map times k tau (the interval is cut there and each piece takes
+ * the rule above); the source S(t) of eq. rfe_s closes every step (B += dt
+ * S(t_mid), the exact integral of the linear interpolant), or opens and
+ * closes it over dt/2 each under Strang splitting.  The maps are FP64 in both
+ * precisions and are regenerated on the device whenever a step ends on a map
+ * time.  Stream-ordered; does
  * not wait for the GPU.  Errors: SFT_ERR_ARG (t_end < t), SFT_ERR_STATE (no
  * realizations), SFT_ERR_HIP. */
 sft_status sft_advance(sft_ctx* ctx, double t_end_hours);
@@ -298,7 +319,8 @@ sft_status sft_surrogate_advance(sft_ctx* ctx, int32_t grid_id, sft_net* net, co
 #define SFT_KFAM_ASSIM 3       /* assimilation passes                               */
 #define SFT_KFAM_DIAG 4        /* analysis reductions                               */
 #define SFT_KFAM_OTHER 5       /* copies and increment closes                       */
-#define SFT_KFAM_COUNT 6
+#define SFT_KFAM_SOURCE 6      /* flux-emergence maps and source sub-advances       */
+#define SFT_KFAM_COUNT 7
 
 /* Turns per-launch event timing on (1) or off (0).  While on, every kernel
  * launch is bracketed by HIP events on the context's stream and HIP graphs are

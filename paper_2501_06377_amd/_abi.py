@@ -22,8 +22,8 @@ SFT_RKG2, SFT_RKL2, SFT_DIFF_FE = 0, 1, 2
 SFT_DTYPE_F64, SFT_DTYPE_F32 = 0, 1
 SFT_WEIGHT_F, SFT_WEIGHT_MU, SFT_WEIGHT_DISK = 0, 1, 2
 SFT_KFAM_STS_STAGE, SFT_KFAM_STS_FIRST, SFT_KFAM_ADV_STAGE = 0, 1, 2
-SFT_KFAM_ASSIM, SFT_KFAM_DIAG, SFT_KFAM_OTHER, SFT_KFAM_COUNT = 3, 4, 5, 6
-KFAM_NAMES = ("sts_stage", "sts_first", "adv_stage", "assim", "diag", "other")
+SFT_KFAM_ASSIM, SFT_KFAM_DIAG, SFT_KFAM_OTHER, SFT_KFAM_SOURCE, SFT_KFAM_COUNT = 3, 4, 5, 6, 7
+KFAM_NAMES = ("sts_stage", "sts_first", "adv_stage", "assim", "diag", "other", "source")
 
 
 class sft_options(ctypes.Structure):
@@ -32,7 +32,9 @@ class sft_options(ctypes.Structure):
                 ("cfl_safety", ctypes.c_double), ("dt_max", ctypes.c_double),
                 ("ptl_dt", ctypes.c_double), ("use_graphs", ctypes.c_int32),
                 ("sts_fuse", ctypes.c_int32), ("diag_every_call", ctypes.c_int32),
-                ("sts_tile", ctypes.c_int32), ("strang", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("sts_tile", ctypes.c_int32), ("strang", ctypes.c_int32),
+                ("rfe_model", ctypes.c_int32), ("rfe_seed", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+                ("rfe_phi_hr", ctypes.c_double), ("rfe_lifetime_h", ctypes.c_double)]
 
 
 class sft_params(ctypes.Structure):

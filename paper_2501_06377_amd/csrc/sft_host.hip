@@ -16,6 +16,7 @@
 #include "../../include/sft.h"
 #include "sft_internal.h"
 #include "adv_att.h"
+#include "rfe.h"
 
 namespace sft {
 sft_status net_predict(sft_net* net, hipStream_t st, int batch, const double* Bin, const float* feats,
@@ -38,7 +39,8 @@ const double KM2_S_TO_RS2_HR = 3600.0 * 1.0e6 / (RSUN_M * RSUN_M);
 struct Phase {
     int kind;        // 0 advection step, 1 diffusion call, 2 copy W1->B (FP64 FE advection),
                      // 3 one-stage diffusion close (mixed), 4 copy W1->B for one-stage
-                     // diffusion (FP64), 5 advection-only close (mixed)
+                     // diffusion (FP64), 5 advection-only close (mixed), 6 source
+                     // sub-advance, 7 next source map
     int ent_off;     // first entry in the plan's entry table
     int n_ent;
     int max_s;
@@ -50,6 +52,8 @@ struct Plan {
     std::vector<Entry> h_ents;
     Entry* d_ents = nullptr;
     StageCoef* d_coefs = nullptr;
+    double* d_alpha = nullptr;   // interpolation weight of each source entry (by coef_off)
+    int ticks = 0;               // source-map times the plan steps onto
     // per realization of the class
     std::vector<int64_t> steps, stages, adv_stages;
     std::vector<double> dt_last;
@@ -75,6 +79,15 @@ struct GridClass {
     double* att_b0 = nullptr;
     double* vf64[2] = {nullptr, nullptr};
     float* vf32[2] = {nullptr, nullptr};
+    // random flux emergence: map k of the class in slot k & 1, per-row scale
+    // of eq. rfe_m1 / rfe_m2, the device's interval index k (the map of the
+    // current interval's start) and its host mirror (-1: no maps yet)
+    double* rfe_S[2] = {nullptr, nullptr};
+    double* rfe_scale = nullptr;
+    int64_t* rfe_kdev = nullptr;
+    int64_t rfe_k = -1;
+    double *rfe_partial = nullptr, *rfe_ratio = nullptr;
+    int rfe_nblk = 0;
     DiffRow<double>* dr64 = nullptr;
     DiffRow<float>* dr32 = nullptr;
     double *sf64 = nullptr, *denth64 = nullptr, *denph64 = nullptr;
@@ -386,135 +399,214 @@ void step_sequence(double len, double lim, double dt_max, std::vector<double>& d
 }
 
 // --------------------------------------------------------------- planning
-sft_status build_plan(sft_ctx* c, GridClass* g, double len, Plan** out)
+// Index k of the source-map interval [k tau, (k+1) tau) holding time t; a
+// time within 1e-10 h below a boundary counts as on it.
+int64_t rfe_interval(double t, double tau)
+{
+    int64_t k = (int64_t)floor(t / tau);
+    if ((double)(k + 1) * tau - t < 1e-10) k += 1;
+    if (t < (double)k * tau - 1e-10) k -= 1;
+    return k;
+}
+
+struct Segment {
+    double a, b;       // absolute start and end, hours
+    int64_t k;         // source-map interval of the segment
+    bool tick_after;   // a step ends on map time (k+1) tau at b
+};
+
+// Pieces of [t0, t_end] cut at the source-map times k tau (Sec. "Time
+// steps": steps land on the times a new source map is generated).  Without
+// finite-lifetime flux emergence: one piece.
+void segments(double t0, double t_end, bool cut, double tau, std::vector<Segment>& out)
+{
+    out.clear();
+    double a = t0;
+    for (;;) {
+        double b = t_end;
+        int64_t k = 0;
+        if (cut) {
+            k = rfe_interval(a, tau);
+            const double nb = (double)(k + 1) * tau;
+            if (nb < t_end - 1e-10) b = nb;
+        }
+        out.push_back(Segment{a, b, k, false});
+        if (b == t_end) break;
+        out.back().tick_after = true;
+        a = b;
+    }
+    if (cut && rfe_interval(t_end, tau) == out.back().k + 1) out.back().tick_after = true;
+}
+
+sft_status build_plan(sft_ctx* c, GridClass* g, double t0, double t_end, double len, Plan** out)
 {
     const sft_options& o = c->opt;
     const bool mixed = o.precision == SFT_FP32_MIXED;
+    const bool rfe = o.rfe_model != 0;
+    const double tau = o.rfe_lifetime_h;
     Plan* p = new Plan();
     p->steps.assign(g->R, 0);
     p->stages.assign(g->R, 0);
     p->adv_stages.assign(g->R, 0);
     p->dt_last.assign(g->R, 0.0);
+    std::vector<Segment> segs;
+    if (rfe && tau > 0.0) segments(t0, t_end, true, tau, segs);
+    else segs.push_back(Segment{t0, t_end, 0, false});
     std::vector<std::vector<double>> seq(g->R);
-    size_t max_steps = 0;
-    // Strang splitting: each advection advance is half a step, so the CFL
-    // limit of the step doubles
-    const bool strang = o.strang != 0;
-    for (int r = 0; r < g->R; ++r) {
-        step_sequence(len, (strang ? 2.0 : 1.0) * o.cfl_safety * g->cfl[r], o.dt_max, seq[r]);
-        max_steps = std::max(max_steps, seq[r].size());
-    }
     std::vector<Entry> ents;
     std::vector<StageCoef> coefs;
     std::vector<StageCoef> tmp;
+    std::vector<double> alphas;
+    // Strang splitting: each advection advance is half a step, so the CFL
+    // limit of the step doubles
+    const bool strang = o.strang != 0;
     const int adv_nst = o.adv_time == SFT_SSPRK43 ? 4 : (o.adv_time == SFT_SSPRK33 ? 3 : 1);
     const double adv_frac = strang ? 0.5 : 1.0;
-    // one advection advance of adv_frac * dt for every realization with flow
-    // that takes step i (FP64 forward Euler: copy the result back to B)
-    auto advection_phase = [&](size_t i) {
-        Phase pa{0, (int)ents.size(), 0, 0, {}};
+    // start of each realization's current step (absolute hours)
+    std::vector<double> el(g->R, 0.0);
+    for (const Segment& sg : segs) {
+        // the first piece has the plan's own length (t_end - t0, as the
+        // caller computed it); later pieces their end minus their start
+        const double slen = segs.size() == 1 ? len : sg.b - sg.a;
+        size_t max_steps = 0;
         for (int r = 0; r < g->R; ++r) {
-            if (i >= seq[r].size() || !g->has_flow[r]) continue;
-            Entry e{r, 0, 0, 0, adv_frac * seq[r][i]};
-            ents.push_back(e);
-            p->adv_stages[r] += adv_nst;
+            step_sequence(slen, (strang ? 2.0 : 1.0) * o.cfl_safety * g->cfl[r], o.dt_max, seq[r]);
+            max_steps = std::max(max_steps, seq[r].size());
+            el[r] = 0.0;
         }
-        pa.n_ent = (int)ents.size() - pa.ent_off;
-        if (pa.n_ent) {
-            p->phases.push_back(pa);
-            if (!mixed && o.adv_time == SFT_FE) {
-                Phase pc{2, pa.ent_off, pa.n_ent, 0, {}};
-                p->phases.push_back(pc);
-            }
-        }
-    };
-    for (size_t i = 0; i < max_steps; ++i) {
-        // advection (eq. num_opsplit_nostrang), or its first half (eq. num_opsplit_strang)
-        advection_phase(i);
-        // diffusion calls (several when the PTL hook splits the step)
-        int ncall_max = 0;
-        std::vector<int> ncall(g->R, 0);
-        for (int r = 0; r < g->R; ++r) {
-            if (i >= seq[r].size() || !(g->prm[r].nu_km2_s > 0.0)) continue;
-            const double dt = seq[r][i];
-            int nc = 1;
-            if (o.ptl_dt > 0.0 && dt > o.ptl_dt) nc = (int)ceil(dt / o.ptl_dt);
-            ncall[r] = nc;
-            ncall_max = std::max(ncall_max, nc);
-        }
-        for (int call = 0; call < ncall_max; ++call) {
-            std::vector<Entry> de;
+        // one advection advance of adv_frac * dt for every realization with flow
+        // that takes step i (FP64 forward Euler: copy the result back to B)
+        auto advection_phase = [&](size_t i) {
+            Phase pa{0, (int)ents.size(), 0, 0, {}};
             for (int r = 0; r < g->R; ++r) {
-                if (call >= ncall[r]) continue;
-                const double tc = seq[r][i] / ncall[r];
-                int s;
-                if (o.diff_time == SFT_DIFF_FE) {
-                    s = (int)ceil(tc / g->dtE[r]);
-                    fe_coefs(s, tc / s, tmp);
-                } else {
-                    s = sts_stages(tc, g->dtE[r], o.diff_time);
-                    sts_coefs(s, o.diff_time, tc, tmp);
+                if (i >= seq[r].size() || !g->has_flow[r]) continue;
+                Entry e{r, 0, 0, 0, adv_frac * seq[r][i]};
+                ents.push_back(e);
+                p->adv_stages[r] += adv_nst;
+            }
+            pa.n_ent = (int)ents.size() - pa.ent_off;
+            if (pa.n_ent) {
+                p->phases.push_back(pa);
+                if (!mixed && o.adv_time == SFT_FE) {
+                    Phase pc{2, pa.ent_off, pa.n_ent, 0, {}};
+                    p->phases.push_back(pc);
                 }
-                Entry e{r, s, (int)coefs.size(), (mixed && call == 0 && g->has_flow[r]) ? 1 : 0, tc};
-                coefs.insert(coefs.end(), tmp.begin(), tmp.end());
-                de.push_back(e);
-                p->stages[r] += s;
             }
-            std::stable_sort(de.begin(), de.end(), [](const Entry& a, const Entry& b) { return a.s > b.s; });
-            Phase pd{1, (int)ents.size(), (int)de.size(), de.empty() ? 0 : de[0].s, {}};
-            pd.n_act.assign(pd.max_s + 1, 0);
-            for (int j = 0; j <= pd.max_s; ++j)
-                for (auto& e : de) pd.n_act[j] += e.s >= j ? 1 : 0;
-            ents.insert(ents.end(), de.begin(), de.end());
-            p->phases.push_back(pd);
-            // one-stage calls (forward Euler only) finish outside the stage loop
-            std::vector<Entry> one;
-            for (auto& e : de)
-                if (e.s == 1) one.push_back(e);
-            if (!one.empty()) {
-                Phase po{mixed ? 3 : 4, (int)ents.size(), (int)one.size(), 0, {}};
-                ents.insert(ents.end(), one.begin(), one.end());
-                p->phases.push_back(po);
-            }
-        }
-        // mixed: realizations with flow but no diffusion fold the increment in
-        if (mixed) {
-            Phase pcl{5, (int)ents.size(), 0, 0, {}};
+        };
+        // source sub-advance of length frac * dt starting at frac0 * dt into
+        // step i (eq. rfe_s integrated exactly: length times the source at the
+        // sub-advance's midpoint)
+        auto source_phase = [&](size_t i, double frac0, double frac) {
+            Phase ps{6, (int)ents.size(), 0, 0, {}};
             for (int r = 0; r < g->R; ++r) {
-                if (i >= seq[r].size() || !g->has_flow[r] || ncall[r] > 0) continue;
-                ents.push_back(Entry{r, 0, 0, 1, seq[r][i]});
+                if (i >= seq[r].size()) continue;
+                const double dt = seq[r][i];
+                const double ta = frac0 > 0.0 ? sg.a + el[r] + frac0 * dt : sg.a + el[r];
+                const double h = frac * dt;
+                double a = 0.0;
+                if (tau > 0.0) a = ((ta + 0.5 * h) - (double)sg.k * tau) / tau;
+                ents.push_back(Entry{r, 0, (int)alphas.size(), 0, h});
+                alphas.push_back(a);
             }
-            pcl.n_ent = (int)ents.size() - pcl.ent_off;
-            if (pcl.n_ent) p->phases.push_back(pcl);
-        }
-        if (strang) {
-            // second half advection after the diffusion; in the mixed path its
-            // increment is folded into B by a close phase
+            ps.n_ent = (int)ents.size() - ps.ent_off;
+            if (ps.n_ent) p->phases.push_back(ps);
+        };
+        for (size_t i = 0; i < max_steps; ++i) {
+            // Strang: the source's first half opens the step (eq. num_opsplit_strang)
+            if (rfe && strang) source_phase(i, 0.0, 0.5);
+            // advection (eq. num_opsplit_nostrang), or its first half (eq. num_opsplit_strang)
             advection_phase(i);
+            // diffusion calls (several when the PTL hook splits the step)
+            int ncall_max = 0;
+            std::vector<int> ncall(g->R, 0);
+            for (int r = 0; r < g->R; ++r) {
+                if (i >= seq[r].size() || !(g->prm[r].nu_km2_s > 0.0)) continue;
+                const double dt = seq[r][i];
+                int nc = 1;
+                if (o.ptl_dt > 0.0 && dt > o.ptl_dt) nc = (int)ceil(dt / o.ptl_dt);
+                ncall[r] = nc;
+                ncall_max = std::max(ncall_max, nc);
+            }
+            for (int call = 0; call < ncall_max; ++call) {
+                std::vector<Entry> de;
+                for (int r = 0; r < g->R; ++r) {
+                    if (call >= ncall[r]) continue;
+                    const double tc = seq[r][i] / ncall[r];
+                    int s;
+                    if (o.diff_time == SFT_DIFF_FE) {
+                        s = (int)ceil(tc / g->dtE[r]);
+                        fe_coefs(s, tc / s, tmp);
+                    } else {
+                        s = sts_stages(tc, g->dtE[r], o.diff_time);
+                        sts_coefs(s, o.diff_time, tc, tmp);
+                    }
+                    Entry e{r, s, (int)coefs.size(), (mixed && call == 0 && g->has_flow[r]) ? 1 : 0, tc};
+                    coefs.insert(coefs.end(), tmp.begin(), tmp.end());
+                    de.push_back(e);
+                    p->stages[r] += s;
+                }
+                std::stable_sort(de.begin(), de.end(), [](const Entry& a, const Entry& b) { return a.s > b.s; });
+                Phase pd{1, (int)ents.size(), (int)de.size(), de.empty() ? 0 : de[0].s, {}};
+                pd.n_act.assign(pd.max_s + 1, 0);
+                for (int j = 0; j <= pd.max_s; ++j)
+                    for (auto& e : de) pd.n_act[j] += e.s >= j ? 1 : 0;
+                ents.insert(ents.end(), de.begin(), de.end());
+                p->phases.push_back(pd);
+                // one-stage calls (forward Euler only) finish outside the stage loop
+                std::vector<Entry> one;
+                for (auto& e : de)
+                    if (e.s == 1) one.push_back(e);
+                if (!one.empty()) {
+                    Phase po{mixed ? 3 : 4, (int)ents.size(), (int)one.size(), 0, {}};
+                    ents.insert(ents.end(), one.begin(), one.end());
+                    p->phases.push_back(po);
+                }
+            }
+            // mixed: realizations with flow but no diffusion fold the increment in
             if (mixed) {
                 Phase pcl{5, (int)ents.size(), 0, 0, {}};
                 for (int r = 0; r < g->R; ++r) {
-                    if (i >= seq[r].size() || !g->has_flow[r]) continue;
-                    ents.push_back(Entry{r, 0, 0, 1, adv_frac * seq[r][i]});
+                    if (i >= seq[r].size() || !g->has_flow[r] || ncall[r] > 0) continue;
+                    ents.push_back(Entry{r, 0, 0, 1, seq[r][i]});
                 }
                 pcl.n_ent = (int)ents.size() - pcl.ent_off;
                 if (pcl.n_ent) p->phases.push_back(pcl);
             }
-        }
-        for (int r = 0; r < g->R; ++r)
-            if (i < seq[r].size()) {
-                p->steps[r] += 1;
-                p->dt_last[r] = seq[r][i];
+            if (strang) {
+                // second half advection after the diffusion; in the mixed path its
+                // increment is folded into B by a close phase
+                advection_phase(i);
+                if (mixed) {
+                    Phase pcl{5, (int)ents.size(), 0, 0, {}};
+                    for (int r = 0; r < g->R; ++r) {
+                        if (i >= seq[r].size() || !g->has_flow[r]) continue;
+                        ents.push_back(Entry{r, 0, 0, 1, adv_frac * seq[r][i]});
+                    }
+                    pcl.n_ent = (int)ents.size() - pcl.ent_off;
+                    if (pcl.n_ent) p->phases.push_back(pcl);
+                }
             }
+            // the source closes the step (its second half under Strang splitting)
+            if (rfe) {
+                if (strang) source_phase(i, 0.5, 0.5);
+                else source_phase(i, 0.0, 1.0);
+            }
+            for (int r = 0; r < g->R; ++r)
+                if (i < seq[r].size()) {
+                    p->steps[r] += 1;
+                    p->dt_last[r] = seq[r][i];
+                    el[r] = el[r] + seq[r][i];
+                }
+        }
+        if (sg.tick_after) {
+            p->phases.push_back(Phase{7, (int)ents.size(), 0, 0, {}});
+            p->ticks += 1;
+        }
     }
     p->h_ents = ents;
     if (!ents.empty()) {
         sft_status st = dalloc(c, &p->d_ents, ents.size());
-        if (st != SFT_OK) {
-            delete p;
-            return st;
-        }
-        st = upload(c, p->d_ents, ents);
+        if (st == SFT_OK) st = upload(c, p->d_ents, ents);
         if (st != SFT_OK) {
             delete p;
             return st;
@@ -522,11 +614,15 @@ sft_status build_plan(sft_ctx* c, GridClass* g, double len, Plan** out)
     }
     if (!coefs.empty()) {
         sft_status st = dalloc(c, &p->d_coefs, coefs.size());
+        if (st == SFT_OK) st = upload(c, p->d_coefs, coefs);
         if (st != SFT_OK) {
             delete p;
             return st;
         }
-        st = upload(c, p->d_coefs, coefs);
+    }
+    if (!alphas.empty()) {
+        sft_status st = dalloc(c, &p->d_alpha, alphas.size());
+        if (st == SFT_OK) st = upload(c, p->d_alpha, alphas);
         if (st != SFT_OK) {
             delete p;
             return st;
@@ -723,6 +819,19 @@ sft_status choose_tile(sft_ctx* c, GridClass* g)
     return SFT_OK;
 }
 
+// Source map (kdev[0] + koff, or kabs without kdev) of every realization of
+// a class: draw, FP64 flux sums, eq. fluxbal balance.
+void rfe_make_map(sft_ctx* c, GridClass* g, const int64_t* kdev, int koff, int64_t kabs)
+{
+    tbeg(c);
+    launch_rfe_gen(c->stream, g->R, g->first_id, c->opt.rfe_seed, kdev, koff, kabs, g->rfe_scale, g->w_row,
+                   g->rfe_S[0], g->rfe_S[1], g->rfe_partial, g->nt, g->np);
+    launch_assim_reduce(c->stream, g->R, g->rfe_partial, g->rfe_nblk, g->rfe_ratio);
+    launch_rfe_balance(c->stream, g->R, kdev, koff, kabs, g->rfe_ratio, g->rfe_S[0], g->rfe_S[1], g->nt,
+                       g->np);
+    tend(c, SFT_KFAM_SOURCE, 24.0 * (double)g->cells() * g->R);
+}
+
 // Enqueue every phase of a plan.
 void run_plan(sft_ctx* c, GridClass* g, Plan* p)
 {
@@ -868,6 +977,20 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p)
             tbeg(c);
             launch_mixed_close(st, E, ph.n_ent, g->B, g->A[0], nullptr, g->cells());
             tend(c, SFT_KFAM_OTHER, 20.0 * cells * ne);
+        } else if (ph.kind == 6) {
+            // source sub-advance on the FP64 state (both precisions)
+            const int inf = o.rfe_lifetime_h > 0.0 ? 0 : 1;
+            tbeg(c);
+            launch_rfe_apply(st, E, ph.n_ent, p->d_alpha, g->rfe_kdev, inf, g->rfe_S[0], g->rfe_S[1], g->B,
+                             g->cells());
+            tend(c, SFT_KFAM_SOURCE, (inf ? 24.0 : 32.0) * cells * ne);
+        } else if (ph.kind == 7) {
+            // a step ended on map time (k+1) tau: k += 1, draw map k + 2 into
+            // the slot map k held
+            tbeg(c);
+            launch_rfe_tick(st, g->rfe_kdev);
+            tend(c, SFT_KFAM_SOURCE, 0.0);
+            rfe_make_map(c, g, g->rfe_kdev, 1, 0);
         }
     }
 }
@@ -923,6 +1046,10 @@ sft_status sft_create(sft_ctx** ctx, const sft_options* opt, void* hip_stream)
     if (o.adv_scheme != SFT_WENO3CSH && o.adv_scheme != SFT_UPWIND) return SFT_ERR_ARG;
     if (o.adv_time != SFT_SSPRK43 && o.adv_time != SFT_FE && o.adv_time != SFT_SSPRK33) return SFT_ERR_ARG;
     if (o.strang != 0 && o.strang != 1) return SFT_ERR_ARG;
+    if (o.rfe_model < 0 || o.rfe_model > 2) return SFT_ERR_ARG;
+    if (o.rfe_model && (!(o.rfe_phi_hr > 0.0) || !std::isfinite(o.rfe_phi_hr) ||
+                        !(o.rfe_lifetime_h >= 0.0) || !std::isfinite(o.rfe_lifetime_h)))
+        return SFT_ERR_ARG;
     if (o.diff_time != SFT_RKG2 && o.diff_time != SFT_RKL2 && o.diff_time != SFT_DIFF_FE)
         return SFT_ERR_ARG;
     if (!(o.cfl_safety > 0.0 && o.cfl_safety <= 1.0) || o.dt_max < 0.0 || o.ptl_dt < 0.0)
@@ -1053,6 +1180,28 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
     for (int r = 0; r < R; ++r) {
         b0[r] = g->prm[r].att_b0;
         g->att |= b0[r] > 0.0;
+    }
+    if (c->opt.rfe_model) {
+        for (int i = 0; i < 2; ++i) TRY(dalloc(c, &g->rfe_S[i], n));
+        // eq. rfe_m1: phi / (dA_j N_cells) sqrt(pi/2), dA_j = R^2 sin(theta_j) dth dph;
+        // eq. rfe_m2: phi / (4 pi R^2) sqrt(pi/2); R in cm
+        const double Rcm = RSUN_M * 100.0, phi = c->opt.rfe_phi_hr;
+        const double dth = M_PI / nt, dph = 2.0 * M_PI / np;
+        std::vector<double> sc(nt);
+        for (int j = 0; j < nt; ++j) {
+            if (c->opt.rfe_model == 1) {
+                const double dA = Rcm * Rcm * sin((j + 0.5) * dth) * dth * dph;
+                sc[j] = phi / (dA * (double)g->cells()) * sqrt(M_PI / 2.0);
+            } else {
+                sc[j] = phi / (4.0 * M_PI * Rcm * Rcm) * sqrt(M_PI / 2.0);
+            }
+        }
+        TRY(dalloc(c, &g->rfe_scale, nt));
+        TRY(upload(c, g->rfe_scale, sc));
+        TRY(dalloc(c, &g->rfe_kdev, 1));
+        g->rfe_nblk = rfe_gen_blocks(nt, np);
+        TRY(dalloc(c, &g->rfe_partial, (size_t)R * g->rfe_nblk * 2));
+        TRY(dalloc(c, &g->rfe_ratio, R));
     }
     if (g->att) {
         TRY(dalloc(c, &g->att_b0, b0.size()));
@@ -1248,6 +1397,34 @@ sft_status sft_get_states(sft_ctx* c, int32_t gid, void* br, int32_t dtype, int3
 
 static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid);
 
+static void dfree(sft_ctx* c, void* ptr)
+{
+    if (!ptr) return;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), ptr);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+    (void)hipFree(ptr);
+}
+
+// Frees every cached plan and graph (after the stream has drained).
+static void drop_plans(sft_ctx* c)
+{
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    c->graphs.clear();
+    for (auto* g : c->grids) {
+        for (auto& kv : g->plans) {
+            dfree(c, kv.second->d_ents);
+            dfree(c, kv.second->d_coefs);
+            dfree(c, kv.second->d_alpha);
+            delete kv.second;
+        }
+        g->plans.clear();
+    }
+}
+
 sft_status sft_advance(sft_ctx* c, double t_end)
 {
     if (!c) return SFT_ERR_ARG;
@@ -1266,6 +1443,21 @@ static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
         if (g->R && g->tile == -2) TRY(choose_tile(c, g));
     const double len = t_end - c->t;
     if (len == 0.0) return SFT_OK;
+    // random flux emergence: a plan also depends on where the advance starts
+    // in its source-map interval; k0 is the interval holding the start
+    const bool rfe = c->opt.rfe_model != 0;
+    const double tau = c->opt.rfe_lifetime_h;
+    int64_t k0 = 0;
+    uint64_t rkey = 0;
+    if (rfe && tau > 0.0) {
+        k0 = rfe_interval(c->t, tau);
+        rkey = dbits(c->t - (double)k0 * tau) * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+        // start phases need not repeat (tau incommensurate with the advances):
+        // keep the caches bounded
+        size_t np_max = 0;
+        for (auto* g : c->grids) np_max = std::max(np_max, g->plans.size());
+        if (np_max >= 64) drop_plans(c);
+    }
     std::vector<Plan*> plans;
     for (size_t gi = 0; gi < c->grids.size(); ++gi) {
         GridClass* g = c->grids[gi];
@@ -1273,11 +1465,11 @@ static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
             plans.push_back(nullptr);
             continue;
         }
-        const uint64_t key = dbits(len);
+        const uint64_t key = dbits(len) ^ rkey;
         auto it = g->plans.find(key);
         Plan* p;
         if (it == g->plans.end()) {
-            TRY(build_plan(c, g, len, &p));
+            TRY(build_plan(c, g, c->t, t_end, len, &p));
             g->plans[key] = p;
         } else {
             p = it->second;
@@ -1298,8 +1490,22 @@ static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
         c->t = t_end;
         return SFT_OK;
     }
+    // source maps of interval k0 (and k0 + 1) unless the device holds them
+    // already (first advance, or a time set by the caller)
+    if (rfe) {
+        for (size_t i = 0; i < c->grids.size(); ++i) {
+            GridClass* g = c->grids[i];
+            if (!plans[i] || g->rfe_k == k0) continue;
+            tbeg(c);
+            launch_rfe_set(c->stream, g->rfe_kdev, k0);
+            tend(c, SFT_KFAM_SOURCE, 0.0);
+            rfe_make_map(c, g, nullptr, 0, k0);
+            if (tau > 0.0) rfe_make_map(c, g, nullptr, 0, k0 + 1);
+            g->rfe_k = k0;
+        }
+    }
     if (c->opt.use_graphs && !c->timing) {
-        const uint64_t key = dbits(len) ^ (c->opt.diag_every_call ? 0x5bd1e995ull : 0) ^
+        const uint64_t key = (dbits(len) ^ rkey) ^ (c->opt.diag_every_call ? 0x5bd1e995ull : 0) ^
                              ((uint64_t)(skip_gid + 1) << 52);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
@@ -1319,6 +1525,7 @@ static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
         GridClass* g = c->grids[i];
         Plan* p = plans[i];
         if (!p) continue;
+        g->rfe_k += p->ticks;
         for (int r = 0; r < g->R; ++r) {
             g->steps[r] += p->steps[r];
             g->stages[r] += p->stages[r];

@@ -39,10 +39,13 @@ def oracle_run(B0, reals, schedule, opts=None):
 
     schedule: list of ("advance", t_end) / ("assim", data, kind, weight, b0, l0).
     Returns the array of final fields [R, nt, np] and per-realization stats."""
-    opts = opts or {}
+    opts = dict(opts or {})
+    first_id = opts.pop("rfe_first_id", 0)
     out, stats = [], []
     R, nt, np_ = B0.shape
     for r, real in enumerate(reals):
+        if opts.get("rfe_model", 0):
+            opts["rfe_id"] = first_id + r       # the generator's key word 1: the realization id
         B = B0[r].copy()
         t = 0.0
         st = {"steps": 0, "stages": 0}

@@ -41,9 +41,12 @@ def test_host_only_entry_points():
     assert L.sft_status_string(_abi.SFT_ERR_NOT_FINITE) == b"field holds NaN or Inf"
     assert L.sft_options_default(None) == _abi.SFT_ERR_ARG
     assert L.sft_advance(None, 1.0) == _abi.SFT_ERR_ARG
-    bad = make_options(cfl_safety=1.5)
     ctx = ctypes.c_void_p()
-    assert L.sft_create(ctypes.byref(ctx), ctypes.byref(bad), None) == _abi.SFT_ERR_ARG
+    for kw in ({"cfl_safety": 1.5}, {"rfe_model": 3, "rfe_phi_hr": 1e23},
+               {"rfe_model": 2, "rfe_phi_hr": 0.0}, {"rfe_model": 1, "rfe_phi_hr": 1e23, "rfe_lifetime_h": -1.0},
+               {"rfe_model": 2, "rfe_phi_hr": float("inf")}, {"strang": 2}):
+        bad = make_options(**kw)
+        assert L.sft_create(ctypes.byref(ctx), ctypes.byref(bad), None) == _abi.SFT_ERR_ARG, kw
     assert L.sft_last_error(None) == b""
 
 
@@ -51,8 +54,9 @@ def test_struct_layouts_match_header(tmp_path):
     """ctypes structures have the sizes and field offsets the C compiler gives."""
     import subprocess
     from paper_2501_06377_amd import _abi
-    fields = {"sft_options": ["cfl_safety", "use_graphs", "diag_every_call"],
-              "sft_params": ["nu_km2_s", "lat_lim_deg", "flux_balance"],
+    fields = {"sft_options": ["cfl_safety", "use_graphs", "diag_every_call", "strang", "rfe_model",
+                              "rfe_seed", "rfe_phi_hr", "rfe_lifetime_h"],
+              "sft_params": ["nu_km2_s", "lat_lim_deg", "flux_balance", "att_b0"],
               "sft_diag": ["steps", "phi_pos", "nonfinite", "surr_accept"]}
     lines = ['#include "sft.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void){"]
     for st, fs in fields.items():
