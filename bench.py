@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--att-b0", type=float, default=0.0,
                     help="flow attenuation saturation field B0 in gauss for every realization (0: off)")
+    ap.add_argument("--rfe-model", type=int, default=0, choices=(0, 1, 2),
+                    help="random flux emergence model (eq. rfe_m1 / rfe_m2; 0: off)")
+    ap.add_argument("--rfe-phi", type=float, default=1.0e23, help="unsigned flux per hour of a map, Mx")
+    ap.add_argument("--rfe-tau", type=float, default=1.0, help="source-map lifetime, hours (0: infinite)")
     ap.add_argument("--sts-tile", type=int, default=-1, help="blocked STS shape (-1: autotuned)")
     ap.add_argument("--surr-batch", type=int, default=64)
     ap.add_argument("--surrogate-only", action="store_true",
@@ -70,7 +74,7 @@ def make_obs(f0, hours, dtype=np.float64):
     return np.stack(maps)
 
 
-def cpu_baseline(nt, np_, reals, f0, obs_first, max_seconds):
+def cpu_baseline(nt, np_, reals, f0, obs_first, max_seconds, rfe=None):
     """FP64 oracle on the first realization-hours of a workload class (hour
     by hour, all realizations of an hour in turn), stopped after about
     max_seconds of CPU work."""
@@ -91,8 +95,9 @@ def cpu_baseline(nt, np_, reals, f0, obs_first, max_seconds):
             b0, l0 = synth.observer(float(h))
             mu = oracle.mu_disk(nt, np_, math.radians(b0), math.radians(l0))
         for r, real in enumerate(reals):
+            extra = dict(rfe, rfe_id=r) if rfe else {}
             B[r], st = oracle.advance(B[r], real.flow, real.nu_km2_s, float(h - 1), float(h),
-                                      att_b0=real.att_b0)
+                                      att_b0=real.att_b0, **extra)
             n = st["stages"] + 4 * st["steps"]
             if obs_first is not None:
                 F = oracle.weight_from_mu(mu, real.alpha_mu, real.mu_lim, math.radians(real.lat_lim_deg))
@@ -246,12 +251,17 @@ def main():
             for r in reals:
                 r.att_b0 = args.att_b0
         w.name += f"+attenuation-B0-{args.att_b0:g}G"
+    rfe_gpu, rfe_cpu = {}, None
+    if args.rfe_model:
+        rfe_gpu = dict(rfe_model=args.rfe_model, rfe_phi_hr=args.rfe_phi, rfe_lifetime_h=args.rfe_tau, rfe_seed=1)
+        rfe_cpu = dict(rfe_model=args.rfe_model, rfe_phi_hr=args.rfe_phi, rfe_tau=args.rfe_tau, rfe_seed=1)
+        w.name += f"+flux-emergence-m{args.rfe_model}-tau{args.rfe_tau:g}h"
     W = args.warmup
     prec = 0 if w.precision == "f64" else 1
     graphs = args.graphs or args.workload == "batching"
     assim = w.assim_every_h > 0
     dev = torch.device("cuda:0")
-    ens = sft.Ensemble(precision=prec, use_graphs=1 if graphs else 0, sts_tile=args.sts_tile)
+    ens = sft.Ensemble(precision=prec, use_graphs=1 if graphs else 0, sts_tile=args.sts_tile, **rfe_gpu)
     gids, inits, obs_d, f0s, obs0 = [], [], [], [], None
     for ci, (nt, np_, reals) in enumerate(w.classes):
         f0 = synth.bipolar_field(nt, np_, synth.bipolar_pairs(w.n_pairs, ci))
@@ -316,6 +326,8 @@ def main():
                    "step": "1 h interval: advection" +
                            (f" (flow attenuation, B0 = {args.att_b0:g} G)" if args.att_b0 > 0.0 else "") +
                            " + RKG2 diffusion" +
+                           (f" + flux emergence (model {args.rfe_model}, {args.rfe_phi:g} Mx/h, "
+                            f"lifetime {args.rfe_tau:g} h)" if args.rfe_model else "") +
                            (" + mu^4 assimilation" if assim else "") + " + diagnostics",
                    "simulated_hours": K, "graphs": bool(graphs), "sts_tiles": tiles},
         "sim_days_per_s": K / 24.0 / wall,
@@ -349,7 +361,7 @@ def main():
     if not args.no_cpu_baseline:
         nt, np_, reals = w.classes[-1]
         out["cpu_baseline"] = cpu_baseline(nt, np_, reals, f0s[-1], obs0 if len(w.classes) == 1 else None,
-                                           args.cpu_seconds)
+                                           args.cpu_seconds, rfe_cpu)
     print(json.dumps(out), flush=True)
 
 
