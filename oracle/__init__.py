@@ -63,6 +63,10 @@ def lib():
             "or_adv_step": (None, [i, i, P, P, P, d, i, i, d]),
             "or_diff_coefs": (None, [i, i, d, P, P, P, P]),
             "or_diff_operator": (None, [i, i, d, P, P]),
+            "or_diff_operator_face": (None, [i, i, P, P, P]),
+            "or_diff_coefs_face": (None, [i, i, P, P, P, P, P]),
+            "or_nu_grid": (None, [i, i, d, P]),
+            "or_diffuse_face": (l, [i, i, P, P, d, i, d]),
             "or_euler_limit": (d, [i, i, d]),
             "or_sts_stages": (i, [d, d, i]),
             "or_sts_coefs": (None, [i, i, P, P, P, P]),
@@ -164,6 +168,34 @@ def diff_operator(B, nu):
     return out
 
 
+def diff_operator_face(B, nu_face):
+    """Eq. diffusion_matrix with a colatitude-dependent corner diffusivity
+    (nu_face[f] on theta face f, R_sun^2/h)."""
+    B = _f64(B)
+    out = np.empty_like(B)
+    lib().or_diff_operator_face(B.shape[0], B.shape[1], _p(_f64(nu_face)), _p(B), _p(out))
+    return out
+
+
+def diff_coefs_face(nt, np_, nu_face):
+    c = [np.empty(nt) for _ in range(4)]
+    lib().or_diff_coefs_face(nt, np_, _p(_f64(nu_face)), *[_p(x) for x in c])
+    return tuple(c)  # a_up, a_dn, a_ph, a_d
+
+
+def nu_grid(nt, np_, alpha):
+    """Eq. diffgrid at the theta faces (alpha in 1/h -> R_sun^2/h)."""
+    nf = np.empty(nt + 1)
+    lib().or_nu_grid(nt, np_, float(alpha), _p(nf))
+    return nf
+
+
+def diffuse_face(B, nu_face, tau, scheme=RKG2, ptl_dt=0.0):
+    B = _f64(B).copy()
+    st = lib().or_diffuse_face(B.shape[0], B.shape[1], _p(B), _p(_f64(nu_face)), tau, scheme, ptl_dt)
+    return B, int(st)
+
+
 def euler_limit(nt, np_, nu):
     return lib().or_euler_limit(nt, np_, nu)
 
@@ -222,15 +254,16 @@ def hh(X, Y):
 
 def advance(B, prm, nu_km2_s, t0, t_end, adv_scheme=WENO3CSH, adv_time=SSPRK43,
             diff_scheme=RKG2, safety=0.9, dt_max=0.0, eps_mode=0.0, ptl_dt=0.0, strang=0, att_b0=0.0,
-            rfe_model=0, rfe_phi_hr=0.0, rfe_tau=0.0, rfe_seed=0, rfe_id=0):
+            rfe_model=0, rfe_phi_hr=0.0, rfe_tau=0.0, rfe_seed=0, rfe_id=0, nu_grid_alpha=0.0):
     """Advance one realization from t0 to t_end (hours), operator split with
     or without Strang splitting, optionally with flow attenuation (att_b0 in
     gauss) and random flux emergence (model 1 / 2, phi_hr Mx per hour,
-    lifetime rfe_tau hours, 0 = infinite; maps keyed by seed and id).
+    lifetime rfe_tau hours, 0 = infinite; maps keyed by seed and id) and the
+    smoother's grid diffusivity (nu_grid_alpha > 0 in 1/h replaces nu).
     Returns (B, stats)."""
     B = _f64(B).copy()
     opts = np.array([adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang, att_b0,
-                     rfe_model, rfe_phi_hr, rfe_tau, rfe_seed, rfe_id], dtype=np.float64)
+                     rfe_model, rfe_phi_hr, rfe_tau, rfe_seed, rfe_id, nu_grid_alpha], dtype=np.float64)
     stats = np.zeros(3)
     lib().or_advance(B.shape[0], B.shape[1], _p(B), _p(_f64(prm)), float(nu_km2_s), float(t0),
                      float(t_end), _p(opts), _p(stats))

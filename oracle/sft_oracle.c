@@ -424,16 +424,46 @@ void or_adv_step_att(int nt, int np, double *B, const double *vph_row, const dou
  *   a_d   = -(a_up + a_dn + a_ph + a_ph)
  * The pole faces have sin = 0, so a_up of row 0 and a_dn of the last row
  * vanish (App. A closure). */
-void or_diff_coefs(int nt, int np, double nu, double *a_up, double *a_dn, double *a_ph, double *a_d)
+/* The same table for a diffusivity that depends on colatitude only, given
+ * at the cell corners: nu_face[f] is nu on theta face f (f = 0..nt, face f
+ * between rows f-1 and f), the same at both corners of a face.  The corner
+ * pairs of the table are then: phi neighbours (nu_face[j+1] + nu_face[j]),
+ * theta neighbours (nu_face[j] + nu_face[j]) and (nu_face[j+1] +
+ * nu_face[j+1]). */
+void or_diff_coefs_face(int nt, int np, const double *nu_face, double *a_up, double *a_dn,
+                        double *a_ph, double *a_d)
 {
     or_geom g;
     geom_init(&g, nt, np);
     for (int j = 0; j < nt; ++j) {
         double s = g.st[j];
-        a_ph[j] = (nu + nu) / (2.0 * g.dph * g.dph * s * s);
-        a_up[j] = (nu + nu) * g.sf[j] / (2.0 * g.dth * g.dth * s);
-        a_dn[j] = (nu + nu) * g.sf[j + 1] / (2.0 * g.dth * g.dth * s);
+        a_ph[j] = (nu_face[j + 1] + nu_face[j]) / (2.0 * g.dph * g.dph * s * s);
+        a_up[j] = (nu_face[j] + nu_face[j]) * g.sf[j] / (2.0 * g.dth * g.dth * s);
+        a_dn[j] = (nu_face[j + 1] + nu_face[j + 1]) * g.sf[j + 1] / (2.0 * g.dth * g.dth * s);
         a_d[j] = -(a_up[j] + a_dn[j] + a_ph[j] + a_ph[j]);
+    }
+    geom_free(&g);
+}
+
+void or_diff_coefs(int nt, int np, double nu, double *a_up, double *a_dn, double *a_ph, double *a_d)
+{
+    double *nf = (double *)malloc(sizeof(double) * (nt + 1));
+    for (int f = 0; f <= nt; ++f) nf[f] = nu;
+    or_diff_coefs_face(nt, np, nf, a_up, a_dn, a_ph, a_d);
+    free(nf);
+}
+
+/* Grid-based diffusivity of the flux-preserving smoother (eq. diffgrid):
+ * nu_g = alpha [dth^2 + (dph sin(theta))^2] at the theta faces (the corners'
+ * colatitudes; sin = 0 at the poles), alpha in 1/h so nu_g is in
+ * R_sun^2 / h on the unit sphere. */
+void or_nu_grid(int nt, int np, double alpha, double *nu_face)
+{
+    or_geom g;
+    geom_init(&g, nt, np);
+    for (int f = 0; f <= nt; ++f) {
+        double x = g.dph * g.sf[f];
+        nu_face[f] = alpha * (g.dth * g.dth + x * x);
     }
     geom_free(&g);
 }
@@ -459,6 +489,14 @@ static void diff_apply(int nt, int np, const double *a_up, const double *a_dn, c
             out[(size_t)j * np + k] = v;
         }
     }
+}
+
+void or_diff_operator_face(int nt, int np, const double *nu_face, const double *B, double *out)
+{
+    double *c = (double *)malloc(sizeof(double) * 4 * nt);
+    or_diff_coefs_face(nt, np, nu_face, c, c + nt, c + 2 * nt, c + 3 * nt);
+    diff_apply(nt, np, c, c + nt, c + 2 * nt, c + 3 * nt, B, out);
+    free(c);
 }
 
 void or_diff_operator(int nt, int np, double nu, const double *B, double *out)
@@ -556,12 +594,27 @@ void or_sts_coefs(int s, int scheme, double *mu, double *nu, double *mut, double
  * ceil(tau/ptl_dt) equal STS calls (a stand-in hook for the practical time
  * step limit, whose formula is not in the paper: parity unpinned).
  * Returns the number of operator applications (stages). */
+long or_diffuse_face(int nt, int np, double *B, const double *nu_face, double tau, int dscheme,
+                     double ptl_dt);
+
 long or_diffuse(int nt, int np, double *B, double nu, double tau, int dscheme, double ptl_dt)
 {
     if (nu == 0.0 || tau <= 0.0) return 0;
+    double *nf = (double *)malloc(sizeof(double) * (nt + 1));
+    for (int f = 0; f <= nt; ++f) nf[f] = nu;
+    long st = or_diffuse_face(nt, np, B, nf, tau, dscheme, ptl_dt);
+    free(nf);
+    return st;
+}
+
+/* The same with the colatitude-dependent corner diffusivity nu_face. */
+long or_diffuse_face(int nt, int np, double *B, const double *nu_face, double tau, int dscheme,
+                     double ptl_dt)
+{
+    if (tau <= 0.0) return 0;
     size_t n = (size_t)nt * np;
     double *c = (double *)malloc(sizeof(double) * 4 * nt);
-    or_diff_coefs(nt, np, nu, c, c + nt, c + 2 * nt, c + 3 * nt);
+    or_diff_coefs_face(nt, np, nu_face, c, c + nt, c + 2 * nt, c + 3 * nt);
     const double *a_up = c, *a_dn = c + nt, *a_ph = c + 2 * nt, *a_d = c + 3 * nt;
     double m = 0.0;
     for (int j = 0; j < nt; ++j) m = fabs(a_d[j]) > m ? fabs(a_d[j]) : m;
@@ -904,12 +957,14 @@ double or_hh(long n, const double *X, const double *Y)
  * leave less than 1e-10 h before the segment's end is stretched to land on it.
  * prm = {d0, d2, d4, m1, m3, m5} (m/s), nu_km2_s scalar diffusivity.
  * opts = {adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang, att_b0,
- *         rfe_model, rfe_phi_hr, rfe_tau, rfe_seed, rfe_id}
+ *         rfe_model, rfe_phi_hr, rfe_tau, rfe_seed, rfe_id, nu_grid_alpha}
  * (att_b0: flow attenuation saturation, gauss, 0 = none; the CFL limit is
  * that of the unattenuated flow, an upper bound of the attenuated speeds;
  * rfe_model 0 = no source, 1 / 2 = eq. rfe_m1 / rfe_m2 maps of phi_hr Mx per
  * hour, lifetime rfe_tau hours (<= 0: infinite, one map), maps keyed by
- * (rfe_seed, rfe_id) and their index k, map k belonging to time k tau).
+ * (rfe_seed, rfe_id) and their index k, map k belonging to time k tau;
+ * nu_grid_alpha > 0, in 1/h: the grid diffusivity of eq. diffgrid replaces
+ * nu).
  * stats = {steps, diffusion stages, last dt}.  Returns 0. */
 int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, double t0,
                double t_end, const double *opts, double *stats)
@@ -924,7 +979,14 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
     int rfe = (int)opts[9];
     double rfe_phi = opts[10], tau = opts[11];
     uint32_t seed = (uint32_t)opts[12], rid = (uint32_t)opts[13];
+    double nu_alpha = opts[14];
     size_t n = (size_t)nt * np;
+    /* eq. diffgrid replaces the scalar diffusivity when nu_alpha > 0 */
+    double *nuf = NULL;
+    if (nu_alpha > 0.0) {
+        nuf = (double *)malloc(sizeof(double) * (nt + 1));
+        or_nu_grid(nt, np, nu_alpha, nuf);
+    }
     double *vph = (double *)malloc(sizeof(double) * nt);
     double *vth = (double *)malloc(sizeof(double) * (nt + 1));
     or_flows(nt, prm, vph, vth);
@@ -975,12 +1037,14 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
             if (strang) {
                 if (rfe) rfe_apply(n, B, Sk, Sk1, k, tau, ta, 0.5 * dt);
                 if (has_flow) or_adv_step_att(nt, np, B, vph, vth, 0.5 * dt, adv_scheme, adv_time, eps_mode, att_b0);
-                stages += or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
+                stages += nuf ? or_diffuse_face(nt, np, B, nuf, dt, dscheme, ptl_dt)
+                              : or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
                 if (has_flow) or_adv_step_att(nt, np, B, vph, vth, 0.5 * dt, adv_scheme, adv_time, eps_mode, att_b0);
                 if (rfe) rfe_apply(n, B, Sk, Sk1, k, tau, ta + 0.5 * dt, 0.5 * dt);
             } else {
                 if (has_flow) or_adv_step_att(nt, np, B, vph, vth, dt, adv_scheme, adv_time, eps_mode, att_b0);
-                stages += or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
+                stages += nuf ? or_diffuse_face(nt, np, B, nuf, dt, dscheme, ptl_dt)
+                              : or_diffuse(nt, np, B, nu, dt, dscheme, ptl_dt);
                 if (rfe) rfe_apply(n, B, Sk, Sk1, k, tau, ta, dt);
             }
             el = final ? len : el + dt;
@@ -995,6 +1059,7 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
     stats[2] = last;
     free(Sk);
     free(Sk1);
+    free(nuf);
     free(vph);
     free(vth);
     return 0;
