@@ -131,6 +131,10 @@ typedef struct {
                              the mean of |B| over the face's two cells of the field at
                              the start of the advance; the step length keeps the
                              unattenuated flow's CFL limit (the factor is <= 1)        */
+    double nu_grid_alpha; /* flux-preserving smoother (eq. diffgrid): > 0 replaces nu_km2_s
+                             by the grid diffusivity alpha [dth^2 + (dph sin theta)^2] at
+                             the cell corners, alpha in 1/h (R_sun^2/h on the unit
+                             sphere); 0 = scalar nu_km2_s                             */
 } sft_params;
 
 /* Analysis record of one realization (Sec. "Analysis"); FP64 reductions. */

@@ -35,6 +35,7 @@ def make_params(r) -> _abi.sft_params:
         setattr(p, name, float(getattr(r, name)))
     p.flux_balance = int(getattr(r, "flux_balance", 0))
     p.att_b0 = float(getattr(r, "att_b0", 0.0))
+    p.nu_grid_alpha = float(getattr(r, "nu_grid_alpha", 0.0))
     return p
 
 

@@ -42,7 +42,8 @@ class sft_params(ctypes.Structure):
                 ("d4", ctypes.c_double), ("m1", ctypes.c_double), ("m3", ctypes.c_double),
                 ("m5", ctypes.c_double), ("alpha_mu", ctypes.c_double), ("mu_lim", ctypes.c_double),
                 ("lat_lim_deg", ctypes.c_double), ("flux_balance", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("att_b0", ctypes.c_double)]
+                ("reserved", ctypes.c_int32), ("att_b0", ctypes.c_double),
+                ("nu_grid_alpha", ctypes.c_double)]
 
 
 class sft_diag(ctypes.Structure):

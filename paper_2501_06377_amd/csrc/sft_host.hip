@@ -300,7 +300,12 @@ double cfl_limit(int nt, int np, const std::vector<double>& vph, const std::vect
 }
 
 // Eq. diffusion_matrix rows for a scalar diffusivity nu (R_sun^2/h).
-void diff_rows(int nt, int np, double nu, std::vector<DiffRow<double>>& out)
+// Eq. diffusion_matrix with the diffusivity at the cell corners given per
+// theta face (nuf[f], f = 0..nt; it depends on colatitude only): phi
+// neighbours take the mean of the row's two faces, theta neighbours the
+// shared face's value.  A scalar nu (all faces equal) gives the constant-
+// coefficient rows.
+void diff_rows(int nt, int np, const std::vector<double>& nuf, std::vector<DiffRow<double>>& out)
 {
     const double dth = M_PI / nt, dph = 2.0 * M_PI / np;
     out.resize(nt);
@@ -309,11 +314,27 @@ void diff_rows(int nt, int np, double nu, std::vector<DiffRow<double>>& out)
         const double sfu = j == 0 ? 0.0 : sin(j * dth);
         const double sfd = j == nt - 1 ? 0.0 : sin((j + 1) * dth);
         DiffRow<double> d;
-        d.ph = (nu + nu) / (2.0 * dph * dph * s * s);
-        d.up = (nu + nu) * sfu / (2.0 * dth * dth * s);
-        d.dn = (nu + nu) * sfd / (2.0 * dth * dth * s);
+        d.ph = (nuf[j + 1] + nuf[j]) / (2.0 * dph * dph * s * s);
+        d.up = (nuf[j] + nuf[j]) * sfu / (2.0 * dth * dth * s);
+        d.dn = (nuf[j + 1] + nuf[j + 1]) * sfd / (2.0 * dth * dth * s);
         d.d = -(d.up + d.dn + d.ph + d.ph);
         out[j] = d;
+    }
+}
+
+// Corner diffusivities of one realization: the scalar nu everywhere, or the
+// grid diffusivity of eq. diffgrid, alpha [dth^2 + (dph sin theta_f)^2]
+// (sin = 0 at the pole faces).
+void corner_nu(int nt, int np, const sft_params& p, std::vector<double>& nuf)
+{
+    const double dth = M_PI / nt, dph = 2.0 * M_PI / np;
+    nuf.assign(nt + 1, p.nu_km2_s * KM2_S_TO_RS2_HR);
+    if (p.nu_grid_alpha > 0.0) {
+        for (int f = 0; f <= nt; ++f) {
+            const double sf = (f == 0 || f == nt) ? 0.0 : sin(f * dth);
+            const double x = dph * sf;
+            nuf[f] = p.nu_grid_alpha * (dth * dth + x * x);
+        }
     }
 }
 
@@ -520,7 +541,7 @@ sft_status build_plan(sft_ctx* c, GridClass* g, double t0, double t_end, double 
             int ncall_max = 0;
             std::vector<int> ncall(g->R, 0);
             for (int r = 0; r < g->R; ++r) {
-                if (i >= seq[r].size() || !(g->prm[r].nu_km2_s > 0.0)) continue;
+                if (i >= seq[r].size() || !std::isfinite(g->dtE[r])) continue;
                 const double dt = seq[r][i];
                 int nc = 1;
                 if (o.ptl_dt > 0.0 && dt > o.ptl_dt) nc = (int)ceil(dt / o.ptl_dt);
@@ -1115,7 +1136,7 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
     g->cfl.assign(R, INFINITY);
     g->dtE.assign(R, INFINITY);
     g->has_flow.assign(R, 0);
-    std::vector<double> vph, vth;
+    std::vector<double> vph, vth, nuf;
     std::vector<DiffRow<double>> drow;
     for (int r = 0; r < R; ++r) {
         const sft_params& p = g->prm[r];
@@ -1151,8 +1172,8 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
             b.vph = (float)a.vph;
             a32[(size_t)r * (nt + 1) + j] = b;
         }
-        const double nu = p.nu_km2_s * KM2_S_TO_RS2_HR;
-        diff_rows(nt, np, nu, drow);
+        corner_nu(nt, np, p, nuf);
+        diff_rows(nt, np, nuf, drow);
         double m = 0.0;
         for (int j = 0; j < nt; ++j) {
             d64[(size_t)r * nt + j] = drow[j];
@@ -1290,7 +1311,8 @@ sft_status sft_add_realizations(sft_ctx* c, int32_t grid_id, int32_t n, const sf
     for (int i = 0; i < n; ++i) {
         const sft_params& p = prm[i];
         if (!(p.nu_km2_s >= 0.0) || !std::isfinite(p.nu_km2_s) || !(p.alpha_mu > 0.0) ||
-            !(p.lat_lim_deg >= 0.0) || !(p.att_b0 >= 0.0) || !std::isfinite(p.att_b0))
+            !(p.lat_lim_deg >= 0.0) || !(p.att_b0 >= 0.0) || !std::isfinite(p.att_b0) ||
+            !(p.nu_grid_alpha >= 0.0) || !std::isfinite(p.nu_grid_alpha))
             return fail(c, SFT_ERR_ARG, "realization %d: invalid parameters", i);
     }
     // ids are consecutive over grid classes in creation order

@@ -135,6 +135,7 @@ class Realization:
     lat_lim_deg: float = 90.0
     flux_balance: int = 0
     att_b0: float = 0.0        # flow attenuation saturation field, gauss (0 = off)
+    nu_grid_alpha: float = 0.0  # grid-diffusivity factor of the smoother, 1/h (0 = scalar nu)
 
     @property
     def flow(self):

@@ -52,7 +52,8 @@ def oracle_run(B0, reals, schedule, opts=None):
         for ev in schedule:
             if ev[0] == "advance":
                 B, s = oracle.advance(B, real.flow, real.nu_km2_s, t, ev[1],
-                                      att_b0=getattr(real, "att_b0", 0.0), **opts)
+                                      att_b0=getattr(real, "att_b0", 0.0),
+                                      nu_grid_alpha=getattr(real, "nu_grid_alpha", 0.0), **opts)
                 st["steps"] += s["steps"]
                 st["stages"] += s["stages"]
                 t = ev[1]

@@ -56,7 +56,7 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_2501_06377_amd import _abi
     fields = {"sft_options": ["cfl_safety", "use_graphs", "diag_every_call", "strang", "rfe_model",
                               "rfe_seed", "rfe_phi_hr", "rfe_lifetime_h"],
-              "sft_params": ["nu_km2_s", "lat_lim_deg", "flux_balance", "att_b0"],
+              "sft_params": ["nu_km2_s", "lat_lim_deg", "flux_balance", "att_b0", "nu_grid_alpha"],
               "sft_diag": ["steps", "phi_pos", "nonfinite", "surr_accept"]}
     lines = ['#include "sft.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void){"]
     for st, fs in fields.items():
