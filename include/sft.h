@@ -261,7 +261,7 @@ sft_status sft_counts(sft_ctx* ctx, int32_t real_id, int64_t* steps, int64_t* st
 
 /* ------------------------------------------------------------------------
  * Learned surrogate of one 1-hour transport interval (no counterpart in the
- * paper; its plain solver above is both the fallback and the judge).
+ * paper; its plain solver above is both the fallback and the arbiter of its error).
  * Network: five 3x3 convolutions 6 -> 64 -> 64 -> 64 -> 64 -> 1 on the
  * sphere (longitude wraps; the ghost row beyond a pole is the pole row
  * shifted by half a turn), ReLU after the first four, input channels

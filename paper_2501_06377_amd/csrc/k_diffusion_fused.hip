@@ -222,13 +222,45 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
                 const size_t i = base + (size_t)j * np + kc[c];
                 a = in1[i];
                 if (has_in2) b = in2[i];
-                l = ly0[i];
-                if constexpr (!MIXED) z = y0[i];
+                if constexpr (MIXED) l = ly0[i];
+                else z = y0[i];
             }
             ya[m][c] = a;
             yb[m][c] = b;
             lyr[m][c] = l;
             if constexpr (!MIXED) y0r[m][c] = z;
+        }
+    }
+
+    // FP64: L(Y0) of the staged region from the staged Y0 (the first-stage
+    // kernel's operator, the same helper and operand order, so the same
+    // bits) instead of reading a fourth array.  The outer ring's value is
+    // wrong (its outer neighbours read as zero) but, being a pointwise term,
+    // it spoils nothing the ring's own wrong stage values do not already.
+    if constexpr (!MIXED) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            xch[1][0][w][lane * CPL + c] = y0r[0][c];
+            xch[1][1][w][lane * CPL + c] = y0r[RPT - 1][c];
+        }
+        __syncthreads();
+        T north[CPL], south[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            north[c] = w > 0 ? xch[1][1][w - 1][lane * CPL + c] : T(0);
+            south[c] = w < NW - 1 ? xch[1][0][w + 1][lane * CPL + c] : T(0);
+        }
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            const DiffRow<T> d = dr[min(max(jw + m, 0), nt - 1)];
+            const T wl = lane_west((T)y0r[m][CPL - 1]), el = lane_east((T)y0r[m][0]);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const T wv = c > 0 ? (T)y0r[m][c - 1] : wl;
+                const T ev = c < CPL - 1 ? (T)y0r[m][c + 1] : el;
+                lyr[m][c] = L5<T>(d, wv, m > 0 ? (T)y0r[m - 1][c] : north[c], (T)y0r[m][c],
+                                  m < RPT - 1 ? (T)y0r[m + 1][c] : south[c], ev);
+            }
         }
     }
 
@@ -326,6 +358,8 @@ static const FusedCfg kCfg32[] = {
 int fused_config_count(bool mixed) { return mixed ? 12 : 12; }
 
 int fused_config_k(bool mixed, int cfg) { return mixed ? kCfg32[cfg].k : kCfg64[cfg].k; }
+
+bool fused_config_reads_ly0(bool mixed, int cfg) { return mixed || cfg < 5; }
 
 void fused_config_desc(bool mixed, int cfg, int* tx, int* ty, int* k, int* nthr)
 {

@@ -740,7 +740,7 @@ void run_fused_groups(sft_ctx* c, GridClass* g, Plan* p, const Phase& ph)
                 if (!mixed) alg += 40.0;
                 else alg += (jj == 2 ? 12.0 : 16.0) + (jj == e.s ? 12.0 + (e.pad ? 4.0 : 0.0) : 0.0);
             }
-            if (!mixed) mn += fin ? 40.0 : 48.0;
+            if (!mixed) mn += (fin ? 40.0 : 48.0) - (fused_config_reads_ly0(false, g->tile) ? 0.0 : 8.0);
             else mn += (in2 ? 12.0 : 8.0) + (fin ? 16.0 + (e.pad ? 4.0 : 0.0) : 8.0);
         }
         tbeg(c);

@@ -102,6 +102,9 @@ void launch_diff_stage_mixed(hipStream_t st, const Entry* ents, int n_act, const
 //   FP64 copy of Y0 (paper form only).
 int fused_config_count(bool mixed);
 int fused_config_k(bool mixed, int cfg);
+// Whether the shape reads L(Y0) from memory (FP64 strip shapes compute it
+// from the staged Y0).
+bool fused_config_reads_ly0(bool mixed, int cfg);
 void fused_config_desc(bool mixed, int cfg, int* tx, int* ty, int* k, int* nthr);
 void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, int n_act,
                        const StageCoef* coefs, int j0, const void* drow, const void* in1,

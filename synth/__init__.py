@@ -197,6 +197,16 @@ def config3(hours: float = 655.2, n: int = 32) -> Workload:
                     1.0, 200)
 
 
+def smoother(n_maps: int = 1, alpha: float = 0.5) -> Workload:
+    """Flux-preserving smoothing: 512x1024 map(s), the grid diffusivity of
+    eq. diffgrid with alpha = 0.5 (the paper's smoothing example), no flows,
+    no assimilation; each hour of the advance smooths further."""
+    rs = [Realization(nu_km2_s=0.0, d0=0.0, d2=0.0, d4=0.0, m1=0.0, nu_grid_alpha=alpha)
+          for _ in range(n_maps)]
+    return Workload(f"smoother-f64-512x1024-r{n_maps}-alpha{alpha:g}", [(512, 1024, rs)], 1.0, "f64", 0.0,
+                    200)
+
+
 def config4(hours: float = 168.0, n_each: int = 32) -> Workload:
     """Batching: 96 realizations of uneven sizes, FP32, 7 days, no assimilation."""
     return Workload("batched-f32-uneven-r96-7d",
