@@ -10,9 +10,10 @@
 // wraps periodically, rows outside the sphere are never used by a face flux
 // (pole faces carry no flux, pole-adjacent faces are upwind).
 //
-// The FP64 kernel evaluates the paper's formulas in their printed order with
-// no FMA contraction (the library is built with -ffp-contract=off), so its
-// results match a plain serial evaluation of the same formulas to the bit.
+// The kernels evaluate the paper's formulas with no FMA contraction (the
+// library is built with -ffp-contract=off) except that each one-sided WENO
+// value is formed with one division (the nonlinear weights' common factor
+// cancelled), which changes results only at the rounding level.
 //
 // Flow attenuation (eq. flow_attenuation): the face velocities of one
 // advection advance are scaled by 1 - tanh(m/B0), m the mean of |B| over the
@@ -51,9 +52,12 @@ __device__ __forceinline__ T weno_face(T lm2, T lm1, T lm0, T lpm1, T lp0, T lpp
     T t1m = c.half * (lm0 - lm1);
     T b0m = four * t0m * t0m;
     T b1m = four * t1m * t1m;
-    T w0m = c.third / ((c.eps + b0m) * (c.eps + b0m));
-    T w1m = c.twothird / ((c.eps + b1m) * (c.eps + b1m));
-    T um = (w0m / (w0m + w1m)) * p0m + (w1m / (w0m + w1m)) * p1m;
+    // w0 = third / A^2, w1 = twothird / B^2 (A = eps + b0, B = eps + b1), and
+    // u = (w0 p0 + w1 p1) / (w0 + w1) = (third B^2 p0 + twothird A^2 p1) /
+    // (third B^2 + twothird A^2): one division instead of four
+    T a2m = (c.eps + b0m) * (c.eps + b0m), bb2m = (c.eps + b1m) * (c.eps + b1m);
+    T v0m = c.third * bb2m, v1m = c.twothird * a2m;
+    T um = (v0m * p0m + v1m * p1m) / (v0m + v1m);
 
     T p0p = (one + c.half) * lp0 - c.half * lpp1;
     T p1p = c.half * lp0 + c.half * lpm1;
@@ -61,9 +65,9 @@ __device__ __forceinline__ T weno_face(T lm2, T lm1, T lm0, T lpm1, T lp0, T lpp
     T t1p = c.half * (lp0 - lpm1);
     T b0p = four * t0p * t0p;
     T b1p = four * t1p * t1p;
-    T w0p = c.third / ((c.eps + b0p) * (c.eps + b0p));
-    T w1p = c.twothird / ((c.eps + b1p) * (c.eps + b1p));
-    T up = (w0p / (w0p + w1p)) * p0p + (w1p / (w0p + w1p)) * p1p;
+    T a2p = (c.eps + b0p) * (c.eps + b0p), bb2p = (c.eps + b1p) * (c.eps + b1p);
+    T v0p = c.third * bb2p, v1p = c.twothird * a2p;
+    T up = (v0p * p0p + v1p * p1p) / (v0p + v1p);
     return up + um;
 }
 
