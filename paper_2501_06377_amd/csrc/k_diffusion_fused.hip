@@ -292,6 +292,11 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
         // coefficients (wave-uniform scalar loads) can be issued early.
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
+            // rows i and closer to the top / bottom of the staged region are
+            // already wrong after this stage whatever is computed for them
+            // (and no row that stays right reads them), so they are skipped
+            const int ly = w * RPT + m;
+            if (ly < i || ly >= LY - i) continue;
             const DiffRow<T> d = dr[min(max(jw + m, 0), nt - 1)];
             const T wl = lane_west(cur[m][CPL - 1]), el = lane_east(cur[m][0]);
 #pragma unroll
