@@ -109,7 +109,12 @@ typedef struct {
                              maps (unsigned flux per unit area)                         */
     uint32_t rfe_seed;    /* key word 0 of every source map's generator; key word 1 is
                              the realization id                                         */
-    int32_t reserved;
+    int32_t lanes;        /* concurrent sub-batches per grid class, 0..16: realizations
+                             r with r mod lanes = l advance on stream l (the context's
+                             stream for l = 0, library streams for the others, joined
+                             before the call returns), so one sub-batch's launches fill
+                             the GPU while another's drain; 0 (default) = min(2, R),
+                             1 = all on the context's stream; results do not depend on it */
     double rfe_phi_hr;    /* total unsigned flux per hour of a source map, Mx (> 0 when
                              rfe_model != 0)                                            */
     double rfe_lifetime_h;/* time between source maps tau, hours; 0 = infinite (one map) */

@@ -33,7 +33,7 @@ class sft_options(ctypes.Structure):
                 ("ptl_dt", ctypes.c_double), ("use_graphs", ctypes.c_int32),
                 ("sts_fuse", ctypes.c_int32), ("diag_every_call", ctypes.c_int32),
                 ("sts_tile", ctypes.c_int32), ("strang", ctypes.c_int32),
-                ("rfe_model", ctypes.c_int32), ("rfe_seed", ctypes.c_uint32), ("reserved", ctypes.c_int32),
+                ("rfe_model", ctypes.c_int32), ("rfe_seed", ctypes.c_uint32), ("lanes", ctypes.c_int32),
                 ("rfe_phi_hr", ctypes.c_double), ("rfe_lifetime_h", ctypes.c_double)]
 
 

@@ -59,7 +59,7 @@ __device__ __forceinline__ void block_sum2_rfe(double& a, double& b, double* red
     b = red[GB];
 }
 
-__global__ __launch_bounds__(GB) void rfe_gen_kernel(int first_id, uint32_t seed,
+__global__ __launch_bounds__(GB) void rfe_gen_kernel(int nl, int lane, int first_id, uint32_t seed,
                                                      const int64_t* __restrict__ kdev, int koff,
                                                      int64_t kabs, const double* __restrict__ scale_row,
                                                      const double* __restrict__ w_row,
@@ -68,6 +68,7 @@ __global__ __launch_bounds__(GB) void rfe_gen_kernel(int first_id, uint32_t seed
 {
     __shared__ double red[2 * GB];
     const int r = blockIdx.y;
+    if (lane >= 0 && r % nl != lane) return;   // another lane's realization (block-uniform)
     const int64_t k = map_index(kdev, koff, kabs);
     const size_t cells = (size_t)nt * np;
     double* S = ((k & 1) ? S1 : S0) + (size_t)r * cells;
@@ -103,12 +104,28 @@ __global__ __launch_bounds__(GB) void rfe_gen_kernel(int first_id, uint32_t seed
     }
 }
 
-__global__ __launch_bounds__(GB) void rfe_balance_kernel(const int64_t* __restrict__ kdev, int koff,
+__global__ __launch_bounds__(GB) void rfe_reduce_kernel(int nl, int lane, const double* __restrict__ partial,
+                                                        int nblk, double* __restrict__ ratio)
+{
+    __shared__ double red[2 * GB];
+    const int r = blockIdx.x;
+    if (lane >= 0 && r % nl != lane) return;
+    double pp = 0.0, pm = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += GB) {
+        pp += partial[((size_t)r * nblk + b) * 2 + 0];
+        pm += partial[((size_t)r * nblk + b) * 2 + 1];
+    }
+    block_sum2_rfe(pp, pm, red);
+    if (threadIdx.x == 0) ratio[r] = (pp != 0.0 && pm != 0.0) ? sqrt(fabs(pp / pm)) : 0.0;
+}
+
+__global__ __launch_bounds__(GB) void rfe_balance_kernel(int nl, int lane, const int64_t* __restrict__ kdev, int koff,
                                                          int64_t kabs, const double* __restrict__ ratio,
                                                          double* __restrict__ S0, double* __restrict__ S1,
                                                          size_t cells)
 {
     const int r = blockIdx.y;
+    if (lane >= 0 && r % nl != lane) return;
     const double rr = ratio[r];
     if (rr == 0.0) return;
     const int64_t k = map_index(kdev, koff, kabs);
@@ -161,12 +178,15 @@ int rfe_gen_blocks(int nt, int np)
     return (int)(nb < (size_t)GMAXB ? nb : (size_t)GMAXB);
 }
 
-void launch_rfe_gen(hipStream_t st, int R, int first_id, uint32_t seed, const int64_t* kdev, int koff,
-                    int64_t kabs, const double* scale_row, const double* w_row, double* S0, double* S1,
-                    double* partial, int nt, int np)
+void launch_rfe_gen(hipStream_t st, int R, int nl, int lane, int first_id, uint32_t seed,
+                    const int64_t* kdev, int koff, int64_t kabs, const double* scale_row,
+                    const double* w_row, double* S0, double* S1, double* partial, double* ratio, int nt,
+                    int np)
 {
-    hipLaunchKernelGGL(rfe_gen_kernel, dim3(rfe_gen_blocks(nt, np), R), dim3(GB), 0, st, first_id, seed,
-                       kdev, koff, kabs, scale_row, w_row, S0, S1, partial, nt, np);
+    const int nblk = rfe_gen_blocks(nt, np);
+    hipLaunchKernelGGL(rfe_gen_kernel, dim3(nblk, R), dim3(GB), 0, st, nl, lane, first_id, seed, kdev, koff,
+                       kabs, scale_row, w_row, S0, S1, partial, nt, np);
+    hipLaunchKernelGGL(rfe_reduce_kernel, dim3(R), dim3(GB), 0, st, nl, lane, partial, nblk, ratio);
 }
 
 static int grid_for(size_t cells)
@@ -175,12 +195,12 @@ static int grid_for(size_t cells)
     return (int)(nb < 2048 ? nb : 2048);
 }
 
-void launch_rfe_balance(hipStream_t st, int R, const int64_t* kdev, int koff, int64_t kabs,
-                        const double* ratio, double* S0, double* S1, int nt, int np)
+void launch_rfe_balance(hipStream_t st, int R, int nl, int lane, const int64_t* kdev, int koff,
+                        int64_t kabs, const double* ratio, double* S0, double* S1, int nt, int np)
 {
     const size_t cells = (size_t)nt * np;
-    hipLaunchKernelGGL(rfe_balance_kernel, dim3(grid_for(cells), R), dim3(GB), 0, st, kdev, koff, kabs,
-                       ratio, S0, S1, cells);
+    hipLaunchKernelGGL(rfe_balance_kernel, dim3(grid_for(cells), R), dim3(GB), 0, st, nl, lane, kdev, koff,
+                       kabs, ratio, S0, S1, cells);
 }
 
 void launch_rfe_set(hipStream_t st, int64_t* kdev, int64_t k)

@@ -101,7 +101,9 @@ struct GridClass {
     void* stage_in = nullptr;    // host-upload staging for assimilation inputs (2 maps)
     bool diag_valid = false;
     int tile = -2;               // blocked tile shape (-1 = unfused, -2 = not chosen yet)
-    std::map<uint64_t, Plan*> plans;
+    std::map<uint64_t, std::vector<Plan*>> plans;   // one plan per lane
+    int nl = 1;                                     // lanes (concurrent sub-batches)
+    std::vector<hipEvent_t> lane_ev;                // fork + one join per extra lane
     // surrogate buffers (allocated on first use)
     double* pred = nullptr;
     float* sfeat = nullptr;
@@ -131,6 +133,7 @@ struct sft_ctx {
     std::map<uint64_t, GraphEntry> graphs;
     std::string err;
     std::vector<void*> allocs;
+    std::vector<hipStream_t> lane_st;   // library streams of lanes 1, 2, ...
     // per-kernel-family event timing (sft_set_timing)
     struct Pending {
         hipEvent_t a, b;
@@ -459,8 +462,10 @@ void segments(double t0, double t_end, bool cut, double tau, std::vector<Segment
     if (cut && rfe_interval(t_end, tau) == out.back().k + 1) out.back().tick_after = true;
 }
 
-sft_status build_plan(sft_ctx* c, GridClass* g, double t0, double t_end, double len, Plan** out)
+sft_status build_plan(sft_ctx* c, GridClass* g, int lane, double t0, double t_end, double len, Plan** out)
 {
+    // the lane's realizations: r % nl == lane
+    auto off = [&](int r) { return r % g->nl != lane; };
     const sft_options& o = c->opt;
     const bool mixed = o.precision == SFT_FP32_MIXED;
     const bool rfe = o.rfe_model != 0;
@@ -491,6 +496,10 @@ sft_status build_plan(sft_ctx* c, GridClass* g, double t0, double t_end, double 
         const double slen = segs.size() == 1 ? len : sg.b - sg.a;
         size_t max_steps = 0;
         for (int r = 0; r < g->R; ++r) {
+            if (off(r)) {
+                seq[r].clear();
+                continue;
+            }
             step_sequence(slen, (strang ? 2.0 : 1.0) * o.cfl_safety * g->cfl[r], o.dt_max, seq[r]);
             max_steps = std::max(max_steps, seq[r].size());
             el[r] = 0.0;
@@ -840,21 +849,22 @@ sft_status choose_tile(sft_ctx* c, GridClass* g)
     return SFT_OK;
 }
 
-// Source map (kdev[0] + koff, or kabs without kdev) of every realization of
-// a class: draw, FP64 flux sums, eq. fluxbal balance.
-void rfe_make_map(sft_ctx* c, GridClass* g, const int64_t* kdev, int koff, int64_t kabs)
+// Source map (kdev[0] + koff, or kabs without kdev) of the realizations of
+// one lane of a class (lane < 0: all): draw, FP64 flux sums, eq. fluxbal
+// balance.
+void rfe_make_map(sft_ctx* c, GridClass* g, const int64_t* kdev, int koff, int64_t kabs, int lane)
 {
+    const double nr = lane < 0 ? g->R : (g->R - lane + g->nl - 1) / g->nl;
     tbeg(c);
-    launch_rfe_gen(c->stream, g->R, g->first_id, c->opt.rfe_seed, kdev, koff, kabs, g->rfe_scale, g->w_row,
-                   g->rfe_S[0], g->rfe_S[1], g->rfe_partial, g->nt, g->np);
-    launch_assim_reduce(c->stream, g->R, g->rfe_partial, g->rfe_nblk, g->rfe_ratio);
-    launch_rfe_balance(c->stream, g->R, kdev, koff, kabs, g->rfe_ratio, g->rfe_S[0], g->rfe_S[1], g->nt,
-                       g->np);
-    tend(c, SFT_KFAM_SOURCE, 24.0 * (double)g->cells() * g->R);
+    launch_rfe_gen(c->stream, g->R, g->nl, lane, g->first_id, c->opt.rfe_seed, kdev, koff, kabs, g->rfe_scale,
+                   g->w_row, g->rfe_S[0], g->rfe_S[1], g->rfe_partial, g->rfe_ratio, g->nt, g->np);
+    launch_rfe_balance(c->stream, g->R, g->nl, lane, kdev, koff, kabs, g->rfe_ratio, g->rfe_S[0], g->rfe_S[1],
+                       g->nt, g->np);
+    tend(c, SFT_KFAM_SOURCE, 24.0 * (double)g->cells() * nr);
 }
 
-// Enqueue every phase of a plan.
-void run_plan(sft_ctx* c, GridClass* g, Plan* p)
+// Enqueue every phase of a lane's plan on the context's current stream.
+void run_plan(sft_ctx* c, GridClass* g, Plan* p, int lane)
 {
     const sft_options& o = c->opt;
     const bool mixed = o.precision == SFT_FP32_MIXED;
@@ -1002,16 +1012,16 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p)
             // source sub-advance on the FP64 state (both precisions)
             const int inf = o.rfe_lifetime_h > 0.0 ? 0 : 1;
             tbeg(c);
-            launch_rfe_apply(st, E, ph.n_ent, p->d_alpha, g->rfe_kdev, inf, g->rfe_S[0], g->rfe_S[1], g->B,
-                             g->cells());
+            launch_rfe_apply(st, E, ph.n_ent, p->d_alpha, g->rfe_kdev + lane, inf, g->rfe_S[0], g->rfe_S[1],
+                             g->B, g->cells());
             tend(c, SFT_KFAM_SOURCE, (inf ? 24.0 : 32.0) * cells * ne);
         } else if (ph.kind == 7) {
             // a step ended on map time (k+1) tau: k += 1, draw map k + 2 into
             // the slot map k held
             tbeg(c);
-            launch_rfe_tick(st, g->rfe_kdev);
+            launch_rfe_tick(st, g->rfe_kdev + lane);
             tend(c, SFT_KFAM_SOURCE, 0.0);
-            rfe_make_map(c, g, g->rfe_kdev, 1, 0);
+            rfe_make_map(c, g, g->rfe_kdev + lane, 1, 0, lane);
         }
     }
 }
@@ -1068,6 +1078,7 @@ sft_status sft_create(sft_ctx** ctx, const sft_options* opt, void* hip_stream)
     if (o.adv_time != SFT_SSPRK43 && o.adv_time != SFT_FE && o.adv_time != SFT_SSPRK33) return SFT_ERR_ARG;
     if (o.strang != 0 && o.strang != 1) return SFT_ERR_ARG;
     if (o.rfe_model < 0 || o.rfe_model > 2) return SFT_ERR_ARG;
+    if (o.lanes < 0 || o.lanes > 16) return SFT_ERR_ARG;
     if (o.rfe_model && (!(o.rfe_phi_hr > 0.0) || !std::isfinite(o.rfe_phi_hr) ||
                         !(o.rfe_lifetime_h >= 0.0) || !std::isfinite(o.rfe_lifetime_h)))
         return SFT_ERR_ARG;
@@ -1119,6 +1130,16 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
     const int nt = g->nt, np = g->np, R = g->R;
     const size_t n = (size_t)R * g->cells();
     const bool mixed = c->opt.precision == SFT_FP32_MIXED;
+    // lanes: concurrent sub-batches r % nl, each on its own stream
+    g->nl = std::max(1, std::min(c->opt.lanes > 0 ? c->opt.lanes : 2, R));
+    while ((int)c->lane_st.size() < g->nl - 1) {
+        hipStream_t s;
+        HIPCHK(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        c->lane_st.push_back(s);
+    }
+    g->lane_ev.assign(g->nl, nullptr);
+    for (int l = 0; l < g->nl && g->nl > 1; ++l)
+        HIPCHK(c, hipEventCreateWithFlags(&g->lane_ev[l], hipEventDisableTiming));
     TRY(dalloc(c, &g->B, n));
     HIPCHK(c, hipMemset(g->B, 0, n * sizeof(double)));
     if (!mixed) {
@@ -1219,7 +1240,7 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
         }
         TRY(dalloc(c, &g->rfe_scale, nt));
         TRY(upload(c, g->rfe_scale, sc));
-        TRY(dalloc(c, &g->rfe_kdev, 1));
+        TRY(dalloc(c, &g->rfe_kdev, g->nl));
         g->rfe_nblk = rfe_gen_blocks(nt, np);
         TRY(dalloc(c, &g->rfe_partial, (size_t)R * g->rfe_nblk * 2));
         TRY(dalloc(c, &g->rfe_ratio, R));
@@ -1438,10 +1459,12 @@ static void drop_plans(sft_ctx* c)
     c->graphs.clear();
     for (auto* g : c->grids) {
         for (auto& kv : g->plans) {
-            dfree(c, kv.second->d_ents);
-            dfree(c, kv.second->d_coefs);
-            dfree(c, kv.second->d_alpha);
-            delete kv.second;
+            for (Plan* p : kv.second) {
+                dfree(c, p->d_ents);
+                dfree(c, p->d_coefs);
+                dfree(c, p->d_alpha);
+                delete p;
+            }
         }
         g->plans.clear();
     }
@@ -1480,7 +1503,7 @@ static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
         for (auto* g : c->grids) np_max = std::max(np_max, g->plans.size());
         if (np_max >= 64) drop_plans(c);
     }
-    std::vector<Plan*> plans;
+    std::vector<std::vector<Plan*>*> plans;   // per class: one plan per lane
     for (size_t gi = 0; gi < c->grids.size(); ++gi) {
         GridClass* g = c->grids[gi];
         if (!g->R || (int)gi == skip_gid) {
@@ -1489,25 +1512,47 @@ static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
         }
         const uint64_t key = dbits(len) ^ rkey;
         auto it = g->plans.find(key);
-        Plan* p;
         if (it == g->plans.end()) {
-            TRY(build_plan(c, g, c->t, t_end, len, &p));
-            g->plans[key] = p;
-        } else {
-            p = it->second;
+            std::vector<Plan*> lp(g->nl, nullptr);
+            for (int l = 0; l < g->nl; ++l) {
+                sft_status st = build_plan(c, g, l, c->t, t_end, len, &lp[l]);
+                if (st != SFT_OK) {
+                    for (Plan* q : lp) delete q;
+                    return st;
+                }
+            }
+            it = g->plans.emplace(key, lp).first;
         }
-        plans.push_back(p);
+        plans.push_back(&it->second);
     }
+    // lanes of a class run on their own streams between a fork and a join
+    // on the context's stream (captured as parallel branches in graphs)
     auto enqueue = [&]() {
+        const hipStream_t main = c->stream;
         for (size_t i = 0; i < c->grids.size(); ++i) {
             GridClass* g = c->grids[i];
             if (!plans[i]) continue;
-            run_plan(c, g, plans[i]);
+            const std::vector<Plan*>& lp = *plans[i];
+            if (g->nl > 1) {
+                (void)hipEventRecord(g->lane_ev[0], main);
+                for (int l = 1; l < g->nl; ++l) (void)hipStreamWaitEvent(c->lane_st[l - 1], g->lane_ev[0], 0);
+            }
+            for (int l = 0; l < g->nl; ++l) {
+                c->stream = l == 0 ? main : c->lane_st[l - 1];
+                run_plan(c, g, lp[l], l);
+            }
+            c->stream = main;
+            if (g->nl > 1) {
+                for (int l = 1; l < g->nl; ++l) {
+                    (void)hipEventRecord(g->lane_ev[l], c->lane_st[l - 1]);
+                    (void)hipStreamWaitEvent(main, g->lane_ev[l], 0);
+                }
+            }
             if (c->opt.diag_every_call) launch_diag_class(c, g);
         }
     };
     bool work = false;
-    for (Plan* p : plans) work |= p != nullptr;
+    for (auto* p : plans) work |= p != nullptr;
     if (!work) {
         c->t = t_end;
         return SFT_OK;
@@ -1519,10 +1564,10 @@ static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
             GridClass* g = c->grids[i];
             if (!plans[i] || g->rfe_k == k0) continue;
             tbeg(c);
-            launch_rfe_set(c->stream, g->rfe_kdev, k0);
+            for (int l = 0; l < g->nl; ++l) launch_rfe_set(c->stream, g->rfe_kdev + l, k0);
             tend(c, SFT_KFAM_SOURCE, 0.0);
-            rfe_make_map(c, g, nullptr, 0, k0);
-            if (tau > 0.0) rfe_make_map(c, g, nullptr, 0, k0 + 1);
+            rfe_make_map(c, g, nullptr, 0, k0, -1);
+            if (tau > 0.0) rfe_make_map(c, g, nullptr, 0, k0 + 1, -1);
             g->rfe_k = k0;
         }
     }
@@ -1545,14 +1590,15 @@ static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
     }
     for (size_t i = 0; i < c->grids.size(); ++i) {
         GridClass* g = c->grids[i];
-        Plan* p = plans[i];
-        if (!p) continue;
-        g->rfe_k += p->ticks;
-        for (int r = 0; r < g->R; ++r) {
-            g->steps[r] += p->steps[r];
-            g->stages[r] += p->stages[r];
-            g->adv_stages[r] += p->adv_stages[r];
-            if (p->steps[r]) g->dt_last[r] = p->dt_last[r];
+        if (!plans[i]) continue;
+        g->rfe_k += (*plans[i])[0]->ticks;   // every lane steps onto the same map times
+        for (Plan* p : *plans[i]) {
+            for (int r = 0; r < g->R; ++r) {
+                g->steps[r] += p->steps[r];
+                g->stages[r] += p->stages[r];
+                g->adv_stages[r] += p->adv_stages[r];
+                if (p->steps[r]) g->dt_last[r] = p->dt_last[r];
+            }
         }
         if (c->opt.diag_every_call) g->diag_valid = true;
         else g->diag_valid = false;
@@ -1807,6 +1853,7 @@ sft_status sft_destroy(sft_ctx* c)
 {
     if (!c) return SFT_ERR_ARG;
     (void)hipStreamSynchronize(c->stream);
+    for (hipStream_t s : c->lane_st) (void)hipStreamSynchronize(s);
     for (auto& kv : c->graphs) {
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
         if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
@@ -1815,8 +1862,12 @@ sft_status sft_destroy(sft_ctx* c)
     for (hipEvent_t e : c->free_ev) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    for (hipStream_t s : c->lane_st) (void)hipStreamDestroy(s);
     for (auto* g : c->grids) {
-        for (auto& kv : g->plans) delete kv.second;
+        for (auto& kv : g->plans)
+            for (Plan* p : kv.second) delete p;
+        for (hipEvent_t e : g->lane_ev)
+            if (e) (void)hipEventDestroy(e);
         delete g;
     }
     delete c;

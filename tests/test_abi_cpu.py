@@ -54,7 +54,7 @@ def test_struct_layouts_match_header(tmp_path):
     """ctypes structures have the sizes and field offsets the C compiler gives."""
     import subprocess
     from paper_2501_06377_amd import _abi
-    fields = {"sft_options": ["cfl_safety", "use_graphs", "diag_every_call", "strang", "rfe_model",
+    fields = {"sft_options": ["cfl_safety", "use_graphs", "diag_every_call", "strang", "rfe_model", "lanes",
                               "rfe_seed", "rfe_phi_hr", "rfe_lifetime_h"],
               "sft_params": ["nu_km2_s", "lat_lim_deg", "flux_balance", "att_b0", "nu_grid_alpha"],
               "sft_diag": ["steps", "phi_pos", "nonfinite", "surr_accept"]}
