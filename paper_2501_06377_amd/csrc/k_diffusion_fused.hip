@@ -14,7 +14,8 @@
 // results are bitwise identical to the one-stage-per-launch path for every
 // tile shape.
 //
-// FP64 paper form: inputs Y_{j0-1}, Y_{j0-2}, a copy of Y0 and L(Y0).
+// FP64 paper form: inputs Y_{j0-1}, Y_{j0-2}, a copy of Y0 and L(Y0) (the
+// strip variant computes L(Y0) from the staged Y0 instead of reading it).
 // FP32 increment form: inputs d_{j0-1}, d_{j0-2} (absent when j0 = 2) and
 // L(Y0).  An entry whose last stage s falls in this launch writes the final
 // field into the FP64 state B (only the cell's own value of B is read, and
@@ -153,7 +154,9 @@ __global__ __launch_bounds__(NT) void diff_fused_kernel(
 // adjacent lanes through whole-wave DPP shifts, the others and north / south
 // from the lane's own registers; only the two end rows of each strip are
 // exchanged through LDS (double-buffered by stage parity, one barrier per
-// stage).  Row coefficients are wave-uniform (scalar loads).
+// stage).  Row coefficients are wave-uniform (scalar loads).  At stage i the
+// strips skip their rows among the i outermost of the staged region.
+//
 // Value of lane l - 1 (west) / l + 1 (east) of the wave, 0 past its ends
 // (bound_ctrl: a lane whose source is out of range reads zero).
 __device__ __forceinline__ double lane_west(double v)
