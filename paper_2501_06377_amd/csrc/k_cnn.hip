@@ -179,6 +179,9 @@ struct PersistShape {
     static constexpr int PTX = CIN == 64 ? 64 : 32;   // tile columns (LDS: 158 KB / 55 KB per block)
     static constexpr int DEPTH = CIN == 64 ? 1 : 2;   // tiles in flight in registers
     static constexpr int BLOCKS_PER_CU = CIN == 64 ? 1 : 2;
+    // threads: with one block per CU, two waves per SIMD, the second four
+    // waves taking the upper 32 output channels of the same rows
+    static constexpr int NTH = CIN == 64 ? 512 : 256;
 };
 
 template <int CIN>
@@ -188,13 +191,15 @@ __device__ __forceinline__ int chunk_swz(int row, int q)
 }
 
 template <int CIN, int MODE>
-__global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __restrict__ x,
+__global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(const uint16_t* __restrict__ x,
                                                            const uint16_t* __restrict__ w,
                                                            const float* __restrict__ bias,
                                                            uint16_t* __restrict__ out, int batch, int H, int W,
                                                            const uint16_t* __restrict__ act)
 {
     constexpr int PTX = PersistShape<CIN>::PTX, DEPTH = PersistShape<CIN>::DEPTH;
+    constexpr int NTH = PersistShape<CIN>::NTH;
+    constexpr int NN = 512 / NTH;                 // 32-channel output halves per wave
     constexpr int NCG = PTX / 32;                 // 32-pixel column groups
     constexpr int NQ = CIN / 8;                   // 16-byte chunks per pixel / weight row
     constexpr int NCH = CIN / 16;                 // K chunks per tap
@@ -203,14 +208,15 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
     constexpr int TILE_E = TR * TC * CIN, OUT_E = PTY * PTX * CTS;
     constexpr int BUF_E = TILE_E > OUT_E ? TILE_E : OUT_E;
     constexpr int WE = 9 * 64 * CIN;
-    constexpr int NV = TR * TC * NQ, VPT = (NV + 255) / 256;
+    constexpr int NV = TR * TC * NQ, VPT = (NV + NTH - 1) / NTH;
     __shared__ __attribute__((aligned(16))) uint16_t wl[WE];
     __shared__ __attribute__((aligned(16))) uint16_t buf[BUF_E];
 
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = (tid >> 6) & 3;
+    const int n0 = NN == 1 ? (tid >> 8) : 0;     // first output half of this wave
     const int col = lane & 31, kh = lane >> 5;
 
-    for (int v = tid; v < 9 * 64 * NQ; v += 256) {
+    for (int v = tid; v < 9 * 64 * NQ; v += NTH) {
         const int row = v / NQ, q = v - (v / NQ) * NQ;   // row = tap * 64 + output channel
         *(uint4*)(wl + (size_t)row * CIN + chunk_swz<CIN>(row, q) * 8) = *(const uint4*)(w + (size_t)v * 8);
     }
@@ -228,7 +234,7 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
         const uint16_t* xb = x + (size_t)b * plane * CIN;
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
-            const int v = tid + i * 256;
+            const int v = tid + i * NTH;
             pre[i] = make_uint4(0, 0, 0, 0);
             if (v < NV) {
                 const int pix = v / NQ, q = v - (v / NQ) * NQ;
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
         __syncthreads();   // the previous tile's epilogue is done with buf
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
-            const int v = tid + i * 256;
+            const int v = tid + i * NTH;
             if (v < NV) {
                 const int pix = v / NQ, q = v - (v / NQ) * NQ;
                 *(uint4*)(buf + (size_t)pix * CIN + chunk_swz<CIN>(pix, q) * 8) = pre[i];
@@ -264,13 +270,13 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
         __syncthreads();
         if (t + DEPTH * G < ntiles) load_tile(t + DEPTH * G, pre);
 
-        f32x16 acc[PMR][NCG][2];
+        f32x16 acc[PMR][NCG][NN];
 #pragma unroll
         for (int m = 0; m < PMR; ++m)
 #pragma unroll
             for (int g = 0; g < NCG; ++g)
 #pragma unroll
-                for (int n = 0; n < 2; ++n)
+                for (int n = 0; n < NN; ++n)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) acc[m][g][n][r] = 0.f;
 #pragma unroll 1
@@ -278,12 +284,12 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 const int q = ch * 2 + kh;
-                bf16x8 bfr[3][2], afr[NCG][PMR + 2];
+                bf16x8 bfr[3][NN], afr[NCG][PMR + 2];
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                    for (int n = 0; n < 2; ++n) {
-                        const int row = (dy * 3 + dx) * 64 + n * 32 + col;
+                    for (int n = 0; n < NN; ++n) {
+                        const int row = (dy * 3 + dx) * 64 + (n0 + n) * 32 + col;
                         bfr[dy][n] = *(const bf16x8*)(wl + (size_t)row * CIN + chunk_swz<CIN>(row, q) * 8);
                     }
 #pragma unroll
@@ -300,7 +306,7 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
 #pragma unroll
                         for (int g = 0; g < NCG; ++g)
 #pragma unroll
-                            for (int n = 0; n < 2; ++n)
+                            for (int n = 0; n < NN; ++n)
                                 acc[m][g][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[g][m + dy], bfr[dy][n],
                                                                                        acc[m][g][n], 0, 0, 0);
             }
@@ -314,8 +320,8 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
 #pragma unroll
             for (int g = 0; g < NCG; ++g)
 #pragma unroll
-                for (int n = 0; n < 2; ++n) {
-                    const int c = n * 32 + col;
+                for (int n = 0; n < NN; ++n) {
+                    const int c = (n0 + n) * 32 + col;
                     const float bv = MODE == 1 ? 0.f : bias[c];
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
@@ -327,7 +333,7 @@ __global__ __launch_bounds__(256) void conv_persist_kernel(const uint16_t* __res
                 }
         }
         __syncthreads();
-        for (int v = tid; v < PTY * PTX * 8; v += 256) {
+        for (int v = tid; v < PTY * PTX * 8; v += NTH) {
             const int cv = v & 7, pix = v >> 3;
             const int rl = pix / PTX, px = pix - (pix / PTX) * PTX;
             const int row = r0 + rl, k = k0 + px;
@@ -903,8 +909,8 @@ static void launch_persist(hipStream_t st, const uint16_t* x, const uint16_t* w,
     const int rows = MODE == 1 ? H - 2 : H;
     const long tiles = (long)batch * ((rows + PTY - 1) / PTY) * ((W + PTX - 1) / PTX);
     const int nb = (int)std::min<long>(tiles, (long)PersistShape<CIN>::BLOCKS_PER_CU * persist_blocks());
-    hipLaunchKernelGGL((conv_persist_kernel<CIN, MODE>), dim3(nb), dim3(256), 0, st, x, w, bias, out, batch, H,
-                       W, act);
+    hipLaunchKernelGGL((conv_persist_kernel<CIN, MODE>), dim3(nb), dim3(PersistShape<CIN>::NTH), 0, st, x, w,
+                       bias, out, batch, H, W, act);
 }
 
 void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,
