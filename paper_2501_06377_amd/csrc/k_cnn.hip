@@ -162,14 +162,16 @@ __global__ __launch_bounds__(64) void pole_dgrad_kernel(const uint16_t* __restri
 // The 64-output convolutions of the forward pass (MODE 0: bias + ReLU) and of
 // the data gradient (MODE 1: interior rows 1..H-2, ReLU mask of the layer
 // input), as implicit GEMMs on v_mfma_f32_32x32x16_bf16 with every operand in
-// LDS.  A 256-thread block keeps all nine taps' weights resident
+// LDS.  A block (256 threads for 16 input channels, 512 for 64: one block
+// per CU, two waves per SIMD) keeps all nine taps' weights resident
 // (9 x 64 x CIN bf16) and walks output tiles of PTY x PTX pixels (with their
 // one-cell halo); a tile's input is loaded into registers DEPTH tiles ahead
 // and goes to LDS once the previous tile's epilogue is done.  Wave w computes
-// rows PMR w .. PMR w + PMR - 1 of the tile, every 32-pixel column group,
-// all 64 outputs: per column shift dx and K chunk it reads the three row
-// shifts' weight fragments and its PMR + 2 input rows once and issues
-// 3 x PMR x (PTX / 32) x 2 MFMAs.  LDS rows are stored in 16-byte chunks
+// rows PMR (w mod 4) .. PMR (w mod 4) + PMR - 1 of the tile, every 32-pixel
+// column group, and all 64 outputs (256 threads) or the 32 outputs of its
+// half w / 4 (512 threads): per column shift dx and K chunk it reads the
+// three row shifts' weight fragments and its PMR + 2 input rows once and
+// issues 3 x PMR x (PTX / 32) x (64 / 32 per wave) MFMAs.  LDS rows are stored in 16-byte chunks
 // permuted by an XOR with the row (pixel) index, so the fragment reads of 8
 // consecutive lanes hit distinct banks without padding.
 constexpr int PTY = 8, PMR = PTY / 4;   // tile rows; rows per wave
