@@ -120,6 +120,21 @@ def observation(field0: np.ndarray, t_hours: float, hour_index: int, noise_g: fl
     return (truth + noise).astype(dtype)
 
 
+# ---------------------------------------------------------- validation maps
+def soccer_ball(nt: int, np_: int) -> np.ndarray:
+    """The soccer-ball map of eq. soccerball at t = 0 on the cell centres,
+    Y_6^0 + sqrt(14/11) Y_6^5 with orthonormal harmonics (the m = 5 term is
+    the real part of the complex harmonic).  Its exact evolution under
+    diffusivity nu is the same map times exp(-42 nu t), and a full rigid
+    rotation brings it back unchanged."""
+    import scipy.special as sps
+    th = (np.arange(nt) + 0.5) * math.pi / nt
+    ph = (np.arange(np_) + 0.5) * 2.0 * math.pi / np_
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    return (sps.sph_harm_y(6, 0, TH, PH).real +
+            math.sqrt(14.0 / 11.0) * sps.sph_harm_y(6, 5, TH, PH).real)
+
+
 # ------------------------------------------------------------- realizations
 @dataclasses.dataclass
 class Realization:
@@ -212,3 +227,36 @@ def config4(hours: float = 168.0, n_each: int = 32) -> Workload:
     return Workload("batched-f32-uneven-r96-7d",
                     [(256, 512, _jittered(n_each, 40)), (512, 1024, _jittered(n_each, 41)),
                      (1024, 2048, _jittered(n_each, 42))], hours, "f32", 0.0, 200)
+
+
+# The paper's validation runs (Sec. "Test cases"): the soccer-ball map for
+# 672 h with nu = 500 km^2/s, with or without a rigid rotation of
+# 1.80766 km/s sin(theta) (one full turn in 672 h), on the default 512x1024
+# grid.  Each case names the schemes and step rule it runs with.
+SOCCER_HOURS = 672.0
+SOCCER_NU_KM2_S = 500.0
+RIGID_ROTATION_M_S = 1807.66
+
+
+@dataclasses.dataclass
+class SoccerCase:
+    name: str
+    flows: bool                 # rigid rotation on (advection + diffusion) or off (diffusion only)
+    adv: str = "ssprk43"        # "ssprk43" | "ssprk33"
+    diff: str = "rkg2"          # "rkg2" | "rkl2"
+    strang: int = 0
+    dt_max: float = 0.0         # hours; 0 = the CFL limit (or one step when there is no flow)
+
+    def realization(self) -> Realization:
+        return Realization(nu_km2_s=SOCCER_NU_KM2_S, d0=RIGID_ROTATION_M_S if self.flows else 0.0,
+                           d2=0.0, d4=0.0, m1=0.0)
+
+
+def soccer_cases() -> List[SoccerCase]:
+    return [SoccerCase("diffusion, RKL2, one 672 h step", False, diff="rkl2"),
+            SoccerCase("diffusion, RKG2, one 672 h step", False),
+            SoccerCase("advection+diffusion, dt 0.5 h", True, dt_max=0.5),
+            SoccerCase("advection+diffusion, dt 0.5 h, Strang", True, dt_max=0.5, strang=1),
+            SoccerCase("advection+diffusion, max CFL dt", True),
+            SoccerCase("advection+diffusion, max CFL dt, Strang", True, strang=1),
+            SoccerCase("advection+diffusion, max CFL dt, SSPRK(3,3)", True, adv="ssprk33")]
