@@ -44,14 +44,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=None, help="1-hour intervals (default: 655 for the "
                     "ensemble workload, 24 for the others)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("ensemble", "precision", "batching", "smoother", "soccer"),
+    ap.add_argument("--workload", choices=("ensemble", "precision", "batching", "smoother", "soccer", "plain"),
                     default="ensemble",
                     help="ensemble: 8 x 512x1024 FP64 with hourly assimilation (the headline); "
                          "precision: 32 x 1024x2048 FP32-mixed with hourly assimilation; "
                          "batching: 96 realizations in three size classes, FP32-mixed, graphs; "
                          "smoother: 512x1024 map(s) smoothed with the grid diffusivity (alpha 0.5); "
                          "soccer: the paper's timed validation runs (soccer-ball map, 512x1024, 672 h; "
-                         "--steps runs per case, default 3)")
+                         "--steps runs per case, default 3); plain: one 180x360 FP64 realization through 168 h "
+                         "in one call (--steps runs, default 10)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graphs", action="store_true", help="replay captured graphs (no per-kernel timing)")
@@ -316,13 +317,15 @@ def soccer_bench(sft, torch, args, K, W):
             w_s, cnt = once(e, g)
             walls.append(w_s)
         B = e.get_states(g)[0]
+        ti = e.tile_choice(g)
+        tile = {"index": ti, "shape_tx_ty_k_threads": sft.tile_info(0, ti) if ti >= 0 else None}
         hh = float(np.sqrt(np.sum((B - exact) ** 2) / np.sum(np.abs(B) * np.abs(exact))))
         e.close()
         wall = float(np.mean(walls))
         upd = nt * np_ * (cnt["stages"] + cnt["adv_stages"])
         pw, ph = PAPER_SOCCER[c.name]
         row = {"case": c.name, "wall_s": wall, "wall_s_min": float(np.min(walls)), "steps": cnt["steps"],
-               "sts_stages": cnt["stages"], "adv_stages": cnt["adv_stages"],
+               "sts_stages": cnt["stages"], "adv_stages": cnt["adv_stages"], "sts_tile": tile,
                "dt_h": synth.SOCCER_HOURS / cnt["steps"], "hh": hh,
                "realization_cell_updates_per_s": upd / wall,
                "paper_rtx3090ti": {"wall_s": pw, "hh": ph}, "paper_wall_over_this": pw / wall}
@@ -377,6 +380,85 @@ def soccer_cpu_baseline(u0, c, max_seconds):
             "sim_days_per_s": t / 24.0 / el}
 
 
+def plain_bench(sft, torch, args, K, W):
+    """The plain single-realization configuration: one 180x360 FP64
+    realization (20 bipolar pairs, eta = 500 km^2/s, the workloads' flow
+    forms) advanced through 168 h in one call, W untimed and K timed times
+    from the same initial field.  Few cells per launch: the cost is launch
+    latency, which replayed graphs remove from the host side."""
+    w = synth.config1()
+    nt, np_, reals = w.classes[0]
+    f0 = synth.bipolar_field(nt, np_, synth.bipolar_pairs(w.n_pairs, 0))
+    x0 = torch.from_numpy(f0[None].copy()).cuda()
+    graphs = bool(args.graphs)
+
+    def make(timing=False):
+        e = sft.Ensemble(precision=0, use_graphs=0 if timing else int(graphs), sts_tile=args.sts_tile)
+        return e, e.add_grid(nt, np_, reals)
+
+    def once(e, g):
+        e.set_states(g, x0)
+        e.set_time(0.0)
+        a = e.counts(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e.advance(w.hours)
+        e.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b = e.counts(0)
+        return dt, {k: b[k] - a[k] for k in ("steps", "stages", "adv_stages")}
+
+    e, g = make()
+    for _ in range(W):
+        once(e, g)
+    walls = []
+    for _ in range(K):
+        w_s, cnt = once(e, g)
+        walls.append(w_s)
+    ti = e.tile_choice(g)
+    tile = {"index": ti, "shape_tx_ty_k_threads": sft.tile_info(0, ti) if ti >= 0 else None}
+    e.close()
+    wall = float(np.mean(walls))
+    upd = nt * np_ * (cnt["stages"] + cnt["adv_stages"])
+    log(f"{w.name}: {wall * 1e3:.2f} ms per run, {cnt['steps']} steps, {cnt['stages']} STS stages")
+    out = {
+        "metric": METRIC, "value": upd / wall, "unit": "realization-cell-updates/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": wall * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "grid": [f"{nt}x{np_}x1"], "realizations": 1,
+                   "step": "one 168 h advance in one call: advection (WENO3-CS(h) + SSPRK(4,3)) + RKG2 "
+                           "diffusion at the CFL step, no assimilation",
+                   "simulated_hours": w.hours, "graphs": graphs, "sts_tiles": [tile],
+                   "run_steps": cnt["steps"], "run_sts_stages": cnt["stages"],
+                   "wall_ms_min": float(np.min(walls)) * 1e3},
+        "sim_days_per_s": w.hours / 24.0 / wall,
+    }
+    if args.timing_steps > 0:
+        e, g = make(timing=True)
+        once(e, g)
+        e.set_timing(True)
+        once(e, g)
+        out.update(roofline_fields(e.timing(), None, "one 168 h run, HIP events around every launch"))
+        e.close()
+    if not args.no_cpu_baseline:
+        import oracle
+        real = reals[0]
+        B, t, updates, el, chunk = f0.copy(), 0.0, 0, 0.0, w.hours / 8.0
+        t0 = time.perf_counter()
+        while el < args.cpu_seconds and t < w.hours:
+            B, st = oracle.advance(B, real.flow, real.nu_km2_s, t, t + chunk)
+            t += chunk
+            updates += nt * np_ * (st["stages"] + 4 * st["steps"])
+            el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": updates / el, "unit": "realization-cell-updates/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": f"first {t:g} h of the run ({nt}x{np_}, calls of {chunk:g} h; "
+                                         f"{el:.2f} s of CPU work, FP64 C oracle, OpenMP over rows)",
+                               "sim_days_per_s": t / 24.0 / el}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -392,6 +474,9 @@ def main():
 
     if args.surrogate_only:
         print(json.dumps({"surrogate": surrogate_bench(sft, torch, args.surr_batch)}), flush=True)
+        return
+    if args.workload == "plain":
+        print(json.dumps(plain_bench(sft, torch, args, args.steps or 10, args.warmup)), flush=True)
         return
     if args.workload == "soccer":
         print(json.dumps(soccer_bench(sft, torch, args, args.steps or 3, args.warmup)), flush=True)

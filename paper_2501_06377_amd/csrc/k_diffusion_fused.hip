@@ -357,13 +357,16 @@ struct FusedCfg {
 static const FusedCfg kCfg64[] = {
     {64, 16, 4, 256}, {64, 32, 8, 256}, {128, 16, 4, 256}, {32, 32, 4, 256}, {64, 32, 6, 256},
     {48, 48, 8, 256}, {48, 112, 8, 512}, {52, 116, 6, 512}, {48, 48, 8, 512},
-    {112, 48, 8, 512}, {116, 52, 6, 512}, {112, 80, 8, 512}};
+    {112, 48, 8, 512}, {116, 52, 6, 512}, {112, 80, 8, 512},
+    // short strips: more, lighter blocks for classes with few cells
+    {48, 16, 8, 512}, {56, 24, 4, 512}, {48, 32, 8, 512}};
 static const FusedCfg kCfg32[] = {
     {64, 16, 4, 256}, {64, 32, 8, 256}, {128, 32, 8, 256}, {128, 16, 8, 256}, {64, 64, 8, 512},
     {48, 48, 8, 256}, {48, 112, 8, 512}, {48, 112, 8, 256}, {52, 116, 6, 512},
-    {112, 48, 8, 512}, {112, 112, 8, 512}, {112, 112, 8, 256}};
+    {112, 48, 8, 512}, {112, 112, 8, 512}, {112, 112, 8, 256},
+    {48, 16, 8, 512}, {56, 24, 4, 512}, {48, 48, 8, 512}};
 
-int fused_config_count(bool mixed) { return mixed ? 12 : 12; }
+int fused_config_count(bool mixed) { return mixed ? 15 : 15; }
 
 int fused_config_k(bool mixed, int cfg) { return mixed ? kCfg32[cfg].k : kCfg64[cfg].k; }
 
@@ -427,7 +430,10 @@ void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, i
         case 8: S1(false, 8, 8, 8, 1); break;
         case 9: S1(false, 8, 8, 8, 2); break;
         case 10: S1(false, 6, 8, 8, 2); break;
-        default: S1(false, 8, 12, 8, 2); break;
+        case 11: S1(false, 8, 12, 8, 2); break;
+        case 12: S1(false, 8, 4, 8, 1); break;
+        case 13: S1(false, 4, 4, 8, 1); break;
+        default: S1(false, 8, 6, 8, 1); break;
         }
     } else {
         switch (cfg) {
@@ -442,7 +448,10 @@ void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, i
         case 8: S1(true, 6, 16, 8, 1); break;
         case 9: S1(true, 8, 8, 8, 2); break;
         case 10: S1(true, 8, 16, 8, 2); break;
-        default: S1(true, 8, 32, 4, 2); break;
+        case 11: S1(true, 8, 32, 4, 2); break;
+        case 12: S1(true, 8, 4, 8, 1); break;
+        case 13: S1(true, 4, 4, 8, 1); break;
+        default: S1(true, 8, 8, 8, 1); break;
         }
     }
 #undef L1
