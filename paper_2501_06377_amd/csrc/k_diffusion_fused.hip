@@ -193,13 +193,17 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     constexpr int LX = 64 * CPL, TX = LX - 2 * K, LY = NW * RPT, TY = LY - 2 * K;
     __shared__ T xch[2][2][NW][LX];   // [stage parity][top, bottom row][wave][column]
 
-    const Entry e = ents[blockIdx.z];
+    // XCD-aware order: the halo a block stages is largely in the L2 its
+    // neighbours just filled
+    int bx, by, bz;
+    xcd_tile((np + TX - 1) / TX, (nt + TY - 1) / TY, bx, by, bz);
+    const Entry e = ents[bz];
     const int kk = min(K, e.s - j0 + 1);
     const bool fin = (j0 + kk - 1 == e.s);
     const size_t base = (size_t)e.r * nt * np;
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int k0 = blockIdx.x * TX, jt0 = blockIdx.y * TY;
+    const int k0 = bx * TX, jt0 = by * TY;
     const int jw = jt0 - K + w * RPT;   // global row of the strip's first cell
     int kc[CPL];                        // global columns of the lane's cells
 #pragma unroll
@@ -402,8 +406,8 @@ static void launch_strip(hipStream_t st, const Entry* ents, int n_act, const Sta
 {
     using T = typename FT<MIXED>::T;
     constexpr int TX = 64 * CPL - 2 * K, TY = NW * RPT - 2 * K;
-    dim3 grid((np + TX - 1) / TX, (nt + TY - 1) / TY, n_act);
-    hipLaunchKernelGGL((diff_strip_kernel<MIXED, K, RPT, NW, CPL>), grid, dim3(64 * NW), 0, st, ents, coefs, j0,
+    const int nblk = ((np + TX - 1) / TX) * ((nt + TY - 1) / TY) * n_act;
+    hipLaunchKernelGGL((diff_strip_kernel<MIXED, K, RPT, NW, CPL>), dim3(nblk), dim3(64 * NW), 0, st, ents, coefs, j0,
                        (const DiffRow<T>*)drow, (const T*)in1, (const T*)in2, y0, (const T*)ly0,
                        (T*)out1, (T*)out2, B, adv, nt, np);
 }

@@ -19,6 +19,22 @@ struct Entry {
     double dt;         // step (advection) or call length (diffusion), hours
 };
 
+// XCD-aware tile order of a 1-D launch over gx * gy * (number of entries)
+// tiles.  The hardware deals consecutive workgroups to the 8 XCDs in turn;
+// renumbering gives each XCD a contiguous run of tiles (x fastest, then y,
+// then the entry), so the halos that neighbouring tiles share are fetched
+// into that XCD's L2 once.  A bijection on [0, gridDim.x): correct under any
+// dispatch order, only the locality depends on it.
+__device__ __forceinline__ void xcd_tile(int gx, int gy, int& bx, int& by, int& bz)
+{
+    const int nb = gridDim.x, id = blockIdx.x;
+    const int xcd = id & 7, pos = id >> 3, q = nb >> 3, rm = nb & 7;
+    const int nid = (xcd < rm ? xcd * (q + 1) : rm * (q + 1) + (xcd - rm) * q) + pos;
+    bx = nid % gx;
+    by = (nid / gx) % gy;
+    bz = nid / (gx * gy);
+}
+
 // Coefficients of diffusion stage j of one call:
 //   Y_j = mu Y_{j-1} + nu Y_{j-2} + cy0 Y0 + cL L(Y_{j-1}) + cLY0 L(Y0)
 // (stage 1: Y_1 = Y0 + cL L(Y0)).  cL = mut_j tau, cLY0 = gamt_j tau.
