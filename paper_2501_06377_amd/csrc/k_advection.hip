@@ -116,11 +116,9 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
     __shared__ T cthM[AHT], cthP[AHT];
     __shared__ AttLds<T, ATT> al;
 
-    int bx, by, bz;
-    xcd_tile((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, bx, by, bz);   // neighbours share an L2
-    const Entry e = ents[bz];
+    const Entry e = ents[blockIdx.z];
     const size_t base = (size_t)e.r * nt * np;
-    const int k0 = bx * ATX, j0 = by * ATY;
+    const int k0 = blockIdx.x * ATX, j0 = blockIdx.y * ATY;
     const AdvRow<T>* rw = rows + (size_t)e.r * (nt + 1);
     const int tid = threadIdx.x;
 
@@ -342,7 +340,7 @@ void launch_adv_stage_f64(hipStream_t st, const Entry* ents, int n_ent, int stag
                           WenoConst<double> wth, WenoConst<double> wph, const double* fn,
                           const double* fin, double* fout, int nt, int np)
 {
-    const dim3 grid(((np + ATX - 1) / ATX) * ((nt + ATY - 1) / ATY) * n_ent);
+    dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
     hipLaunchKernelGGL((adv_stage_kernel<double, false, false>), grid, dim3(256), 0, st, ents, stage,
                        time_scheme, upwind, rows, g, wth, wph, fn, fin, fout, nullptr, nullptr, nt,
                        np);
@@ -353,7 +351,7 @@ void launch_adv_stage_mixed(hipStream_t st, const Entry* ents, int n_ent, int st
                             WenoConst<float> wth, WenoConst<float> wph, double* fn,
                             const float* din, float* dout, int nt, int np)
 {
-    const dim3 grid(((np + ATX - 1) / ATX) * ((nt + ATY - 1) / ATY) * n_ent);
+    dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
     hipLaunchKernelGGL((adv_stage_kernel<float, true, false>), grid, dim3(256), 0, st, ents, stage,
                        time_scheme, upwind, rows, g, wth, wph, fn, din, dout, nullptr, nullptr, nt, np);
 }
@@ -382,7 +380,7 @@ void launch_adv_stage_att_f64(hipStream_t st, const Entry* ents, int n_ent, int 
                               const double* fn, const double* fin, double* fout, const double* vphf,
                               const double* vthf, int nt, int np)
 {
-    const dim3 grid(((np + ATX - 1) / ATX) * ((nt + ATY - 1) / ATY) * n_ent);
+    dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
     hipLaunchKernelGGL((adv_stage_kernel<double, false, true>), grid, dim3(256), 0, st, ents, stage,
                        time_scheme, upwind, rows, g, wth, wph, fn, fin, fout, vphf, vthf, nt, np);
 }
@@ -393,7 +391,7 @@ void launch_adv_stage_att_mixed(hipStream_t st, const Entry* ents, int n_ent, in
                                 double* fn, const float* din, float* dout, const float* vphf,
                                 const float* vthf, int nt, int np)
 {
-    const dim3 grid(((np + ATX - 1) / ATX) * ((nt + ATY - 1) / ATY) * n_ent);
+    dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
     hipLaunchKernelGGL((adv_stage_kernel<float, true, true>), grid, dim3(256), 0, st, ents, stage,
                        time_scheme, upwind, rows, g, wth, wph, fn, din, dout, vphf, vthf, nt, np);
 }
