@@ -194,34 +194,76 @@ __device__ void block_merge(DiagRec& v, DiagRec* red)
     v = red[0];
 }
 
+// Wave-wide fixed-order merge (butterfly over the 64 lanes); every lane ends
+// with the wave's record.
+__device__ __forceinline__ void wave_merge(DiagRec& v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        DiagRec o;
+        o.pp = __shfl_xor(v.pp, m);
+        o.pm = __shfl_xor(v.pm, m);
+        o.h1 = __shfl_xor(v.h1, m);
+        o.h2 = __shfl_xor(v.h2, m);
+        o.dax = __shfl_xor(v.dax, m);
+        o.bmin = __shfl_xor(v.bmin, m);
+        o.bmax = __shfl_xor(v.bmax, m);
+        o.babs = __shfl_xor(v.babs, m);
+        o.nonfinite = __shfl_xor(v.nonfinite, m);
+        diag_merge(v, o);
+    }
+}
+
+// A block owns the rows j = blockIdx.x, blockIdx.x + gridDim.x, ... of one
+// realization, its threads the columns k = threadIdx.x + n RB of each row:
+// row factors are block-uniform, no index division per cell, and the block's
+// record is merged across lanes, then across its four waves.
 __global__ __launch_bounds__(RB) void diag_partial_kernel(
     const double* __restrict__ B, const double* st_row, const double* ct_row, const double* w_row,
     const double* sph, const double* cph, DiagRec* __restrict__ partial, int nt, int np)
 {
-    __shared__ DiagRec red[RB];
+    __shared__ DiagRec red[RB / 64];
     const int r = blockIdx.y;
-    const size_t cells = (size_t)nt * np;
-    const double* b = B + (size_t)r * cells;
+    const double* b = B + (size_t)r * nt * np;
     DiagRec v = diag_zero();
-    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < cells; i += (size_t)gridDim.x * RB) {
-        const int j = (int)(i / np), k = (int)(i - (size_t)j * np);
-        const double x = b[i];
-        if (!isfinite(x)) {
-            v.nonfinite += 1.0;
-            continue;
+    for (int j = blockIdx.x; j < nt; j += gridDim.x) {
+        const double w = w_row[j], sw = st_row[j] * w, cw = ct_row[j] * w;
+        const double* bj = b + (size_t)j * np;
+        // four columns per thread and pass: their loads are issued together
+        for (int k0 = threadIdx.x; k0 < np; k0 += 4 * RB) {
+            double xs[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = k0 + q * RB;
+                xs[q] = k < np ? bj[k] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = k0 + q * RB;
+                if (k >= np) break;
+                const double x = xs[q];
+                if (!isfinite(x)) {
+                    v.nonfinite += 1.0;
+                    continue;
+                }
+                if (x > 0.0) v.pp += x * w;
+                else if (x < 0.0) v.pm += x * w;
+                v.h1 += x * sw * cph[k];
+                v.h2 += x * sw * sph[k];
+                v.dax += x * cw;
+                v.bmin = fmin(v.bmin, x);
+                v.bmax = fmax(v.bmax, x);
+                v.babs = fmin(v.babs, fabs(x));
+            }
         }
-        const double w = w_row[j];
-        if (x > 0.0) v.pp += x * w;
-        else if (x < 0.0) v.pm += x * w;
-        v.h1 += x * st_row[j] * cph[k] * w;
-        v.h2 += x * st_row[j] * sph[k] * w;
-        v.dax += x * ct_row[j] * w;
-        v.bmin = fmin(v.bmin, x);
-        v.bmax = fmax(v.bmax, x);
-        v.babs = fmin(v.babs, fabs(x));
     }
-    block_merge(v, red);
-    if (threadIdx.x == 0) partial[(size_t)r * gridDim.x + blockIdx.x] = v;
+    wave_merge(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < RB / 64; ++q) diag_merge(v, red[q]);
+        partial[(size_t)r * gridDim.x + blockIdx.x] = v;
+    }
 }
 
 __global__ __launch_bounds__(RB) void diag_final_kernel(const DiagRec* __restrict__ partial, int nblk,
@@ -245,9 +287,15 @@ void launch_diag(hipStream_t st, int R, const double* B, const double* st_row, c
                  const double* w_row, const double* sph, const double* cph, DiagRec* partial,
                  int nblk, DiagRec* out, int nt, int np)
 {
-    hipLaunchKernelGGL(diag_partial_kernel, dim3(nblk, R), dim3(RB), 0, st, B, st_row, ct_row, w_row,
+    // row blocks per realization: enough blocks to fill the chip, at most
+    // one per row and at most the partial buffer's nblk
+    int nb = 1024 / (R > 0 ? R : 1);
+    if (nb < 64) nb = 64;
+    if (nb > nt) nb = nt;
+    if (nb > nblk) nb = nblk;
+    hipLaunchKernelGGL(diag_partial_kernel, dim3(nb, R), dim3(RB), 0, st, B, st_row, ct_row, w_row,
                        sph, cph, partial, nt, np);
-    hipLaunchKernelGGL(diag_final_kernel, dim3(R), dim3(RB), 0, st, partial, nblk, out);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(R), dim3(RB), 0, st, partial, nb, out);
 }
 
 // ------------------------------------------------------------ conversions
