@@ -162,8 +162,8 @@ __global__ __launch_bounds__(64) void pole_dgrad_kernel(const uint16_t* __restri
 // The 64-output convolutions of the forward pass (MODE 0: bias + ReLU) and of
 // the data gradient (MODE 1: interior rows 1..H-2, ReLU mask of the layer
 // input), as implicit GEMMs on v_mfma_f32_32x32x16_bf16 with every operand in
-// LDS.  A block (256 threads for 16 input channels, 512 for 64: one block
-// per CU, two waves per SIMD) keeps all nine taps' weights resident
+// LDS.  A block (256 threads for 16 input channels, two blocks per CU; 512
+// for 64, one per CU; two waves per SIMD either way) keeps all nine taps' weights resident
 // (9 x 64 x CIN bf16) and walks output tiles of PTY x PTX pixels (with their
 // one-cell halo); a tile's input is loaded into registers DEPTH tiles ahead
 // and goes to LDS once the previous tile's epilogue is done.  Wave w computes
@@ -174,11 +174,12 @@ __global__ __launch_bounds__(64) void pole_dgrad_kernel(const uint16_t* __restri
 // issues 3 x PMR x (PTX / 32) x (64 / 32 per wave) MFMAs.  LDS rows are stored in 16-byte chunks
 // permuted by an XOR with the row (pixel) index, so the fragment reads of 8
 // consecutive lanes hit distinct banks without padding.
-constexpr int PTY = 8, PMR = PTY / 4;   // tile rows; rows per wave
-
 template <int CIN>
 struct PersistShape {
-    static constexpr int PTX = CIN == 64 ? 64 : 32;   // tile columns (LDS: 158 KB / 55 KB per block)
+    // tile rows and columns: 16 x 32 for 64 input channels (LDS: 78 KB of
+    // staged input + 74 KB of weights per block), 8 x 32 for 16
+    static constexpr int PTY = CIN == 64 ? 16 : 8;
+    static constexpr int PTX = 32;
     static constexpr int DEPTH = CIN == 64 ? 1 : 2;   // tiles in flight in registers
     static constexpr int BLOCKS_PER_CU = CIN == 64 ? 1 : 2;
     // threads: with one block per CU, two waves per SIMD, the second four
@@ -200,6 +201,7 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
                                                            const uint16_t* __restrict__ act)
 {
     constexpr int PTX = PersistShape<CIN>::PTX, DEPTH = PersistShape<CIN>::DEPTH;
+    constexpr int PTY = PersistShape<CIN>::PTY, PMR = PTY / 4;   // tile rows; rows per wave
     constexpr int NTH = PersistShape<CIN>::NTH;
     constexpr int NN = 512 / NTH;                 // 32-channel output halves per wave
     constexpr int NCG = PTX / 32;                 // 32-pixel column groups
@@ -907,7 +909,7 @@ template <int CIN, int MODE>
 static void launch_persist(hipStream_t st, const uint16_t* x, const uint16_t* w, const float* bias,
                            uint16_t* out, int batch, int H, int W, const uint16_t* act)
 {
-    constexpr int PTX = PersistShape<CIN>::PTX;
+    constexpr int PTX = PersistShape<CIN>::PTX, PTY = PersistShape<CIN>::PTY;
     const int rows = MODE == 1 ? H - 2 : H;
     const long tiles = (long)batch * ((rows + PTY - 1) / PTY) * ((W + PTX - 1) / PTX);
     const int nb = (int)std::min<long>(tiles, (long)PersistShape<CIN>::BLOCKS_PER_CU * persist_blocks());
