@@ -145,12 +145,12 @@ def surrogate_bench(sft, torch, batch, n_real=16, hours=3, tol=1e-3):
     B = torch.tensor(np.concatenate([f0] * reps)[:batch], dtype=torch.float64, device="cuda")
     F = torch.tensor(np.concatenate([feats] * reps)[:batch], device="cuda")
     y = torch.empty((batch, nt, np_), dtype=torch.float32, device="cuda")
-    net.forward(B, F, y)
+    net.predict(B, F, y)
     net.sync()
     iters = 5
     t0 = time.perf_counter()
     for _ in range(iters):
-        net.forward(B, F, y)
+        net.predict(B, F, y)
     net.sync()
     ms = (time.perf_counter() - t0) / iters * 1e3
     flop = S.FLOP_PER_PIXEL * nt * np_ * batch

@@ -221,6 +221,15 @@ class Net:
         check(self.L.sft_net_forward(self.h, b_in.shape[0], p, code, f, yp), None, "sft_net_forward")
         return y
 
+    def predict(self, b_in, feats, y=None):
+        """Inference only (sft_net_predict): the same y as forward, without
+        keeping the last hidden layer's activations."""
+        p, code, _ = _ptr(b_in)
+        f, _, _ = _ptr(feats)
+        yp = _ptr(y)[0] if y is not None else ctypes.c_void_p(0)
+        check(self.L.sft_net_predict(self.h, b_in.shape[0], p, code, f, yp), None, "sft_net_predict")
+        return y
+
     def activation(self, layer: int, out):
         """Copies bf16 activations into a torch CUDA tensor (int16 storage)."""
         check(self.L.sft_net_get_activation(self.h, layer, ctypes.c_void_p(out.data_ptr())), None,

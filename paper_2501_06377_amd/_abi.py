@@ -90,6 +90,7 @@ SIGNATURES = {
     "sft_net_get_params": (_I, [_P, _P, _I]),
     "sft_net_get_grads": (_I, [_P, _P, _I]),
     "sft_net_forward": (_I, [_P, _I, _P, _I, _P, _P]),
+    "sft_net_predict": (_I, [_P, _I, _P, _I, _P, _P]),
     "sft_net_get_activation": (_I, [_P, _I, _P]),
     "sft_net_train_step": (_I, [_P, _I, _P, _P, _I, _P, ctypes.c_float, _I, ctypes.POINTER(_D)]),
     "sft_net_sync": (_I, [_P]),

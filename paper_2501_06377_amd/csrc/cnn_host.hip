@@ -18,6 +18,8 @@ void cnn_features(hipStream_t st, const void* Bin, int dtype, const float* feats
                   int H, int W);
 void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,
                   uint16_t* out, int batch, int H, int W);
+void cnn_conv_fwd_out(hipStream_t st, const uint16_t* x, const uint16_t* wf, const float* bias,
+                      const uint16_t* wf5, const float* b5, float* z, float* y, int batch, int H, int W);
 void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
                   int batch, int H, int W);
 void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, const uint16_t* act,
@@ -62,6 +64,7 @@ struct sft_net {
     float *wpart = nullptr, *bpart = nullptr;
     double* losspart = nullptr;
     int last_batch = 0;
+    bool layer4_valid = false;   // the layer-4 activations of the last forward pass are held
     std::vector<void*> allocs;
     std::string err;
 };
@@ -99,16 +102,24 @@ void pack_all(sft_net* net)
     cnn_pack(net->stream, net->p + net->woff[4], 64, 1, 64, 32, 16, net->wf[4], net->wd[4]);
 }
 
-void forward(sft_net* net, int batch, const void* Bin, int dtype, const float* feats)
+// predict = true (inference only): the last hidden layer and the output
+// layer's tap products run as one pass and the layer-4 activations are not
+// kept (their buffer holds the tap products instead); y is bitwise the same.
+void forward(sft_net* net, int batch, const void* Bin, int dtype, const float* feats, bool predict = false)
 {
     hipStream_t st = net->stream;
     const int H = net->H, W = net->W;
     cnn_features(st, Bin, dtype, feats, net->X0, batch, H, W);
     cnn_conv_fwd(st, 16, net->X0, net->wf[0], net->p + net->boff[0], net->X[0], batch, H, W);
-    for (int l = 1; l < 4; ++l)
+    for (int l = 1; l < (predict ? 3 : 4); ++l)
         cnn_conv_fwd(st, 64, net->X[l - 1], net->wf[l], net->p + net->boff[l], net->X[l], batch, H, W);
-    cnn_conv_out(st, net->X[3], net->wf[4], net->p + net->boff[4], net->y, batch, H, W);
+    if (predict)
+        cnn_conv_fwd_out(st, net->X[2], net->wf[3], net->p + net->boff[3], net->wf[4], net->p + net->boff[4],
+                         (float*)net->X[3], net->y, batch, H, W);
+    else
+        cnn_conv_out(st, net->X[3], net->wf[4], net->p + net->boff[4], net->y, batch, H, W);
     net->last_batch = batch;
+    net->layer4_valid = !predict;
 }
 
 }  // namespace
@@ -233,9 +244,22 @@ sft_status sft_net_forward(sft_net* net, int32_t batch, const void* b_in, int32_
     return hipGetLastError() == hipSuccess ? SFT_OK : SFT_ERR_HIP;
 }
 
+sft_status sft_net_predict(sft_net* net, int32_t batch, const void* b_in, int32_t dtype, const float* feats,
+                           float* y)
+{
+    if (!net || !b_in || !feats || batch < 1 || batch > net->maxb) return SFT_ERR_ARG;
+    if (dtype != SFT_DTYPE_F64 && dtype != SFT_DTYPE_F32) return SFT_ERR_ARG;
+    forward(net, batch, b_in, dtype, feats, true);
+    if (y)
+        (void)hipMemcpyAsync(y, net->y, (size_t)batch * net->H * net->W * sizeof(float),
+                             hipMemcpyDeviceToDevice, net->stream);
+    return hipGetLastError() == hipSuccess ? SFT_OK : SFT_ERR_HIP;
+}
+
 sft_status sft_net_get_activation(sft_net* net, int32_t layer, void* out)
 {
     if (!net || !out || layer < 0 || layer > 4 || !net->last_batch) return SFT_ERR_ARG;
+    if (layer == 4 && !net->layer4_valid) return SFT_ERR_STATE;
     const size_t plane = (size_t)net->H * net->W * net->last_batch;
     const void* src = layer == 0 ? (const void*)net->X0 : (const void*)net->X[layer - 1];
     const size_t bytes = plane * (layer == 0 ? 16 : 64) * sizeof(uint16_t);
@@ -317,7 +341,7 @@ sft_status net_predict(sft_net* net, hipStream_t st, int batch, const double* Bi
     if (!net) return SFT_ERR_ARG;
     hipStream_t saved = net->stream;
     net->stream = st;
-    forward(net, batch, Bin, SFT_DTYPE_F64, feats);
+    forward(net, batch, Bin, SFT_DTYPE_F64, feats, true);
     net->stream = saved;
     *y_out = net->y;
     return SFT_OK;

@@ -198,7 +198,9 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
                                                            const uint16_t* __restrict__ w,
                                                            const float* __restrict__ bias,
                                                            uint16_t* __restrict__ out, int batch, int H, int W,
-                                                           const uint16_t* __restrict__ act)
+                                                           const uint16_t* __restrict__ act,
+                                                           const uint16_t* __restrict__ w5,
+                                                           float* __restrict__ zout)
 {
     constexpr int PTX = PersistShape<CIN>::PTX, DEPTH = PersistShape<CIN>::DEPTH;
     constexpr int PTY = PersistShape<CIN>::PTY, PMR = PTY / 4;   // tile rows; rows per wave
@@ -225,6 +227,17 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
         *(uint4*)(wl + (size_t)row * CIN + chunk_swz<CIN>(row, q) * 8) = *(const uint4*)(w + (size_t)v * 8);
     }
 
+    // MODE 2: the output layer's weights as B fragments (taps as columns,
+    // zero beyond the ninth), w5 in the packed layout [tap][32][64]
+    bf16x8 b5[MODE == 2 ? 4 : 1];
+    if constexpr (MODE == 2) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            b5[ch] = bf16x8{};
+            if (col < 9) b5[ch] = *(const bf16x8*)(w5 + (size_t)col * 32 * 64 + ch * 16 + kh * 8);
+        }
+    }
+
     const int out_rows = MODE == 1 ? H - 2 : H, r_base = MODE == 1 ? 1 : 0;
     const int tiles_x = (W + PTX - 1) / PTX, tiles_y = (out_rows + PTY - 1) / PTY;
     const long ntiles = (long)batch * tiles_y * tiles_x;
@@ -244,7 +257,7 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
                 const int pix = v / NQ, q = v - (v / NQ) * NQ;
                 const int tr = pix / TC, tc = pix - (pix / TC) * TC;
                 const int j = r0 - 1 + tr, k = k0 - 1 + tc;
-                if (MODE == 0) {
+                if (MODE != 1) {   // forward passes: spherical padding
                     int sj, sk;
                     if (sphere_src(j, k, H, W, sj, sk))
                         pre[i] = *(const uint4*)(xb + ((size_t)sj * W + sk) * CIN + q * 8);
@@ -331,12 +344,37 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
                     for (int r = 0; r < 16; ++r) {
                         const int px = g * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
                         float v = acc[m][g][n][r] + bv;
-                        if (MODE == 0) v = v > 0.f ? v : 0.f;
+                        if (MODE != 1) v = v > 0.f ? v : 0.f;
                         buf[(rl * PTX + px) * CTS + c] = f2bf(v);
                     }
                 }
         }
         __syncthreads();
+        if constexpr (MODE == 2) {
+            // Z[p][t] = sum_c a[p][c] w5[t][c] for the nine taps of the output
+            // layer, from the staged bf16 activations (the values the other
+            // modes store), one tile row (32 pixels) per MFMA group
+            static_assert(PTX == 32, "one tile row per 32-pixel group");
+            for (int rl = tid >> 6; rl < PTY; rl += NTH / 64) {
+                const int row = r0 + rl;
+                f32x16 za;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) za[r] = 0.f;
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) {
+                    const bf16x8 a = *(const bf16x8*)(buf + (rl * PTX + col) * CTS + ch * 16 + kh * 8);
+                    za = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b5[ch], za, 0, 0, 0);
+                }
+                if (col < 9 && row < r_base + out_rows) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int k = k0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                        if (k < W) zout[(((size_t)b * H + row) * W + k) * 9 + col] = za[r];
+                    }
+                }
+            }
+            return;
+        }
         for (int v = tid; v < PTY * PTX * 8; v += NTH) {
             const int cv = v & 7, pix = v >> 3;
             const int rl = pix / PTX, px = pix - (pix / PTX) * PTX;
@@ -436,6 +474,27 @@ __global__ __launch_bounds__(256) void conv_out_kernel(const uint16_t* __restric
         }
         y[((size_t)b * H + j) * W + k] = acc;
     }
+}
+
+// y[j][k] = bias + the nine taps' Z at the tap's spherically padded
+// neighbour, summed in the tap order of conv_out_kernel over the same Z
+// values: the same bits as the unfused output layer.
+__global__ __launch_bounds__(256) void conv_out_gather_kernel(const float* __restrict__ z,
+                                                              const float* __restrict__ bias,
+                                                              float* __restrict__ y, int H, int W)
+{
+    const int b = blockIdx.z, j = blockIdx.y, k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= W) return;
+    const float* zb = z + (size_t)b * H * W * 9;
+    float acc = bias[0];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3, dx = t - (t / 3) * 3;
+        int sj = 0, sk = 0;
+        const bool ok = sphere_src(j + dy - 1, k + dx - 1, H, W, sj, sk);
+        acc += ok ? zb[((size_t)sj * W + sk) * 9 + t] : 0.f;
+    }
+    y[((size_t)b * H + j) * W + k] = acc;
 }
 
 // Pole rows of the input gradient: edge rows (-1, 0, H-1, H) -> rows 0 and
@@ -907,14 +966,15 @@ static int persist_blocks()
 
 template <int CIN, int MODE>
 static void launch_persist(hipStream_t st, const uint16_t* x, const uint16_t* w, const float* bias,
-                           uint16_t* out, int batch, int H, int W, const uint16_t* act)
+                           uint16_t* out, int batch, int H, int W, const uint16_t* act,
+                           const uint16_t* w5 = nullptr, float* zout = nullptr)
 {
     constexpr int PTX = PersistShape<CIN>::PTX, PTY = PersistShape<CIN>::PTY;
     const int rows = MODE == 1 ? H - 2 : H;
     const long tiles = (long)batch * ((rows + PTY - 1) / PTY) * ((W + PTX - 1) / PTX);
     const int nb = (int)std::min<long>(tiles, (long)PersistShape<CIN>::BLOCKS_PER_CU * persist_blocks());
     hipLaunchKernelGGL((conv_persist_kernel<CIN, MODE>), dim3(nb), dim3(PersistShape<CIN>::NTH), 0, st, x, w,
-                       bias, out, batch, H, W, act);
+                       bias, out, batch, H, W, act, w5, zout);
 }
 
 void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,
@@ -922,6 +982,18 @@ void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf
 {
     if (cin == 16) launch_persist<16, 0>(st, x, wf, bias, out, batch, H, W, nullptr);
     else launch_persist<64, 0>(st, x, wf, bias, out, batch, H, W, nullptr);
+}
+
+// Inference: the last hidden layer with the output layer's tap products
+// fused into its epilogue (its 64-channel activations are never stored:
+// 36 bytes of Z per pixel instead of 128 written and read back), then the
+// gather of the nine taps.  z holds batch x H x W x 9 floats.
+void cnn_conv_fwd_out(hipStream_t st, const uint16_t* x, const uint16_t* wf, const float* bias,
+                      const uint16_t* wf5, const float* b5, float* z, float* y, int batch, int H, int W)
+{
+    launch_persist<64, 2>(st, x, wf, bias, nullptr, batch, H, W, nullptr, wf5, z);
+    dim3 g((W + 255) / 256, H, batch);
+    hipLaunchKernelGGL(conv_out_gather_kernel, g, dim3(256), 0, st, z, b5, y, H, W);
 }
 
 void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
