@@ -296,17 +296,17 @@ sft_status sft_net_get_grads(sft_net* net, float* grads, int32_t on_device);
 sft_status sft_net_forward(sft_net* net, int32_t batch, const void* b_in, int32_t dtype,
                            const float* feats, float* y);
 /* Inference only, same arguments and the same y (bitwise) as sft_net_forward:
- * the last hidden layer and the output layer's nine tap products run as one
- * pass, so the layer-4 activations are never written (36 instead of 256
- * bytes per pixel of traffic between those layers).  Afterwards
- * sft_net_get_activation(4) returns SFT_ERR_STATE until the next
- * sft_net_forward or sft_net_train_step.  The context's surrogate advance
- * uses this path. */
+ * the first layer forms its input channels from b_in while staging its
+ * tiles, and the last hidden layer and the output layer's nine tap products
+ * run as one pass, so neither the 16-channel input nor the layer-4
+ * activations are written.  Afterwards sft_net_get_activation(0) and (4)
+ * return SFT_ERR_STATE until the next sft_net_forward or sft_net_train_step.
+ * The context's surrogate advance uses this path. */
 sft_status sft_net_predict(sft_net* net, int32_t batch, const void* b_in, int32_t dtype,
                            const float* feats, float* y);
 /* Copies the bf16 activations (NHWC, uint16 storage) of the last forward pass:
  * layer 0 = the 16-channel input, 1..4 = hidden layer outputs (64 channels);
- * SFT_ERR_STATE for layer 4 after sft_net_predict. */
+ * SFT_ERR_STATE for layers 0 and 4 after sft_net_predict. */
 sft_status sft_net_get_activation(sft_net* net, int32_t layer, void* out);
 /* One training step on device arrays b_in, b_target [batch][nt][np] (dtype F64
  * or F32) and feats [batch][3]: forward, loss, backward; with apply = 1 also

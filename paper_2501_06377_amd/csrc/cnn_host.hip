@@ -18,6 +18,8 @@ void cnn_features(hipStream_t st, const void* Bin, int dtype, const float* feats
                   int H, int W);
 void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,
                   uint16_t* out, int batch, int H, int W);
+void cnn_conv_fwd_first(hipStream_t st, const void* Bin, int dtype, const float* feats, const uint16_t* wf,
+                        const float* bias, uint16_t* out, int batch, int H, int W);
 void cnn_conv_fwd_out(hipStream_t st, const uint16_t* x, const uint16_t* wf, const float* bias,
                       const uint16_t* wf5, const float* b5, float* z, float* y, int batch, int H, int W);
 void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
@@ -64,7 +66,7 @@ struct sft_net {
     float *wpart = nullptr, *bpart = nullptr;
     double* losspart = nullptr;
     int last_batch = 0;
-    bool layer4_valid = false;   // the layer-4 activations of the last forward pass are held
+    bool acts_kept = false;   // the input and layer-4 activations of the last forward pass are held
     std::vector<void*> allocs;
     std::string err;
 };
@@ -102,15 +104,21 @@ void pack_all(sft_net* net)
     cnn_pack(net->stream, net->p + net->woff[4], 64, 1, 64, 32, 16, net->wf[4], net->wd[4]);
 }
 
-// predict = true (inference only): the last hidden layer and the output
-// layer's tap products run as one pass and the layer-4 activations are not
-// kept (their buffer holds the tap products instead); y is bitwise the same.
+// predict = true (inference only): the first layer forms its input channels
+// from the field while staging its tiles, and the last hidden layer and the
+// output layer's tap products run as one pass; the input and layer-4
+// activations are not kept (the latter's buffer holds the tap products
+// instead).  y is bitwise the same.
 void forward(sft_net* net, int batch, const void* Bin, int dtype, const float* feats, bool predict = false)
 {
     hipStream_t st = net->stream;
     const int H = net->H, W = net->W;
-    cnn_features(st, Bin, dtype, feats, net->X0, batch, H, W);
-    cnn_conv_fwd(st, 16, net->X0, net->wf[0], net->p + net->boff[0], net->X[0], batch, H, W);
+    if (predict) {
+        cnn_conv_fwd_first(st, Bin, dtype, feats, net->wf[0], net->p + net->boff[0], net->X[0], batch, H, W);
+    } else {
+        cnn_features(st, Bin, dtype, feats, net->X0, batch, H, W);
+        cnn_conv_fwd(st, 16, net->X0, net->wf[0], net->p + net->boff[0], net->X[0], batch, H, W);
+    }
     for (int l = 1; l < (predict ? 3 : 4); ++l)
         cnn_conv_fwd(st, 64, net->X[l - 1], net->wf[l], net->p + net->boff[l], net->X[l], batch, H, W);
     if (predict)
@@ -119,7 +127,7 @@ void forward(sft_net* net, int batch, const void* Bin, int dtype, const float* f
     else
         cnn_conv_out(st, net->X[3], net->wf[4], net->p + net->boff[4], net->y, batch, H, W);
     net->last_batch = batch;
-    net->layer4_valid = !predict;
+    net->acts_kept = !predict;
 }
 
 }  // namespace
@@ -259,7 +267,7 @@ sft_status sft_net_predict(sft_net* net, int32_t batch, const void* b_in, int32_
 sft_status sft_net_get_activation(sft_net* net, int32_t layer, void* out)
 {
     if (!net || !out || layer < 0 || layer > 4 || !net->last_batch) return SFT_ERR_ARG;
-    if (layer == 4 && !net->layer4_valid) return SFT_ERR_STATE;
+    if ((layer == 0 || layer == 4) && !net->acts_kept) return SFT_ERR_STATE;
     const size_t plane = (size_t)net->H * net->W * net->last_batch;
     const void* src = layer == 0 ? (const void*)net->X0 : (const void*)net->X[layer - 1];
     const size_t bytes = plane * (layer == 0 ? 16 : 64) * sizeof(uint16_t);

@@ -67,6 +67,30 @@ __device__ __forceinline__ bool sphere_src(int j, int k, int H, int W, int& sj, 
 // of ~1% of B is resolved), three per-sample features, cos(theta),
 // sin(theta), zeros.  The first layer applies the field channel's weight to
 // both hi and lo.
+// cos(theta), sin(theta) of row j as bf16 (low, high half).
+__device__ __forceinline__ uint32_t cnn_row_trig(int j, int H)
+{
+    const double th = (j + 0.5) * (M_PI / H);
+    return (uint32_t)f2bf((float)cos(th)) | ((uint32_t)f2bf((float)sin(th)) << 16);
+}
+
+// The first eight input channels of one pixel (field value bv, row factors
+// trig of cnn_row_trig, per-sample features fb), packed as bf16; channels
+// 8..15 are zero.
+__device__ __forceinline__ uint4 cnn_feature_chunk(double bv, uint32_t trig, const float* __restrict__ fb)
+{
+    const float f = (float)(bv / 500.0);
+    const uint16_t hi = f2bf(f);
+    const uint16_t c[6] = {hi, f2bf(f - bf2f(hi)), f2bf(fb[0]), f2bf(fb[1]), f2bf(fb[2]), 0};
+    return make_uint4((uint32_t)c[0] | ((uint32_t)c[1] << 16), (uint32_t)c[2] | ((uint32_t)c[3] << 16),
+                      (uint32_t)c[4] | ((trig & 0xFFFFu) << 16), trig >> 16);
+}
+
+__device__ __forceinline__ double load_field(const void* Bin, int dtype, size_t i)
+{
+    return dtype == 1 ? (double)((const float*)Bin)[i] : ((const double*)Bin)[i];
+}
+
 template <typename TB>
 __global__ void cnn_features_kernel(const TB* __restrict__ Bin, const float* __restrict__ feats,
                                     uint16_t* __restrict__ X0, int H, int W)
@@ -76,20 +100,9 @@ __global__ void cnn_features_kernel(const TB* __restrict__ Bin, const float* __r
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
          p += (size_t)gridDim.x * blockDim.x) {
         const int j = (int)(p / W);
-        const double th = (j + 0.5) * (M_PI / H);
-        const float f = (float)((double)Bin[(size_t)b * n + p] / 500.0);
-        const uint16_t hi = f2bf(f);
-        float v[16];
-        v[0] = bf2f(hi);
-        v[1] = f - bf2f(hi);
-        v[2] = feats[b * 3 + 0];
-        v[3] = feats[b * 3 + 1];
-        v[4] = feats[b * 3 + 2];
-        v[5] = (float)cos(th);
-        v[6] = (float)sin(th);
-        for (int c = 7; c < 16; ++c) v[c] = 0.f;
-        uint16_t* o = X0 + ((size_t)b * n + p) * 16;
-        for (int c = 0; c < 16; ++c) o[c] = f2bf(v[c]);
+        uint4* o = (uint4*)(X0 + ((size_t)b * n + p) * 16);
+        o[0] = cnn_feature_chunk((double)Bin[(size_t)b * n + p], cnn_row_trig(j, H), feats + b * 3);
+        o[1] = make_uint4(0, 0, 0, 0);
     }
 }
 
@@ -200,7 +213,9 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
                                                            uint16_t* __restrict__ out, int batch, int H, int W,
                                                            const uint16_t* __restrict__ act,
                                                            const uint16_t* __restrict__ w5,
-                                                           float* __restrict__ zout)
+                                                           float* __restrict__ zout,
+                                                           const void* __restrict__ bsrc, int bdtype,
+                                                           const float* __restrict__ feats)
 {
     constexpr int PTX = PersistShape<CIN>::PTX, DEPTH = PersistShape<CIN>::DEPTH;
     constexpr int PTY = PersistShape<CIN>::PTY, PMR = PTY / 4;   // tile rows; rows per wave
@@ -217,6 +232,7 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
     constexpr int NV = TR * TC * NQ, VPT = (NV + NTH - 1) / NTH;
     __shared__ __attribute__((aligned(16))) uint16_t wl[WE];
     __shared__ __attribute__((aligned(16))) uint16_t buf[BUF_E];
+    __shared__ uint32_t trig[MODE == 3 ? PTY + 2 : 1];   // MODE 3: row factors of the staged rows
 
     const int tid = threadIdx.x, lane = tid & 63, wv = (tid >> 6) & 3;
     const int n0 = NN == 1 ? (tid >> 8) : 0;     // first output half of this wave
@@ -257,7 +273,13 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
                 const int pix = v / NQ, q = v - (v / NQ) * NQ;
                 const int tr = pix / TC, tc = pix - (pix / TC) * TC;
                 const int j = r0 - 1 + tr, k = k0 - 1 + tc;
-                if (MODE != 1) {   // forward passes: spherical padding
+                if (MODE == 3) {   // first layer: the raw field value, converted when staged
+                    int sj, sk;
+                    if (q == 0 && sphere_src(j, k, H, W, sj, sk)) {
+                        const double bv = load_field(bsrc, bdtype, (size_t)b * plane + (size_t)sj * W + sk);
+                        pre[i] = make_uint4((uint32_t)__double2loint(bv), (uint32_t)__double2hiint(bv), 1u, 0u);
+                    }
+                } else if (MODE != 1) {   // forward passes: spherical padding
                     int sj, sk;
                     if (sphere_src(j, k, H, W, sj, sk))
                         pre[i] = *(const uint4*)(xb + ((size_t)sj * W + sk) * CIN + q * 8);
@@ -275,13 +297,25 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
         const int b = (int)(t / ((long)tiles_y * tiles_x));
         const int rem = (int)(t - (long)b * tiles_y * tiles_x);
         const int r0 = r_base + (rem / tiles_x) * PTY, k0 = (rem - (rem / tiles_x) * tiles_x) * PTX;
+        if constexpr (MODE == 3) {
+            // row factors of the staged rows (ghost rows take their source row)
+            if (tid < PTY + 2) trig[tid] = cnn_row_trig(min(max(r0 - 1 + tid, 0), H - 1), H);
+        }
         __syncthreads();   // the previous tile's epilogue is done with buf
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             const int v = tid + i * NTH;
             if (v < NV) {
                 const int pix = v / NQ, q = v - (v / NQ) * NQ;
-                *(uint4*)(buf + (size_t)pix * CIN + chunk_swz<CIN>(pix, q) * 8) = pre[i];
+                uint4 val = pre[i];
+                if constexpr (MODE == 3) {
+                    if (val.z)
+                        val = cnn_feature_chunk(__hiloint2double((int)val.y, (int)val.x), trig[pix / TC],
+                                                feats + b * 3);
+                    else
+                        val = make_uint4(0, 0, 0, 0);
+                }
+                *(uint4*)(buf + (size_t)pix * CIN + chunk_swz<CIN>(pix, q) * 8) = val;
             }
         }
         __syncthreads();
@@ -967,14 +1001,23 @@ static int persist_blocks()
 template <int CIN, int MODE>
 static void launch_persist(hipStream_t st, const uint16_t* x, const uint16_t* w, const float* bias,
                            uint16_t* out, int batch, int H, int W, const uint16_t* act,
-                           const uint16_t* w5 = nullptr, float* zout = nullptr)
+                           const uint16_t* w5 = nullptr, float* zout = nullptr, const void* bsrc = nullptr,
+                           int bdtype = 0, const float* feats = nullptr)
 {
     constexpr int PTX = PersistShape<CIN>::PTX, PTY = PersistShape<CIN>::PTY;
     const int rows = MODE == 1 ? H - 2 : H;
     const long tiles = (long)batch * ((rows + PTY - 1) / PTY) * ((W + PTX - 1) / PTX);
     const int nb = (int)std::min<long>(tiles, (long)PersistShape<CIN>::BLOCKS_PER_CU * persist_blocks());
     hipLaunchKernelGGL((conv_persist_kernel<CIN, MODE>), dim3(nb), dim3(PersistShape<CIN>::NTH), 0, st, x, w,
-                       bias, out, batch, H, W, act, w5, zout);
+                       bias, out, batch, H, W, act, w5, zout, bsrc, bdtype, feats);
+}
+
+// Inference: the first layer with its input channels formed from the field
+// while its tiles are staged (the same values the features kernel stores).
+void cnn_conv_fwd_first(hipStream_t st, const void* Bin, int dtype, const float* feats, const uint16_t* wf,
+                        const float* bias, uint16_t* out, int batch, int H, int W)
+{
+    launch_persist<16, 3>(st, nullptr, wf, bias, out, batch, H, W, nullptr, nullptr, nullptr, Bin, dtype, feats);
 }
 
 void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,

@@ -129,11 +129,12 @@ def test_cnn_forward_layers_match_oracle(H, W):
 
 @pytest.mark.parametrize("H,W,batch", [(20, 40, 2), (13, 64, 3), (48, 96, 5)])
 def test_predict_is_forward_bitwise(H, W, batch):
-    """The inference path (the last hidden layer and the output layer's tap
-    products in one pass, its activations never stored) gives the forward
-    pass's output bit for bit, over partial and several tiles; afterwards the
-    layer-4 activations are reported unavailable until the next forward pass,
-    and a smaller batch on the same network matches too."""
+    """The inference path (input channels formed while the first layer stages
+    its tiles; the last hidden layer and the output layer's tap products in
+    one pass) gives the forward pass's output bit for bit, over partial and
+    several tiles, from FP64 and FP32 fields; afterwards the input and layer-4
+    activations are reported unavailable until the next forward pass, and a
+    smaller batch on the same network matches too."""
     import paper_2501_06377_amd as sft
     say(f"case cnn predict {H}x{W} batch {batch}")
     torch, net, params, B, feats = setup_net(H, W, batch, 21)
@@ -144,16 +145,22 @@ def test_predict_is_forward_bitwise(H, W, batch):
     torch.cuda.synchronize()
     assert torch.equal(y1, y2)
     t = torch.empty((batch, H, W, 64), dtype=torch.int16, device="cuda")
-    with pytest.raises(sft.SftError) as ex:
-        net.activation(4, t)
-    assert ex.value.status == sft.SFT_ERR_STATE
-    net.activation(3, t)                      # the earlier layers are still held
+    for layer in (0, 4):
+        with pytest.raises(sft.SftError) as ex:
+            net.activation(layer, t)
+        assert ex.value.status == sft.SFT_ERR_STATE
+    net.activation(3, t)                      # the hidden layers before the last are held
     net.forward(B, feats, y1)
     net.activation(4, t)
     net.predict(B[:1], feats[:1], y2[:1])
     net.forward(B[:1], feats[:1], y1[:1])
     torch.cuda.synchronize()
     assert torch.equal(y1[:1], y2[:1])
+    B32 = B.float()
+    net.forward(B32, feats, y1)
+    net.predict(B32, feats, y2)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
     net.close()
 
 
