@@ -403,7 +403,7 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const int k = k0 + 8 * (r >> 2) + 4 * kh + (r & 3);
-                        if (k < W) zout[(((size_t)b * H + row) * W + k) * 9 + col] = za[r];
+                        if (k < W) zout[(((size_t)b * 9 + col) * H + row) * W + k] = za[r];
                     }
                 }
             }
@@ -519,14 +519,14 @@ __global__ __launch_bounds__(256) void conv_out_gather_kernel(const float* __res
 {
     const int b = blockIdx.z, j = blockIdx.y, k = blockIdx.x * 256 + threadIdx.x;
     if (k >= W) return;
-    const float* zb = z + (size_t)b * H * W * 9;
+    const float* zb = z + (size_t)b * 9 * H * W;   // tap planes [t][H][W]
     float acc = bias[0];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
         const int dy = t / 3, dx = t - (t / 3) * 3;
         int sj = 0, sk = 0;
         const bool ok = sphere_src(j + dy - 1, k + dx - 1, H, W, sj, sk);
-        acc += ok ? zb[((size_t)sj * W + sk) * 9 + t] : 0.f;
+        acc += ok ? zb[((size_t)t * H + sj) * W + sk] : 0.f;
     }
     y[((size_t)b * H + j) * W + k] = acc;
 }
@@ -1030,7 +1030,8 @@ void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf
 // Inference: the last hidden layer with the output layer's tap products
 // fused into its epilogue (its 64-channel activations are never stored:
 // 36 bytes of Z per pixel instead of 128 written and read back), then the
-// gather of the nine taps.  z holds batch x H x W x 9 floats.
+// gather of the nine taps.  z holds batch x 9 x H x W floats (one plane per
+// tap, so the gather's reads are contiguous in k).
 void cnn_conv_fwd_out(hipStream_t st, const uint16_t* x, const uint16_t* wf, const float* bias,
                       const uint16_t* wf5, const float* b5, float* z, float* y, int batch, int H, int W)
 {
