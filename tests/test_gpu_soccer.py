@@ -60,3 +60,36 @@ def test_soccer_error_falls_with_resolution(case):
     e1 = run_case(case, 48, 96)
     e2 = run_case(case, 96, 192)
     assert e2 < e1 / 4.0, (e1, e2)
+
+
+# HH errors the paper prints for its 512x1024 validation runs (Sec. "Diffusion
+# temporal schemes" and the Strang table): the same test problem on its node
+# grid, so agreement is approximate (the cell-centred grid here differs by a
+# few per cent to 15 per cent).
+PAPER_HH = {"diffusion, RKL2, one 672 h step": 8.0e-5, "diffusion, RKG2, one 672 h step": 6.3e-5,
+            "advection+diffusion, max CFL dt": 4.8e-5, "advection+diffusion, max CFL dt, Strang": 4.8e-5}
+
+
+@pytest.mark.parametrize("case", [c for c in CASES if c.name in PAPER_HH], ids=lambda c: c.name)
+def test_soccer_full_size_error_matches_paper(case):
+    """At the paper's 512x1024 the error against the analytic solution is
+    within 20% of the HH error the paper prints for the same run, with the
+    paper's step and stage rules (one 672 h STS step: 9,194 RKG2 / 7,508
+    RKL2 stages; the CFL step: 0.59 h, 1.18 h with Strang splitting)."""
+    nt, np_ = 512, 1024
+    say(f"case soccer ball full size: {case.name}")
+    u0 = synth.soccer_ball(nt, np_)[None]
+    got, ens = gpu_run(u0, [case.realization()], [("advance", synth.SOCCER_HOURS)],
+                       adv_time=GPU_OPT[case.adv], diff_time=GPU_OPT[case.diff], strang=case.strang,
+                       dt_max=case.dt_max)
+    c = ens.counts(0)
+    ens.close()
+    _, k2 = oracle.units()
+    exact = u0[0] * math.exp(-42.0 * synth.SOCCER_NU_KM2_S * k2 * synth.SOCCER_HOURS)
+    hh = oracle.hh(got[0], exact)
+    say(f"  steps {c['steps']} stages {c['stages']} HH {hh:.3e} (paper {PAPER_HH[case.name]:.1e})")
+    assert abs(hh / PAPER_HH[case.name] - 1.0) < 0.2
+    if not case.flows:
+        assert c["steps"] == 1 and c["stages"] == (7508 if case.diff == "rkl2" else 9194)
+    else:
+        assert c["steps"] == (569 if case.strang else 1138)
