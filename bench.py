@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--surr-batch", type=int, default=64)
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the surrogate measurement (inference batch, plain vs surrogate intervals)")
+    ap.add_argument("--no-f64-compare", action="store_true",
+                    help="precision workload: skip the FP64 run that the FP32-mixed result is compared with")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -605,6 +607,28 @@ def main():
     out["final_diag_r0"] = {k: diag[k] for k in ("phi_pos", "phi_neg", "dax", "bmin", "bmax")}
     if w.precision == "f32":
         out["state_dtype"] = "f64 (state, flux and weight reductions)"
+    if w.precision == "f32" and args.workload == "precision" and not args.no_f64_compare:
+        # the FP32-mixed result of the timed region against the FP64 path on
+        # the same inputs (the FP64 path is itself held to the FP64 oracle)
+        got = [ens.get_states(g) for g in gids]
+        log(f"{w.name}: the same {K} intervals on the FP64 path")
+        e64 = sft.Ensemble(precision=0, sts_tile=-1, lanes=args.lanes)
+        g64 = [e64.add_grid(nt, np_, reals) for nt, np_, reals in w.classes]
+        reset(e64, g64)
+        run(e64, g64, K)
+        e64.sync()
+        ref = [e64.get_states(g) for g in g64]
+        e64.close()
+        rel, mx = [], []
+        for a, b in zip(got, ref):
+            for r in range(a.shape[0]):
+                rel.append(float(np.linalg.norm(a[r] - b[r]) / np.linalg.norm(b[r])))
+                mx.append(float(np.abs(a[r] - b[r]).max()))
+        out["f32_vs_f64"] = {"hours": K, "reference": "the library's FP64 path on the same inputs",
+                             "rel_l2_per_realization": rel, "max_abs_G_per_realization": mx,
+                             "rel_l2_max": max(rel), "tolerance": 1e-5}
+        log(f"{w.name}: FP32-mixed vs FP64 after {K} h: rel-L2 max {max(rel):.3e}, "
+            f"max-abs max {max(mx):.3e} G")
     ens.close()
     del obs_d, inits
     log(f"{w.name}: {wall:.2f} s for {K} intervals")

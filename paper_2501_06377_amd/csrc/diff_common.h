@@ -30,6 +30,22 @@ __device__ __forceinline__ T L5(const DiffRow<T>& d, T w, T n, T c, T s, T e)
     return v;
 }
 
+// FP32 (the increment form's operator): the same operator summed as
+// coefficient x (neighbour - centre), the diagonal being minus the sum of the
+// neighbours' coefficients in every row.  The plain five-term sum cancels a
+// large diagonal term against the neighbour sum and, in FP32, loses digits
+// in proportion to diagonal / result over every one of a call's thousand or
+// more stages; the differences of neighbouring values are nearly exact.
+template <>
+__device__ __forceinline__ float L5<float>(const DiffRow<float>& d, float w, float n, float c, float s, float e)
+{
+    float v = d.ph * (w - c);
+    v = __builtin_fmaf(d.up, n - c, v);
+    v = __builtin_fmaf(d.dn, s - c, v);
+    v = __builtin_fmaf(d.ph, e - c, v);
+    return v;
+}
+
 // FP64 stage: Y_j = nu Y_{j-2} + mu Y_{j-1} + cy0 Y0 + cL L + cLY0 L(Y0)
 // (the Y_{j-2} term first: its register, dead afterwards, takes the result).
 __device__ __forceinline__ double sts_f64(const StageCoef& c, double ym1, double ym2, double y0,
@@ -43,12 +59,20 @@ __device__ __forceinline__ double sts_f64(const StageCoef& c, double ym1, double
     return v;
 }
 
-// FP32 increment stage: d_j = mu d_{j-1} [+ nu d_{j-2}] + cL L + (cL + cLY0) L(Y0).
-__device__ __forceinline__ float sts_mixed(const StageCoef& c, float dm1, float dm2, bool has_dm2,
-                                           float L, float ly0)
+// FP32 increment stage, carried as the increment d and its last change
+// e = d_{j-1} - d_{j-2} (e = d_1 at the first blocked stage, d_0 being 0):
+//   e_j = (mu + nu - 1) d_{j-1} - nu e_{j-1} + cL L(d_{j-1}) + (cL + cLY0) L(Y0),
+//   d_j = d_{j-1} + e_j,
+// the three-term recurrence d_j = mu d_{j-1} + nu d_{j-2} + ... rewritten.
+// With mu -> 2 and nu -> -1 over a long call that recurrence has a double
+// root at 1: a rounding error of d in its own form grows linearly over the
+// remaining stages (s^2 eps in all), while here the rounding of d enters the
+// non-growing mode and the rounding of e, a change of size d / s, is the one
+// that grows (about s eps in all).  mu + nu - 1 = -cy0.
+__device__ __forceinline__ float sts_mixed(const StageCoef& c, float d, float e, float L, float ly0)
 {
-    float v = (float)c.mu * dm1;
-    if (has_dm2) v = __builtin_fmaf((float)c.nu, dm2, v);
+    float v = (float)(-c.cy0) * d;
+    v = __builtin_fmaf((float)(-c.nu), e, v);
     v = __builtin_fmaf((float)c.cL, L, v);
     v = __builtin_fmaf((float)(c.cL + c.cLY0), ly0, v);
     return v;

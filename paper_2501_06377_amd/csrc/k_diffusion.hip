@@ -8,7 +8,8 @@
 //                            + cLY0 L(Y0), evaluated in that order.
 // FP32 mixed ("increment form", algebraically identical because L is linear):
 //   d_j = Y_j - Y0 = mu d_{j-1} + nu d_{j-2} + cL L(d_{j-1}) + (cL + cLY0) L(Y0),
-//   with Y0 and the result kept in FP64 and L(Y0) formed in FP64 arithmetic.
+//   with Y0 and the result kept in FP64 and L(Y0) formed in FP64 arithmetic;
+//   carried as (d, e = d_{j-1} - d_{j-2}) (sts_mixed).
 //
 // Layout: fields [r][j][k] (k = phi contiguous).  Entries of a launch are the
 // realizations still active at stage j (blockIdx.z indexes them).
@@ -130,28 +131,33 @@ __global__ __launch_bounds__(256) void diff_first_mixed_kernel(
     d1[i] = (float)coefs[e.coef_off + 1].cL * lf;
 }
 
+// Reads d_{j-1} (with neighbours) and e_{j-1} (absent at j = 2: e_1 = d_1),
+// writes d_j to dout (never din) and e_j over e (each cell reads only its own).
 __global__ __launch_bounds__(256) void diff_stage_mixed_kernel(
     const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs, int jst,
     const DiffRow<float>* __restrict__ drow, double* __restrict__ B, const float* __restrict__ adv,
-    const float* __restrict__ dm1, const float* dm2, const float* __restrict__ ly0, float* out,
-    int nt, int np)
+    const float* __restrict__ din, const float* ein, const float* __restrict__ ly0, float* dout,
+    float* eout, int nt, int np)
 {
-    const Entry e = ents[blockIdx.z];
+    const Entry en = ents[blockIdx.z];
     const int k = blockIdx.x * DTX + threadIdx.x;
     const int j = blockIdx.y * DTY + threadIdx.y;
     if (k >= np || j >= nt) return;
-    const size_t base = (size_t)e.r * nt * np;
-    const DiffRow<float> d = drow[(size_t)e.r * nt + j];
-    const StageCoef c = coefs[e.coef_off + jst];
-    const float L = apply_L<float>(d, dm1 + base, j, k, nt, np);
+    const size_t base = (size_t)en.r * nt * np;
+    const DiffRow<float> d = drow[(size_t)en.r * nt + j];
+    const StageCoef c = coefs[en.coef_off + jst];
+    const float L = apply_L<float>(d, din + base, j, k, nt, np);
     const size_t i = base + (size_t)j * np + k;
-    const float v = sts_mixed(c, dm1[i], dm2 ? dm2[i] : 0.0f, dm2 != nullptr, L, ly0[i]);
-    if (jst == e.s) {
+    const float dv = din[i];
+    const float ev = sts_mixed(c, dv, ein ? ein[i] : dv, L, ly0[i]);
+    const float v = dv + ev;
+    if (jst == en.s) {
         double y0 = B[i];
-        if (e.pad) y0 += (double)adv[i];
+        if (en.pad) y0 += (double)adv[i];
         B[i] = y0 + (double)v;
     } else {
-        out[i] = v;
+        dout[i] = v;
+        eout[i] = ev;
     }
 }
 
@@ -166,12 +172,12 @@ void launch_diff_first_mixed(hipStream_t st, const Entry* ents, int n_ent, const
 
 void launch_diff_stage_mixed(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs,
                              int j, const DiffRow<float>* drow, double* B, const float* adv,
-                             const float* dm1, const float* dm2, const float* ly0, float* out,
-                             int nt, int np)
+                             const float* din, const float* ein, const float* ly0, float* dout,
+                             float* eout, int nt, int np)
 {
     dim3 grid((np + DTX - 1) / DTX, (nt + DTY - 1) / DTY, n_act);
     hipLaunchKernelGGL(diff_stage_mixed_kernel, grid, dim3(DTX, DTY), 0, st, ents, coefs, j, drow, B,
-                       adv, dm1, dm2, ly0, out, nt, np);
+                       adv, din, ein, ly0, dout, eout, nt, np);
 }
 
 // Closes a step in the increment form: B = B (+ adv) (+ d).  Used for

@@ -16,10 +16,12 @@
 //
 // FP64 paper form: inputs Y_{j0-1}, Y_{j0-2}, a copy of Y0 and L(Y0) (the
 // strip variant computes L(Y0) from the staged Y0 instead of reading it).
-// FP32 increment form: inputs d_{j0-1}, d_{j0-2} (absent when j0 = 2) and
-// L(Y0).  An entry whose last stage s falls in this launch writes the final
-// field into the FP64 state B (only the cell's own value of B is read, and
-// only in the increment form), otherwise the last two stages go to out1/out2.
+// FP32 increment form: inputs d_{j0-1}, its change e = d_{j0-1} - d_{j0-2}
+// (absent when j0 = 2: e = d_1) and L(Y0).  An entry whose last stage s falls
+// in this launch writes the final field into the FP64 state B (only the
+// cell's own value of B is read, and only in the increment form), otherwise
+// the last two stages (FP64) or the last stage and its change (FP32) go to
+// out1/out2.
 #include "diff_common.h"
 #include "sft_internal.h"
 
@@ -92,7 +94,8 @@ __global__ __launch_bounds__(NT) void diff_fused_kernel(
             buf[1][idx] = a;
         }
         ycur[m] = a;
-        ym2[m] = b;
+        // FP32: ym2 carries e = d_{j0-1} - d_{j0-2} (d_1 itself at j0 = 2)
+        ym2[m] = MIXED && !has_in2 ? a : b;
         lyr[m] = l;
         if constexpr (!MIXED) y0r[m] = z;
     }
@@ -101,7 +104,6 @@ __global__ __launch_bounds__(NT) void diff_fused_kernel(
     int p = 0;
     for (int i = 0; i < kk; ++i) {
         const StageCoef c = coefs[e.coef_off + j0 + i];
-        const bool h2 = has_in2 || i > 0;
         const T* cb = buf[p];
         T* nb = buf[p ^ 1];
 #pragma unroll
@@ -110,12 +112,18 @@ __global__ __launch_bounds__(NT) void diff_fused_kernel(
                 const int idx = tid + m * NT;
                 const DiffRow<T> d = rowc[idx / LX];
                 const T L = L5<T>(d, cb[idx - 1], cb[idx - LX], ycur[m], cb[idx + LX], cb[idx + 1]);
-                T v;
-                if constexpr (MIXED) v = sts_mixed(c, ycur[m], ym2[m], h2, L, lyr[m]);
-                else v = sts_f64(c, ycur[m], ym2[m], y0r[m], L, lyr[m]);
-                nb[idx] = v;
-                ym2[m] = ycur[m];
-                ycur[m] = v;
+                if constexpr (MIXED) {
+                    const T ev = sts_mixed(c, ycur[m], ym2[m], L, lyr[m]);
+                    const T v = ycur[m] + ev;
+                    nb[idx] = v;
+                    ym2[m] = ev;
+                    ycur[m] = v;
+                } else {
+                    const T v = sts_f64(c, ycur[m], ym2[m], y0r[m], L, lyr[m]);
+                    nb[idx] = v;
+                    ym2[m] = ycur[m];
+                    ycur[m] = v;
+                }
             }
         }
         p ^= 1;
@@ -218,6 +226,8 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     // at zero
     T ya[RPT][CPL], yb[RPT][CPL], lyr[RPT][CPL];
     double y0r[MIXED ? 1 : RPT][MIXED ? 1 : CPL];
+    // FP32: e = d_{j-1} - d_{j-2}, updated in place (d_1 itself at j0 = 2)
+    T ez[MIXED ? RPT : 1][MIXED ? CPL : 1];
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
         const int j = jw + m;
@@ -236,6 +246,7 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
             yb[m][c] = b;
             lyr[m][c] = l;
             if constexpr (!MIXED) y0r[m][c] = z;
+            else ez[m][c] = has_in2 ? b : a;
         }
     }
 
@@ -278,7 +289,6 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     // region lies K cells inside the ring, as in the tiled variant.
     auto stage = [&](int i, T (&cur)[RPT][CPL], T (&prv)[RPT][CPL]) {
         const StageCoef cf = coefs[e.coef_off + j0 + i];
-        const bool h2 = has_in2 || i > 0;
         const int q = i & 1;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
@@ -312,8 +322,13 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
                 const T ev = c < CPL - 1 ? cur[m][c + 1] : el;
                 const T L = L5<T>(d, wv, m > 0 ? cur[m - 1][c] : north[c], cur[m][c],
                                   m < RPT - 1 ? cur[m + 1][c] : south[c], ev);
-                if constexpr (MIXED) prv[m][c] = sts_mixed(cf, cur[m][c], prv[m][c], h2, L, lyr[m][c]);
-                else prv[m][c] = sts_f64(cf, cur[m][c], prv[m][c], y0r[m][c], L, lyr[m][c]);
+                if constexpr (MIXED) {
+                    const T ev = sts_mixed(cf, cur[m][c], ez[m][c], L, lyr[m][c]);
+                    ez[m][c] = ev;
+                    prv[m][c] = cur[m][c] + ev;
+                } else {
+                    prv[m][c] = sts_f64(cf, cur[m][c], prv[m][c], y0r[m][c], L, lyr[m][c]);
+                }
             }
         }
     };
@@ -324,6 +339,16 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     }
     const bool odd = i < kk;
     if (odd) stage(i, ya, yb);
+    if constexpr (MIXED) {
+        // the slot of the stage before the last takes e, the output's partner
+#pragma unroll
+        for (int m = 0; m < RPT; ++m)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                if (odd) ya[m][c] = ez[m][c];
+                else yb[m][c] = ez[m][c];
+            }
+    }
 
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
@@ -333,6 +358,7 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
         for (int m = 0; m < RPT; ++m) {
             const int ly = w * RPT + m, j = jw + m;
             if (ly < K || ly >= K + TY || j >= nt) continue;
+            // FP64: the last two stages; FP32: the last stage and its change e
             const T last = odd ? yb[m][c] : ya[m][c], before = odd ? ya[m][c] : yb[m][c];
             const size_t gi = base + (size_t)j * np + k;
             if (fin) {

@@ -820,7 +820,7 @@ sft_status choose_tile(sft_ctx* c, GridClass* g)
     else
         best = time_it([&] {
             launch_diff_stage_mixed(c->stream, d_ents, R, d_coefs, 10, g->dr32, g->B, g->A[0], g->A[1],
-                                    g->A[2], g->A[3], g->A[4], nt, np);
+                                    g->A[2], g->A[3], g->A[4], g->A[2], nt, np);
         }, 4);
     for (int cfg = 0; cfg < fused_config_count(mixed); ++cfg) {
         const int K = fused_config_k(mixed, cfg);
@@ -971,25 +971,15 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p, int lane)
                 if (fused) {
                     run_fused_groups(c, g, p, ph);
                 } else {
+                    // d alternates between P1 and P2 (a stage reads its
+                    // neighbours); e = d_{j-1} - d_{j-2} is updated in place in A[4]
+                    float* EA = g->A[4];
                     for (int j = 2; j <= ph.max_s; ++j) {
-                        const float *dm1, *dm2;
-                        float* out;
-                        if (j == 2) {
-                            dm1 = P1;
-                            dm2 = nullptr;
-                            out = P2;
-                        } else if (j & 1) {
-                            dm1 = P2;
-                            dm2 = P1;
-                            out = P1;
-                        } else {
-                            dm1 = P1;
-                            dm2 = P2;
-                            out = P2;
-                        }
+                        const float* din = (j & 1) ? P2 : P1;
+                        float* dout = (j & 1) ? P1 : P2;
                         tbeg(c);
-                        launch_diff_stage_mixed(st, E, ph.n_act[j], p->d_coefs, j, g->dr32, g->B, A0, dm1,
-                                                dm2, LY, out, nt, np);
+                        launch_diff_stage_mixed(st, E, ph.n_act[j], p->d_coefs, j, g->dr32, g->B, A0, din,
+                                                j == 2 ? nullptr : EA, LY, dout, EA, nt, np);
                         tend(c, SFT_KFAM_STS_STAGE, stage_bytes(p, ph, j, true, g->cells()));
                     }
                 }

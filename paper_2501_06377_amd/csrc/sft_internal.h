@@ -111,8 +111,8 @@ void launch_diff_first_mixed(hipStream_t st, const Entry* ents, int n_ent, const
                              float* ly0, float* d1, int nt, int np);
 void launch_diff_stage_mixed(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs,
                              int j, const DiffRow<float>* drow, double* B, const float* adv,
-                             const float* dm1, const float* dm2, const float* ly0, float* out,
-                             int nt, int np);
+                             const float* din, const float* ein, const float* ly0, float* dout,
+                             float* eout, int nt, int np);
 //   Temporally blocked stages j0 .. j0+K-1 (K of tile configuration cfg).
 //   in1/in2/ly0/out1/out2 are double (FP64) or float (mixed) arrays; y0 is the
 //   FP64 copy of Y0 (paper form only).
