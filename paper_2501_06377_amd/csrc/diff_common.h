@@ -30,22 +30,6 @@ __device__ __forceinline__ T L5(const DiffRow<T>& d, T w, T n, T c, T s, T e)
     return v;
 }
 
-// FP32 (the increment form's operator): the same operator summed as
-// coefficient x (neighbour - centre), the diagonal being minus the sum of the
-// neighbours' coefficients in every row.  The plain five-term sum cancels a
-// large diagonal term against the neighbour sum and, in FP32, loses digits
-// in proportion to diagonal / result over every one of a call's thousand or
-// more stages; the differences of neighbouring values are nearly exact.
-template <>
-__device__ __forceinline__ float L5<float>(const DiffRow<float>& d, float w, float n, float c, float s, float e)
-{
-    float v = d.ph * (w - c);
-    v = __builtin_fmaf(d.up, n - c, v);
-    v = __builtin_fmaf(d.dn, s - c, v);
-    v = __builtin_fmaf(d.ph, e - c, v);
-    return v;
-}
-
 // FP64 stage: Y_j = nu Y_{j-2} + mu Y_{j-1} + cy0 Y0 + cL L + cLY0 L(Y0)
 // (the Y_{j-2} term first: its register, dead afterwards, takes the result).
 __device__ __forceinline__ double sts_f64(const StageCoef& c, double ym1, double ym2, double y0,
