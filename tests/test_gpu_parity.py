@@ -293,6 +293,27 @@ def test_full_size_mixed_precision_first_hour():
         assert e <= TOL32
 
 
+def test_full_size_precision_grid_f64_first_hour():
+    """The FP64 path on the precision workload's 1024 x 2048 grid against the
+    FP64 oracle over its first hour: a realization of that workload and a
+    pure-diffusion one at 800 km^2/s whose single STS call is ~1,800 stages
+    long (the longest calls of the workloads)."""
+    nt, np_ = 1024, 2048
+    w = synth.config3(n=1)
+    reals = [w.classes[0][2][0], synth.Realization(nu_km2_s=800.0, d0=0.0, d2=0.0, d4=0.0, m1=0.0)]
+    say("case 1024x2048 FP64 first hour")
+    f0 = random_field(nt, np_, w.n_pairs, 570)
+    B0 = np.stack([f0, f0])
+    ref, st = oracle_run(B0, reals, [("advance", 1.0)])
+    got, ens = gpu_run(B0, reals, [("advance", 1.0)])
+    assert st[1]["stages"] > 1500
+    for r in range(2):
+        assert ens.counts(r)["stages"] == st[r]["stages"]
+        e = rel_l2(got[r], ref[r])
+        say(f"  realization {r}: stages {st[r]['stages']} rel-L2 {e:.3e}")
+        assert e <= TOL64
+
+
 def test_full_size_uneven_batch_first_hour():
     """The batching workload's three size classes (256x512, 512x1024,
     1024x2048; one realization each here) in one graph-captured context,
