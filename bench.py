@@ -12,10 +12,17 @@ assimilation and the FP64 analysis reductions.  The default --steps 655
 covers the configuration's 27.3 days (655 one-hour intervals).
 
 Inputs (initial fields and every observation map) are resident in HBM
-before the timed region.  Every kernel launch of the timed region is
-bracketed by HIP events on the library's stream; the roofline object reports
-the dominant kernel family from those events.  The CPU baseline times the
-FP64 oracle (as is) on the first hours of the same workload.
+before the timed region, which runs without per-launch events.  A second
+pass over the first intervals of the same workload, in a one-lane context,
+brackets every kernel launch with HIP events on the stream it is launched
+on; the roofline object reports the dominant kernel family from those
+events.  The CPU baseline times the FP64 oracle (as is) on the first hours
+of the same workload.
+
+Other workloads (--workload): the FP32-mixed precision configuration (with
+its per-realization difference from the FP64 path), the uneven batch, the
+flux-preserving smoother, the paper's timed soccer-ball validation runs, and
+the plain single-realization configuration.
 
 Prints one JSON line.
 """
