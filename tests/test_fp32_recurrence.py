@@ -1,0 +1,77 @@
+"""The FP32 increment form of the super-time-stepping recurrence, modelled in
+numpy (CPU): carried as the increment d and its last change e it is the same
+recurrence as the three-term form (equal to the FP64 oracle in FP64), and in
+FP32 its rounding error stays far below the three-term form's over a call of
+about a thousand stages (the three-term form's errors grow with the square
+of the stage count).  This pins the arithmetic the GPU's FP32 kernels use."""
+import numpy as np
+import pytest
+
+import oracle
+
+NT, NP = 128, 256
+
+
+def operator(coefs, y):
+    """The five-diagonal operator with the oracle's row coefficients (pole
+    rows carry a zero pole-face coefficient; their clamped neighbour meets it)."""
+    up, dn, ph, dd = coefs
+    n = np.concatenate([y[:1], y[:-1]], axis=0)
+    s = np.concatenate([y[1:], y[-1:]], axis=0)
+    w, e = np.roll(y, 1, axis=1), np.roll(y, -1, axis=1)
+    return ph[:, None] * w + up[:, None] * n + dd[:, None] * y + dn[:, None] * s + ph[:, None] * e
+
+
+def run(y0, nu, tau, s, dtype, carried):
+    mu, nv, mut, gamt = oracle.sts_coefs(s, oracle.RKG2)
+    coefs = tuple(c.astype(dtype) for c in oracle.diff_coefs(NT, NP, nu))
+    ly0 = operator(oracle.diff_coefs(NT, NP, nu), y0).astype(dtype)   # L(Y0) formed in FP64
+    d = (dtype(mut[1] * tau) * ly0).astype(dtype)
+    e = d.copy()                               # d_1 - d_0, d_0 = 0
+    dprev = np.zeros_like(d)
+    for j in range(2, s + 1):
+        L = operator(coefs, d)
+        c1, c2 = dtype(mut[j] * tau), dtype((mut[j] + gamt[j]) * tau)
+        if carried:
+            en = dtype(mu[j] + nv[j] - 1.0) * d - dtype(nv[j]) * e + c1 * L + c2 * ly0
+            d, e = (d + en).astype(dtype), en.astype(dtype)
+        else:
+            dn = dtype(mu[j]) * d + dtype(nv[j]) * dprev + c1 * L + c2 * ly0
+            dprev, d = d, dn.astype(dtype)
+    return y0 + d.astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def case():
+    th = (np.arange(NT) + 0.5) * np.pi / NT
+    ph = (np.arange(NP) + 0.5) * 2 * np.pi / NP
+    TH, PH = np.meshgrid(th, ph, indexing="ij")
+    y0 = 300.0 * np.exp(-((TH - 1.2) ** 2 + (PH - 2.0) ** 2) / 0.05) - 200.0 * np.sin(TH) ** 3 * np.cos(3 * PH)
+    _, k2 = oracle.units()
+    nu = 500.0 * k2
+    dte = oracle.euler_limit(NT, NP, nu)
+    tau = 1.7e5 * dte
+    s = oracle.sts_stages(tau, dte, oracle.RKG2)
+    ref, st = oracle.diffuse(y0, nu, tau, oracle.RKG2)
+    assert st == s and s > 900
+    return y0, nu, tau, s, ref
+
+
+def test_carried_form_is_the_same_recurrence(case):
+    """In FP64 both forms land on the oracle's result (the same recurrence,
+    rounded differently)."""
+    y0, nu, tau, s, ref = case
+    for carried in (False, True):
+        got = run(y0, nu, tau, s, np.float64, carried)
+        e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert e < 1e-11, (carried, e)
+
+
+def test_carried_form_keeps_fp32_rounding_small(case):
+    """In FP32 the three-term form drifts by ~s^2 eps of the increment; the
+    carried form stays orders of magnitude closer to the FP64 oracle."""
+    y0, nu, tau, s, ref = case
+    e3 = np.linalg.norm(run(y0, nu, tau, s, np.float32, False) - ref) / np.linalg.norm(ref)
+    ec = np.linalg.norm(run(y0, nu, tau, s, np.float32, True) - ref) / np.linalg.norm(ref)
+    assert ec < 1e-6, ec
+    assert ec < e3 / 30.0, (e3, ec)
