@@ -24,8 +24,9 @@
  * B in gauss.
  *
  * Parity notes: every function here is pinned by a test in tests/ against
- * closed forms, library routines or brute force, except where its header
- * says "parity unpinned".
+ * closed forms, library routines or brute force.  The one rule the paper
+ * only cites, the practical time step limit of the diffusion advance, enters
+ * as an input (ptl_dt); what is pinned there is the split it drives.
  */
 #include <math.h>
 #include <stdint.h>
@@ -591,8 +592,10 @@ void or_sts_coefs(int s, int scheme, double *mu, double *nu, double *mut, double
 /* One diffusion advance of length tau (Sec. "Diffusion temporal schemes").
  * dscheme: 0 = RKG2(3/2), 1 = RKL2, 2 = forward Euler with n = ceil(tau/dt_E)
  * equal sub-steps (the paper's reference scheme).  ptl_dt > 0 splits tau into
- * ceil(tau/ptl_dt) equal STS calls (a stand-in hook for the practical time
- * step limit, whose formula is not in the paper: parity unpinned).
+ * n = ceil(tau/ptl_dt) STS calls of equal length tau/n (Sec. "Diffusion
+ * temporal schemes": the practical time step limit cycles the STS advance
+ * over sub-steps; the rule that picks the limit is only cited there, so the
+ * limit is an input).  Pinned: one advance equals R_s(tau/n A)^n Y0.
  * Returns the number of operator applications (stages). */
 long or_diffuse_face(int nt, int np, double *B, const double *nu_face, double tau, int dscheme,
                      double ptl_dt);

@@ -105,6 +105,57 @@ def test_cfl_limits_rigid_rotation():
     assert oracle.cfl_dt(nt, np_, vph * 0, vth, oracle.SSPRK43) == math.inf
 
 
+
+@pytest.mark.parametrize("case", ["top", "bottom"])
+def test_cfl_takes_the_larger_flanking_theta_speed(case):
+    """Eq. ssprk43_dt evaluates each velocity at a cell as the larger of its
+    two flanking staggered values.  One row carries azimuthal speed and its
+    two theta faces carry different speeds (the larger one on top, then on
+    the bottom); every other face is at rest, so that row binds and the limit
+    is 1/(max(a, b)/dth + vp/(sin(theta) dph)).  Reading one face only, or the
+    mean of the two, gives a different number in one of the two cases."""
+    nt, np_ = 24, 48
+    dth, dph = np.pi / nt, 2 * np.pi / np_
+    j = 7
+    a, b = (3.0, 1.0) if case == "top" else (1.0, 3.0)
+    vth = np.zeros(nt + 1)
+    vth[j], vth[j + 1] = -a, b
+    vph = np.zeros(nt)
+    vph[j] = 0.8
+    s = math.sin((j + 0.5) * dth)
+    want = 1.0 / (3.0 / dth + 0.8 / (s * dph))
+    lim = oracle.cfl_dt(nt, np_, vph, vth, oracle.SSPRK43)
+    assert lim == pytest.approx(want, rel=1e-14)
+    for wrong in (1.0 / (2.0 / dth + 0.8 / (s * dph)),                       # mean of the flanks
+                  1.0 / max(1.0 / dth + 0.8 / (s * dph), 3.0 / dth)):        # the other face only
+        assert abs(lim - wrong) > 1e-3 * want
+    # forward Euler and SSPRK(3,3) take half of it (eq. advection_timestep)
+    assert oracle.cfl_dt(nt, np_, vph, vth, oracle.FE) == pytest.approx(0.5 * want, rel=1e-14)
+    assert oracle.cfl_dt(nt, np_, vph, vth, oracle.SSPRK33) == pytest.approx(0.5 * want, rel=1e-14)
+
+
+def test_cfl_closed_form_for_the_workload_flows():
+    """Eq. mf with m1 only is v_theta = -m1 cos(theta) sin(theta), whose
+    largest speed m1/2 sits on the face at 45 degrees (a face of the grid when
+    nt is a multiple of 4).  Alone it gives dth/(m1/2); with rigid rotation
+    added (eq. dr with d0 only, so v_phi/(sin(theta) dph) is the same Omega/dph
+    in every row) the limit is 1/((m1/2)/dth + Omega/dph).  The mean of two
+    flanks never reaches the peak, so that reading fails both."""
+    nt, np_ = 40, 80
+    dth, dph = np.pi / nt, 2 * np.pi / np_
+    ms, _ = oracle.units()
+    m1, d0 = 24.0, 140.0
+    for with_dr in (False, True):
+        vph, vth = oracle.flows(nt, (d0 if with_dr else 0.0, 0, 0, m1, 0, 0))
+        omega = d0 * ms if with_dr else 0.0
+        want = 1.0 / (0.5 * m1 * ms / dth + omega / dph)
+        assert oracle.cfl_dt(nt, np_, vph, vth, oracle.SSPRK43) == pytest.approx(want, rel=1e-13)
+        # the factor 1/2 of forward Euler and SSPRK(3,3)
+        for ts in (oracle.FE, oracle.SSPRK33):
+            assert oracle.cfl_dt(nt, np_, vph, vth, ts) == pytest.approx(0.5 * want, rel=1e-13)
+        mean_flank = np.maximum(0.5 * (np.abs(vth[:-1]) + np.abs(vth[1:])), 0.0).max()
+        assert mean_flank < 0.5 * m1 * ms * (1 - 1e-3)
+
 # --------------------------------------------------------------- WENO3
 @pytest.mark.parametrize("nonuniform", [False, True])
 @pytest.mark.parametrize("sign", [1.0, -1.0])
@@ -376,6 +427,63 @@ def test_sts_matches_stability_polynomial_brute_force(scheme, tau):
     assert np.allclose(got.ravel(), exact, rtol=1e-11, atol=1e-11 * np.abs(Y0).max())
     assert np.all(np.abs(R(tau * ev)) <= 1 + 1e-12)
 
+
+
+def _fewest_stages(tau, dtE, scheme):
+    """Fewest stages (>= 2) whose stability interval [-2/w, 0] covers the
+    Gershgorin bound 2/dtE of the operator's spectrum, from the polynomials."""
+    s = 2
+    while 2.0 / sts_poly(s, scheme)[1] < tau * (2.0 / dtE) * (1 - 1e-12):
+        s += 1
+    return s
+
+
+@pytest.mark.parametrize("scheme", [oracle.RKG2, oracle.RKL2])
+@pytest.mark.parametrize("tau,ptl", [(9.0, 2.5), (9.0, 3.0), (0.7, 2.0)])
+def test_ptl_hook_splits_into_equal_sts_calls(scheme, tau, ptl):
+    """With a step limit ptl_dt the diffusion advance of length tau runs as
+    n = ceil(tau/ptl_dt) super-time-stepping calls of the same length tau/n
+    (one call when tau <= ptl_dt), so the result is R_s(tau/n M)^n Y0 with s
+    the fewest stages for tau/n, and n s stages are counted (dense
+    eigen-decomposition on a 6 x 12 grid).  A floor instead of the ceiling,
+    or unequal calls (full ptl_dt steps and a remainder), land elsewhere."""
+    nt, np_ = 6, 12
+    _, k2 = oracle.units()
+    nu = 400.0 * k2 * 1e3
+    M = dense(lambda x: oracle.diff_operator(x, nu), nt, np_)
+    dtE = oracle.euler_limit(nt, np_, nu)
+    n = math.ceil(tau / ptl) if tau > ptl else 1
+    tc = tau / n
+    s = _fewest_stages(tc, dtE, scheme)
+    R, _ = sts_poly(s, scheme)
+    ev, V = sla.eig(M)
+    ev, V = ev.real, V.real
+    Y0 = np.random.default_rng(11).standard_normal(nt * np_)
+    Vi = np.linalg.inv(V)
+
+    def run(lengths):
+        y = Y0.copy()
+        for h in lengths:
+            Rh, _ = sts_poly(_fewest_stages(h, dtE, scheme), scheme)
+            y = V @ (Rh(h * ev) * (Vi @ y))
+        return y
+
+    exact = V @ (R(tc * ev) ** n * (Vi @ Y0))
+    got, st = oracle.diffuse(Y0.reshape(nt, np_), nu, tau, scheme, ptl_dt=ptl)
+    assert st == n * s
+    scale = np.abs(Y0).max()
+    assert np.allclose(got.ravel(), exact, rtol=1e-10, atol=1e-10 * scale)
+    if n > 1:
+        nf = math.floor(tau / ptl)
+        for wrong in (run([tau / nf] * nf) if nf * ptl != tau else None,
+                      run([ptl] * nf + ([tau - nf * ptl] if tau > nf * ptl else []))):
+            if wrong is not None and not np.allclose(wrong, exact, rtol=1e-10, atol=1e-10 * scale):
+                assert np.abs(got.ravel() - wrong).max() > 1e-6 * scale
+    # the grid-diffusivity path (eq. diffgrid) runs the same hook
+    nf_face = np.full(nt + 1, nu)
+    got_f, st_f = oracle.diffuse_face(Y0.reshape(nt, np_), nf_face, tau, scheme, ptl_dt=ptl)
+    assert st_f == n * s
+    assert np.array_equal(got_f, got)
 
 def test_forward_euler_diffusion_reference():
     nt, np_ = 6, 12
