@@ -57,6 +57,7 @@ def lib():
             "or_cell_weights": (None, [i, i, P]),
             "or_flows": (None, [i, P, P, P]),
             "or_cfl_dt": (d, [i, i, P, P, i]),
+            "or_cfl_dt_att": (d, [i, i, P, P, P, d, i]),
             "or_line_flux": (None, [i, i, P, P, P, i, d, P]),
             "or_adv_operator": (None, [i, i, P, P, P, i, d, P]),
             "or_adv_operator_att": (None, [i, i, P, P, P, i, d, P, d, P]),
@@ -125,6 +126,13 @@ def flows(nt, prm):
 
 def cfl_dt(nt, np_, vph, vth, time_scheme=SSPRK43):
     return lib().or_cfl_dt(nt, np_, _p(_f64(vph)), _p(_f64(vth)), time_scheme)
+
+
+def cfl_dt_att(vph, vth, Batt, b0, time_scheme=SSPRK43):
+    """CFL limit of the flow attenuated by the field Batt (eq. flow_attenuation)."""
+    Batt = _f64(Batt)
+    nt, np_ = Batt.shape
+    return lib().or_cfl_dt_att(nt, np_, _p(_f64(vph)), _p(_f64(vth)), _p(Batt), float(b0), time_scheme)
 
 
 def line_flux(B, dx, v, periodic, scheme=WENO3CSH, eps_mode=0.0):
@@ -254,16 +262,20 @@ def hh(X, Y):
 
 def advance(B, prm, nu_km2_s, t0, t_end, adv_scheme=WENO3CSH, adv_time=SSPRK43,
             diff_scheme=RKG2, safety=0.9, dt_max=0.0, eps_mode=0.0, ptl_dt=0.0, strang=0, att_b0=0.0,
-            rfe_model=0, rfe_phi_hr=0.0, rfe_tau=0.0, rfe_seed=0, rfe_id=0, nu_grid_alpha=0.0):
+            rfe_model=0, rfe_phi_hr=0.0, rfe_tau=0.0, rfe_seed=0, rfe_id=0, nu_grid_alpha=0.0,
+            dt_min=0.0, att_cfl=0):
     """Advance one realization from t0 to t_end (hours), operator split with
     or without Strang splitting, optionally with flow attenuation (att_b0 in
     gauss) and random flux emergence (model 1 / 2, phi_hr Mx per hour,
     lifetime rfe_tau hours, 0 = infinite; maps keyed by seed and id) and the
     smoother's grid diffusivity (nu_grid_alpha > 0 in 1/h replaces nu).
-    Returns (B, stats)."""
+    dt_min > 0 raises the step limit to at least dt_min hours; att_cfl = 1
+    takes each step's CFL limit from the attenuated flow of the field at the
+    step's start.  Returns (B, stats)."""
     B = _f64(B).copy()
     opts = np.array([adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang, att_b0,
-                     rfe_model, rfe_phi_hr, rfe_tau, rfe_seed, rfe_id, nu_grid_alpha], dtype=np.float64)
+                     rfe_model, rfe_phi_hr, rfe_tau, rfe_seed, rfe_id, nu_grid_alpha, dt_min, att_cfl],
+                    dtype=np.float64)
     stats = np.zeros(3)
     lib().or_advance(B.shape[0], B.shape[1], _p(B), _p(_f64(prm)), float(nu_km2_s), float(t0),
                      float(t_end), _p(opts), _p(stats))

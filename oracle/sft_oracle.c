@@ -150,6 +150,42 @@ double or_cfl_dt(int nt, int np, const double *vph_row, const double *vth_face, 
     return lim;
 }
 
+/* Eq. ssprk43_dt (or eq. advection_timestep) for the attenuated flow of
+ * eq. flow_attenuation: each face velocity is scaled by 1 - tanh(m/b0), m
+ * the mean of |Batt| over the face's two cells (as in the advection
+ * operator), and each cell takes the larger of its two flanking face speeds
+ * in theta and in phi.  Batt is the field at the start of the step.  Returns
+ * the limit without safety factor; +inf when nothing moves. */
+double or_cfl_dt_att(int nt, int np, const double *vph_row, const double *vth_face, const double *Batt,
+                     double b0, int time_scheme)
+{
+    double dth = M_PI / nt, dph = 2.0 * M_PI / np;
+    double rmax = 0.0;
+    for (int j = 0; j < nt; ++j) {
+        double s = sin((j + 0.5) * dth);
+        for (int k = 0; k < np; ++k) {
+            size_t c = (size_t)j * np + k;
+            size_t w = (size_t)j * np + (k + np - 1) % np, e = (size_t)j * np + (k + 1) % np;
+            double vw = fabs(vph_row[j] * (1.0 - tanh(0.5 * (fabs(Batt[w]) + fabs(Batt[c])) / b0)));
+            double ve = fabs(vph_row[j] * (1.0 - tanh(0.5 * (fabs(Batt[c]) + fabs(Batt[e])) / b0)));
+            double vn = j == 0 ? fabs(vth_face[0])
+                               : fabs(vth_face[j] *
+                                      (1.0 - tanh(0.5 * (fabs(Batt[c - np]) + fabs(Batt[c])) / b0)));
+            double vs = j == nt - 1 ? fabs(vth_face[nt])
+                                    : fabs(vth_face[j + 1] *
+                                           (1.0 - tanh(0.5 * (fabs(Batt[c]) + fabs(Batt[c + np])) / b0)));
+            double vt = vn > vs ? vn : vs;
+            double vp = vw > ve ? vw : ve;
+            double r = vt / dth + vp / (s * dph);
+            if (r > rmax) rmax = r;
+        }
+    }
+    if (rmax == 0.0) return INFINITY;
+    double lim = 1.0 / rmax;
+    if (time_scheme != 0) lim *= 0.5;
+    return lim;
+}
+
 /* ------------------------------------------------------- advection fluxes */
 /* Upwind / central face flux (Sec. "Advection spatial schemes"):
  * F_{i-1/2} = v_{i-1/2} (1/2)[(1-uw) B_i + (1+uw) B_{i-1}],
@@ -960,9 +996,15 @@ double or_hh(long n, const double *X, const double *Y)
  * leave less than 1e-10 h before the segment's end is stretched to land on it.
  * prm = {d0, d2, d4, m1, m3, m5} (m/s), nu_km2_s scalar diffusivity.
  * opts = {adv_scheme, adv_time, diff_scheme, safety, dt_max, eps_mode, ptl_dt, strang, att_b0,
- *         rfe_model, rfe_phi_hr, rfe_tau, rfe_seed, rfe_id, nu_grid_alpha}
- * (att_b0: flow attenuation saturation, gauss, 0 = none; the CFL limit is
- * that of the unattenuated flow, an upper bound of the attenuated speeds;
+ *         rfe_model, rfe_phi_hr, rfe_tau, rfe_seed, rfe_id, nu_grid_alpha, dt_min, att_cfl}
+ * (att_b0: flow attenuation saturation, gauss, 0 = none; with att_cfl = 0
+ * the CFL limit is that of the unattenuated flow, an upper bound of the
+ * attenuated speeds, with att_cfl = 1 that of the attenuated flow of the
+ * field at the start of each step (eq. ssprk43_dt per step, doubled under
+ * Strang splitting);
+ * dt_min > 0: the step limit min(safety CFL, dt_max) is raised to dt_min
+ * (Sec. "Time steps" lists a minimum step among the user's controls), the
+ * step still ending no later than the segment's end;
  * rfe_model 0 = no source, 1 / 2 = eq. rfe_m1 / rfe_m2 maps of phi_hr Mx per
  * hour, lifetime rfe_tau hours (<= 0: infinite, one map), maps keyed by
  * (rfe_seed, rfe_id) and their index k, map k belonging to time k tau;
@@ -983,6 +1025,8 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
     double rfe_phi = opts[10], tau = opts[11];
     uint32_t seed = (uint32_t)opts[12], rid = (uint32_t)opts[13];
     double nu_alpha = opts[14];
+    double dt_min = opts[15];
+    int att_cfl = (int)opts[16];
     size_t n = (size_t)nt * np;
     /* eq. diffgrid replaces the scalar diffusivity when nu_alpha > 0 */
     double *nuf = NULL;
@@ -1028,9 +1072,16 @@ int or_advance(int nt, int np, double *B, const double *prm, double nu_km2_s, do
         double el = 0.0;
         while (el < len) {
             double rem = len - el;
+            double lim = cfl;
+            if (att_cfl && att_b0 > 0.0 && has_flow) {
+                lim = or_cfl_dt_att(nt, np, vph, vth, B, att_b0, adv_time);
+                if (strang) lim *= 2.0;
+            }
+            double cap = safety * lim;
+            if (dt_max > 0.0 && dt_max < cap) cap = dt_max;
+            if (dt_min > 0.0 && cap < dt_min) cap = dt_min;
             double dt = rem;
-            if (safety * cfl < dt) dt = safety * cfl;
-            if (dt_max > 0.0 && dt_max < dt) dt = dt_max;
+            if (cap < dt) dt = cap;
             int final = 0;
             if (rem - dt < 1e-10) {
                 dt = rem;

@@ -583,6 +583,86 @@ def test_time_loop_dt_rule_and_conservation():
     assert np.allclose(Ba, B, atol=1e-2 * np.abs(B0).max())
 
 
+def test_time_loop_minimum_step():
+    """A minimum step (Sec. "Time steps" lists it among the user's controls)
+    raises the step limit min(0.9 CFL, dt_max) to dt_min; the step still ends
+    on the interval's end.  Below the limit it changes nothing."""
+    nt, np_ = 24, 48
+    prm = (0.0, -337.4, -253.1, 30.0, 0.0, 0.0)
+    vph, vth = oracle.flows(nt, prm)
+    lim = 0.9 * oracle.cfl_dt(nt, np_, vph, vth)
+    B0 = np.random.default_rng(12).standard_normal((nt, np_)) * 30
+    T = 7.3 * lim
+    ref, st0 = oracle.advance(B0, prm, 300.0, 0.0, T)
+    same, st1 = oracle.advance(B0, prm, 300.0, 0.0, T, dt_min=0.5 * lim)
+    assert np.array_equal(ref, same) and st1 == st0
+    dmin = 2.5 * lim
+    _, st = oracle.advance(B0, prm, 300.0, 0.0, T, dt_min=dmin)
+    assert st["steps"] == math.ceil(T / dmin) == 3
+    assert st["dt_last"] == pytest.approx(T - 2 * dmin, rel=1e-12)
+    # dt_min also overrides a smaller dt_max
+    _, st = oracle.advance(B0, prm, 300.0, 0.0, T, dt_max=0.3 * lim, dt_min=dmin)
+    assert st["steps"] == 3
+    # and never carries a step past the end
+    _, st = oracle.advance(B0, prm, 300.0, 0.0, 0.4 * lim, dt_min=dmin)
+    assert st["steps"] == 1 and st["dt_last"] == pytest.approx(0.4 * lim, rel=1e-15)
+
+
+def test_attenuated_cfl_closed_forms():
+    """CFL limit of the attenuated flow (eq. flow_attenuation inside eq.
+    ssprk43_dt): a zero field leaves the flow and the limit as they are; a
+    field of uniform magnitude c scales every speed by 1 - tanh(c/B0), so the
+    limit by its inverse; a field saturating everywhere except two adjacent
+    rows j, j+1 stops every face but the phi faces of those rows and the
+    theta face between them, leaving 1/(|v_theta(face j+1)|/dth + Omega/dph)
+    under rigid rotation (Omega/dph the same in every row)."""
+    nt, np_ = 24, 48
+    dth, dph = np.pi / nt, 2 * np.pi / np_
+    ms, _ = oracle.units()
+    d0, m1, b0 = 14.0, 240.0, 50.0
+    vph, vth = oracle.flows(nt, (d0, 0, 0, m1, 0, 0))
+    plain = oracle.cfl_dt(nt, np_, vph, vth)
+    assert oracle.cfl_dt_att(vph, vth, np.zeros((nt, np_)), b0) == plain
+    c = 37.0
+    for sign in (1.0, -1.0):
+        lim = oracle.cfl_dt_att(vph, vth, np.full((nt, np_), sign * c), b0)
+        assert lim == pytest.approx(plain / (1.0 - math.tanh(c / b0)), rel=1e-13)
+    for ts in (oracle.FE, oracle.SSPRK33):
+        assert (oracle.cfl_dt_att(vph, vth, np.full((nt, np_), c), b0, ts) ==
+                pytest.approx(0.5 * plain / (1.0 - math.tanh(c / b0)), rel=1e-13))
+    j = 1
+    Batt = np.full((nt, np_), 1e4 * b0)
+    Batt[j:j + 2] = 0.0
+    want = 1.0 / (abs(vth[j + 1]) / dth + d0 * ms / dph)
+    assert oracle.cfl_dt_att(vph, vth, Batt, b0) == pytest.approx(want, rel=1e-13)
+    assert want > 1.5 * plain
+
+
+def test_time_loop_attenuated_cfl_step_count():
+    """Under rigid rotation a constant field stays constant (the flow is
+    divergence-free and constants are a fixed point of diffusion), so with
+    the per-step attenuated limit every step is 0.9 dph/(Omega (1 - tanh(c/B0)))
+    long, and the interval takes the closed-form number of steps; the static
+    (unattenuated) limit takes more, shorter steps."""
+    nt, np_ = 16, 32
+    dph = 2 * np.pi / np_
+    ms, _ = oracle.units()
+    d0, b0, c = 1807.66, 40.0, 30.0
+    omega = d0 * ms
+    f = 1.0 - math.tanh(c / b0)
+    B0 = np.full((nt, np_), c)
+    T = 40.0
+    B, st = oracle.advance(B0, (d0, 0, 0, 0, 0, 0), 500.0, 0.0, T, att_b0=b0, att_cfl=1)
+    step = 0.9 * dph / (omega * f)
+    assert st["steps"] == math.ceil(T / step)
+    assert st["dt_last"] == pytest.approx(T - (st["steps"] - 1) * step, rel=1e-9)
+    assert np.allclose(B, c, rtol=1e-12)
+    _, st_static = oracle.advance(B0, (d0, 0, 0, 0, 0, 0), 500.0, 0.0, T, att_b0=b0)
+    assert st_static["steps"] == math.ceil(T / (0.9 * dph / omega)) > st["steps"]
+    # under Strang splitting each advection advance is half a step: the limit doubles
+    _, st2 = oracle.advance(B0, (d0, 0, 0, 0, 0, 0), 500.0, 0.0, T, att_b0=b0, att_cfl=1, strang=1)
+    assert st2["steps"] == math.ceil(T / (2.0 * step))
+
 def test_rigid_rotation_returns_map():
     """A full rigid rotation (Sec. "Test cases", v_phi = 1.80766 km/s sin
     theta for 672 h) through the full time loop returns the soccer-ball map
