@@ -118,6 +118,19 @@ typedef struct {
     double rfe_phi_hr;    /* total unsigned flux per hour of a source map, Mx (> 0 when
                              rfe_model != 0)                                            */
     double rfe_lifetime_h;/* time between source maps tau, hours; 0 = infinite (one map) */
+    double dt_min;        /* minimum step, hours (Sec. "Time steps" lists a minimum and a
+                             maximum step among the user's controls): the step limit
+                             min(cfl_safety * CFL, dt_max) is raised to dt_min, which
+                             overrides the flow's stability limit; a step still ends on
+                             t_end.  0 (default) = none                                 */
+    int32_t att_cfl;      /* 0 (default): with flow attenuation the step keeps the
+                             unattenuated flow's CFL limit (an upper bound of the
+                             attenuated speeds, so one plan per interval length);
+                             1: each step of an attenuated realization takes eq.
+                             ssprk43_dt of the attenuated flow of the field at the start
+                             of the step (a device max-reduction read back per step;
+                             no graphs for such advances; not with rfe_model != 0)   */
+    int32_t reserved0;
 } sft_options;
 
 /* Per-realization parameters (Sec. "Multiple Realizations"). */
@@ -202,8 +215,8 @@ sft_status sft_get_states(sft_ctx* ctx, int32_t grid_id, void* br_out, int32_t d
 
 /* Advances every realization from the context time t to t_end (hours),
  * landing exactly on t_end (Sec. "Time steps": each realization takes steps
- * dt = min(t_end - t, cfl_safety * flow CFL limit, dt_max); a step that would
- * leave less than 1e-10 h is stretched to t_end).  Each step applies
+ * dt = min(t_end - t, max(min(cfl_safety * flow CFL limit, dt_max), dt_min));
+ * a step that would leave less than 1e-10 h is stretched to t_end).  Each step applies
  * advection then diffusion (eq. num_opsplit_nostrang), or with opt.strang
  * half an advection, the diffusion and the other half (eq.
  * num_opsplit_strang, CFL limit doubled).
@@ -315,21 +328,46 @@ sft_status sft_net_get_activation(sft_net* net, int32_t layer, void* out);
 sft_status sft_net_train_step(sft_net* net, int32_t batch, const void* b_in, const void* b_target,
                               int32_t dtype, const float* feats, float lr, int32_t apply,
                               double* loss);
+/* Limits the number of blocks of the network's persistent convolution and
+ * weight-gradient launches to max_blocks (0, the default: one wave over the
+ * compute units).  Each block walks tiles (or weight-gradient work items) at
+ * a stride of the grid size, so a small limit runs many per block even on
+ * small fields; the convolution outputs do not depend on it, and the weight
+ * gradients change only by the regrouping of their FP32 partial sums.  For
+ * testing the persistent loops at sizes a CPU reference can follow.
+ * Errors: SFT_ERR_ARG. */
+sft_status sft_net_set_grid_limit(sft_net* net, int32_t max_blocks);
 sft_status sft_net_sync(sft_net* net);
 sft_status sft_net_destroy(sft_net* net);
 
-/* Advances the context from its time to t_end with the surrogate for grid
- * class grid_id (the network must be trained for t_end - t = 1 h and have the
+/* Advances the context by one 1-hour interval (t_end - t must be 1 h within
+ * 1e-9 h, else SFT_ERR_ARG: the network stands in for one such interval)
+ * with the surrogate for grid class grid_id (the network must have the
  * class's resolution); other classes take the plain path.  feats: host
- * [R][3] features of the class's realizations.  check = 1: the plain solver
- * also runs, each realization keeps the surrogate field only if its relative
- * L2 distance (FP64) to the plain field is <= tol, else the plain field (the
- * fallback); err_out (host [R], may be NULL) receives the distances.
- * check = 0: the surrogate field is taken unverified.  Counts accepted and
- * rejected intervals in sft_diag.  Errors: SFT_ERR_ARG, SFT_ERR_SHAPE,
- * SFT_ERR_STATE, SFT_ERR_HIP. */
+ * [R][3] features of the class's realizations.
+ * A checked realization also runs the plain solver (the arbiter) and keeps
+ * the surrogate field only if its relative L2 distance (FP64, unweighted
+ * over cells) to the plain field is <= tol, else the plain field (the
+ * fallback); an unchecked one takes the surrogate field.  Which are checked:
+ *   check = 0: none (unverified);
+ *   check = 1: all, every interval (validation);
+ *   check = K >= 2: throughput mode: a realization is checked on every K-th
+ *     surrogate interval it takes (its 1st, (K+1)-th, ...; counted per
+ *     realization since the context was created), and after a rejection on
+ *     every interval until a check passes again.
+ * err_out (host [R], may be NULL) receives the distances (-1 where not
+ * checked).  Counts accepted, rejected and unchecked intervals (sft_diag,
+ * sft_surrogate_counts).  Errors: SFT_ERR_ARG, SFT_ERR_SHAPE, SFT_ERR_STATE,
+ * SFT_ERR_HIP. */
 sft_status sft_surrogate_advance(sft_ctx* ctx, int32_t grid_id, sft_net* net, const float* feats,
                                  double t_end, double tol, int32_t check, double* err_out);
+
+/* Surrogate counters of one realization: intervals accepted and rejected by
+ * the check, intervals taken unchecked, and whether its last check failed
+ * (1: every interval is checked until one passes).  Any output pointer may
+ * be NULL.  Errors: SFT_ERR_ARG. */
+sft_status sft_surrogate_counts(sft_ctx* ctx, int32_t real_id, int64_t* accepted, int64_t* rejected,
+                                int64_t* unchecked, int32_t* escalated);
 
 /* Kernel families for sft_get_timing. */
 #define SFT_KFAM_STS_STAGE 0   /* diffusion stages j >= 2 (the hot loop)            */

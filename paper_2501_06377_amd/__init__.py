@@ -250,6 +250,10 @@ class Net:
               None, "sft_net_train_step")
         return loss.value
 
+    def set_grid_limit(self, max_blocks: int):
+        """sft_net_set_grid_limit: at most max_blocks blocks per persistent launch (0: default)."""
+        check(self.L.sft_net_set_grid_limit(self.h, int(max_blocks)), None, "sft_net_set_grid_limit")
+
     def sync(self):
         check(self.L.sft_net_sync(self.h), None, "sft_net_sync")
 
@@ -266,8 +270,10 @@ class Net:
 
 
 def surrogate_advance(ens: "Ensemble", gid: int, net: Net, feats: np.ndarray, t_end: float, tol: float,
-                      check_: bool = True):
-    """sft_surrogate_advance; returns the per-realization relative L2 distances."""
+                      check_: int = 1):
+    """sft_surrogate_advance (check_: 0 none, 1 every interval, K >= 2 every
+    K-th interval per realization with escalation after a rejection); returns
+    the per-realization relative L2 distances (-1 where not checked)."""
     feats = np.ascontiguousarray(feats, dtype=np.float32)
     R = ens.grids[gid][3]
     err = np.zeros(R)
@@ -276,3 +282,13 @@ def surrogate_advance(ens: "Ensemble", gid: int, net: Net, feats: np.ndarray, t_
                                       err.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
           ens.ctx, "sft_surrogate_advance")
     return err
+
+
+def surrogate_counts(ens: "Ensemble", rid: int) -> dict:
+    """sft_surrogate_counts: accepted, rejected and unchecked surrogate
+    intervals of a realization, and whether it is escalated."""
+    v = [ctypes.c_int64() for _ in range(3)]
+    esc = ctypes.c_int32()
+    check(ens.L.sft_surrogate_counts(ens.ctx, rid, *[ctypes.byref(x) for x in v], ctypes.byref(esc)),
+          ens.ctx, "sft_surrogate_counts")
+    return {"accepted": v[0].value, "rejected": v[1].value, "unchecked": v[2].value, "escalated": esc.value}

@@ -34,7 +34,8 @@ class sft_options(ctypes.Structure):
                 ("sts_fuse", ctypes.c_int32), ("diag_every_call", ctypes.c_int32),
                 ("sts_tile", ctypes.c_int32), ("strang", ctypes.c_int32),
                 ("rfe_model", ctypes.c_int32), ("rfe_seed", ctypes.c_uint32), ("lanes", ctypes.c_int32),
-                ("rfe_phi_hr", ctypes.c_double), ("rfe_lifetime_h", ctypes.c_double)]
+                ("rfe_phi_hr", ctypes.c_double), ("rfe_lifetime_h", ctypes.c_double),
+                ("dt_min", ctypes.c_double), ("att_cfl", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
 class sft_params(ctypes.Structure):
@@ -93,9 +94,11 @@ SIGNATURES = {
     "sft_net_predict": (_I, [_P, _I, _P, _I, _P, _P]),
     "sft_net_get_activation": (_I, [_P, _I, _P]),
     "sft_net_train_step": (_I, [_P, _I, _P, _P, _I, _P, ctypes.c_float, _I, ctypes.POINTER(_D)]),
+    "sft_net_set_grid_limit": (_I, [_P, _I]),
     "sft_net_sync": (_I, [_P]),
     "sft_net_destroy": (_I, [_P]),
     "sft_surrogate_advance": (_I, [_P, _I, _P, _P, _D, _D, _I, ctypes.POINTER(_D)]),
+    "sft_surrogate_counts": (_I, [_P, _I, _PI64, _PI64, _PI64, _PI]),
     "sft_status_string": (ctypes.c_char_p, [_I]),
     "sft_last_error": (ctypes.c_char_p, [_P]),
 }

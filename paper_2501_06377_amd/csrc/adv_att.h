@@ -19,6 +19,16 @@ void launch_att_faces_f32(hipStream_t st, const Entry* ents, int n_ent, const Ad
                           const double* b0s, const double* fn, float* vphf, float* vthf, int nt,
                           int np);
 
+// Per-step CFL of the attenuated flow (eq. ssprk43_dt on the face speeds of
+// eq. flow_attenuation for the field fn): rmax[r] receives, for each entry's
+// realization r, the largest over its cells of max(theta-face speeds)/dth +
+// max(phi-face speeds)/(sin(theta) dph); the limit is 1/rmax.  partial holds
+// n_ent * nt * att_cfl_blocks_per_row(np) doubles of scratch.
+int att_cfl_blocks_per_row(int np);
+void launch_att_cfl(hipStream_t st, const Entry* ents, int n_ent, const AdvRow<double>* rows,
+                    const double* b0s, const double* fn, const double* den_ph, double dth, double* partial,
+                    double* rmax, int nt, int np);
+
 // Advection stages as launch_adv_stage_f64 / launch_adv_stage_mixed, with the
 // face velocities (and the LLF split factors built from them) taken from
 // vphf / vthf.

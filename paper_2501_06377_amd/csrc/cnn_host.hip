@@ -4,6 +4,7 @@
 // a grid class with the residual check against the plain solver.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -16,16 +17,18 @@
 namespace sft {
 void cnn_features(hipStream_t st, const void* Bin, int dtype, const float* feats, uint16_t* X0, int batch,
                   int H, int W);
-void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,
+// cap > 0 limits the blocks of the persistent launches (0: one wave over
+// the compute units)
+void cnn_conv_fwd(hipStream_t st, int cap, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,
                   uint16_t* out, int batch, int H, int W);
-void cnn_conv_fwd_first(hipStream_t st, const void* Bin, int dtype, const float* feats, const uint16_t* wf,
-                        const float* bias, uint16_t* out, int batch, int H, int W);
-void cnn_conv_fwd_out(hipStream_t st, const uint16_t* x, const uint16_t* wf, const float* bias,
+void cnn_conv_fwd_first(hipStream_t st, int cap, const void* Bin, int dtype, const float* feats,
+                        const uint16_t* wf, const float* bias, uint16_t* out, int batch, int H, int W);
+void cnn_conv_fwd_out(hipStream_t st, int cap, const uint16_t* x, const uint16_t* wf, const float* bias,
                       const uint16_t* wf5, const float* b5, float* z, float* y, int batch, int H, int W);
 void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const float* b5, float* y,
                   int batch, int H, int W);
-void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, const uint16_t* act,
-                    uint16_t* dx, float* edge, int batch, int H, int W);
+void cnn_conv_dgrad(hipStream_t st, int cap, int cin, const uint16_t* dz, const uint16_t* wd,
+                    const uint16_t* act, uint16_t* dx, float* edge, int batch, int H, int W);
 void cnn_wgrad(hipStream_t st, int cin, int cout, int cin_out, int cout_out, const uint16_t* x,
                const uint16_t* dz, float* part, float* bpart, int nblk, float* grad, float* gbias,
                int batch, int H, int W);
@@ -67,11 +70,14 @@ struct sft_net {
     double* losspart = nullptr;
     int last_batch = 0;
     bool acts_kept = false;   // the input and layer-4 activations of the last forward pass are held
+    int grid_cap = 0;         // > 0: at most this many blocks per persistent / weight-gradient launch
     std::vector<void*> allocs;
     std::string err;
 };
 
 namespace {
+
+int wgrad_blocks(const sft_net* net) { return net->grid_cap > 0 ? std::min(kWGB, net->grid_cap) : kWGB; }
 
 sft_status nfail(sft_net* n, sft_status st, const char* msg)
 {
@@ -114,15 +120,15 @@ void forward(sft_net* net, int batch, const void* Bin, int dtype, const float* f
     hipStream_t st = net->stream;
     const int H = net->H, W = net->W;
     if (predict) {
-        cnn_conv_fwd_first(st, Bin, dtype, feats, net->wf[0], net->p + net->boff[0], net->X[0], batch, H, W);
+        cnn_conv_fwd_first(st, net->grid_cap, Bin, dtype, feats, net->wf[0], net->p + net->boff[0], net->X[0], batch, H, W);
     } else {
         cnn_features(st, Bin, dtype, feats, net->X0, batch, H, W);
-        cnn_conv_fwd(st, 16, net->X0, net->wf[0], net->p + net->boff[0], net->X[0], batch, H, W);
+        cnn_conv_fwd(st, net->grid_cap, 16, net->X0, net->wf[0], net->p + net->boff[0], net->X[0], batch, H, W);
     }
     for (int l = 1; l < (predict ? 3 : 4); ++l)
-        cnn_conv_fwd(st, 64, net->X[l - 1], net->wf[l], net->p + net->boff[l], net->X[l], batch, H, W);
+        cnn_conv_fwd(st, net->grid_cap, 64, net->X[l - 1], net->wf[l], net->p + net->boff[l], net->X[l], batch, H, W);
     if (predict)
-        cnn_conv_fwd_out(st, net->X[2], net->wf[3], net->p + net->boff[3], net->wf[4], net->p + net->boff[4],
+        cnn_conv_fwd_out(st, net->grid_cap, net->X[2], net->wf[3], net->p + net->boff[3], net->wf[4], net->p + net->boff[4],
                          (float*)net->X[3], net->y, batch, H, W);
     else
         cnn_conv_out(st, net->X[3], net->wf[4], net->p + net->boff[4], net->y, batch, H, W);
@@ -288,17 +294,17 @@ sft_status sft_net_train_step(sft_net* net, int32_t batch, const void* b_in, con
     cnn_loss_grad(st, net->y, b_in, b_target, dtype, net->dyb, net->losspart, kRED, npx);
     // output layer: weight/bias gradient, then the gradient into the layer-4
     // output masked by its ReLU
-    cnn_wgrad(st, 64, 16, 64, 1, net->X[3], net->dyb, net->wpart, net->bpart, kWGB, net->g + net->woff[4],
+    cnn_wgrad(st, 64, 16, 64, 1, net->X[3], net->dyb, net->wpart, net->bpart, wgrad_blocks(net), net->g + net->woff[4],
               net->g + net->boff[4], batch, H, W);
-    cnn_conv_dgrad(st, 16, net->dyb, net->wd[4], net->X[3], net->dz[0], net->dxp, batch, H, W);
+    cnn_conv_dgrad(st, net->grid_cap, 16, net->dyb, net->wd[4], net->X[3], net->dz[0], net->dxp, batch, H, W);
     int cur = 0;
     for (int l = 3; l >= 0; --l) {
         const uint16_t* xin = l == 0 ? net->X0 : net->X[l - 1];
         const int cin = l == 0 ? 16 : 64;
-        cnn_wgrad(st, cin, 64, kCin[l], 64, xin, net->dz[cur], net->wpart, net->bpart, kWGB,
+        cnn_wgrad(st, cin, 64, kCin[l], 64, xin, net->dz[cur], net->wpart, net->bpart, wgrad_blocks(net),
                   net->g + net->woff[l], net->g + net->boff[l], batch, H, W);
         if (l > 0) {
-            cnn_conv_dgrad(st, 64, net->dz[cur], net->wd[l], net->X[l - 1], net->dz[cur ^ 1], net->dxp, batch,
+            cnn_conv_dgrad(st, net->grid_cap, 64, net->dz[cur], net->wd[l], net->X[l - 1], net->dz[cur ^ 1], net->dxp, batch,
                            H, W);
             cur ^= 1;
         }
@@ -321,6 +327,13 @@ sft_status sft_net_train_step(sft_net* net, int32_t batch, const void* b_in, con
         *loss = s / (double)npx;
     }
     return hipGetLastError() == hipSuccess ? SFT_OK : SFT_ERR_HIP;
+}
+
+sft_status sft_net_set_grid_limit(sft_net* net, int32_t max_blocks)
+{
+    if (!net || max_blocks < 0) return SFT_ERR_ARG;
+    net->grid_cap = max_blocks;
+    return SFT_OK;
 }
 
 sft_status sft_net_sync(sft_net* net)

@@ -335,6 +335,96 @@ __global__ __launch_bounds__(256) void att_faces_kernel(const Entry* __restrict_
     }
 }
 
+// CFL rate of every cell under the attenuated flow (eq. ssprk43_dt with the
+// face velocities of eq. flow_attenuation for the field fn, the same factors
+// att_faces_kernel forms): the larger of the cell's two theta-face speeds over
+// dth plus the larger of its two phi-face speeds over sin(theta_j) dph.  Each
+// block reduces the largest rate of its cells (a wavefront max, then across
+// the block's waves) into partial[entry][row][block column].
+__global__ __launch_bounds__(256) void att_cfl_partial_kernel(const Entry* __restrict__ ents,
+                                                              const AdvRow<double>* __restrict__ rows,
+                                                              const double* __restrict__ b0s,
+                                                              const double* __restrict__ fn,
+                                                              const double* __restrict__ den_ph, double dth,
+                                                              double* __restrict__ partial, int nt, int np)
+{
+    __shared__ double wmax[4];
+    const Entry e = ents[blockIdx.z];
+    const int j = blockIdx.y;
+    const double b0 = b0s[e.r];
+    const double vph = rows[(size_t)e.r * (nt + 1) + j].vph;
+    const double vn0 = rows[(size_t)e.r * (nt + 1) + j].vth;       // face j (above the row)
+    const double vs0 = rows[(size_t)e.r * (nt + 1) + j + 1].vth;   // face j + 1 (below)
+    const double den = den_ph[j];
+    const size_t row = ((size_t)e.r * nt + j) * np;
+    double m = 0.0;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < np; k += gridDim.x * 256) {
+        const double b = fabs(fn[row + k]);
+        double fw = 1.0, fe = 1.0, fnn = 1.0, fs = 1.0;
+        if (b0 > 0.0) {
+            const double bw = fabs(fn[row + (k == 0 ? np - 1 : k - 1)]);
+            const double be = fabs(fn[row + (k == np - 1 ? 0 : k + 1)]);
+            fw = 1.0 - tanh(0.5 * (bw + b) / b0);
+            fe = 1.0 - tanh(0.5 * (b + be) / b0);
+            if (j > 0) fnn = 1.0 - tanh(0.5 * (fabs(fn[row - np + k]) + b) / b0);
+            if (j < nt - 1) fs = 1.0 - tanh(0.5 * (b + fabs(fn[row + np + k])) / b0);
+        }
+        const double vw = fabs(vph * fw), ve = fabs(vph * fe);
+        const double vn = fabs(vn0 * fnn), vs = fabs(vs0 * fs);
+        const double vt = vn > vs ? vn : vs, vp = vw > ve ? vw : ve;
+        const double r = vt / dth + vp / den;
+        m = r > m ? r : m;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double q = __shfl_xor(m, o);
+        m = q > m ? q : m;
+    }
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = wmax[0];
+        for (int w = 1; w < 4; ++w) x = wmax[w] > x ? wmax[w] : x;
+        partial[((size_t)blockIdx.z * nt + j) * gridDim.x + blockIdx.x] = x;
+    }
+}
+
+// Largest CFL rate of each entry's realization from the partials: rmax[r].
+__global__ __launch_bounds__(256) void att_cfl_final_kernel(const Entry* __restrict__ ents,
+                                                            const double* __restrict__ partial, int nper,
+                                                            double* __restrict__ rmax)
+{
+    __shared__ double wmax[4];
+    const Entry e = ents[blockIdx.x];
+    const double* p = partial + (size_t)blockIdx.x * nper;
+    double m = 0.0;
+    for (int i = threadIdx.x; i < nper; i += 256) m = p[i] > m ? p[i] : m;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double q = __shfl_xor(m, o);
+        m = q > m ? q : m;
+    }
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = wmax[0];
+        for (int w = 1; w < 4; ++w) x = wmax[w] > x ? wmax[w] : x;
+        rmax[e.r] = x;
+    }
+}
+
+int att_cfl_blocks_per_row(int np) { return np > 1024 ? 4 : (np + 255) / 256; }
+
+void launch_att_cfl(hipStream_t st, const Entry* ents, int n_ent, const AdvRow<double>* rows,
+                    const double* b0s, const double* fn, const double* den_ph, double dth, double* partial,
+                    double* rmax, int nt, int np)
+{
+    const int gx = att_cfl_blocks_per_row(np);
+    hipLaunchKernelGGL(att_cfl_partial_kernel, dim3(gx, nt, n_ent), dim3(256), 0, st, ents, rows, b0s, fn,
+                       den_ph, dth, partial, nt, np);
+    hipLaunchKernelGGL(att_cfl_final_kernel, dim3(n_ent), dim3(256), 0, st, ents, partial, gx * nt, rmax);
+}
+
 void launch_adv_stage_f64(hipStream_t st, const Entry* ents, int n_ent, int stage, int time_scheme,
                           int upwind, const AdvRow<double>* rows, Geom<double> g,
                           WenoConst<double> wth, WenoConst<double> wph, const double* fn,

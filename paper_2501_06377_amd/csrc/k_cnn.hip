@@ -915,10 +915,12 @@ __global__ void surrogate_pred_kernel(const double* __restrict__ Bin, const floa
 // per-block FP64 sums of (a - b)^2 and b^2 per realization
 __global__ __launch_bounds__(256) void diff_norm_kernel(const double* __restrict__ a,
                                                         const double* __restrict__ bref,
-                                                        double* __restrict__ part, size_t n)
+                                                        double* __restrict__ part, size_t n,
+                                                        const int* __restrict__ want)
 {
     __shared__ double r1[256], r2[256];
     const int r = blockIdx.y;
+    if (want && !want[r]) return;   // not checked this interval
     double s1 = 0.0, s2 = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
         const double d = a[(size_t)r * n + i] - bref[(size_t)r * n + i];
@@ -941,12 +943,20 @@ __global__ __launch_bounds__(256) void diff_norm_kernel(const double* __restrict
     }
 }
 
-// err[r] = sqrt(sum (a-b)^2 / sum b^2); accepted realizations take a.
+// err[r] = sqrt(sum (a-b)^2 / sum b^2); accepted realizations take a.  A
+// realization not checked this interval (want[r] = 0) takes a unverified:
+// err[r] = -1, accept[r] = 1.
 __global__ void accept_reduce_kernel(const double* __restrict__ part, int nblk, double tol,
-                                     double* __restrict__ err, int* __restrict__ accept)
+                                     double* __restrict__ err, int* __restrict__ accept,
+                                     const int* __restrict__ want)
 {
     const int r = blockIdx.x;
     if (threadIdx.x != 0) return;
+    if (want && !want[r]) {
+        err[r] = -1.0;
+        accept[r] = 1;
+        return;
+    }
     double s1 = 0.0, s2 = 0.0;
     for (int b = 0; b < nblk; ++b) {
         s1 += part[((size_t)r * nblk + b) * 2];
@@ -998,8 +1008,12 @@ static int persist_blocks()
     return n;
 }
 
+// Persistent launch: one wave of blocks over the compute units (fewer when
+// there are fewer tiles, at most cap when cap > 0), each walking tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...; a tile's arithmetic does not
+// depend on the grid, so neither does the result.
 template <int CIN, int MODE>
-static void launch_persist(hipStream_t st, const uint16_t* x, const uint16_t* w, const float* bias,
+static void launch_persist(hipStream_t st, int cap, const uint16_t* x, const uint16_t* w, const float* bias,
                            uint16_t* out, int batch, int H, int W, const uint16_t* act,
                            const uint16_t* w5 = nullptr, float* zout = nullptr, const void* bsrc = nullptr,
                            int bdtype = 0, const float* feats = nullptr)
@@ -1007,24 +1021,26 @@ static void launch_persist(hipStream_t st, const uint16_t* x, const uint16_t* w,
     constexpr int PTX = PersistShape<CIN>::PTX, PTY = PersistShape<CIN>::PTY;
     const int rows = MODE == 1 ? H - 2 : H;
     const long tiles = (long)batch * ((rows + PTY - 1) / PTY) * ((W + PTX - 1) / PTX);
-    const int nb = (int)std::min<long>(tiles, (long)PersistShape<CIN>::BLOCKS_PER_CU * persist_blocks());
+    long nbl = std::min<long>(tiles, (long)PersistShape<CIN>::BLOCKS_PER_CU * persist_blocks());
+    if (cap > 0) nbl = std::min<long>(nbl, cap);
+    const int nb = (int)nbl;
     hipLaunchKernelGGL((conv_persist_kernel<CIN, MODE>), dim3(nb), dim3(PersistShape<CIN>::NTH), 0, st, x, w,
                        bias, out, batch, H, W, act, w5, zout, bsrc, bdtype, feats);
 }
 
 // Inference: the first layer with its input channels formed from the field
 // while its tiles are staged (the same values the features kernel stores).
-void cnn_conv_fwd_first(hipStream_t st, const void* Bin, int dtype, const float* feats, const uint16_t* wf,
-                        const float* bias, uint16_t* out, int batch, int H, int W)
+void cnn_conv_fwd_first(hipStream_t st, int cap, const void* Bin, int dtype, const float* feats,
+                        const uint16_t* wf, const float* bias, uint16_t* out, int batch, int H, int W)
 {
-    launch_persist<16, 3>(st, nullptr, wf, bias, out, batch, H, W, nullptr, nullptr, nullptr, Bin, dtype, feats);
+    launch_persist<16, 3>(st, cap, nullptr, wf, bias, out, batch, H, W, nullptr, nullptr, nullptr, Bin, dtype, feats);
 }
 
-void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,
+void cnn_conv_fwd(hipStream_t st, int cap, int cin, const uint16_t* x, const uint16_t* wf, const float* bias,
                   uint16_t* out, int batch, int H, int W)
 {
-    if (cin == 16) launch_persist<16, 0>(st, x, wf, bias, out, batch, H, W, nullptr);
-    else launch_persist<64, 0>(st, x, wf, bias, out, batch, H, W, nullptr);
+    if (cin == 16) launch_persist<16, 0>(st, cap, x, wf, bias, out, batch, H, W, nullptr);
+    else launch_persist<64, 0>(st, cap, x, wf, bias, out, batch, H, W, nullptr);
 }
 
 // Inference: the last hidden layer with the output layer's tap products
@@ -1032,10 +1048,10 @@ void cnn_conv_fwd(hipStream_t st, int cin, const uint16_t* x, const uint16_t* wf
 // 36 bytes of Z per pixel instead of 128 written and read back), then the
 // gather of the nine taps.  z holds batch x 9 x H x W floats (one plane per
 // tap, so the gather's reads are contiguous in k).
-void cnn_conv_fwd_out(hipStream_t st, const uint16_t* x, const uint16_t* wf, const float* bias,
+void cnn_conv_fwd_out(hipStream_t st, int cap, const uint16_t* x, const uint16_t* wf, const float* bias,
                       const uint16_t* wf5, const float* b5, float* z, float* y, int batch, int H, int W)
 {
-    launch_persist<64, 2>(st, x, wf, bias, nullptr, batch, H, W, nullptr, wf5, z);
+    launch_persist<64, 2>(st, cap, x, wf, bias, nullptr, batch, H, W, nullptr, wf5, z);
     dim3 g((W + 255) / 256, H, batch);
     hipLaunchKernelGGL(conv_out_gather_kernel, g, dim3(256), 0, st, z, b5, y, H, W);
 }
@@ -1051,15 +1067,15 @@ void cnn_conv_out(hipStream_t st, const uint16_t* x4, const uint16_t* wf5, const
 // cin = channels of the gradient input (64, or 16 for the output layer's dy),
 // act = the layer input (post-ReLU activation), edge = FP32 scratch of
 // batch x 4 x W x 64.
-void cnn_conv_dgrad(hipStream_t st, int cin, const uint16_t* dz, const uint16_t* wd, const uint16_t* act,
-                    uint16_t* dx, float* edge, int batch, int H, int W)
+void cnn_conv_dgrad(hipStream_t st, int cap, int cin, const uint16_t* dz, const uint16_t* wd,
+                    const uint16_t* act, uint16_t* dx, float* edge, int batch, int H, int W)
 {
     dim3 ge2((W + 31) / 32, 2, batch);
     if (cin == 16) {
-        launch_persist<16, 1>(st, dz, wd, nullptr, dx, batch, H, W, act);
+        launch_persist<16, 1>(st, cap, dz, wd, nullptr, dx, batch, H, W, act);
         hipLaunchKernelGGL(pole_dgrad_kernel<16>, ge2, dim3(64), 0, st, dz, wd, edge, H, W);
     } else {
-        launch_persist<64, 1>(st, dz, wd, nullptr, dx, batch, H, W, act);
+        launch_persist<64, 1>(st, cap, dz, wd, nullptr, dx, batch, H, W, act);
         hipLaunchKernelGGL(pole_dgrad_kernel<64>, ge2, dim3(64), 0, st, dz, wd, edge, H, W);
     }
     dim3 ge(gblocks((size_t)2 * W * 64, 256, 1024), batch);
@@ -1123,10 +1139,10 @@ void cnn_pred(hipStream_t st, const double* Bin, const float* y, double* pred, s
 }
 
 void cnn_check(hipStream_t st, const double* pred, const double* plain, double* part, int nblk, int R,
-               size_t n, double tol, double* err, int* accept, double* B)
+               size_t n, double tol, double* err, int* accept, double* B, const int* want)
 {
-    hipLaunchKernelGGL(diff_norm_kernel, dim3(nblk, R), dim3(256), 0, st, pred, plain, part, n);
-    hipLaunchKernelGGL(accept_reduce_kernel, dim3(R), dim3(64), 0, st, part, nblk, tol, err, accept);
+    hipLaunchKernelGGL(diff_norm_kernel, dim3(nblk, R), dim3(256), 0, st, pred, plain, part, n, want);
+    hipLaunchKernelGGL(accept_reduce_kernel, dim3(R), dim3(64), 0, st, part, nblk, tol, err, accept, want);
     hipLaunchKernelGGL(accept_copy_kernel, dim3(gblocks(n, 256, 2048), R), dim3(256), 0, st, pred, accept, B,
                        n);
 }

@@ -24,7 +24,7 @@ sft_status net_predict(sft_net* net, hipStream_t st, int batch, const double* Bi
 void net_dims(const sft_net* net, int* H, int* W, int* maxb);
 void cnn_pred(hipStream_t st, const double* Bin, const float* y, double* pred, size_t n);
 void cnn_check(hipStream_t st, const double* pred, const double* plain, double* part, int nblk, int R,
-               size_t n, double tol, double* err, int* accept, double* B);
+               size_t n, double tol, double* err, int* accept, double* B, const int* want);
 }  // namespace sft
 
 using namespace sft;
@@ -35,6 +35,8 @@ namespace {
 const double RSUN_M = 6.96e8;
 const double M_S_TO_RS_HR = 3600.0 / RSUN_M;
 const double KM2_S_TO_RS2_HR = 3600.0 * 1.0e6 / (RSUN_M * RSUN_M);
+// the interval one surrogate evaluation stands in for, hours
+const double SURROGATE_INTERVAL_H = 1.0;
 
 struct Phase {
     int kind;        // 0 advection step, 1 diffusion call, 2 copy W1->B (FP64 FE advection),
@@ -79,6 +81,11 @@ struct GridClass {
     double* att_b0 = nullptr;
     double* vf64[2] = {nullptr, nullptr};
     float* vf32[2] = {nullptr, nullptr};
+    // per-step attenuated CFL (att_cfl): entries of the realizations still
+    // stepping, per-block partial maxima and the per-realization largest rate
+    Entry* cfl_ents = nullptr;
+    double *cfl_partial = nullptr, *cfl_rmax = nullptr;
+    std::vector<Entry> h_cfl_ents;
     // random flux emergence: map k of the class in slot k & 1, per-row scale
     // of eq. rfe_m1 / rfe_m2, the device's interval index k (the map of the
     // current interval's start) and its host mirror (-1: no maps yet)
@@ -108,9 +115,14 @@ struct GridClass {
     double* pred = nullptr;
     float* sfeat = nullptr;
     double *spart = nullptr, *serr = nullptr;
-    int* sacc = nullptr;
+    int *sacc = nullptr, *swant = nullptr;
+    std::vector<int> h_swant;   // realizations checked in the current surrogate interval
     // counters since creation
     std::vector<int64_t> steps, stages, adv_stages, assim, s_acc, s_rej, s_unchk;
+    // surrogate intervals taken per realization, and whether its last check
+    // failed (then every interval is checked until one passes)
+    std::vector<int64_t> s_count;
+    std::vector<int> s_esc;
     std::vector<double> dt_last;
     size_t cells() const { return (size_t)nt * np; }
 };
@@ -402,21 +414,34 @@ void fe_coefs(int n, double h, std::vector<StageCoef>& out)
     }
 }
 
+// Length of the next step with time rem left (Sec. "Time steps"): the
+// remaining time, cut to the flow limit lim (safety included) and dt_max,
+// that cap raised to dt_min, and stretched to the end when it would leave
+// less than 1e-10 h.  *fin tells whether the step ends the interval.
+double next_step(double rem, double lim, double dt_max, double dt_min, bool* fin)
+{
+    double cap = lim;
+    if (dt_max > 0.0 && dt_max < cap) cap = dt_max;
+    if (dt_min > 0.0 && cap < dt_min) cap = dt_min;
+    double dt = rem;
+    if (cap < dt) dt = cap;
+    *fin = false;
+    if (rem - dt < 1e-10) {
+        dt = rem;
+        *fin = true;
+    }
+    return dt;
+}
+
 // Greedy step sequence over an interval of length len (Sec. "Time steps").
-void step_sequence(double len, double lim, double dt_max, std::vector<double>& dts)
+void step_sequence(double len, double lim, double dt_max, double dt_min, std::vector<double>& dts)
 {
     dts.clear();
     double el = 0.0;
     while (el < len) {
         const double rem = len - el;
-        double dt = rem;
-        if (lim < dt) dt = lim;
-        if (dt_max > 0.0 && dt_max < dt) dt = dt_max;
         bool fin = false;
-        if (rem - dt < 1e-10) {
-            dt = rem;
-            fin = true;
-        }
+        const double dt = next_step(rem, lim, dt_max, dt_min, &fin);
         dts.push_back(dt);
         el = fin ? len : el + dt;
     }
@@ -462,10 +487,15 @@ void segments(double t0, double t_end, bool cut, double tau, std::vector<Segment
     if (cut && rfe_interval(t_end, tau) == out.back().k + 1) out.back().tick_after = true;
 }
 
-sft_status build_plan(sft_ctx* c, GridClass* g, int lane, double t0, double t_end, double len, Plan** out)
+// Plan of one lane's share of an advance from t0 to t_end.  With fixed_dt
+// the plan is a single step of fixed_dt[r] hours for each realization r
+// (none where it is 0), the step rule having been applied by the caller.
+// With mask, only the realizations r with mask[r] != 0 take part.
+sft_status build_plan(sft_ctx* c, GridClass* g, int lane, double t0, double t_end, double len, Plan** out,
+                      const std::vector<double>* fixed_dt = nullptr, const std::vector<char>* mask = nullptr)
 {
     // the lane's realizations: r % nl == lane
-    auto off = [&](int r) { return r % g->nl != lane; };
+    auto off = [&](int r) { return r % g->nl != lane || (mask && !(*mask)[r]); };
     const sft_options& o = c->opt;
     const bool mixed = o.precision == SFT_FP32_MIXED;
     const bool rfe = o.rfe_model != 0;
@@ -500,7 +530,13 @@ sft_status build_plan(sft_ctx* c, GridClass* g, int lane, double t0, double t_en
                 seq[r].clear();
                 continue;
             }
-            step_sequence(slen, (strang ? 2.0 : 1.0) * o.cfl_safety * g->cfl[r], o.dt_max, seq[r]);
+            if (fixed_dt) {
+                seq[r].clear();
+                if ((*fixed_dt)[r] > 0.0) seq[r].push_back((*fixed_dt)[r]);
+            } else {
+                step_sequence(slen, (strang ? 2.0 : 1.0) * o.cfl_safety * g->cfl[r], o.dt_max, o.dt_min,
+                              seq[r]);
+            }
             max_steps = std::max(max_steps, seq[r].size());
             el[r] = 0.0;
         }
@@ -1076,6 +1112,9 @@ sft_status sft_create(sft_ctx** ctx, const sft_options* opt, void* hip_stream)
         return SFT_ERR_ARG;
     if (!(o.cfl_safety > 0.0 && o.cfl_safety <= 1.0) || o.dt_max < 0.0 || o.ptl_dt < 0.0)
         return SFT_ERR_ARG;
+    if (!(o.dt_min >= 0.0) || !std::isfinite(o.dt_min) || (o.att_cfl != 0 && o.att_cfl != 1))
+        return SFT_ERR_ARG;
+    if (o.att_cfl && o.rfe_model) return SFT_ERR_UNSUPPORTED;
     if (o.sts_fuse < 0 || o.sts_fuse > 1 || o.sts_tile < -1 ||
         o.sts_tile >= fused_config_count(o.precision == SFT_FP32_MIXED))
         return SFT_ERR_ARG;
@@ -1242,6 +1281,11 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
             if (!mixed) TRY(dalloc(c, &g->vf64[i], n));
             else TRY(dalloc(c, &g->vf32[i], n));
         }
+        if (c->opt.att_cfl) {
+            TRY(dalloc(c, &g->cfl_ents, (size_t)R));
+            TRY(dalloc(c, &g->cfl_partial, (size_t)R * nt * att_cfl_blocks_per_row(np)));
+            TRY(dalloc(c, &g->cfl_rmax, (size_t)R));
+        }
     }
     // geometry
     const double dth = M_PI / nt, dph = 2.0 * M_PI / np;
@@ -1307,6 +1351,8 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
     g->s_acc.assign(R, 0);
     g->s_rej.assign(R, 0);
     g->s_unchk.assign(R, 0);
+    g->s_count.assign(R, 0);
+    g->s_esc.assign(R, 0);
     g->dt_last.assign(R, 0.0);
     return SFT_OK;
 }
@@ -1428,7 +1474,8 @@ sft_status sft_get_states(sft_ctx* c, int32_t gid, void* br, int32_t dtype, int3
     return copy_out(c, br, g->B, (size_t)g->R * g->cells(), dtype, on_device);
 }
 
-static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid);
+static sft_status advance_impl(sft_ctx* c, double t_end, int sub_gid = -1,
+                               const std::vector<char>* sub_mask = nullptr);
 
 static void dfree(sft_ctx* c, void* ptr)
 {
@@ -1466,8 +1513,126 @@ sft_status sft_advance(sft_ctx* c, double t_end)
     return advance_impl(c, t_end, -1);
 }
 
-static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
+// Runs one plan per lane of a class: lanes other than 0 on the library's
+// streams, forked from and joined back into the context's stream.
+static void run_class_lanes(sft_ctx* c, GridClass* g, const std::vector<Plan*>& lp)
 {
+    const hipStream_t main = c->stream;
+    if (g->nl > 1) {
+        (void)hipEventRecord(g->lane_ev[0], main);
+        for (int l = 1; l < g->nl; ++l) (void)hipStreamWaitEvent(c->lane_st[l - 1], g->lane_ev[0], 0);
+    }
+    for (int l = 0; l < g->nl; ++l) {
+        c->stream = l == 0 ? main : c->lane_st[l - 1];
+        run_plan(c, g, lp[l], l);
+    }
+    c->stream = main;
+    if (g->nl > 1) {
+        for (int l = 1; l < g->nl; ++l) {
+            (void)hipEventRecord(g->lane_ev[l], c->lane_st[l - 1]);
+            (void)hipStreamWaitEvent(main, g->lane_ev[l], 0);
+        }
+    }
+}
+
+static void free_plans(sft_ctx* c, std::vector<Plan*>& lp)
+{
+    for (Plan* p : lp) {
+        if (!p) continue;
+        dfree(c, p->d_ents);
+        dfree(c, p->d_coefs);
+        dfree(c, p->d_alpha);
+        delete p;
+    }
+    lp.clear();
+}
+
+static bool att_cfl_class(const sft_ctx* c, const GridClass* g) { return c->opt.att_cfl && g->att && g->R; }
+
+// Advance of a class with attenuated flow under the per-step CFL limit
+// (opt.att_cfl; Sec. "Time steps" with eq. ssprk43_dt of the flow of eq.
+// flow_attenuation): each step starts with a device max-reduction of the
+// attenuated flow's CFL rate over the current field of every realization
+// with time left, read back to the host; each realization's step then
+// follows the step rule, and the step runs as a one-step plan per lane.
+static sft_status advance_att_cfl(sft_ctx* c, GridClass* g, double t0, double t_end, double len,
+                                  const std::vector<char>* mask)
+{
+    const sft_options& o = c->opt;
+    const double fac = (o.adv_time == SFT_SSPRK43 ? 1.0 : 0.5) * (o.strang ? 2.0 : 1.0);
+    const double dth = M_PI / g->nt;
+    std::vector<double> el(g->R, 0.0), rmax(g->R, 0.0), fixed(g->R, 0.0);
+    std::vector<char> done(g->R, 0);
+    if (mask)
+        for (int r = 0; r < g->R; ++r) done[r] = !(*mask)[r];
+    std::vector<Plan*> prev;
+    for (;;) {
+        g->h_cfl_ents.clear();
+        for (int r = 0; r < g->R; ++r)
+            if (!done[r]) g->h_cfl_ents.push_back(Entry{r, 0, 0, 0, 0.0});
+        if (g->h_cfl_ents.empty()) break;
+        const int ne = (int)g->h_cfl_ents.size();
+        HIPCHK(c, hipMemcpyAsync(g->cfl_ents, g->h_cfl_ents.data(), ne * sizeof(Entry), hipMemcpyHostToDevice,
+                                 c->stream));
+        tbeg(c);
+        launch_att_cfl(c->stream, g->cfl_ents, ne, g->adv64, g->att_b0, g->B, g->denph64, dth, g->cfl_partial,
+                       g->cfl_rmax, g->nt, g->np);
+        tend(c, SFT_KFAM_OTHER, 8.0 * (double)g->cells() * ne);
+        HIPCHK(c, hipMemcpyAsync(rmax.data(), g->cfl_rmax, g->R * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        free_plans(c, prev);   // the previous step has drained
+        for (int r = 0; r < g->R; ++r) {
+            fixed[r] = 0.0;
+            if (done[r]) continue;
+            const double lim = rmax[r] > 0.0 ? fac / rmax[r] : INFINITY;
+            bool fin = false;
+            fixed[r] = next_step(len - el[r], o.cfl_safety * lim, o.dt_max, o.dt_min, &fin);
+            el[r] = fin ? len : el[r] + fixed[r];
+            if (fin) done[r] = 1;
+        }
+        prev.assign(g->nl, nullptr);
+        for (int l = 0; l < g->nl; ++l) {
+            sft_status st = build_plan(c, g, l, t0, t_end, len, &prev[l], &fixed);
+            if (st != SFT_OK) {
+                free_plans(c, prev);
+                return st;
+            }
+        }
+        run_class_lanes(c, g, prev);
+        HIPCHK(c, hipGetLastError());
+        for (Plan* p : prev)
+            for (int r = 0; r < g->R; ++r) {
+                g->steps[r] += p->steps[r];
+                g->stages[r] += p->stages[r];
+                g->adv_stages[r] += p->adv_stages[r];
+                if (p->steps[r]) g->dt_last[r] = p->dt_last[r];
+            }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    free_plans(c, prev);
+    return SFT_OK;
+}
+
+// 64-bit hash of a realization mask (0 for none), for plan and graph keys.
+static uint64_t mask_hash(const std::vector<char>* m)
+{
+    if (!m) return 0;
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (char x : *m) h = (h ^ (uint64_t)(x != 0)) * 0x100000001b3ull;
+    return h | 1;
+}
+
+// Advances every class to t_end.  Class sub_gid (if >= 0) advances only the
+// realizations r with (*sub_mask)[r] != 0, none when sub_mask is NULL.
+static sft_status advance_impl(sft_ctx* c, double t_end, int sub_gid, const std::vector<char>* sub_mask)
+{
+    const uint64_t mh = mask_hash(sub_mask);
+    bool sub_none = sub_gid >= 0 && !sub_mask;
+    if (sub_mask) {
+        sub_none = true;
+        for (char x : *sub_mask) sub_none &= x == 0;
+    }
     if (!(t_end >= c->t) || !std::isfinite(t_end))
         return fail(c, SFT_ERR_ARG, "t_end %.17g before context time %.17g", t_end, c->t);
     bool any = false;
@@ -1496,16 +1661,17 @@ static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
     std::vector<std::vector<Plan*>*> plans;   // per class: one plan per lane
     for (size_t gi = 0; gi < c->grids.size(); ++gi) {
         GridClass* g = c->grids[gi];
-        if (!g->R || (int)gi == skip_gid) {
+        const bool sub = (int)gi == sub_gid;
+        if (!g->R || (sub && sub_none) || att_cfl_class(c, g)) {
             plans.push_back(nullptr);
             continue;
         }
-        const uint64_t key = dbits(len) ^ rkey;
+        const uint64_t key = dbits(len) ^ rkey ^ (sub ? mh : 0);
         auto it = g->plans.find(key);
         if (it == g->plans.end()) {
             std::vector<Plan*> lp(g->nl, nullptr);
             for (int l = 0; l < g->nl; ++l) {
-                sft_status st = build_plan(c, g, l, c->t, t_end, len, &lp[l]);
+                sft_status st = build_plan(c, g, l, c->t, t_end, len, &lp[l], nullptr, sub ? sub_mask : nullptr);
                 if (st != SFT_OK) {
                     for (Plan* q : lp) delete q;
                     return st;
@@ -1522,28 +1688,16 @@ static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
         for (size_t i = 0; i < c->grids.size(); ++i) {
             GridClass* g = c->grids[i];
             if (!plans[i]) continue;
-            const std::vector<Plan*>& lp = *plans[i];
-            if (g->nl > 1) {
-                (void)hipEventRecord(g->lane_ev[0], main);
-                for (int l = 1; l < g->nl; ++l) (void)hipStreamWaitEvent(c->lane_st[l - 1], g->lane_ev[0], 0);
-            }
-            for (int l = 0; l < g->nl; ++l) {
-                c->stream = l == 0 ? main : c->lane_st[l - 1];
-                run_plan(c, g, lp[l], l);
-            }
             c->stream = main;
-            if (g->nl > 1) {
-                for (int l = 1; l < g->nl; ++l) {
-                    (void)hipEventRecord(g->lane_ev[l], c->lane_st[l - 1]);
-                    (void)hipStreamWaitEvent(main, g->lane_ev[l], 0);
-                }
-            }
+            run_class_lanes(c, g, *plans[i]);
             if (c->opt.diag_every_call) launch_diag_class(c, g);
         }
     };
-    bool work = false;
+    bool work = false, dyn = false;
     for (auto* p : plans) work |= p != nullptr;
-    if (!work) {
+    for (size_t gi = 0; gi < c->grids.size(); ++gi)
+        dyn |= !((int)gi == sub_gid && sub_none) && att_cfl_class(c, c->grids[gi]);
+    if (!work && !dyn) {
         c->t = t_end;
         return SFT_OK;
     }
@@ -1561,9 +1715,11 @@ static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
             g->rfe_k = k0;
         }
     }
-    if (c->opt.use_graphs && !c->timing) {
+    if (!work) {
+        // only classes stepped under the per-step attenuated CFL limit
+    } else if (c->opt.use_graphs && !c->timing) {
         const uint64_t key = (dbits(len) ^ rkey) ^ (c->opt.diag_every_call ? 0x5bd1e995ull : 0) ^
-                             ((uint64_t)(skip_gid + 1) << 52);
+                             ((uint64_t)(sub_gid + 1) << 52) ^ mh;
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             GraphEntry ge;
@@ -1592,6 +1748,14 @@ static sft_status advance_impl(sft_ctx* c, double t_end, int skip_gid)
         }
         if (c->opt.diag_every_call) g->diag_valid = true;
         else g->diag_valid = false;
+    }
+    for (size_t gi = 0; gi < c->grids.size(); ++gi) {
+        GridClass* g = c->grids[gi];
+        const bool sub = (int)gi == sub_gid;
+        if ((sub && sub_none) || !att_cfl_class(c, g)) continue;
+        TRY(advance_att_cfl(c, g, c->t, t_end, len, sub ? sub_mask : nullptr));
+        if (c->opt.diag_every_call) launch_diag_class(c, g);
+        g->diag_valid = c->opt.diag_every_call != 0;
     }
     c->t = t_end;
     return SFT_OK;
@@ -1704,7 +1868,11 @@ sft_status sft_surrogate_advance(sft_ctx* c, int32_t gid, sft_net* net, const fl
     net_dims(net, &H, &W, &maxb);
     if (H != g->nt || W != g->np) return fail(c, SFT_ERR_SHAPE, "network grid %dx%d != class %dx%d", H, W,
                                               g->nt, g->np);
-    if (!(t_end > c->t)) return fail(c, SFT_ERR_ARG, "t_end must be after the context time");
+    if (!(fabs(t_end - c->t - SURROGATE_INTERVAL_H) <= 1e-9))
+        return fail(c, SFT_ERR_ARG, "the surrogate advances one %g h interval (t_end - t = %.17g)",
+                    SURROGATE_INTERVAL_H, t_end - c->t);
+    if (check < 0) return fail(c, SFT_ERR_ARG, "check must be >= 0 (got %d)", check);
+    if (!(tol >= 0.0)) return fail(c, SFT_ERR_ARG, "tol must be >= 0");
     const size_t n = g->cells();
     if (!g->pred) {
         TRY(dalloc(c, &g->pred, (size_t)g->R * n));
@@ -1712,8 +1880,21 @@ sft_status sft_surrogate_advance(sft_ctx* c, int32_t gid, sft_net* net, const fl
         TRY(dalloc(c, &g->spart, (size_t)g->R * g->red_nblk * 2));
         TRY(dalloc(c, &g->serr, (size_t)g->R));
         TRY(dalloc(c, &g->sacc, (size_t)g->R));
+        TRY(dalloc(c, &g->swant, (size_t)g->R));
+    }
+    // which realizations the plain solver checks this interval: all (check
+    // = 1), none (0), or every check-th surrogate interval of each
+    // realization and every interval of one whose last check failed
+    g->h_swant.assign(g->R, 0);
+    int nwant = 0;
+    for (int r = 0; r < g->R; ++r) {
+        const bool w = check == 1 || (check > 1 && (g->s_esc[r] || g->s_count[r] % check == 0));
+        g->h_swant[r] = w ? 1 : 0;
+        nwant += w ? 1 : 0;
     }
     HIPCHK(c, hipMemcpyAsync(g->sfeat, feats, (size_t)g->R * 3 * sizeof(float), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(g->swant, g->h_swant.data(), (size_t)g->R * sizeof(int), hipMemcpyHostToDevice,
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->started = true;
@@ -1725,23 +1906,33 @@ sft_status sft_surrogate_advance(sft_ctx* c, int32_t gid, sft_net* net, const fl
         TRY(net_predict(net, c->stream, nb, g->B + (size_t)r0 * n, g->sfeat + (size_t)r0 * 3, &y));
         cnn_pred(c->stream, g->B + (size_t)r0 * n, y, g->pred + (size_t)r0 * n, (size_t)nb * n);
     }
-    if (check) {
-        // plain advance of everything, then accept the surrogate where it is
-        // within tol (relative L2) of the plain result
-        TRY(advance_impl(c, t_end, -1));
-        cnn_check(c->stream, g->pred, g->B, g->spart, g->red_nblk, g->R, n, tol, g->serr, g->sacc, g->B);
+    if (nwant) {
+        // plain advance of the checked realizations (and of every other
+        // class), then each checked realization keeps the surrogate field
+        // only within tol (relative L2) of the plain one; the unchecked ones
+        // take the surrogate field
+        std::vector<char> mask(g->R);
+        for (int r = 0; r < g->R; ++r) mask[r] = (char)g->h_swant[r];
+        TRY(advance_impl(c, t_end, nwant == g->R ? -1 : gid, nwant == g->R ? nullptr : &mask));
+        cnn_check(c->stream, g->pred, g->B, g->spart, g->red_nblk, g->R, n, tol, g->serr, g->sacc, g->B,
+                  nwant == g->R ? nullptr : g->swant);
         std::vector<int> acc(g->R);
         std::vector<double> err(g->R);
         HIPCHK(c, hipMemcpyAsync(acc.data(), g->sacc, g->R * sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipMemcpyAsync(err.data(), g->serr, g->R * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         for (int r = 0; r < g->R; ++r) {
-            if (acc[r]) g->s_acc[r] += 1;
-            else g->s_rej[r] += 1;
-            if (err_out) err_out[r] = err[r];
+            if (g->h_swant[r]) {
+                if (acc[r]) g->s_acc[r] += 1;
+                else g->s_rej[r] += 1;
+                g->s_esc[r] = acc[r] ? 0 : 1;
+            } else {
+                g->s_unchk[r] += 1;
+            }
+            if (err_out) err_out[r] = g->h_swant[r] ? err[r] : -1.0;
         }
     } else {
-        TRY(advance_impl(c, t_end, gid));
+        TRY(advance_impl(c, t_end, gid, nullptr));
         HIPCHK(c, hipMemcpyAsync(g->B, g->pred, (size_t)g->R * n * sizeof(double), hipMemcpyDeviceToDevice,
                                  c->stream));
         for (int r = 0; r < g->R; ++r) {
@@ -1750,9 +1941,24 @@ sft_status sft_surrogate_advance(sft_ctx* c, int32_t gid, sft_net* net, const fl
         }
         c->t = t_end;
     }
+    for (int r = 0; r < g->R; ++r) g->s_count[r] += 1;
     if (c->opt.diag_every_call) launch_diag_class(c, g);
     else g->diag_valid = false;
     HIPCHK(c, hipGetLastError());
+    return SFT_OK;
+}
+
+sft_status sft_surrogate_counts(sft_ctx* c, int32_t id, int64_t* accepted, int64_t* rejected,
+                                int64_t* unchecked, int32_t* escalated)
+{
+    if (!c) return SFT_ERR_ARG;
+    GridClass* g;
+    int r;
+    if (!find_real(c, id, &g, &r)) return fail(c, SFT_ERR_ARG, "bad realization id %d", id);
+    if (accepted) *accepted = g->s_acc[r];
+    if (rejected) *rejected = g->s_rej[r];
+    if (unchecked) *unchecked = g->s_unchk[r];
+    if (escalated) *escalated = g->s_esc[r];
     return SFT_OK;
 }
 

@@ -44,10 +44,14 @@ def test_host_only_entry_points():
     ctx = ctypes.c_void_p()
     for kw in ({"cfl_safety": 1.5}, {"rfe_model": 3, "rfe_phi_hr": 1e23},
                {"rfe_model": 2, "rfe_phi_hr": 0.0}, {"rfe_model": 1, "rfe_phi_hr": 1e23, "rfe_lifetime_h": -1.0},
-               {"rfe_model": 2, "rfe_phi_hr": float("inf")}, {"strang": 2}):
+               {"rfe_model": 2, "rfe_phi_hr": float("inf")}, {"strang": 2}, {"dt_min": -1.0},
+               {"dt_min": float("nan")}, {"att_cfl": 2}):
         bad = make_options(**kw)
         assert L.sft_create(ctypes.byref(ctx), ctypes.byref(bad), None) == _abi.SFT_ERR_ARG, kw
     assert L.sft_last_error(None) == b""
+    # the per-step attenuated CFL limit is not combined with flux emergence
+    both = make_options(att_cfl=1, rfe_model=2, rfe_phi_hr=1e23)
+    assert L.sft_create(ctypes.byref(ctx), ctypes.byref(both), None) == _abi.SFT_ERR_UNSUPPORTED
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -55,7 +59,7 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     from paper_2501_06377_amd import _abi
     fields = {"sft_options": ["cfl_safety", "use_graphs", "diag_every_call", "strang", "rfe_model", "lanes",
-                              "rfe_seed", "rfe_phi_hr", "rfe_lifetime_h"],
+                              "rfe_seed", "rfe_phi_hr", "rfe_lifetime_h", "dt_min", "att_cfl"],
               "sft_params": ["nu_km2_s", "lat_lim_deg", "flux_balance", "att_b0", "nu_grid_alpha"],
               "sft_diag": ["steps", "phi_pos", "nonfinite", "surr_accept"]}
     lines = ['#include "sft.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void){"]

@@ -71,9 +71,9 @@ def test_attenuation_mixed_precision(strang):
     ref, _ = oracle_run(B0, reals, sched, {"strang": strang})
     got, _ = gpu_run(B0, reals, sched, precision=1, strang=strang)
     for r in range(4):
-        e = rel_l2(got[r], ref[r])
-        say(f"  realization {r}: rel-L2 {e:.3e}")
-        assert e <= TOL32
+        e, m = rel_l2(got[r], ref[r]), max_rel(got[r], ref[r])
+        say(f"  realization {r}: rel-L2 {e:.3e}  max-abs / max|B| {m:.3e}")
+        assert e <= TOL32 and m <= TOL32
 
 
 def test_attenuation_graph_replay_bitwise():
@@ -113,3 +113,84 @@ def test_negative_or_nonfinite_b0_rejected():
         ens = sft.Ensemble()
         with pytest.raises(sft.SftError):
             ens.add_grid(16, 32, att_reals((bad,)))
+
+
+def fast_reals(b0s):
+    """Flows ten times the workloads' (meridional 150 / 250 m/s, ten times the
+    rotation shear, a 2500 m/s drift on odd realizations), so that an hour
+    takes several CFL steps even on small grids."""
+    out = []
+    for i, b0 in enumerate(b0s):
+        r = synth.Realization(nu_km2_s=(500.0, 0.0, 750.0, 250.0)[i % 4],
+                              **synth.dr_mf(amp_mf=(150.0, 250.0)[i % 2]))
+        r.d2 *= 10.0
+        r.d4 *= 10.0
+        if i % 2:
+            r.d0 = 2500.0
+        r.att_b0 = float(b0)
+        out.append(r)
+    return out
+
+
+def polar_field(nt, np_, sub):
+    """A bipolar field on a 300 G axial dipole, so that the flow is strongly
+    attenuated towards the poles and the CFL limit moves with the field."""
+    th = (np.arange(nt) + 0.5) * np.pi / nt
+    return random_field(nt, np_, 8, sub) + 300.0 * np.cos(th)[:, None]
+
+
+@pytest.mark.parametrize("nt,np_,opts", [
+    (36, 72, {}), (48, 96, {"strang": 1}), (24, 48, {"adv_time": 2}), (40, 80, {"lanes": 2}),
+    (32, 64, {"adv_scheme": 1, "adv_time": 1})])
+def test_attenuated_cfl_per_step_f64(nt, np_, opts):
+    """att_cfl = 1: every step of an attenuated realization takes eq.
+    ssprk43_dt of the attenuated flow of the field at the step's start (a
+    device max-reduction read back per step).  Same steps, stages and fields
+    as the oracle's per-step rule; the strongly attenuated realizations take
+    fewer steps than under the static limit."""
+    say(f"case attenuated per-step CFL f64 {nt}x{np_} {opts}")
+    reals = fast_reals((100.0, 60.0, 0.0, 500.0))
+    B0 = np.stack([polar_field(nt, np_, 230 + i) for i in range(4)])
+    sched = [("advance", 10.0), ("advance", 25.5)]
+    ok = {k: v for k, v in opts.items() if k != "lanes"}
+    ref, st = oracle_run(B0, reals, sched, {**okw_of(ok), "att_cfl": 1})
+    got, ens = gpu_run(B0, reals, sched, att_cfl=1, **opts)
+    for r in range(4):
+        c = ens.counts(r)
+        e = rel_l2(got[r], ref[r])
+        say(f"  realization {r} (B0 {reals[r].att_b0}): steps {c['steps']} / oracle {st[r]['steps']}, "
+            f"rel-L2 {e:.3e}")
+        assert c["steps"] == st[r]["steps"] and c["stages"] == st[r]["stages"]
+        assert e <= TOL64
+    _, st0 = oracle_run(B0, reals, sched, okw_of(ok))
+    for r in (0, 1, 3):
+        assert st[r]["steps"] < st0[r]["steps"]
+    assert st[2]["steps"] == st0[2]["steps"]      # B0 = 0: the static limit
+
+
+def test_attenuated_cfl_per_step_mixed_and_full_grid():
+    """The same rule in the FP32-mixed path (the limit is taken from the FP64
+    state), and on the ensemble workload's 512x1024 grid for one hour."""
+    nt, np_ = 64, 128
+    say("case attenuated per-step CFL fp32 mixed 64x128, 6 h")
+    reals = fast_reals((100.0, 60.0, 0.0))
+    B0 = np.stack([polar_field(nt, np_, 240 + i) for i in range(3)])
+    sched = [("advance", float(h)) for h in range(1, 7)]
+    ref, st = oracle_run(B0, reals, sched, {"att_cfl": 1})
+    got, ens = gpu_run(B0, reals, sched, precision=1, att_cfl=1)
+    for r in range(3):
+        e, m = rel_l2(got[r], ref[r]), max_rel(got[r], ref[r])
+        say(f"  realization {r}: steps {ens.counts(r)['steps']} / {st[r]['steps']}, rel-L2 {e:.3e}, "
+            f"max-abs / max|B| {m:.3e}")
+        assert e <= TOL32 and m <= TOL32
+    nt, np_ = 512, 1024
+    reals = fast_reals((100.0, 500.0, 60.0, 0.0))
+    say(f"case attenuated per-step CFL f64 {nt}x{np_}, 4 realizations, first hour")
+    B0 = np.stack([polar_field(nt, np_, 250 + i) for i in range(4)])
+    ref, st = oracle_run(B0, reals, [("advance", 1.0)], {"att_cfl": 1})
+    got, ens = gpu_run(B0, reals, [("advance", 1.0)], att_cfl=1)
+    for r in range(4):
+        e = rel_l2(got[r], ref[r])
+        say(f"  realization {r}: steps {ens.counts(r)['steps']} / {st[r]['steps']}, rel-L2 {e:.3e}")
+        assert ens.counts(r)["steps"] == st[r]["steps"]
+        assert e <= TOL64

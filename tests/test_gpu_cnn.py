@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import rel_l2, say
+from gpu_helpers import random_field, rel_l2, say
 from oracle import cnn
 
 pytestmark = pytest.mark.gpu
@@ -95,14 +95,23 @@ def get_acts(torch, net, batch, H, W):
     return acts
 
 
-@pytest.mark.parametrize("H,W", [(20, 40), (13, 64)])
-def test_cnn_forward_layers_match_oracle(H, W):
-    say(f"case cnn forward {H}x{W}")
-    batch = 2
+@pytest.mark.parametrize("H,W,batch,cap", [(20, 40, 2, 0), (13, 64, 2, 0), (20, 40, 2, 4), (48, 96, 3, 7)])
+def test_cnn_forward_layers_match_oracle(H, W, batch, cap):
+    """Each layer against the oracle.  With a grid limit (cap > 0) every
+    persistent block walks several tiles (the last round ragged), so the
+    loads of the next tiles issued during a tile's matrix products are
+    checked as well; the output does not depend on the grid."""
+    say(f"case cnn forward {H}x{W} batch {batch} grid limit {cap}")
     torch, net, params, B, feats = setup_net(H, W, batch, 11)
     y = torch.empty((batch, H, W), dtype=torch.float32, device="cuda")
+    if cap:
+        y0 = torch.empty_like(y)
+        net.forward(B, feats, y0)
+        net.set_grid_limit(cap)
     net.forward(B, feats, y)
     torch.cuda.synchronize()
+    if cap:
+        assert torch.equal(y, y0)
     acts = get_acts(torch, net, batch, H, W)
     ref6 = cnn.features(B.cpu().numpy(), H, feats.cpu().numpy().astype(np.float64))
     hi, lo = cnn.split_bf16(ref6[:, 0])
@@ -127,8 +136,9 @@ def test_cnn_forward_layers_match_oracle(H, W):
     assert e < 1e-5
 
 
-@pytest.mark.parametrize("H,W,batch", [(20, 40, 2), (13, 64, 3), (48, 96, 5)])
-def test_predict_is_forward_bitwise(H, W, batch):
+@pytest.mark.parametrize("H,W,batch,cap", [(20, 40, 2, 0), (13, 64, 3, 0), (48, 96, 5, 0), (48, 96, 5, 3),
+                                           (20, 40, 2, 5)])
+def test_predict_is_forward_bitwise(H, W, batch, cap):
     """The inference path (input channels formed while the first layer stages
     its tiles; the last hidden layer and the output layer's tap products in
     one pass) gives the forward pass's output bit for bit, over partial and
@@ -136,11 +146,12 @@ def test_predict_is_forward_bitwise(H, W, batch):
     activations are reported unavailable until the next forward pass, and a
     smaller batch on the same network matches too."""
     import paper_2501_06377_amd as sft
-    say(f"case cnn predict {H}x{W} batch {batch}")
+    say(f"case cnn predict {H}x{W} batch {batch} grid limit {cap}")
     torch, net, params, B, feats = setup_net(H, W, batch, 21)
     y1 = torch.empty((batch, H, W), dtype=torch.float32, device="cuda")
     y2 = torch.full((batch, H, W), float("nan"), dtype=torch.float32, device="cuda")
-    net.forward(B, feats, y1)
+    net.forward(B, feats, y1)      # on the default grid
+    net.set_grid_limit(cap)
     net.predict(B, feats, y2)
     torch.cuda.synchronize()
     assert torch.equal(y1, y2)
@@ -164,12 +175,17 @@ def test_predict_is_forward_bitwise(H, W, batch):
     net.close()
 
 
-def test_cnn_gradients_match_oracle():
-    H, W, batch = 16, 32, 2
-    say(f"case cnn gradients {H}x{W}")
+@pytest.mark.parametrize("H,W,batch,cap", [(16, 32, 2, 0), (32, 128, 3, 2), (40, 192, 2, 5)])
+def test_cnn_gradients_match_oracle(H, W, batch, cap):
+    """Weight and bias gradients of every layer against the oracle's
+    backward pass.  With a grid limit each weight-gradient block accumulates
+    several work items (16-row strips of a 64-pixel column segment) and each
+    data-gradient block several tiles."""
+    say(f"case cnn gradients {H}x{W} batch {batch} grid limit {cap}")
     torch, net, params, B, feats = setup_net(H, W, batch, 12)
     rng = np.random.default_rng(13)
     Bt = B + torch.tensor(rng.standard_normal((batch, H, W)) * 3.0, dtype=torch.float64, device="cuda")
+    net.set_grid_limit(cap)
     loss = net.train_step(B, Bt, feats, lr=0.0, apply=False)
     g = unflat(net.get_grads(), params)
     acts = get_acts(torch, net, batch, H, W)
@@ -310,3 +326,65 @@ def test_trained_surrogate_gain():
     say(f"  surrogate rel-L2 median {np.median(errs):.3e} (max {errs.max():.3e}), identity median "
         f"{np.median(ident):.3e}, gain {gain:.1f}x, accepted {acc:.0%} at {tol}")
     assert gain > 5.0 and acc >= 0.5
+
+
+def test_surrogate_strided_checks_and_escalation():
+    """Throughput mode (check = K = 3): a realization is checked on its 1st,
+    4th, 7th... surrogate interval and takes the surrogate field unverified
+    in between; a rejection switches it to a check every interval until one
+    passes.  Realizations 0 and 1 pass every check (tol 1e30): their fields
+    equal the unchecked surrogate's bit for bit and the plain solver ran only
+    on their checked intervals.  Realization 2 holds a zero field, which the
+    plain solver keeps exactly and the network does not (relative distance
+    inf): it is rejected every interval, stays escalated and stays zero."""
+    import paper_2501_06377_amd as sft
+    nt, np_ = 24, 48
+    say("case surrogate strided checks K = 3, 7 intervals, one realization always rejected")
+    reals = [synth.Realization(nu_km2_s=(500.0, 800.0, 300.0)[i], **synth.dr_mf(amp_mf=15.0 + 5 * i))
+             for i in range(3)]
+    B0 = np.stack([random_field(nt, np_, 6, 90 + i) for i in range(2)] + [np.zeros((nt, np_))])
+    feats = np.array([[0.5, 1.0, 0.75], [0.8, 1.0, 1.0], [0.3, 1.0, 1.0]], np.float32)
+    params = random_params(np.random.default_rng(16), scale_last=0.01)
+    net = sft.Net(nt, np_, 3)
+    net.set_params(flat(params))
+
+    def run(check, hours=7):
+        e = sft.Ensemble()
+        g = e.add_grid(nt, np_, reals)
+        e.set_states(g, B0)
+        errs = [sft.surrogate_advance(e, g, net, feats, float(h), 1e30, check) for h in range(1, hours + 1)]
+        return e, g, np.array(errs)
+
+    ens, g, errs = run(3)
+    free, gf, _ = run(0)
+    got, ref = ens.get_states(g), free.get_states(gf)
+    assert np.array_equal(got[:2], ref[:2])
+    assert np.array_equal(got[2], np.zeros((nt, np_))) and np.abs(ref[2]).max() > 0
+    checked = [0, 3, 6]
+    for h in range(7):
+        for r in range(2):
+            assert (errs[h, r] >= 0) == (h in checked), (h, r, errs[h])
+        assert errs[h, 2] == np.inf
+    c = [sft.surrogate_counts(ens, r) for r in range(3)]
+    say(f"  counters {c}")
+    for r in range(2):
+        assert c[r] == {"accepted": 3, "rejected": 0, "unchecked": 4, "escalated": 0}
+    assert c[2] == {"accepted": 0, "rejected": 7, "unchecked": 0, "escalated": 1}
+    # the plain solver advanced realization r only on its checked intervals
+    one = sft.Ensemble()
+    g1 = one.add_grid(nt, np_, reals)
+    one.set_states(g1, B0)
+    one.advance(1.0)
+    per_hour = [one.counts(r)["steps"] for r in range(3)]
+    assert [ens.counts(r)["steps"] for r in range(3)] == [3 * per_hour[0], 3 * per_hour[1], 7 * per_hour[2]]
+    # a check that passes clears the escalation: realization 2 from a nonzero field
+    ens.set_states(g, np.stack([got[0], got[1], B0[0]]))
+    e8 = sft.surrogate_advance(ens, g, net, feats, 8.0, 1e30, 3)
+    assert 0 <= e8[2] < np.inf and sft.surrogate_counts(ens, 2)["escalated"] == 0
+    assert e8[0] == -1.0 and e8[1] == -1.0   # their 8th interval is not a checked one
+    # one surrogate evaluation stands in for one hour, no other length
+    with pytest.raises(sft.SftError):
+        sft.surrogate_advance(ens, g, net, feats, 10.0, 1e30, 1)
+    assert ens.time() == 8.0
+    with pytest.raises(sft.SftError):
+        sft.surrogate_advance(ens, g, net, feats, 9.0, 1e30, -1)

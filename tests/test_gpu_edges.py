@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import gpu_run, oracle_run, random_field, rel_l2, say
+from gpu_helpers import gpu_run, max_rel, oracle_run, random_field, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -35,8 +35,9 @@ def test_smallest_grids(nt, np_, prec):
     for r in range(3):
         assert ens.counts(r)["steps"] == st[r]["steps"] and ens.counts(r)["stages"] == st[r]["stages"]
         e = rel_l2(got[r], ref[r])
-        say(f"  realization {r}: rel-L2 {e:.3e}")
+        say(f"  realization {r}: rel-L2 {e:.3e}  max-abs / max|B| {max_rel(got[r], ref[r]):.3e}")
         assert e <= (TOL64 if prec == 0 else TOL32)
+        assert prec == 0 or max_rel(got[r], ref[r]) <= TOL32
 
 
 def test_degenerate_realizations():
@@ -133,3 +134,31 @@ def test_fp32_long_sts_call_stays_accurate():
     e = rel_l2(got[0], ref[0])
     say(f"  stages {st[0]['stages']} rel-L2 {e:.3e}")
     assert e <= 1e-7
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_minimum_step_matches_oracle(prec):
+    """dt_min raises the step limit min(0.9 CFL, dt_max) (here above the CFL
+    limit and over a smaller dt_max): the same fewer, longer steps as the
+    oracle's rule, each advance still ending on its t_end."""
+    import oracle
+    nt, np_ = 64, 128
+    say(f"case minimum step, precision {prec}")
+    reals = mix(3)
+    vph, vth = oracle.flows(nt, reals[1].flow)
+    lim = 0.9 * oracle.cfl_dt(nt, np_, vph, vth)
+    dmin = 1.3 * lim
+    B0 = np.stack([random_field(nt, np_, 6, 520 + i) for i in range(3)])
+    sched = [("advance", 9.0), ("advance", 9.0 + 0.4 * dmin), ("advance", 31.0)]
+    ref, st = oracle_run(B0, reals, sched, {"dt_min": dmin, "dt_max": 0.5 * lim})
+    got, ens = gpu_run(B0, reals, sched, precision=prec, dt_min=dmin, dt_max=0.5 * lim)
+    _, st0 = oracle_run(B0, reals, sched)
+    for r in range(3):
+        c = ens.counts(r)
+        e = rel_l2(got[r], ref[r])
+        say(f"  realization {r}: steps {c['steps']} / oracle {st[r]['steps']} (without dt_min "
+            f"{st0[r]['steps']}), rel-L2 {e:.3e}")
+        assert c["steps"] == st[r]["steps"] and c["stages"] == st[r]["stages"]
+        assert e <= (TOL64 if prec == 0 else TOL32)
+        assert prec == 0 or max_rel(got[r], ref[r]) <= TOL32
+    assert st[1]["steps"] < st0[1]["steps"]

@@ -54,9 +54,9 @@ def test_smoother_with_transport_and_mixed_precision():
     for prec, tol in ((0, TOL64), (1, TOL32)):
         got, _ = gpu_run(B0, reals, sched, precision=prec)
         for r in range(2):
-            e = rel_l2(got[r], ref[r])
-            say(f"  precision {prec} realization {r}: rel-L2 {e:.3e}")
-            assert e <= tol
+            e, m = rel_l2(got[r], ref[r]), max_rel(got[r], ref[r])
+            say(f"  precision {prec} realization {r}: rel-L2 {e:.3e}  max-abs / max|B| {m:.3e}")
+            assert e <= tol and (prec == 0 or m <= TOL32)
 
 
 def test_smoothing_a_full_size_map():
