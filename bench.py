@@ -1,28 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark of the surface-flux-transport hot path on one MI355X.
 
-Workload (the ensemble configuration): 8 realizations on a 512 x 1024 grid,
-FP64, diffusivity {250, 500, 750, 1000} km^2/s x meridional amplitude
-{10, 20} m/s, differential rotation 13.2 - 2.4 sin^2 - 1.8 sin^4 deg/day minus
-a 13.2 deg/day frame, a seeded 200-pair bipolar initial field, and hourly
-assimilation of synthetic observations (observed map + N(0, 5 G)) weighted
-mu^4 on the visible disk.  One step = one 1-hour interval for all
-realizations: advection (WENO3-CS(h) + SSPRK(4,3)), RKG2 diffusion,
-assimilation and the FP64 analysis reductions.  The default --steps 655
-covers the configuration's 27.3 days (655 one-hour intervals).
+Default workload (the precision configuration, the largest that the
+configurations define): 32 realizations on a 1024 x 2048 grid, FP32 stencil
+arithmetic with FP64 state, flux and weight reductions, diffusivity
+U(200, 800) km^2/s, differential rotation 13.2 - 2.4 f sin^2 - 1.8 f sin^4
+deg/day minus a 13.2 deg/day frame and a poleward meridional flow 15 g
+sin(2 lat) m/s with f, g ~ U(0.8, 1.2) per realization, a seeded 200-pair
+bipolar initial field, and hourly assimilation, weighted mu^4 on the visible
+disk, of observed maps: the hourly state of a nominal realization (eta = 500
+km^2/s, 15 m/s) evolved from the same field by the library's FP64 path, plus
+N(0, 5 G).  One step = one 1-hour interval for all realizations: advection
+(WENO3-CS(h) + SSPRK(4,3)), RKG2 diffusion, assimilation and the FP64
+analysis reductions.  The FP64 path is timed on the same inputs, and the
+FP32-mixed result is compared with it per realization.
 
 Inputs (initial fields and every observation map) are resident in HBM
-before the timed region, which runs without per-launch events.  A second
-pass over the first intervals of the same workload, in a one-lane context,
-brackets every kernel launch with HIP events on the stream it is launched
-on; the roofline object reports the dominant kernel family from those
-events.  The CPU baseline times the FP64 oracle (as is) on the first hours
-of the same workload.
+before the timed region.  Per-launch HIP events on the launch stream give
+the roofline of the dominant kernel: inside the timed region for this
+workload (one lane; its launches are long), in a second, one-lane pass for
+the others.  The learned surrogate (512 x 1024, BF16 MFMA) is measured
+against the plain solver in FP64 and FP32-mixed, with checks every K-th
+interval (throughput mode).  The CPU baseline times the FP64 oracle (as is)
+on the first hours of the same workload.
 
-Other workloads (--workload): the FP32-mixed precision configuration (with
-its per-realization difference from the FP64 path), the uneven batch, the
-flux-preserving smoother, the paper's timed soccer-ball validation runs, and
-the plain single-realization configuration.
+Other workloads (--workload): the FP64 ensemble configuration, the uneven
+batch, the flux-preserving smoother, the paper's timed soccer-ball
+validation runs, and the plain single-realization configuration.
 
 Prints one JSON line.
 """
@@ -52,9 +56,10 @@ def parse():
                     "ensemble workload, 24 for the others)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=("ensemble", "precision", "batching", "smoother", "soccer", "plain"),
-                    default="ensemble",
-                    help="ensemble: 8 x 512x1024 FP64 with hourly assimilation (the headline); "
-                         "precision: 32 x 1024x2048 FP32-mixed with hourly assimilation; "
+                    default="precision",
+                    help="precision (default, the largest configuration): 32 x 1024x2048 FP32-mixed with "
+                         "hourly assimilation, with the FP64 path timed on the same inputs; "
+                         "ensemble: 8 x 512x1024 FP64 with hourly assimilation; "
                          "batching: 96 realizations in three size classes, FP32-mixed, graphs; "
                          "smoother: 512x1024 map(s) smoothed with the grid diffusivity (alpha 0.5); "
                          "soccer: the paper's timed validation runs (soccer-ball map, 512x1024, 672 h; "
@@ -67,8 +72,13 @@ def parse():
     ap.add_argument("--att-b0", type=float, default=0.0,
                     help="flow attenuation saturation field B0 in gauss for every realization (0: off)")
     ap.add_argument("--smooth-maps", type=int, default=1, help="maps smoothed together (smoother workload)")
-    ap.add_argument("--lanes", type=int, default=0,
-                    help="concurrent sub-batches per grid class in the timed region (0: library default)")
+    ap.add_argument("--lanes", type=int, default=None,
+                    help="concurrent sub-batches per grid class in the timed region (0: library default; "
+                         "default 1 for the precision workload, whose launches each fill the GPU, else 0)")
+    ap.add_argument("--events-in-region", type=int, default=None, choices=(0, 1),
+                    help="1: HIP events around every launch inside the timed region itself (the roofline "
+                         "then comes from the timed run; default for the precision workload, whose launches "
+                         "are long enough that the events cost nothing); 0: a separate timing pass")
     ap.add_argument("--timing-steps", type=int, default=100,
                     help="intervals of the per-kernel event-timing pass (0: none)")
     ap.add_argument("--rfe-model", type=int, default=0, choices=(0, 1, 2),
@@ -81,22 +91,69 @@ def parse():
                     help="only the surrogate measurement (inference batch, plain vs surrogate intervals)")
     ap.add_argument("--no-f64-compare", action="store_true",
                     help="precision workload: skip the FP64 run that the FP32-mixed result is compared with")
+    ap.add_argument("--sts-fuse", type=int, default=0, choices=(0, 1),
+                    help="1: one diffusion stage per launch (the unfused kernel)")
+    ap.add_argument("--att-cfl", type=int, default=0, choices=(0, 1),
+                    help="with --att-b0: 1 = per-step CFL limit of the attenuated flow")
+    ap.add_argument("--obs", choices=("truth", "sheared"), default="truth",
+                    help="observations: truth = hourly maps of a nominal realization run by the library's "
+                         "FP64 path plus N(0, 5 G); sheared = the initial field sheared in longitude plus "
+                         "N(0, 5 G)")
+    ap.add_argument("--surr-stride", type=int, default=8, help="surrogate throughput mode: check every K-th interval")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
 
 
 def make_obs(f0, hours, dtype=np.float64):
+    """Sheared-field observations (synth.observation) for the given hours."""
     import concurrent.futures as cf
     with cf.ThreadPoolExecutor(max_workers=8) as ex:
         maps = list(ex.map(lambda h: synth.observation(f0, float(h), h, dtype=dtype), hours))
     return np.stack(maps)
 
 
-def cpu_baseline(nt, np_, reals, f0, obs_first, max_seconds, rfe=None):
+def truth_obs_gpu(sft, torch, f0, n_hours):
+    """Observed maps of hours 1..n_hours on the device: a nominal realization
+    (eta = 500 km^2/s, meridional 15 m/s, the workloads' rotation) evolved
+    from the initial field by the library's FP64 path, plus seeded N(0, 5 G)
+    per cell and hour (synth.truth_observation).  Untimed input preparation."""
+    nt, np_ = f0.shape
+    ens = sft.Ensemble(precision=0)
+    g = ens.add_grid(nt, np_, [synth.nominal_truth_realization()])
+    ens.set_states(g, f0[None].copy())
+    out = torch.empty((n_hours, nt, np_), dtype=torch.float64, device="cuda")
+    cur = torch.empty((1, nt, np_), dtype=torch.float64, device="cuda")
+    for h in range(1, n_hours + 1):
+        ens.advance(float(h))
+        ens.get_states(g, cur)
+        ens.sync()
+        out[h - 1] = torch.from_numpy(synth.truth_observation(cur[0].cpu().numpy(), h)).to(out.device)
+    ens.close()
+    return out
+
+
+def oracle_truth_stream(f0):
+    """obs(h): the same observed map of hour h with the truth run by the
+    oracle, hour after hour, for the CPU baseline (the oracle takes no input
+    from the GPU path)."""
+    import oracle
+    r = synth.nominal_truth_realization()
+    st = {"B": f0.copy(), "h": 0}
+
+    def obs(h):
+        while st["h"] < h:
+            st["B"], _ = oracle.advance(st["B"], r.flow, r.nu_km2_s, float(st["h"]), float(st["h"] + 1))
+            st["h"] += 1
+        return synth.truth_observation(st["B"], h)
+    return obs
+
+
+def cpu_baseline(nt, np_, reals, f0, obs_first, max_seconds, rfe=None, obs_fn=None):
     """FP64 oracle on the first realization-hours of a workload class (hour
     by hour, all realizations of an hour in turn), stopped after about
-    max_seconds of CPU work."""
+    max_seconds of CPU work.  obs_fn(h) gives the observed map of hour h
+    when obs_first is None (its own cost is not counted)."""
     import math
 
     import oracle
@@ -106,11 +163,18 @@ def cpu_baseline(nt, np_, reals, f0, obs_first, max_seconds, rfe=None):
     t0 = time.perf_counter()
     h = 0
     el = 0.0
+    obs_h = None
     while el < max_seconds:
         h += 1
-        if obs_first is not None:
+        if obs_fn is not None:
+            t_obs = time.perf_counter()
+            obs_h = obs_fn(h)
+            t0 += time.perf_counter() - t_obs
+        elif obs_first is not None:
             if h > len(obs_first):
                 break
+            obs_h = obs_first[h - 1]
+        if obs_h is not None:
             b0, l0 = synth.observer(float(h))
             mu = oracle.mu_disk(nt, np_, math.radians(b0), math.radians(l0))
         for r, real in enumerate(reals):
@@ -118,9 +182,9 @@ def cpu_baseline(nt, np_, reals, f0, obs_first, max_seconds, rfe=None):
             B[r], st = oracle.advance(B[r], real.flow, real.nu_km2_s, float(h - 1), float(h),
                                       att_b0=real.att_b0, nu_grid_alpha=real.nu_grid_alpha, **extra)
             n = st["stages"] + 4 * st["steps"]
-            if obs_first is not None:
+            if obs_h is not None:
                 F = oracle.weight_from_mu(mu, real.alpha_mu, real.mu_lim, math.radians(real.lat_lim_deg))
-                B[r] = oracle.assimilate(B[r], obs_first[h - 1], F, real.flux_balance)
+                B[r] = oracle.assimilate(B[r], obs_h, F, real.flux_balance)
                 n += 1
             updates += nt * np_ * n
             done += 1
@@ -138,21 +202,25 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def surrogate_bench(sft, torch, batch, n_real=16, hours=3, tol=1e-3):
-    """The learned surrogate at 512 x 1024: BF16-MFMA inference throughput of
-    a batch, then plain and surrogate intervals on the same realizations
-    (drawn from the surrogate's training distribution: no assimilation),
-    with the acceptance rate of the checked surrogate at tol."""
+def surrogate_bench(sft, torch, batch, n_real=64, hours=16, stride=8, tol=1e-3):
+    """The learned surrogate at 512 x 1024 on realizations of its training
+    distribution (no assimilation): BF16-MFMA inference throughput of a
+    batch, then the cost of a realization-interval over `hours` one-hour
+    intervals from the same initial fields, for the plain solver (FP64 and
+    FP32-mixed) and for the surrogate unverified, checked every `stride`-th
+    interval per realization (throughput mode, every interval after a
+    rejection), and checked every interval (validation).  A checked interval
+    runs the context's plain solver (FP64 or FP32-mixed) as the arbiter."""
     from paper_2501_06377_amd import surrogate as S
     nt, np_ = 512, 1024
     params, wname = S.load_weights(nt, np_)
     reals, feats = S.sample_realizations(n_real, 2)
     f0 = S.initial_fields(nt, np_, n_real, 2)
-    reps = (batch + n_real - 1) // n_real
-    net = sft.Net(nt, np_, batch)
+    x0 = torch.tensor(f0, dtype=torch.float64, device="cuda")
+    net = sft.Net(nt, np_, max(batch, n_real))
     net.set_params(params)
-    B = torch.tensor(np.concatenate([f0] * reps)[:batch], dtype=torch.float64, device="cuda")
-    F = torch.tensor(np.concatenate([feats] * reps)[:batch], device="cuda")
+    B = x0[torch.arange(batch, device="cuda") % n_real].contiguous()
+    F = torch.tensor(feats[np.arange(batch) % n_real], device="cuda")
     y = torch.empty((batch, nt, np_), dtype=torch.float32, device="cuda")
     net.predict(B, F, y)
     net.sync()
@@ -164,56 +232,109 @@ def surrogate_bench(sft, torch, batch, n_real=16, hours=3, tol=1e-3):
     ms = (time.perf_counter() - t0) / iters * 1e3
     flop = S.FLOP_PER_PIXEL * nt * np_ * batch
     tflops = flop / (ms * 1e-3) / 1e12
-    net.close()
     del B, F, y
     log(f"surrogate inference: batch {batch} in {ms:.2f} ms ({tflops:.1f} TFLOP/s)")
 
-    net = sft.Net(nt, np_, n_real)
-    net.set_params(params)
-    ens = sft.Ensemble()
-    gid = ens.add_grid(nt, np_, reals)
-    ens.set_states(gid, f0)
-    ens.advance(1.0)
-    ens.sync()
-    t0 = time.perf_counter()
-    ens.advance(2.0)
-    ens.sync()
-    plain = (time.perf_counter() - t0) * 1e3
-    t0 = time.perf_counter()
-    sft.surrogate_advance(ens, gid, net, feats, 3.0, tol, check_=False)
-    ens.sync()
-    unchecked = (time.perf_counter() - t0) * 1e3
-    # checked intervals from a plain state
-    ens.set_states(gid, f0)
-    ens.set_time(0.0)
-    errs, ident = [], []
-    prev = f0
-    checked = 0.0
-    for h in range(1, hours + 1):
-        t0 = time.perf_counter()
-        e = sft.surrogate_advance(ens, gid, net, feats, float(h), tol)
+    def context(prec):
+        ens = sft.Ensemble(precision=prec)
+        gid = ens.add_grid(nt, np_, reals)
+        return ens, gid
+
+    def plain(prec):
+        ens, gid = context(prec)
+        ens.set_states(gid, x0)
+        ens.advance(1.0)             # first interval: the tile autotuner
+        ens.set_states(gid, x0)
+        ens.set_time(0.0)
         ens.sync()
-        checked += (time.perf_counter() - t0) * 1e3
-        cur = ens.get_states(gid)
-        ident += list(np.linalg.norm((cur - prev).reshape(n_real, -1), axis=1) /
-                      np.linalg.norm(cur.reshape(n_real, -1), axis=1))
-        errs += e.tolist()
-        prev = cur
-    acc = sum(ens.diagnostics(r)["surr_accept"] for r in range(n_real))
-    rej = sum(ens.diagnostics(r)["surr_reject"] for r in range(n_real))
+        t0 = time.perf_counter()
+        for h in range(1, hours + 1):
+            ens.advance(float(h))
+        ens.sync()
+        wall = time.perf_counter() - t0
+        out = ens.get_states(gid)
+        ens.close()
+        return wall, out
+
+    def surrogate(check, prec=0):
+        ens, gid = context(prec)
+        ens.set_states(gid, x0)
+        ens.advance(1.0)             # the tile autotuner, outside the timed intervals
+        ens.set_states(gid, x0)
+        ens.set_time(0.0)
+        # one untimed surrogate interval (first-call allocations), from the initial state again
+        sft.surrogate_advance(ens, gid, net, feats, 1.0, tol, check)
+        ens.set_states(gid, x0)
+        ens.set_time(0.0)
+        c0 = [sft.surrogate_counts(ens, r) for r in range(n_real)]
+        ens.sync()
+        errs = []
+        t0 = time.perf_counter()
+        for h in range(1, hours + 1):
+            errs.append(sft.surrogate_advance(ens, gid, net, feats, float(h), tol, check))
+        ens.sync()
+        wall = time.perf_counter() - t0
+        c1 = [sft.surrogate_counts(ens, r) for r in range(n_real)]
+        cnt = {k: sum(b[k] - a[k] for a, b in zip(c0, c1)) for k in ("accepted", "rejected", "unchecked")}
+        out = ens.get_states(gid)
+        ens.close()
+        return wall, out, np.array(errs), cnt
+
+    def per(wall):
+        return wall / hours / n_real * 1e3
+
+    w64, ref64 = plain(0)
+    w32, ref32 = plain(1)
+    wun, fin_un, _, _ = surrogate(0)
+    wst, fin_st, err_st, cnt_st = surrogate(stride)
+    wst32, fin_st32, err_st32, cnt_st32 = surrogate(stride, 1)
+    wck, fin_ck, err_ck, cnt_ck = surrogate(1)
     net.close()
-    ens.close()
-    errs = np.array(errs)
-    return {"weights": wname, "grid": f"{nt}x{np_}",
+
+    def drift(a):
+        return [float(np.linalg.norm(a[r] - ref64[r]) / np.linalg.norm(ref64[r])) for r in range(n_real)]
+
+    d_st, d_un, d_ck = drift(fin_st), drift(fin_un), drift(fin_ck)
+    # the method without the surrogate: the identity map over one interval
+    e1 = sft.Ensemble()
+    g1 = e1.add_grid(nt, np_, reals)
+    e1.set_states(g1, x0)
+    e1.advance(1.0)
+    one = e1.get_states(g1)
+    e1.close()
+    ident = [float(np.linalg.norm(one[r] - f0[r]) / np.linalg.norm(one[r])) for r in range(n_real)]
+    chk = err_st[err_st >= 0]
+    log(f"surrogate: ms per realization-interval plain f64 {per(w64):.4f}, plain f32 {per(w32):.4f}, "
+        f"unchecked {per(wun):.4f}, every {stride}th checked {per(wst):.4f} (f32 arbiter {per(wst32):.4f}), "
+        f"every interval checked {per(wck):.4f}")
+    return {"weights": wname, "grid": f"{nt}x{np_}", "realizations": n_real, "intervals": hours,
+            "data": "synthetic (the training distribution: seeded 200-pair fields, eta U(250, 1000) km^2/s, "
+                    "MF U(10, 20) m/s, DR shear U(0.8, 1.2); no assimilation)",
             "inference": {"batch": batch, "ms_per_batch": ms, "flop_per_batch": flop, "TFLOP_s": tflops,
                           "peak_TFLOP_s": 2500.0, "mfma_frac": tflops / 2500.0, "dtype": "bf16 (fp32 acc)"},
-            "ms_per_realization_interval": {"plain_f64": plain / n_real, "surrogate_unchecked": unchecked / n_real,
-                                            "surrogate_checked": checked / hours / n_real},
-            "speedup_unchecked_vs_plain": plain / unchecked,
-            "tol_rel_l2": tol, "checked_intervals": int(errs.size), "accept_rate": acc / max(acc + rej, 1),
-            "err_median": float(np.median(errs)), "err_max": float(errs.max()),
+            "ms_per_realization_interval": {
+                "plain_f64": per(w64), "plain_f32_mixed": per(w32), "surrogate_unchecked": per(wun),
+                f"surrogate_checked_every_{stride}": per(wst),
+                f"surrogate_checked_every_{stride}_f32_arbiter": per(wst32),
+                "surrogate_checked_every_interval": per(wck)},
+            "speedup_checked_every_%d_vs_plain_f64" % stride: w64 / wst,
+            "speedup_checked_every_%d_vs_plain_f32_mixed" % stride: w32 / wst,
+            "speedup_checked_every_%d_f32_arbiter_vs_plain_f32_mixed" % stride: w32 / wst32,
+            "speedup_unchecked_vs_plain_f64": w64 / wun,
+            "tol_rel_l2": tol, "check_stride": stride,
+            "strided_counts": cnt_st, "strided_counts_f32_arbiter": cnt_st32, "every_interval_counts": cnt_ck,
+            "strided_checked_err_median": float(np.median(chk)) if chk.size else None,
+            "strided_checked_err_max": float(chk.max()) if chk.size else None,
+            "every_interval_err_median": float(np.median(err_ck)), "every_interval_err_max": float(err_ck.max()),
+            "accept_rate_every_interval": cnt_ck["accepted"] / max(cnt_ck["accepted"] + cnt_ck["rejected"], 1),
+            "trajectory_rel_l2_vs_plain_f64_after": {
+                "hours": hours, f"checked_every_{stride}_median": float(np.median(d_st)),
+                f"checked_every_{stride}_max": float(np.max(d_st)),
+                "unchecked_median": float(np.median(d_un)), "every_interval_median": float(np.median(d_ck)),
+                "plain_f32_mixed_max": float(max(np.linalg.norm(ref32[r] - ref64[r]) / np.linalg.norm(ref64[r])
+                                                 for r in range(n_real)))},
             "identity_err_median": float(np.median(ident)),
-            "gain_over_identity": float(np.median(ident) / max(np.median(errs), 1e-300))}
+            "gain_over_identity": float(np.median(ident) / max(np.median(err_ck), 1e-300))}
 
 
 def copy_probe(mib):
@@ -229,41 +350,57 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n * 4, "launches": 5}))
 
 
-def traffic_from_profiles(family, tile_index):
+def traffic_from_profiles(family, tile_index, workload, precision, sts_fuse):
     """HBM bytes per launch of a kernel family from the committed rocprofv3
-    counter summary, if it was taken on the same kernel (tile shape) and the
-    current kernel sources (else None)."""
+    counter record (profiles/traffic.json) taken on the same workload, kernel
+    (precision, tile shape) and kernel sources; None without one."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path)).get(family)
-    if not rec or rec.get("tile_index") != tile_index:
-        return None
-    for f, h in rec["sources_sha256"].items():
-        src = open(os.path.join(ROOT, "paper_2501_06377_amd", "csrc", f), "rb").read()
-        if hashlib.sha256(src).hexdigest() != h:
-            return None
-    return rec["hbm_bytes_per_launch"]
+    for rec in json.load(open(path)).get("records", []):
+        if (rec.get("family") != family or rec.get("workload") != workload or
+                rec.get("precision") != precision or rec.get("sts_fuse", 0) != sts_fuse or
+                (not sts_fuse and rec.get("tile_index") != tile_index)):
+            continue
+        ok = True
+        for f, h in rec["sources_sha256"].items():
+            src = open(os.path.join(ROOT, "paper_2501_06377_amd", "csrc", f), "rb").read()
+            ok &= hashlib.sha256(src).hexdigest() == h
+        if ok:
+            return rec["hbm_bytes_per_launch"]
+    return None
 
 
 def roofline_fields(fams, traffic, how):
     """The roofline object of the dominant kernel family (by event time) and
-    the per-family table, from the library's per-launch event timing."""
+    the per-family table, from the library's per-launch event timing.
+
+    achieved: the bytes a launch must move (its inputs read once, its outputs
+    written once; for a launch that fuses k diffusion stages, the
+    algorithm's bytes of one k-stage pass) over the average launch time, so
+    frac <= 1.  effective_GB_s: the method's bytes per stage (e.g. 16 B per
+    cell and FP32-mixed diffusion stage) over the same time; it exceeds the
+    peak when stages are fused.  traffic: measured HBM bytes per launch from
+    the committed counter record of this workload and kernel, else null."""
     dom = max(fams, key=lambda k: fams[k]["ms"])
     f = fams[dom]
-    achieved = f["bytes"] / (f["ms"] * 1e-3) / 1e9
+    n = max(f["launches"], 1)
+    t = f["ms"] * 1e-3
+    achieved = f["min_bytes"] / t / 1e9
+    eff = f["bytes"] / t / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "avg_launch_us": f["ms"] / max(f["launches"], 1) * 1e3,
-            "alg_bytes_per_launch": f["bytes"] / max(f["launches"], 1),
+            "avg_launch_us": f["ms"] / n * 1e3,
+            "alg_bytes_per_launch": f["min_bytes"] / n,
             "launches": f["launches"], "timing_pass": how,
-            # bytes a fused multi-stage launch must move at least
-            # (one read of its inputs, one write of its outputs)
-            "min_hbm_GB_s": f["min_bytes"] / (f["ms"] * 1e-3) / 1e9,
-            "min_hbm_frac": f["min_bytes"] / (f["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "traffic_GB_s": traffic / (t / n) / 1e9 if traffic else None,
+            "traffic_frac": traffic / (t / n) / 1e9 / HBM_PEAK_GBS if traffic else None,
+            "effective_GB_s": eff, "effective_frac": eff / HBM_PEAK_GBS,
+            "method_bytes_per_launch": f["bytes"] / n}
     kernels = {k: {"ms": v["ms"], "launches": v["launches"],
-                   "GB_s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
+                   "GB_s": (v["min_bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None,
+                   "effective_GB_s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
                for k, v in fams.items() if v["launches"]}
     return {"roofline": roof, "kernels": kernels}
 
@@ -504,6 +641,10 @@ def main():
         rfe_cpu = dict(rfe_model=args.rfe_model, rfe_phi_hr=args.rfe_phi, rfe_tau=args.rfe_tau, rfe_seed=1)
         w.name += f"+flux-emergence-m{args.rfe_model}-tau{args.rfe_tau:g}h"
     W = args.warmup
+    if args.lanes is None:
+        args.lanes = 1 if args.workload == "precision" else 0
+    in_region = (args.events_in_region if args.events_in_region is not None
+                 else int(args.workload == "precision"))
     prec = 0 if w.precision == "f64" else 1
     graphs = args.graphs or args.workload == "batching"
     assim = w.assim_every_h > 0
@@ -513,17 +654,21 @@ def main():
         f0 = synth.bipolar_field(nt, np_, synth.bipolar_pairs(w.n_pairs, ci))
         f0s.append(f0)
         if assim:
-            obs = make_obs(f0, range(1, max(K, W) + 1))
-            if ci == 0:
-                obs0 = obs[:24]
-            obs_d.append(torch.from_numpy(obs).to(dev))
-            del obs
+            if args.obs == "truth":
+                obs_d.append(truth_obs_gpu(sft, torch, f0, max(K, W)))
+            else:
+                obs = make_obs(f0, range(1, max(K, W) + 1))
+                if ci == 0:
+                    obs0 = obs[:24]
+                obs_d.append(torch.from_numpy(obs).to(dev))
+                del obs
         inits.append(torch.from_numpy(np.ascontiguousarray(np.broadcast_to(f0, (len(reals), nt, np_)))).to(dev))
     R = w.n_real
+    okw = dict(sts_fuse=args.sts_fuse, att_cfl=args.att_cfl)
 
-    def make(lanes):
-        e = sft.Ensemble(precision=prec, use_graphs=1 if graphs else 0, sts_tile=args.sts_tile, lanes=lanes,
-                         **rfe_gpu)
+    def make(lanes, tile=None):
+        e = sft.Ensemble(precision=prec, use_graphs=1 if graphs and not in_region else 0,
+                         sts_tile=args.sts_tile if tile is None else tile, lanes=lanes, **rfe_gpu, **okw)
         return e, [e.add_grid(nt, np_, reals) for nt, np_, reals in w.classes]
 
     def run(ens, gids, n_steps):
@@ -548,6 +693,8 @@ def main():
     # timed region starts from the initial state at t = 0
     reset(ens, gids)
     c0 = [ens.counts(r) for r in range(R)]
+    if in_region:
+        ens.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run(ens, gids, K)
@@ -555,14 +702,19 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     c1 = [ens.counts(r) for r in range(R)]
-    # per-kernel timing: a second pass over the first intervals of the same
-    # workload in a one-lane context (every launch covers the whole class, as
-    # in the counter record), with HIP events around every launch; the events
-    # themselves cost wall time, so the timed region above runs without them
-    Kt = min(K, args.timing_steps)
+    # per-kernel timing: the timed region's own events, or a second pass
+    # over the first intervals of the same workload in a one-lane context
+    # with the same tile shape (every launch covers the whole class), with
+    # HIP events around every launch; where the events would cost wall time
+    # (short launches), the timed region above runs without them
+    Kt = K if in_region else min(K, args.timing_steps)
     fams = {}
-    if Kt > 0:
-        ens_t, gids_t = make(1)
+    if in_region:
+        fams = ens.timing()
+        ens.set_timing(False)
+    elif Kt > 0:
+        one_tile = ens.tile_choice(gids[0]) if len(gids) == 1 else None
+        ens_t, gids_t = make(1, one_tile)
         reset(ens_t, gids_t)
         run(ens_t, gids_t, 1)
         ens_t.sync()
@@ -598,16 +750,26 @@ def main():
                             f"lifetime {args.rfe_tau:g} h)" if args.rfe_model else "") +
                            (" + mu^4 assimilation" if assim else "") + " + diagnostics",
                    "simulated_hours": K, "graphs": bool(graphs), "sts_tiles": tiles,
-                   "lanes": args.lanes or "library default (min(2, realizations per class))"},
+                   "sts_fuse": args.sts_fuse, "att_cfl": args.att_cfl,
+                   "observations": (("hourly maps of a nominal realization (eta 500 km^2/s, MF 15 m/s) run by "
+                                     "the library's FP64 path from the same initial field, + N(0, 5 G)")
+                                    if args.obs == "truth" else
+                                    "the initial field sheared in longitude, + N(0, 5 G)") if assim else None,
+                   "lanes": args.lanes or "library default (min(2, realizations per class))",
+                   "events_in_timed_region": bool(in_region)},
         "sim_days_per_s": K / 24.0 / wall,
     }
     if fams:
         dom = max(fams, key=lambda k: fams[k]["ms"])
-        # the counter record was taken on the ensemble workload's launches
-        traffic = (traffic_from_profiles(dom, tiles[0]["index"])
-                   if len(tiles) == 1 and args.workload == "ensemble" else None)
+        # a counter record applies when taken on this workload's launches of
+        # the same kernel (tile shape) and sources
+        traffic = (traffic_from_profiles(dom, tiles[0]["index"], w.name, prec, args.sts_fuse)
+                   if len(tiles) == 1 and not (args.att_b0 or args.rfe_model) else None)
         out.update(roofline_fields(fams, traffic,
-                                   f"{Kt} intervals of the same workload, HIP events around every launch"))
+                                   f"the timed region's {Kt} intervals, HIP events around every launch on its "
+                                   f"stream" if in_region else
+                                   f"{Kt} intervals of the same workload in one lane, HIP events around every "
+                                   f"launch"))
         # kernel time per interval in the timing pass, against the timed region's
         # interval time (the difference is launch gaps and the events' own cost)
         out["kernel_ms_per_interval_timing_pass"] = sum(v["ms"] for v in fams.values()) / Kt
@@ -619,13 +781,30 @@ def main():
         # the same inputs (the FP64 path is itself held to the FP64 oracle)
         got = [ens.get_states(g) for g in gids]
         log(f"{w.name}: the same {K} intervals on the FP64 path")
-        e64 = sft.Ensemble(precision=0, sts_tile=-1, lanes=args.lanes)
+        e64 = sft.Ensemble(precision=0, sts_tile=-1, lanes=args.lanes, **okw)
         g64 = [e64.add_grid(nt, np_, reals) for nt, np_, reals in w.classes]
         reset(e64, g64)
+        run(e64, g64, W)
+        e64.sync()
+        reset(e64, g64)
+        a64 = [e64.counts(r) for r in range(R)]
+        torch.cuda.synchronize()
+        t64 = time.perf_counter()
         run(e64, g64, K)
         e64.sync()
+        torch.cuda.synchronize()
+        wall64 = time.perf_counter() - t64
+        b64 = [e64.counts(r) for r in range(R)]
+        upd64 = sum(n * ((b["stages"] - a["stages"]) + (b["adv_stages"] - a["adv_stages"]) +
+                         (b["assim"] - a["assim"])) for n, a, b in zip(cells, a64, b64))
         ref = [e64.get_states(g) for g in g64]
         e64.close()
+        out["f64_path"] = {"value": upd64 / wall64, "unit": "realization-cell-updates/s",
+                           "ms_per_step": wall64 / K * 1e3, "sim_days_per_s": K / 24.0 / wall64,
+                           "steps": K, "warmup": W, "inputs": "the same initial fields and observations",
+                           "f32_mixed_speedup": wall64 / wall}
+        log(f"{w.name}: FP64 path {wall64 / K * 1e3:.2f} ms per interval ({upd64 / wall64:.3e} "
+            f"realization-cell-updates/s)")
         rel, mx = [], []
         for a, b in zip(got, ref):
             for r in range(a.shape[0]):
@@ -639,12 +818,14 @@ def main():
     ens.close()
     del obs_d, inits
     log(f"{w.name}: {wall:.2f} s for {K} intervals")
-    if not args.no_surrogate and args.workload == "ensemble":
-        out["surrogate"] = surrogate_bench(sft, torch, args.surr_batch)
+    if not args.no_surrogate and args.workload in ("ensemble", "precision"):
+        out["surrogate"] = surrogate_bench(sft, torch, args.surr_batch, stride=args.surr_stride)
     if not args.no_cpu_baseline:
         nt, np_, reals = w.classes[-1]
-        out["cpu_baseline"] = cpu_baseline(nt, np_, reals, f0s[-1], obs0 if len(w.classes) == 1 else None,
-                                           args.cpu_seconds, rfe_cpu)
+        one = len(w.classes) == 1
+        out["cpu_baseline"] = cpu_baseline(nt, np_, reals, f0s[-1], obs0 if one else None, args.cpu_seconds,
+                                           rfe_cpu, oracle_truth_stream(f0s[-1]) if (one and assim and
+                                                                                      args.obs == "truth") else None)
     print(json.dumps(out), flush=True)
 
 

@@ -17,9 +17,14 @@ flows of tens of m/s):
   latitudes U(-35, 35) deg, longitudes U(0, 360) deg, peak |B| U(50, 500) G,
   tilt 0.5|lat| + N(0, 10) deg (Joy's law, leading spot equatorward), Hale
   polarity (leading spot positive in the north, negative in the south);
-* observations: the initial field sheared in longitude (each row shifted by
-  a whole number of columns, -3 sin^2(lat) deg/day), plus N(0, 5 G) noise per
-  cell and hour; the weight of the visible disk is left to the library;
+* observations: a 'truth' field plus N(0, 5 G) noise per cell and hour; the
+  truth is either the hourly state of a nominal realization evolved by a
+  solver (the benchmark: the library's FP64 path for the GPU run, the oracle
+  for the CPU baseline; truth_observation) or, where the observations only
+  need to be plausible inputs (parity tests), the initial field sheared in
+  longitude (each row shifted by a whole number of columns, -3 sin^2(lat)
+  deg/day; observation); the weight of the visible disk is left to the
+  library;
 * observer: sub-observer latitude 0, longitude 180 deg - 13.2 deg/day * t.
 """
 from __future__ import annotations
@@ -118,6 +123,23 @@ def observation(field0: np.ndarray, t_hours: float, hour_index: int, noise_g: fl
     truth = np.take_along_axis(field0, k, axis=1)
     noise = rng("obs_noise", hour_index).standard_normal((nt, np_)) * noise_g
     return (truth + noise).astype(dtype)
+
+
+def nominal_truth_realization() -> "Realization":
+    """Parameters of the 'truth' realization whose evolved field the
+    synthetic observers see: the first configuration's eta = 500 km^2/s and
+    15 m/s meridional amplitude, with the workloads' rotation profile."""
+    return Realization(nu_km2_s=500.0, **dr_mf(amp_mf=15.0))
+
+
+def truth_observation(truth_map: np.ndarray, hour_index: int, noise_g: float = 5.0,
+                      dtype=np.float64) -> np.ndarray:
+    """Observed map of one hour: the truth field at that hour (evolved by a
+    solver elsewhere; this module only adds noise) plus seeded N(0, noise_g)
+    per cell, from the same noise stream as synth.observation."""
+    nt, np_ = truth_map.shape
+    noise = rng("obs_noise", hour_index).standard_normal((nt, np_)) * noise_g
+    return (truth_map + noise).astype(dtype)
 
 
 # ---------------------------------------------------------- validation maps
