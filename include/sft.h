@@ -174,7 +174,10 @@ typedef struct sft_ctx sft_ctx;   /* opaque; owns every internal device buffer *
 /* Fills *opt with the defaults listed above.  Errors: SFT_ERR_ARG if opt is NULL. */
 sft_status sft_options_default(sft_options* opt);
 
-/* Creates a context on the current HIP device.  hip_stream is a hipStream_t
+/* Creates a context on the current HIP device (Sec. "Inputs": the run's
+ * parameters; the options are the user choices of Sec. "Time steps",
+ * "Operator splitting", "Advection temporal schemes", "Diffusion temporal
+ * schemes" and "Flux emergence").  hip_stream is a hipStream_t
  * the context enqueues all work on; the context does not own it.  With NULL
  * the context creates (and later destroys) its own blocking stream, which is
  * ordered with the null stream.  opt may be NULL for the defaults.  On success *ctx receives the
@@ -197,7 +200,10 @@ sft_status sft_add_grid(sft_ctx* ctx, int32_t ntheta, int32_t nphi, int32_t* gri
 sft_status sft_add_realizations(sft_ctx* ctx, int32_t grid_id, int32_t n, const sft_params* prm,
                                 int32_t* first_id);
 
-/* Copies one realization's field in (set) or out (get).  br points to nt*np
+/* Copies one realization's field in (set) or out (get): the radial field B_r
+ * of eq. main_model in gauss on the grid of Sec. "Grid" (Sec. "Inputs": the
+ * initial map; Sec. "Outputs": the maps written during and after a run; a
+ * map must match the run's resolution).  br points to nt*np
  * values of dtype SFT_DTYPE_F64 or SFT_DTYPE_F32, on the device when
  * on_device = 1, else in host memory.  Errors: SFT_ERR_ARG (bad id/dtype,
  * NULL), SFT_ERR_HIP. */
@@ -259,7 +265,8 @@ sft_status sft_assimilate(sft_ctx* ctx, int32_t grid_id, const void* data, const
  * the field holds NaN or Inf.  Errors: SFT_ERR_ARG, SFT_ERR_HIP. */
 sft_status sft_diagnostics(sft_ctx* ctx, int32_t real_id, sft_diag* out);
 
-/* Context time in hours. */
+/* Context time in hours (Sec. "Units": time in hours; Sec. "Time steps":
+ * every advance ends exactly on its t_end).  Errors: SFT_ERR_ARG. */
 sft_status sft_time(sft_ctx* ctx, double* t_hours);
 
 /* Sets the context time (hours) without touching the fields: with
