@@ -53,12 +53,28 @@ __device__ __forceinline__ double sts_f64(const StageCoef& c, double ym1, double
 // remaining stages (s^2 eps in all), while here the rounding of d enters the
 // non-growing mode and the rounding of e, a change of size d / s, is the one
 // that grows (about s eps in all).  mu + nu - 1 = -cy0.
-__device__ __forceinline__ float sts_mixed(const StageCoef& c, float d, float e, float L, float ly0)
+//
+// The stage coefficient cL and the diagonal term -cy0 are folded into the
+// operator row once per row and stage, in FP64 and rounded to FP32:
+//   A = cL ph, U = cL up, C = cL dd - cy0, S = cL dn,
+// so that with t = d(k-1) + d(k+1) (the two phi neighbours share ph)
+//   e_j = A t + U d(j-1) + C d + S d(j+1) - nu e_{j-1} + (cL + cLY0) L(Y0).
+__device__ __forceinline__ float4 fold_row(const StageCoef& c, const DiffRow<double>& d)
 {
-    float v = (float)(-c.cy0) * d;
-    v = __builtin_fmaf((float)(-c.nu), e, v);
-    v = __builtin_fmaf((float)c.cL, L, v);
-    v = __builtin_fmaf((float)(c.cL + c.cLY0), ly0, v);
+    return make_float4((float)(c.cL * d.ph), (float)(c.cL * d.up), (float)(c.cL * d.d - c.cy0),
+                       (float)(c.cL * d.dn));
+}
+
+// e_j of one cell: f the folded row, nnu = (float)(-nu), g = (float)(cL + cLY0).
+__device__ __forceinline__ float sts_fold(const float4& f, float nnu, float g, float t, float n, float c,
+                                          float s, float e, float ly)
+{
+    float v = f.x * t;
+    v = __builtin_fmaf(f.y, n, v);
+    v = __builtin_fmaf(f.z, c, v);
+    v = __builtin_fmaf(f.w, s, v);
+    v = __builtin_fmaf(nnu, e, v);
+    v = __builtin_fmaf(g, ly, v);
     return v;
 }
 

@@ -9,7 +9,8 @@
 // FP32 mixed ("increment form", algebraically identical because L is linear):
 //   d_j = Y_j - Y0 = mu d_{j-1} + nu d_{j-2} + cL L(d_{j-1}) + (cL + cLY0) L(Y0),
 //   with Y0 and the result kept in FP64 and L(Y0) formed in FP64 arithmetic;
-//   carried as (d, e = d_{j-1} - d_{j-2}) (sts_mixed).
+//   carried as (d, e = d_{j-1} - d_{j-2}), the stage coefficients folded into
+//   the operator row (fold_row, sts_fold).
 //
 // Layout: fields [r][j][k] (k = phi contiguous).  Entries of a launch are the
 // realizations still active at stage j (blockIdx.z indexes them).
@@ -133,9 +134,11 @@ __global__ __launch_bounds__(256) void diff_first_mixed_kernel(
 
 // Reads d_{j-1} (with neighbours) and e_{j-1} (absent at j = 2: e_1 = d_1),
 // writes d_j to dout (never din) and e_j over e (each cell reads only its own).
+// Pole rows have zero up/down coefficients; their out-of-sphere neighbour is
+// read from a real row and multiplied by that zero.
 __global__ __launch_bounds__(256) void diff_stage_mixed_kernel(
     const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs, int jst,
-    const DiffRow<float>* __restrict__ drow, double* __restrict__ B, const float* __restrict__ adv,
+    const DiffRow<double>* __restrict__ drow, double* __restrict__ B, const float* __restrict__ adv,
     const float* __restrict__ din, const float* ein, const float* __restrict__ ly0, float* dout,
     float* eout, int nt, int np)
 {
@@ -144,12 +147,18 @@ __global__ __launch_bounds__(256) void diff_stage_mixed_kernel(
     const int j = blockIdx.y * DTY + threadIdx.y;
     if (k >= np || j >= nt) return;
     const size_t base = (size_t)en.r * nt * np;
-    const DiffRow<float> d = drow[(size_t)en.r * nt + j];
     const StageCoef c = coefs[en.coef_off + jst];
-    const float L = apply_L<float>(d, din + base, j, k, nt, np);
-    const size_t i = base + (size_t)j * np + k;
-    const float dv = din[i];
-    const float ev = sts_mixed(c, dv, ein ? ein[i] : dv, L, ly0[i]);
+    const float4 f = fold_row(c, drow[(size_t)en.r * nt + j]);
+    const float* y = din + base;
+    const int km = k == 0 ? np - 1 : k - 1;
+    const int kp = k == np - 1 ? 0 : k + 1;
+    const int ju = j > 0 ? j - 1 : 0;
+    const int jd = j < nt - 1 ? j + 1 : nt - 1;
+    const size_t row = (size_t)j * np;
+    const size_t i = base + row + k;
+    const float dv = y[row + k];
+    const float ev = sts_fold(f, (float)(-c.nu), (float)(c.cL + c.cLY0), y[row + km] + y[row + kp],
+                              y[(size_t)ju * np + k], dv, y[(size_t)jd * np + k], ein ? ein[i] : dv, ly0[i]);
     const float v = dv + ev;
     if (jst == en.s) {
         double y0 = B[i];
@@ -171,7 +180,7 @@ void launch_diff_first_mixed(hipStream_t st, const Entry* ents, int n_ent, const
 }
 
 void launch_diff_stage_mixed(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs,
-                             int j, const DiffRow<float>* drow, double* B, const float* adv,
+                             int j, const DiffRow<double>* drow, double* B, const float* adv,
                              const float* din, const float* ein, const float* ly0, float* dout,
                              float* eout, int nt, int np)
 {

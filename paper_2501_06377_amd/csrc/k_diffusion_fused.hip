@@ -1,5 +1,6 @@
-// Temporally blocked diffusion stages: one launch advances every active
-// realization by up to K super-time-stepping stages.
+// Temporally blocked diffusion stages, FP64 paper form: one launch advances
+// every active realization by up to K super-time-stepping stages (the FP32
+// increment form has its own kernel, k_diffusion_mixed.hip).
 //
 // A block owns a TY x TX tile of output cells and stages the tile plus a
 // K-cell halo in LDS (phi wraps periodically; rows beyond the poles are held
@@ -14,38 +15,23 @@
 // results are bitwise identical to the one-stage-per-launch path for every
 // tile shape.
 //
-// FP64 paper form: inputs Y_{j0-1}, Y_{j0-2}, a copy of Y0 and L(Y0) (the
-// strip variant computes L(Y0) from the staged Y0 instead of reading it).
-// FP32 increment form: inputs d_{j0-1}, its change e = d_{j0-1} - d_{j0-2}
-// (absent when j0 = 2: e = d_1) and L(Y0).  An entry whose last stage s falls
-// in this launch writes the final field into the FP64 state B (only the
-// cell's own value of B is read, and only in the increment form), otherwise
-// the last two stages (FP64) or the last stage and its change (FP32) go to
-// out1/out2.
+// Inputs Y_{j0-1}, Y_{j0-2}, a copy of Y0 and L(Y0) (the strip variant
+// computes L(Y0) from the staged Y0 instead of reading it).  An entry whose
+// last stage s falls in this launch writes the final field into B, otherwise
+// the last two stages go to out1/out2.
 #include "diff_common.h"
 #include "sft_internal.h"
 
 namespace sft {
 
-template <bool MIXED>
-struct FT {
-    using T = double;
-};
-template <>
-struct FT<true> {
-    using T = float;
-};
-
-template <bool MIXED, int TX, int TY, int K, int NT>
+template <int TX, int TY, int K, int NT>
 __global__ __launch_bounds__(NT) void diff_fused_kernel(
     const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs, int j0,
-    const DiffRow<typename FT<MIXED>::T>* __restrict__ drow,
-    const typename FT<MIXED>::T* __restrict__ in1, const typename FT<MIXED>::T* __restrict__ in2,
-    const double* __restrict__ y0, const typename FT<MIXED>::T* __restrict__ ly0,
-    typename FT<MIXED>::T* __restrict__ out1, typename FT<MIXED>::T* __restrict__ out2,
-    double* __restrict__ B, const float* __restrict__ adv, int nt, int np)
+    const DiffRow<double>* __restrict__ drow, const double* __restrict__ in1,
+    const double* __restrict__ in2, const double* __restrict__ y0, const double* __restrict__ ly0,
+    double* __restrict__ out1, double* __restrict__ out2, double* __restrict__ B, int nt, int np)
 {
-    using T = typename FT<MIXED>::T;
+    using T = double;
     constexpr int LX = TX + 2 * K, LY = TY + 2 * K, NC = LX * LY;
     constexpr int CPT = (NC + NT - 1) / NT;
     static_assert(CPT <= 32, "cell mask holds 32 cells per thread");
@@ -69,8 +55,7 @@ __global__ __launch_bounds__(NT) void diff_fused_kernel(
         rowc[l] = d;
     }
 
-    T ycur[CPT], ym2[CPT], lyr[CPT];
-    double y0r[MIXED ? 1 : CPT];
+    T ycur[CPT], ym2[CPT], lyr[CPT], y0r[CPT];
     uint32_t act = 0;
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
@@ -87,17 +72,16 @@ __global__ __launch_bounds__(NT) void diff_fused_kernel(
                 a = in1[i];
                 if (has_in2) b = in2[i];
                 l = ly0[i];
-                if constexpr (!MIXED) z = y0[i];
+                z = y0[i];
                 if (ly >= 1 && ly <= LY - 2 && lx >= 1 && lx <= LX - 2) act |= 1u << m;
             }
             buf[0][idx] = a;
             buf[1][idx] = a;
         }
         ycur[m] = a;
-        // FP32: ym2 carries e = d_{j0-1} - d_{j0-2} (d_1 itself at j0 = 2)
-        ym2[m] = MIXED && !has_in2 ? a : b;
+        ym2[m] = b;
         lyr[m] = l;
-        if constexpr (!MIXED) y0r[m] = z;
+        y0r[m] = z;
     }
     __syncthreads();
 
@@ -112,18 +96,10 @@ __global__ __launch_bounds__(NT) void diff_fused_kernel(
                 const int idx = tid + m * NT;
                 const DiffRow<T> d = rowc[idx / LX];
                 const T L = L5<T>(d, cb[idx - 1], cb[idx - LX], ycur[m], cb[idx + LX], cb[idx + 1]);
-                if constexpr (MIXED) {
-                    const T ev = sts_mixed(c, ycur[m], ym2[m], L, lyr[m]);
-                    const T v = ycur[m] + ev;
-                    nb[idx] = v;
-                    ym2[m] = ev;
-                    ycur[m] = v;
-                } else {
-                    const T v = sts_f64(c, ycur[m], ym2[m], y0r[m], L, lyr[m]);
-                    nb[idx] = v;
-                    ym2[m] = ycur[m];
-                    ycur[m] = v;
-                }
+                const T v = sts_f64(c, ycur[m], ym2[m], y0r[m], L, lyr[m]);
+                nb[idx] = v;
+                ym2[m] = ycur[m];
+                ycur[m] = v;
             }
         }
         p ^= 1;
@@ -140,13 +116,7 @@ __global__ __launch_bounds__(NT) void diff_fused_kernel(
         if (j >= nt || k >= np) continue;
         const size_t gi = base + (size_t)j * np + k;
         if (fin) {
-            if constexpr (MIXED) {
-                double yv = B[gi];
-                if (e.pad) yv += (double)adv[gi];
-                B[gi] = yv + (double)ycur[m];
-            } else {
-                B[gi] = ycur[m];
-            }
+            B[gi] = ycur[m];
         } else {
             out1[gi] = ycur[m];
             out2[gi] = ym2[m];
@@ -179,25 +149,14 @@ __device__ __forceinline__ double lane_east(double v)
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ float lane_west(float v)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));
-}
-__device__ __forceinline__ float lane_east(float v)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xF, 0xF, true));
-}
-
-template <bool MIXED, int K, int RPT, int NW, int CPL>
+template <int K, int RPT, int NW, int CPL>
 __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs, int j0,
-    const DiffRow<typename FT<MIXED>::T>* __restrict__ drow,
-    const typename FT<MIXED>::T* __restrict__ in1, const typename FT<MIXED>::T* __restrict__ in2,
-    const double* __restrict__ y0, const typename FT<MIXED>::T* __restrict__ ly0,
-    typename FT<MIXED>::T* __restrict__ out1, typename FT<MIXED>::T* __restrict__ out2,
-    double* __restrict__ B, const float* __restrict__ adv, int nt, int np)
+    const DiffRow<double>* __restrict__ drow, const double* __restrict__ in1,
+    const double* __restrict__ in2, const double* __restrict__ y0, double* __restrict__ out1,
+    double* __restrict__ out2, double* __restrict__ B, int nt, int np)
 {
-    using T = typename FT<MIXED>::T;
+    using T = double;
     constexpr int LX = 64 * CPL, TX = LX - 2 * K, LY = NW * RPT, TY = LY - 2 * K;
     __shared__ T xch[2][2][NW][LX];   // [stage parity][top, bottom row][wave][column]
 
@@ -224,38 +183,31 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
 
     // ya / yb alternate as (current, previous); rows beyond the poles start
     // at zero
-    T ya[RPT][CPL], yb[RPT][CPL], lyr[RPT][CPL];
-    double y0r[MIXED ? 1 : RPT][MIXED ? 1 : CPL];
-    // FP32: e = d_{j-1} - d_{j-2}, updated in place (d_1 itself at j0 = 2)
-    T ez[MIXED ? RPT : 1][MIXED ? CPL : 1];
+    T ya[RPT][CPL], yb[RPT][CPL], lyr[RPT][CPL], y0r[RPT][CPL];
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
         const int j = jw + m;
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            T a = T(0), b = T(0), l = T(0);
-            double z = 0.0;
+            T a = T(0), b = T(0), z = T(0);
             if (j >= 0 && j < nt) {
                 const size_t i = base + (size_t)j * np + kc[c];
                 a = in1[i];
                 if (has_in2) b = in2[i];
-                if constexpr (MIXED) l = ly0[i];
-                else z = y0[i];
+                z = y0[i];
             }
             ya[m][c] = a;
             yb[m][c] = b;
-            lyr[m][c] = l;
-            if constexpr (!MIXED) y0r[m][c] = z;
-            else ez[m][c] = has_in2 ? b : a;
+            y0r[m][c] = z;
         }
     }
 
-    // FP64: L(Y0) of the staged region from the staged Y0 (the first-stage
+    // L(Y0) of the staged region from the staged Y0 (the first-stage
     // kernel's operator, the same helper and operand order, so the same
     // bits) instead of reading a fourth array.  The outer ring's value is
     // wrong (its outer neighbours read as zero) but, being a pointwise term,
     // it spoils nothing the ring's own wrong stage values do not already.
-    if constexpr (!MIXED) {
+    {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             xch[1][0][w][lane * CPL + c] = y0r[0][c];
@@ -271,13 +223,13 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
             const DiffRow<T> d = dr[min(max(jw + m, 0), nt - 1)];
-            const T wl = lane_west((T)y0r[m][CPL - 1]), el = lane_east((T)y0r[m][0]);
+            const T wl = lane_west(y0r[m][CPL - 1]), el = lane_east(y0r[m][0]);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                const T wv = c > 0 ? (T)y0r[m][c - 1] : wl;
-                const T ev = c < CPL - 1 ? (T)y0r[m][c + 1] : el;
-                lyr[m][c] = L5<T>(d, wv, m > 0 ? (T)y0r[m - 1][c] : north[c], (T)y0r[m][c],
-                                  m < RPT - 1 ? (T)y0r[m + 1][c] : south[c], ev);
+                const T wv = c > 0 ? y0r[m][c - 1] : wl;
+                const T ev = c < CPL - 1 ? y0r[m][c + 1] : el;
+                lyr[m][c] = L5<T>(d, wv, m > 0 ? y0r[m - 1][c] : north[c], y0r[m][c],
+                                  m < RPT - 1 ? y0r[m + 1][c] : south[c], ev);
             }
         }
     }
@@ -322,13 +274,7 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
                 const T ev = c < CPL - 1 ? cur[m][c + 1] : el;
                 const T L = L5<T>(d, wv, m > 0 ? cur[m - 1][c] : north[c], cur[m][c],
                                   m < RPT - 1 ? cur[m + 1][c] : south[c], ev);
-                if constexpr (MIXED) {
-                    const T ev = sts_mixed(cf, cur[m][c], ez[m][c], L, lyr[m][c]);
-                    ez[m][c] = ev;
-                    prv[m][c] = cur[m][c] + ev;
-                } else {
-                    prv[m][c] = sts_f64(cf, cur[m][c], prv[m][c], y0r[m][c], L, lyr[m][c]);
-                }
+                prv[m][c] = sts_f64(cf, cur[m][c], prv[m][c], y0r[m][c], L, lyr[m][c]);
             }
         }
     };
@@ -339,16 +285,6 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
     }
     const bool odd = i < kk;
     if (odd) stage(i, ya, yb);
-    if constexpr (MIXED) {
-        // the slot of the stage before the last takes e, the output's partner
-#pragma unroll
-        for (int m = 0; m < RPT; ++m)
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                if (odd) ya[m][c] = ez[m][c];
-                else yb[m][c] = ez[m][c];
-            }
-    }
 
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
@@ -358,17 +294,10 @@ __global__ __launch_bounds__(64 * NW) void diff_strip_kernel(
         for (int m = 0; m < RPT; ++m) {
             const int ly = w * RPT + m, j = jw + m;
             if (ly < K || ly >= K + TY || j >= nt) continue;
-            // FP64: the last two stages; FP32: the last stage and its change e
             const T last = odd ? yb[m][c] : ya[m][c], before = odd ? ya[m][c] : yb[m][c];
             const size_t gi = base + (size_t)j * np + k;
             if (fin) {
-                if constexpr (MIXED) {
-                    double yv = B[gi];
-                    if (e.pad) yv += (double)adv[gi];
-                    B[gi] = yv + (double)last;
-                } else {
-                    B[gi] = last;
-                }
+                B[gi] = last;
             } else {
                 out1[gi] = last;
                 out2[gi] = before;
@@ -390,52 +319,47 @@ static const FusedCfg kCfg64[] = {
     {112, 48, 8, 512}, {116, 52, 6, 512}, {112, 80, 8, 512},
     // short strips: more, lighter blocks for classes with few cells
     {48, 16, 8, 512}, {56, 24, 4, 512}, {48, 32, 8, 512}};
-static const FusedCfg kCfg32[] = {
-    {64, 16, 4, 256}, {64, 32, 8, 256}, {128, 32, 8, 256}, {128, 16, 8, 256}, {64, 64, 8, 512},
-    {48, 48, 8, 256}, {48, 112, 8, 512}, {48, 112, 8, 256}, {52, 116, 6, 512},
-    {112, 48, 8, 512}, {112, 112, 8, 512}, {112, 112, 8, 256},
-    {48, 16, 8, 512}, {56, 24, 4, 512}, {48, 48, 8, 512}};
 
-int fused_config_count(bool mixed) { return mixed ? 15 : 15; }
+int fused_config_count(bool mixed) { return mixed ? mixed_config_count() : 15; }
 
-int fused_config_k(bool mixed, int cfg) { return mixed ? kCfg32[cfg].k : kCfg64[cfg].k; }
+int fused_config_k(bool mixed, int cfg) { return mixed ? mixed_config_k(cfg) : kCfg64[cfg].k; }
 
 bool fused_config_reads_ly0(bool mixed, int cfg) { return mixed || cfg < 5; }
 
 void fused_config_desc(bool mixed, int cfg, int* tx, int* ty, int* k, int* nthr)
 {
-    const FusedCfg& c = mixed ? kCfg32[cfg] : kCfg64[cfg];
+    if (mixed) {
+        mixed_config_desc(cfg, tx, ty, k, nthr);
+        return;
+    }
+    const FusedCfg& c = kCfg64[cfg];
     *tx = c.tx;
     *ty = c.ty;
     *k = c.k;
     *nthr = c.nt;
 }
 
-template <bool MIXED, int TX, int TY, int K, int NT>
+template <int TX, int TY, int K, int NT>
 static void launch_one(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs, int j0,
                        const void* drow, const void* in1, const void* in2, const double* y0,
-                       const void* ly0, void* out1, void* out2, double* B, const float* adv, int nt,
-                       int np)
+                       const void* ly0, void* out1, void* out2, double* B, int nt, int np)
 {
-    using T = typename FT<MIXED>::T;
     dim3 grid((np + TX - 1) / TX, (nt + TY - 1) / TY, n_act);
-    hipLaunchKernelGGL((diff_fused_kernel<MIXED, TX, TY, K, NT>), grid, dim3(NT), 0, st, ents, coefs, j0,
-                       (const DiffRow<T>*)drow, (const T*)in1, (const T*)in2, y0, (const T*)ly0,
-                       (T*)out1, (T*)out2, B, adv, nt, np);
+    hipLaunchKernelGGL((diff_fused_kernel<TX, TY, K, NT>), grid, dim3(NT), 0, st, ents, coefs, j0,
+                       (const DiffRow<double>*)drow, (const double*)in1, (const double*)in2, y0,
+                       (const double*)ly0, (double*)out1, (double*)out2, B, nt, np);
 }
 
-template <bool MIXED, int K, int RPT, int NW, int CPL>
+template <int K, int RPT, int NW, int CPL>
 static void launch_strip(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs, int j0,
                          const void* drow, const void* in1, const void* in2, const double* y0,
-                         const void* ly0, void* out1, void* out2, double* B, const float* adv, int nt,
-                         int np)
+                         void* out1, void* out2, double* B, int nt, int np)
 {
-    using T = typename FT<MIXED>::T;
     constexpr int TX = 64 * CPL - 2 * K, TY = NW * RPT - 2 * K;
     const int nblk = ((np + TX - 1) / TX) * ((nt + TY - 1) / TY) * n_act;
-    hipLaunchKernelGGL((diff_strip_kernel<MIXED, K, RPT, NW, CPL>), dim3(nblk), dim3(64 * NW), 0, st, ents, coefs, j0,
-                       (const DiffRow<T>*)drow, (const T*)in1, (const T*)in2, y0, (const T*)ly0,
-                       (T*)out1, (T*)out2, B, adv, nt, np);
+    hipLaunchKernelGGL((diff_strip_kernel<K, RPT, NW, CPL>), dim3(nblk), dim3(64 * NW), 0, st, ents, coefs, j0,
+                       (const DiffRow<double>*)drow, (const double*)in1, (const double*)in2, y0,
+                       (double*)out1, (double*)out2, B, nt, np);
 }
 
 void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, int n_act,
@@ -443,46 +367,30 @@ void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, i
                        const void* in2, const double* y0, const void* ly0, void* out1, void* out2,
                        double* B, const float* adv, int nt, int np)
 {
-#define L1(M, a, b, c, d) \
-    launch_one<M, a, b, c, d>(st, ents, n_act, coefs, j0, drow, in1, in2, y0, ly0, out1, out2, B, adv, nt, np)
-#define S1(M, k, r, w, c) \
-    launch_strip<M, k, r, w, c>(st, ents, n_act, coefs, j0, drow, in1, in2, y0, ly0, out1, out2, B, adv, nt, np)
-    if (!mixed) {
-        switch (cfg) {
-        case 0: L1(false, 64, 16, 4, 256); break;
-        case 1: L1(false, 64, 32, 8, 256); break;
-        case 2: L1(false, 128, 16, 4, 256); break;
-        case 3: L1(false, 32, 32, 4, 256); break;
-        case 4: L1(false, 64, 32, 6, 256); break;
-        case 5: S1(false, 8, 16, 4, 1); break;
-        case 6: S1(false, 8, 16, 8, 1); break;
-        case 7: S1(false, 6, 16, 8, 1); break;
-        case 8: S1(false, 8, 8, 8, 1); break;
-        case 9: S1(false, 8, 8, 8, 2); break;
-        case 10: S1(false, 6, 8, 8, 2); break;
-        case 11: S1(false, 8, 12, 8, 2); break;
-        case 12: S1(false, 8, 4, 8, 1); break;
-        case 13: S1(false, 4, 4, 8, 1); break;
-        default: S1(false, 8, 6, 8, 1); break;
-        }
-    } else {
-        switch (cfg) {
-        case 0: L1(true, 64, 16, 4, 256); break;
-        case 1: L1(true, 64, 32, 8, 256); break;
-        case 2: L1(true, 128, 32, 8, 256); break;
-        case 3: L1(true, 128, 16, 8, 256); break;
-        case 4: L1(true, 64, 64, 8, 512); break;
-        case 5: S1(true, 8, 16, 4, 1); break;
-        case 6: S1(true, 8, 16, 8, 1); break;
-        case 7: S1(true, 8, 32, 4, 1); break;
-        case 8: S1(true, 6, 16, 8, 1); break;
-        case 9: S1(true, 8, 8, 8, 2); break;
-        case 10: S1(true, 8, 16, 8, 2); break;
-        case 11: S1(true, 8, 32, 4, 2); break;
-        case 12: S1(true, 8, 4, 8, 1); break;
-        case 13: S1(true, 4, 4, 8, 1); break;
-        default: S1(true, 8, 8, 8, 1); break;
-        }
+    if (mixed) {
+        launch_diff_mixed_blocked(st, cfg, ents, n_act, coefs, j0, (const DiffRow<double>*)drow,
+                                  (const float*)in1, (const float*)in2, (const float*)ly0, (float*)out1,
+                                  (float*)out2, B, adv, nt, np);
+        return;
+    }
+#define L1(a, b, c, d) launch_one<a, b, c, d>(st, ents, n_act, coefs, j0, drow, in1, in2, y0, ly0, out1, out2, B, nt, np)
+#define S1(k, r, w, c) launch_strip<k, r, w, c>(st, ents, n_act, coefs, j0, drow, in1, in2, y0, out1, out2, B, nt, np)
+    switch (cfg) {
+    case 0: L1(64, 16, 4, 256); break;
+    case 1: L1(64, 32, 8, 256); break;
+    case 2: L1(128, 16, 4, 256); break;
+    case 3: L1(32, 32, 4, 256); break;
+    case 4: L1(64, 32, 6, 256); break;
+    case 5: S1(8, 16, 4, 1); break;
+    case 6: S1(8, 16, 8, 1); break;
+    case 7: S1(6, 16, 8, 1); break;
+    case 8: S1(8, 8, 8, 1); break;
+    case 9: S1(8, 8, 8, 2); break;
+    case 10: S1(6, 8, 8, 2); break;
+    case 11: S1(8, 12, 8, 2); break;
+    case 12: S1(8, 4, 8, 1); break;
+    case 13: S1(4, 4, 8, 1); break;
+    default: S1(8, 6, 8, 1); break;
     }
 #undef L1
 #undef S1

@@ -96,7 +96,6 @@ struct GridClass {
     double *rfe_partial = nullptr, *rfe_ratio = nullptr;
     int rfe_nblk = 0;
     DiffRow<double>* dr64 = nullptr;
-    DiffRow<float>* dr32 = nullptr;
     double *sf64 = nullptr, *denth64 = nullptr, *denph64 = nullptr;
     float *sf32 = nullptr, *denth32 = nullptr, *denph32 = nullptr;
     double *st_row = nullptr, *ct_row = nullptr, *lat_row = nullptr, *w_row = nullptr;
@@ -772,7 +771,7 @@ void run_fused_groups(sft_ctx* c, GridClass* g, Plan* p, const Phase& ph)
             out1 = (grp & 1) ? g->A[1] : g->A[4];
             out2 = (grp & 1) ? g->A[2] : g->A[5];
             ly0 = g->A[3];
-            drow = g->dr32;
+            drow = g->dr64;
         }
         // algorithmic bytes (per cell and stage of the method) and the
         // launch's own minimum traffic (inputs read once, outputs written once)
@@ -807,8 +806,18 @@ sft_status choose_tile(sft_ctx* c, GridClass* g)
         g->tile = -1;
         return SFT_OK;
     }
+    // the blocked FP32 kernel addresses one realization's FP64 state with
+    // 32-bit byte offsets
+    const bool fits32 = g->cells() * sizeof(double) <= 0xFFFFFFFFull;
     if (o.sts_tile >= 0) {
+        if (mixed && !fits32)
+            return fail(c, SFT_ERR_UNSUPPORTED, "blocked FP32 stages need nt*np*8 < 2^32 bytes (grid %dx%d)",
+                        g->nt, g->np);
         g->tile = o.sts_tile;
+        return SFT_OK;
+    }
+    if (mixed && !fits32) {
+        g->tile = -1;
         return SFT_OK;
     }
     const int S = 1000;
@@ -855,7 +864,7 @@ sft_status choose_tile(sft_ctx* c, GridClass* g)
         }, 4);
     else
         best = time_it([&] {
-            launch_diff_stage_mixed(c->stream, d_ents, R, d_coefs, 10, g->dr32, g->B, g->A[0], g->A[1],
+            launch_diff_stage_mixed(c->stream, d_ents, R, d_coefs, 10, g->dr64, g->B, g->A[0], g->A[1],
                                     g->A[2], g->A[3], g->A[4], g->A[2], nt, np);
         }, 4);
     for (int cfg = 0; cfg < fused_config_count(mixed); ++cfg) {
@@ -868,7 +877,7 @@ sft_status choose_tile(sft_ctx* c, GridClass* g)
             }, 3);
         else
             t = time_it([&] {
-                launch_diff_fused(c->stream, true, cfg, d_ents, R, d_coefs, 10, g->dr32, g->A[1],
+                launch_diff_fused(c->stream, true, cfg, d_ents, R, d_coefs, 10, g->dr64, g->A[1],
                                   g->A[2], nullptr, g->A[3], g->A[4], g->A[5], g->B, g->A[0], nt, np);
             }, 3);
         if (t / K < best) {
@@ -1014,7 +1023,7 @@ void run_plan(sft_ctx* c, GridClass* g, Plan* p, int lane)
                         const float* din = (j & 1) ? P2 : P1;
                         float* dout = (j & 1) ? P1 : P2;
                         tbeg(c);
-                        launch_diff_stage_mixed(st, E, ph.n_act[j], p->d_coefs, j, g->dr32, g->B, A0, din,
+                        launch_diff_stage_mixed(st, E, ph.n_act[j], p->d_coefs, j, g->dr64, g->B, A0, din,
                                                 j == 2 ? nullptr : EA, LY, dout, EA, nt, np);
                         tend(c, SFT_KFAM_STS_STAGE, stage_bytes(p, ph, j, true, g->cells()));
                     }
@@ -1181,7 +1190,6 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
     std::vector<AdvRow<double>> a64((size_t)R * (nt + 1));
     std::vector<AdvRow<float>> a32((size_t)R * (nt + 1));
     std::vector<DiffRow<double>> d64((size_t)R * nt);
-    std::vector<DiffRow<float>> d32((size_t)R * nt);
     std::vector<AssimReal> ar(R);
     g->cfl.assign(R, INFINITY);
     g->dtE.assign(R, INFINITY);
@@ -1227,8 +1235,6 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
         double m = 0.0;
         for (int j = 0; j < nt; ++j) {
             d64[(size_t)r * nt + j] = drow[j];
-            DiffRow<float> f{(float)drow[j].up, (float)drow[j].dn, (float)drow[j].ph, (float)drow[j].d};
-            d32[(size_t)r * nt + j] = f;
             m = std::max(m, fabs(drow[j].d));
         }
         g->dtE[r] = m > 0.0 ? 1.0 / m : INFINITY;
@@ -1243,8 +1249,6 @@ static sft_status class_alloc(sft_ctx* c, GridClass* g)
     TRY(upload(c, g->adv32, a32));
     TRY(dalloc(c, &g->dr64, d64.size()));
     TRY(upload(c, g->dr64, d64));
-    TRY(dalloc(c, &g->dr32, d32.size()));
-    TRY(upload(c, g->dr32, d32));
     TRY(dalloc(c, &g->ar, ar.size()));
     TRY(upload(c, g->ar, ar));
     std::vector<double> b0(R);

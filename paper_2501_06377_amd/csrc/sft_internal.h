@@ -110,7 +110,7 @@ void launch_diff_first_mixed(hipStream_t st, const Entry* ents, int n_ent, const
                              const DiffRow<double>* drow64, const double* B, const float* adv,
                              float* ly0, float* d1, int nt, int np);
 void launch_diff_stage_mixed(hipStream_t st, const Entry* ents, int n_act, const StageCoef* coefs,
-                             int j, const DiffRow<float>* drow, double* B, const float* adv,
+                             int j, const DiffRow<double>* drow, double* B, const float* adv,
                              const float* din, const float* ein, const float* ly0, float* dout,
                              float* eout, int nt, int np);
 //   Temporally blocked stages j0 .. j0+K-1 (K of tile configuration cfg).
@@ -126,6 +126,15 @@ void launch_diff_fused(hipStream_t st, bool mixed, int cfg, const Entry* ents, i
                        const StageCoef* coefs, int j0, const void* drow, const void* in1,
                        const void* in2, const double* y0, const void* ly0, void* out1, void* out2,
                        double* B, const float* adv, int nt, int np);
+//   FP32 increment form, blocked (k_diffusion_mixed.hip): configurations
+//   0 .. mixed_config_count() - 1 of launch_diff_fused(mixed = true).
+int mixed_config_count();
+int mixed_config_k(int cfg);
+void mixed_config_desc(int cfg, int* tx, int* ty, int* k, int* nthr);
+void launch_diff_mixed_blocked(hipStream_t st, int cfg, const Entry* ents, int n_act, const StageCoef* coefs,
+                               int j0, const DiffRow<double>* drow, const float* in1, const float* in2,
+                               const float* ly0, float* out1, float* out2, double* B, const float* adv, int nt,
+                               int np);
 //   B = B (+ adv when Entry.pad) (+ d when d != NULL), per entry.
 void launch_mixed_close(hipStream_t st, const Entry* ents, int n_ent, double* B, const float* adv,
                         const float* d, size_t cells);

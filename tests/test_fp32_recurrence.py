@@ -3,7 +3,11 @@ numpy (CPU): carried as the increment d and its last change e it is the same
 recurrence as the three-term form (equal to the FP64 oracle in FP64), and in
 FP32 its rounding error stays far below the three-term form's over a call of
 about a thousand stages (the three-term form's errors grow with the square
-of the stage count).  This pins the arithmetic the GPU's FP32 kernels use."""
+of the stage count).  The GPU's FP32 kernels fold the stage coefficients
+into the operator rows (per row and stage, formed in FP64 and rounded to
+FP32: cL ph, cL up, cL dd - cy0, cL dn) and sum the two longitude neighbours
+first; that arithmetic is modelled too.  This pins the arithmetic the GPU's
+FP32 kernels use."""
 import numpy as np
 import pytest
 
@@ -22,9 +26,22 @@ def operator(coefs, y):
     return ph[:, None] * w + up[:, None] * n + dd[:, None] * y + dn[:, None] * s + ph[:, None] * e
 
 
-def run(y0, nu, tau, s, dtype, carried):
+def folded_increment(c64, cl, cy0, nu_j, g, d, e, ly0, dtype):
+    """e_j in the folded form: A (w + e) + U n + C d + S s - nu e + G L(Y0),
+    with A, U, C, S formed per row in FP64 and rounded (dtype arithmetic)."""
+    up, dn, ph, dd = c64
+    A, U = (cl * ph).astype(dtype)[:, None], (cl * up).astype(dtype)[:, None]
+    C, S = (cl * dd - cy0).astype(dtype)[:, None], (cl * dn).astype(dtype)[:, None]
+    n = np.concatenate([d[:1], d[:-1]], axis=0)
+    s = np.concatenate([d[1:], d[-1:]], axis=0)
+    t = (np.roll(d, 1, axis=1) + np.roll(d, -1, axis=1)).astype(dtype)
+    return A * t + U * n + C * d + S * s + dtype(-nu_j) * e + dtype(g) * ly0
+
+
+def run(y0, nu, tau, s, dtype, carried, folded=False):
     mu, nv, mut, gamt = oracle.sts_coefs(s, oracle.RKG2)
-    coefs = tuple(c.astype(dtype) for c in oracle.diff_coefs(NT, NP, nu))
+    c64 = oracle.diff_coefs(NT, NP, nu)
+    coefs = tuple(c.astype(dtype) for c in c64)
     ly0 = operator(oracle.diff_coefs(NT, NP, nu), y0).astype(dtype)   # L(Y0) formed in FP64
     d = (dtype(mut[1] * tau) * ly0).astype(dtype)
     e = d.copy()                               # d_1 - d_0, d_0 = 0
@@ -32,7 +49,11 @@ def run(y0, nu, tau, s, dtype, carried):
     for j in range(2, s + 1):
         L = operator(coefs, d)
         c1, c2 = dtype(mut[j] * tau), dtype((mut[j] + gamt[j]) * tau)
-        if carried:
+        if folded:
+            en = folded_increment(c64, mut[j] * tau, 1.0 - mu[j] - nv[j], nv[j], (mut[j] + gamt[j]) * tau,
+                                  d, e, ly0, dtype)
+            d, e = (d + en).astype(dtype), en.astype(dtype)
+        elif carried:
             en = dtype(mu[j] + nv[j] - 1.0) * d - dtype(nv[j]) * e + c1 * L + c2 * ly0
             d, e = (d + en).astype(dtype), en.astype(dtype)
         else:
@@ -61,10 +82,10 @@ def test_carried_form_is_the_same_recurrence(case):
     """In FP64 both forms land on the oracle's result (the same recurrence,
     rounded differently)."""
     y0, nu, tau, s, ref = case
-    for carried in (False, True):
-        got = run(y0, nu, tau, s, np.float64, carried)
+    for carried, folded in ((False, False), (True, False), (True, True)):
+        got = run(y0, nu, tau, s, np.float64, carried, folded)
         e = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-        assert e < 1e-11, (carried, e)
+        assert e < 1e-11, (carried, folded, e)
 
 
 def test_carried_form_keeps_fp32_rounding_small(case):
@@ -73,5 +94,8 @@ def test_carried_form_keeps_fp32_rounding_small(case):
     y0, nu, tau, s, ref = case
     e3 = np.linalg.norm(run(y0, nu, tau, s, np.float32, False) - ref) / np.linalg.norm(ref)
     ec = np.linalg.norm(run(y0, nu, tau, s, np.float32, True) - ref) / np.linalg.norm(ref)
+    ef = np.linalg.norm(run(y0, nu, tau, s, np.float32, True, True) - ref) / np.linalg.norm(ref)
     assert ec < 1e-6, ec
     assert ec < e3 / 30.0, (e3, ec)
+    assert ef < 1e-6, ef
+    assert ef < e3 / 30.0, (e3, ef)

@@ -208,15 +208,15 @@ def test_full_size_ensemble_first_hour_f64():
         assert e <= TOL64
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_blocked_tiles_bitwise_equal_unfused(prec):
-    """Every blocked tile shape (temporal blocking in LDS) gives bitwise the
-    same fields as one stage per launch: grid 70 x 150 spans several tiles
-    with ragged tails, realizations with different stage counts end in
-    different groups, and advection increments feed the mixed path."""
+@pytest.mark.parametrize("prec,nt,np_", [(0, 70, 150), (1, 70, 150), (1, 300, 256), (1, 257, 130)])
+def test_blocked_tiles_bitwise_equal_unfused(prec, nt, np_):
+    """Every blocked tile shape (temporal blocking in LDS / registers) gives
+    bitwise the same fields as one stage per launch: the grids span several
+    column tiles with ragged tails (and, at 300 and 257 rows, several
+    pole-aligned row tiles for the FP32 shapes), realizations with different stage counts end in
+    different launches, and advection increments feed the mixed path."""
     import paper_2501_06377_amd as sft
-    nt, np_ = 70, 150
-    say(f"case tile invariance precision {prec}")
+    say(f"case tile invariance precision {prec} grid {nt}x{np_}")
     reals = [synth.Realization(nu_km2_s=nu, **synth.dr_mf(amp_mf=a))
              for nu, a in ((200.0, 10.0), (600.0, 20.0), (1000.0, 15.0))]
     B0 = np.stack([random_field(nt, np_, 8, 70 + i) for i in range(3)])
@@ -235,9 +235,10 @@ def test_blocked_tiles_bitwise_equal_unfused(prec):
     auto, e3 = gpu_run(B0, reals, sched, precision=prec)
     say(f"  autotuned choice {e3.tile_choice(0)}")
     assert np.array_equal(auto, ref)
-    if prec == 0:
-        oref, _ = oracle_run(B0, reals, sched)
-        assert rel_l2(ref, oref) <= TOL64
+    oref, _ = oracle_run(B0, reals, sched)
+    e = rel_l2(ref, oref)
+    say(f"  one stage per launch vs oracle: rel-L2 {e:.3e}")
+    assert e <= (TOL64 if prec == 0 else TOL32)
 
 
 def run_classes(classes, fields, hours, **optkw):
