@@ -259,6 +259,21 @@ sft_status sft_assimilate(sft_ctx* ctx, int32_t grid_id, const void* data, const
                           int32_t dtype, int32_t weight_kind, double b0_deg, double l0_deg,
                           int32_t on_device);
 
+/* The same assimilation as sft_assimilate (the same bits), for callers that
+ * cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  It allocates nothing: data and
+ * weight must be device arrays on the context's device (no host staging),
+ * the flux-balance partial sums and ratios live in a 2 MiB device scratch
+ * array that the library holds per GPU (no stored increment: the apply pass
+ * forms it again), and the analysis record is left to sft_diagnostics.  A
+ * grid class needs R x (2 nblk + 1) <= 262144 scratch doubles (nblk =
+ * min(512, ceil(cells / 256)): about 255 realizations at 512 x 1024 and
+ * above), else SFT_ERR_ARG.  Every call on one GPU shares that GPU's scratch:
+ * calls that overlap on one GPU (other streams or threads) race.
+ * Stream-ordered.  Errors: SFT_ERR_ARG, SFT_ERR_STATE, SFT_ERR_HIP. */
+sft_status sft_assimilate_noalloc(sft_ctx* ctx, int32_t grid_id, const void* data, const void* weight,
+                                  int32_t dtype, int32_t weight_kind, double b0_deg, double l0_deg);
+
 /* Returns the latest analysis record of one realization (computed in FP64 on
  * the device after the last advance/assimilate, or now if none is pending).
  * Waits for the stream.  Returns SFT_ERR_NOT_FINITE (with *out filled) when

@@ -119,6 +119,21 @@ class Ensemble:
         self._chk(self.L.sft_assimilate(self.ctx, gid, p, w, code, kind, float(b0_deg), float(l0_deg),
                                         dev), "sft_assimilate")
 
+    def assimilate_noalloc(self, gid: int, data, weight=None, kind: int = _abi.SFT_WEIGHT_DISK,
+                           b0_deg: float = 0.0, l0_deg: float = 0.0):
+        """sft_assimilate_noalloc: device arrays only; allocates nothing."""
+        p, code, dev = _ptr(data)
+        if not dev:
+            raise ValueError("sft_assimilate_noalloc takes device arrays")
+        if weight is not None:
+            w, wcode, wdev = _ptr(weight)
+            if wcode != code or not wdev:
+                raise ValueError("data and weight must share dtype and device")
+        else:
+            w = ctypes.c_void_p(0)
+        self._chk(self.L.sft_assimilate_noalloc(self.ctx, gid, p, w, code, kind, float(b0_deg),
+                                                float(l0_deg)), "sft_assimilate_noalloc")
+
     def diagnostics(self, rid: int) -> dict:
         d = _abi.sft_diag()
         st = self.L.sft_diagnostics(self.ctx, rid, ctypes.byref(d))

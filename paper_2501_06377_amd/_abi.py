@@ -75,6 +75,7 @@ SIGNATURES = {
     "sft_get_states": (_I, [_P, _I, _P, _I, _I]),
     "sft_advance": (_I, [_P, _D]),
     "sft_assimilate": (_I, [_P, _I, _P, _P, _I, _I, _D, _D, _I]),
+    "sft_assimilate_noalloc": (_I, [_P, _I, _P, _P, _I, _I, _D, _D]),
     "sft_diagnostics": (_I, [_P, _I, ctypes.POINTER(sft_diag)]),
     "sft_time": (_I, [_P, ctypes.POINTER(_D)]),
     "sft_set_time": (_I, [_P, _D]),

@@ -60,8 +60,8 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red)
     b = red[RB];
 }
 
-// dB = F (data - B) for every realization of the class; per-block FP64
-// sums of dB w over dB > 0 and dB < 0.
+// dB = F (data - B) for every realization of the class (stored when dB is
+// not NULL); per-block FP64 sums of dB w over dB > 0 and dB < 0.
 __global__ __launch_bounds__(RB) void assim_delta_kernel(
     const AssimReal* __restrict__ ar, const void* data, const void* weight, int dtype, int kind,
     double sb0, double cb0, double l0, const double* __restrict__ B, const double* st_row,
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(RB) void assim_delta_kernel(
         const double F = weight_at(a, weight, dtype, kind, sb0, cb0, l0, i, j, k, np, st_row, ct_row,
                                    lat_row);
         const double d = F * (load_any(data, dtype, i) - B[base + i]);
-        dB[base + i] = d;
+        if (dB) dB[base + i] = d;
         if (d > 0.0) pp += d * w_row[j];
         else if (d < 0.0) pm += d * w_row[j];
     }
@@ -105,8 +105,9 @@ __global__ __launch_bounds__(RB) void assim_reduce_kernel(const double* __restri
     if (threadIdx.x == 0) ratio[r] = (pp != 0.0 && pm != 0.0) ? sqrt(fabs(pp / pm)) : 0.0;
 }
 
-// Balanced realizations: B += dB / r (dB > 0) or dB * r (dB <= 0).
-// Others: B = F data + (1 - F) B.
+// Balanced realizations: B += dB / r (dB > 0) or dB * r (dB <= 0), with dB
+// read back or, when dB is NULL, formed again exactly as the delta pass
+// formed it.  Others: B = F data + (1 - F) B.
 __global__ __launch_bounds__(RB) void assim_apply_kernel(
     const AssimReal* __restrict__ ar, const void* data, const void* weight, int dtype, int kind,
     double sb0, double cb0, double l0, double* __restrict__ B, const double* __restrict__ dB,
@@ -120,7 +121,15 @@ __global__ __launch_bounds__(RB) void assim_apply_kernel(
     for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < cells; i += (size_t)gridDim.x * RB) {
         if (a.balance) {
             const double rr = ratio[r];
-            double d = dB[base + i];
+            double d;
+            if (dB) {
+                d = dB[base + i];
+            } else {
+                const int j = (int)(i / np), k = (int)(i - (size_t)j * np);
+                const double F = weight_at(a, weight, dtype, kind, sb0, cb0, l0, i, j, k, np, st_row, ct_row,
+                                           lat_row);
+                d = F * (load_any(data, dtype, i) - B[base + i]);
+            }
             if (rr != 0.0) d = d > 0.0 ? d / rr : d * rr;
             B[base + i] = B[base + i] + d;
         } else {

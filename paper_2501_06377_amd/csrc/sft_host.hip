@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1101,6 +1102,45 @@ sft_status sft_options_default(sft_options* opt)
     return SFT_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free scratch
+// Device scratch of sft_assimilate_noalloc: the flux-balance partial sums and
+// ratios of one call, R x (2 nblk + 1) doubles, in a file-scope device array
+// that every GPU the library runs on holds until the process ends.  Host code
+// never uses the array's name as an address: its device address is looked
+// up once per device, with that device current (scratch_setup, from
+// sft_create), and kept per device.
+constexpr size_t kNoAllocDoubles = 262144;   // 2 MiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxDevices] = {};
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Looks up this device's address of `scratch` (first context on a device).
+static sft_status scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return SFT_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return SFT_ERR_HIP;
+        g_scratch_ptr[device] = (double*)ptr;
+        g_scratch_done[device] = true;
+    }
+    return SFT_OK;
+}
+
+static double* scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
 sft_status sft_create(sft_ctx** ctx, const sft_options* opt, void* hip_stream)
 {
     if (!ctx) return SFT_ERR_ARG;
@@ -1133,6 +1173,10 @@ sft_status sft_create(sft_ctx** ctx, const sft_options* opt, void* hip_stream)
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return SFT_ERR_HIP;
+    }
+    if (const sft_status sst = scratch_setup(c->device); sst != SFT_OK) {
+        delete c;
+        return sst;
     }
     if (!c->stream) {
         // an own blocking stream (default priority): it orders with the null
@@ -1826,6 +1870,42 @@ sft_status sft_assimilate(sft_ctx* c, int32_t gid, const void* data, const void*
     for (int r = 0; r < g->R; ++r) g->assim[r] += 1;
     if (c->opt.diag_every_call) launch_diag_class(c, g);
     else g->diag_valid = false;
+    HIPCHK(c, hipGetLastError());
+    return SFT_OK;
+}
+
+sft_status sft_assimilate_noalloc(sft_ctx* c, int32_t gid, const void* data, const void* weight,
+                                  int32_t dtype, int32_t kind, double b0_deg, double l0_deg)
+{
+    if (!c || !data || gid < 0 || gid >= (int)c->grids.size()) return SFT_ERR_ARG;
+    if (kind != SFT_WEIGHT_F && kind != SFT_WEIGHT_MU && kind != SFT_WEIGHT_DISK)
+        return fail(c, SFT_ERR_ARG, "bad weight kind %d", kind);
+    if (kind != SFT_WEIGHT_DISK && !weight) return fail(c, SFT_ERR_ARG, "weight array missing");
+    if (dtype != SFT_DTYPE_F64 && dtype != SFT_DTYPE_F32) return fail(c, SFT_ERR_ARG, "bad dtype");
+    GridClass* g = c->grids[gid];
+    if (!g->R) return fail(c, SFT_ERR_STATE, "grid %d has no realizations", gid);
+    const size_t need = (size_t)g->R * (2 * (size_t)g->red_nblk + 1);
+    if (need > kNoAllocDoubles)
+        return fail(c, SFT_ERR_ARG, "grid %d needs %zu scratch doubles, the limit is %zu", gid, need,
+                    kNoAllocDoubles);
+    double* sp = scratch_ptr(c->device);
+    if (!sp) return fail(c, SFT_ERR_HIP, "no scratch address for device %d", c->device);
+    double* partial = sp;
+    double* ratio = sp + (size_t)g->R * 2 * g->red_nblk;
+    bool any_bal = false;
+    for (auto& p : g->prm) any_bal |= p.flux_balance != 0;
+    const double b0 = b0_deg * (M_PI / 180.0), l0 = l0_deg * (M_PI / 180.0);
+    const double sb0 = sin(b0), cb0 = cos(b0);
+    // no stored increment: the apply pass forms dB again, with the same bits
+    if (any_bal) {
+        launch_assim_delta(c->stream, g->R, g->ar, data, weight, dtype, kind, sb0, cb0, l0, g->B, g->st_row,
+                           g->ct_row, g->lat_row, g->w_row, nullptr, partial, g->red_nblk, g->nt, g->np);
+        launch_assim_reduce(c->stream, g->R, partial, g->red_nblk, ratio);
+    }
+    launch_assim_apply(c->stream, g->R, g->ar, data, weight, dtype, kind, sb0, cb0, l0, g->B, nullptr, ratio,
+                       g->st_row, g->ct_row, g->lat_row, g->red_nblk, g->nt, g->np);
+    for (int r = 0; r < g->R; ++r) g->assim[r] += 1;
+    g->diag_valid = false;
     HIPCHK(c, hipGetLastError());
     return SFT_OK;
 }
