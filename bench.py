@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--rfe-tau", type=float, default=1.0, help="source-map lifetime, hours (0: infinite)")
     ap.add_argument("--sts-tile", type=int, default=-1, help="blocked STS shape (-1: autotuned)")
     ap.add_argument("--surr-batch", type=int, default=64)
+    ap.add_argument("--inference-only", action="store_true",
+                    help="only the batch inference timing of the surrogate (few launches: counter runs)")
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only the surrogate measurement (inference batch, plain vs surrogate intervals)")
     ap.add_argument("--no-f64-compare", action="store_true",
@@ -202,7 +204,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def surrogate_bench(sft, torch, batch, n_real=64, hours=16, stride=8, tol=1e-3):
+def surrogate_bench(sft, torch, batch, n_real=64, hours=16, stride=8, tol=1e-3, inference_only=False):
     """The learned surrogate at 512 x 1024 on realizations of its training
     distribution (no assimilation): BF16-MFMA inference throughput of a
     batch, then the cost of a realization-interval over `hours` one-hour
@@ -234,6 +236,11 @@ def surrogate_bench(sft, torch, batch, n_real=64, hours=16, stride=8, tol=1e-3):
     tflops = flop / (ms * 1e-3) / 1e12
     del B, F, y
     log(f"surrogate inference: batch {batch} in {ms:.2f} ms ({tflops:.1f} TFLOP/s)")
+    if inference_only:
+        net.close()
+        return {"weights": wname, "grid": f"{nt}x{np_}",
+                "inference": {"batch": batch, "ms_per_batch": ms, "flop_per_batch": flop, "TFLOP_s": tflops,
+                              "peak_TFLOP_s": 2500.0, "mfma_frac": tflops / 2500.0, "dtype": "bf16 (fp32 acc)"}}
 
     def context(prec):
         ens = sft.Ensemble(precision=prec)
@@ -618,8 +625,9 @@ def main():
 
     import paper_2501_06377_amd as sft
 
-    if args.surrogate_only:
-        print(json.dumps({"surrogate": surrogate_bench(sft, torch, args.surr_batch)}), flush=True)
+    if args.surrogate_only or args.inference_only:
+        print(json.dumps({"surrogate": surrogate_bench(sft, torch, args.surr_batch,
+                                                       inference_only=args.inference_only)}), flush=True)
         return
     if args.workload == "plain":
         print(json.dumps(plain_bench(sft, torch, args, args.steps or 10, args.warmup)), flush=True)
