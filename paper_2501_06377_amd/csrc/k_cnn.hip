@@ -200,10 +200,11 @@ struct PersistShape {
     static constexpr int NTH = CIN == 64 ? 512 : 256;
 };
 
-template <int CIN>
+// 16-byte chunk q of an LDS row of SC bf16 channels, XOR-permuted by the row
+template <int SC>
 __device__ __forceinline__ int chunk_swz(int row, int q)
 {
-    return q ^ (row & (CIN / 8 - 1));
+    return q ^ (row & (SC / 8 - 1));
 }
 
 template <int CIN, int MODE>
@@ -222,13 +223,18 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
     constexpr int NTH = PersistShape<CIN>::NTH;
     constexpr int NN = 512 / NTH;                 // 32-channel output halves per wave
     constexpr int NCG = PTX / 32;                 // 32-pixel column groups
-    constexpr int NQ = CIN / 8;                   // 16-byte chunks per pixel / weight row
+    // first layer (16 packed input slots, 7 live): two taps share one K chunk
+    // of 16, the lanes of K half kh taking tap 2p + kh of tap pair p, so only
+    // the first 8 channels of a pixel and of a weight row are staged
+    constexpr bool PAIR = CIN == 16 && MODE != 1;
+    constexpr int SC = PAIR ? 8 : CIN;            // staged channels per pixel / weight row
+    constexpr int NQ = SC / 8;                    // 16-byte chunks per staged pixel / weight row
     constexpr int NCH = CIN / 16;                 // K chunks per tap
     constexpr int TR = PTY + 2, TC = PTX + 2;
     constexpr int CTS = 64 + 8;                   // channel stride of the staged output tile
-    constexpr int TILE_E = TR * TC * CIN, OUT_E = PTY * PTX * CTS;
+    constexpr int TILE_E = TR * TC * SC, OUT_E = PTY * PTX * CTS;
     constexpr int BUF_E = TILE_E > OUT_E ? TILE_E : OUT_E;
-    constexpr int WE = 9 * 64 * CIN;
+    constexpr int WE = 9 * 64 * SC;
     constexpr int NV = TR * TC * NQ, VPT = (NV + NTH - 1) / NTH;
     __shared__ __attribute__((aligned(16))) uint16_t wl[WE];
     __shared__ __attribute__((aligned(16))) uint16_t buf[BUF_E];
@@ -240,7 +246,8 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
 
     for (int v = tid; v < 9 * 64 * NQ; v += NTH) {
         const int row = v / NQ, q = v - (v / NQ) * NQ;   // row = tap * 64 + output channel
-        *(uint4*)(wl + (size_t)row * CIN + chunk_swz<CIN>(row, q) * 8) = *(const uint4*)(w + (size_t)v * 8);
+        *(uint4*)(wl + (size_t)row * SC + chunk_swz<SC>(row, q) * 8) =
+            *(const uint4*)(w + (size_t)row * CIN + q * 8);
     }
 
     // MODE 2: the output layer's weights as B fragments (taps as columns,
@@ -253,6 +260,15 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
             if (col < 9) b5[ch] = *(const bf16x8*)(w5 + (size_t)col * 32 * 64 + ch * 16 + kh * 8);
         }
     }
+
+    // bias of the channels this lane's accumulator registers hold: register r
+    // of output half n is channel (n0 + n) 32 + 8 (r / 4) + 4 kh + r mod 4
+    float bcol[NN][16];
+#pragma unroll
+    for (int n = 0; n < NN; ++n)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            bcol[n][r] = MODE == 1 ? 0.f : bias[(n0 + n) * 32 + 8 * (r >> 2) + 4 * kh + (r & 3)];
 
     const int out_rows = MODE == 1 ? H - 2 : H, r_base = MODE == 1 ? 1 : 0;
     const int tiles_x = (W + PTX - 1) / PTX, tiles_y = (out_rows + PTY - 1) / PTY;
@@ -315,7 +331,7 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
                     else
                         val = make_uint4(0, 0, 0, 0);
                 }
-                *(uint4*)(buf + (size_t)pix * CIN + chunk_swz<CIN>(pix, q) * 8) = val;
+                *(uint4*)(buf + (size_t)pix * SC + chunk_swz<SC>(pix, q) * 8) = val;
             }
         }
         __syncthreads();
@@ -330,6 +346,37 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
                 for (int n = 0; n < NN; ++n)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) acc[m][g][n][r] = 0.f;
+        if constexpr (PAIR) {
+            // tap pairs (0, 1), (2, 3), (4, 5), (6, 7), (8, -): the absent
+            // tenth tap has zero weights (and reads a valid input fragment)
+#pragma unroll
+            for (int p = 0; p < 5; ++p) {
+                const int t = 2 * p + kh;
+                const bool live = t < 9;
+                const int dy = live ? t / 3 : 0, dx = live ? t - (t / 3) * 3 : 0;
+                bf16x8 wfr[NN], xfr[NCG][PMR];
+#pragma unroll
+                for (int n = 0; n < NN; ++n) {
+                    wfr[n] = bf16x8{};
+                    if (live) wfr[n] = *(const bf16x8*)(wl + (size_t)(t * 64 + (n0 + n) * 32 + col) * SC);
+                }
+#pragma unroll
+                for (int g = 0; g < NCG; ++g)
+#pragma unroll
+                    for (int m = 0; m < PMR; ++m) {
+                        const int pix = (wv * PMR + m + dy) * TC + g * 32 + col + dx;
+                        xfr[g][m] = *(const bf16x8*)(buf + (size_t)pix * SC);
+                    }
+#pragma unroll
+                for (int m = 0; m < PMR; ++m)
+#pragma unroll
+                    for (int g = 0; g < NCG; ++g)
+#pragma unroll
+                        for (int n = 0; n < NN; ++n)
+                            acc[m][g][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wfr[n], xfr[g][m], acc[m][g][n],
+                                                                                   0, 0, 0);
+            }
+        } else {
 #pragma unroll 1
         for (int dx = 0; dx < 3; ++dx) {
 #pragma unroll
@@ -341,14 +388,14 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
 #pragma unroll
                     for (int n = 0; n < NN; ++n) {
                         const int row = (dy * 3 + dx) * 64 + (n0 + n) * 32 + col;
-                        bfr[dy][n] = *(const bf16x8*)(wl + (size_t)row * CIN + chunk_swz<CIN>(row, q) * 8);
+                        bfr[dy][n] = *(const bf16x8*)(wl + (size_t)row * SC + chunk_swz<SC>(row, q) * 8);
                     }
 #pragma unroll
                 for (int g = 0; g < NCG; ++g)
 #pragma unroll
                     for (int rr = 0; rr < PMR + 2; ++rr) {
                         const int pix = (wv * PMR + rr) * TC + g * 32 + col + dx;
-                        afr[g][rr] = *(const bf16x8*)(buf + (size_t)pix * CIN + chunk_swz<CIN>(pix, q) * 8);
+                        afr[g][rr] = *(const bf16x8*)(buf + (size_t)pix * SC + chunk_swz<SC>(pix, q) * 8);
                     }
 #pragma unroll
                 for (int dy = 0; dy < 3; ++dy)
@@ -358,12 +405,15 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
                         for (int g = 0; g < NCG; ++g)
 #pragma unroll
                             for (int n = 0; n < NN; ++n)
-                                acc[m][g][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr[g][m + dy], bfr[dy][n],
+                                acc[m][g][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bfr[dy][n], afr[g][m + dy],
                                                                                        acc[m][g][n], 0, 0, 0);
             }
         }
+        }
 
-        // epilogue through LDS: C row = pixel column within the group, C column = channel
+        // epilogue through LDS: the weights are the MFMA's A operand, so C
+        // row = output channel, C column = pixel: a lane holds one pixel and
+        // four runs of four consecutive channels, stored as 8-byte words
         __syncthreads();   // every wave is done reading the input tile
 #pragma unroll
         for (int m = 0; m < PMR; ++m) {
@@ -372,14 +422,17 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
             for (int g = 0; g < NCG; ++g)
 #pragma unroll
                 for (int n = 0; n < NN; ++n) {
-                    const int c = (n0 + n) * 32 + col;
-                    const float bv = MODE == 1 ? 0.f : bias[c];
+                    uint16_t* o = buf + (rl * PTX + g * 32 + col) * CTS + (n0 + n) * 32 + 4 * kh;
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int px = g * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-                        float v = acc[m][g][n][r] + bv;
-                        if (MODE != 1) v = v > 0.f ? v : 0.f;
-                        buf[(rl * PTX + px) * CTS + c] = f2bf(v);
+                    for (int q4 = 0; q4 < 4; ++q4) {
+                        uint32_t h[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            float v = acc[m][g][n][4 * q4 + i] + (MODE == 1 ? 0.f : bcol[n][4 * q4 + i]);
+                            if (MODE != 1) v = v > 0.f ? v : 0.f;
+                            h[i] = f2bf(v);
+                        }
+                        *(uint2*)(o + 8 * q4) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
                     }
                 }
         }
