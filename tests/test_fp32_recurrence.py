@@ -99,3 +99,35 @@ def test_carried_form_keeps_fp32_rounding_small(case):
     assert ec < e3 / 30.0, (e3, ec)
     assert ef < 1e-6, ef
     assert ef < e3 / 30.0, (e3, ef)
+
+
+def run_paper(y0, nu, tau, s, dtype):
+    """The paper's three-term recurrence in Y itself, in the given precision."""
+    mu, nv, mut, gamt = oracle.sts_coefs(s, oracle.RKG2)
+    coefs = tuple(c.astype(dtype) for c in oracle.diff_coefs(NT, NP, nu))
+    Y0 = y0.astype(dtype)
+    ly0 = operator(coefs, Y0)
+    ym2, ym1 = Y0, Y0 + dtype(mut[1] * tau) * ly0
+    for j in range(2, s + 1):
+        y = (dtype(mu[j]) * ym1 + dtype(nv[j]) * ym2 + dtype(1.0 - mu[j] - nv[j]) * Y0 +
+             dtype(mut[j] * tau) * operator(coefs, ym1) + dtype(gamt[j] * tau) * ly0)
+        ym2, ym1 = ym1, y
+    return ym1
+
+
+def test_fp64_paper_form_drifts_and_increment_form_does_not(case):
+    """In FP64 the three-term recurrence in Y (the paper's form, which the
+    oracle evaluates) drifts from an 80-bit run of the same recurrence by far
+    more than rounding level over a ~1,000-stage call, while the carried
+    increment form stays at rounding level: the FP64 oracle's own error on
+    long calls is this drift (it grows with resolution and stage count)."""
+    y0, nu, tau, s, ref = case
+    ext = run_paper(y0, nu, tau, s, np.longdouble).astype(np.float64)
+    paper = run_paper(y0, nu, tau, s, np.float64)
+    inc = run(y0, nu, tau, s, np.float64, True, True)
+    e_paper = np.linalg.norm(paper - ext) / np.linalg.norm(ext)
+    e_inc = np.linalg.norm(inc - ext) / np.linalg.norm(ext)
+    e_oracle = np.linalg.norm(ref - ext) / np.linalg.norm(ext)
+    assert 1e-14 < e_paper < 1e-12, e_paper
+    assert e_inc < 1e-14, e_inc
+    assert abs(e_oracle - e_paper) < 0.1 * e_paper, (e_oracle, e_paper)
