@@ -12,7 +12,9 @@
 // adjacent lanes through whole-wave DPP shifts, folded into the add that
 // forms their sum; north / south inside a strip are the lane's own
 // registers, and only each strip's two end rows go through LDS (double
-// buffered by stage parity, one barrier per stage).
+// buffered by stage parity, one barrier per stage; two zero rows stand for
+// the neighbours beyond the first and last strip, so every wave reads both
+// rows without a branch).
 //
 // Tiles.  Columns: 128 - 2K owned per block, phi wrapping periodically.
 // Rows: aligned to the poles.  A staged region that ends at a pole needs no
@@ -120,7 +122,10 @@ __device__ __forceinline__ void tall_rows(int t, int n, int nt, int LY, int K, i
     }
 }
 
-template <int K, int RPT, int NW>
+// ONE: the class has a single row tile (nt <= LY), whose staged rows beyond
+// the south pole read the pole row and are set to zero; with more tiles
+// every staged row exists.
+template <int K, int RPT, int NW, bool ONE>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void diff_mixed_blocked_kernel(
     const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs, int j0,
     const DiffRow<double>* __restrict__ drow, const float* __restrict__ in1, const float* __restrict__ in2,
@@ -128,7 +133,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     double* __restrict__ B, const float* __restrict__ adv, int nt, int np)
 {
     constexpr int LX = 128, TX = LX - 2 * K, LY = NW * RPT;
-    __shared__ float xch[2][2][NW][LX];   // [stage parity][top, bottom row][wave][column]
+    // [stage parity][top, bottom row][wave + 1][column]; [.][1][0] and
+    // [.][0][NW + 1] stay zero
+    __shared__ float xch[2][2][NW + 2][LX];   // [stage parity][top, bottom row][wave][column]
     __shared__ float4 cft[K][LY];         // folded row coefficients [stage][staged row]
 
     const int nty = tall_tiles_y(nt, LY, K);
@@ -157,6 +164,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         const int i = idx / LY, row = idx - i * LY;
         cft[i][row] = fold_row(coefs[e.coef_off + j0 + i], dr[min(jl0 + row, nt - 1)]);
     }
+    for (int idx = threadIdx.x; idx < 4 * LX; idx += 64 * NW) {
+        const int q = idx / (2 * LX), h = (idx / LX) & 1, c = idx % LX;
+        xch[q][h][h ? 0 : NW + 1][c] = 0.f;
+    }
 
     const uint32_t fbytes = (uint32_t)((size_t)nt * np * 4);
     const auto r_in1 = rsrc(in1 + base, fbytes);
@@ -165,15 +176,14 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
     int kc0 = (k0 - K + 2 * lane) % np;   // even, and kc0 + 1 < np
     if (kc0 < 0) kc0 += np;
 
-    // d: the last stage's increment; ez: its last change; ly: L(Y0).  Rows
-    // beyond the south pole read the pole row and are set to zero.
+    // d: the last stage's increment; ez: its last change; ly: L(Y0)
     float d[RPT][2], ez[RPT][2], ly[RPT][2];
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
         const int j = jw + m;
-        const uint32_t so = uniform((uint32_t)min(j, nt - 1) * (uint32_t)np * 4u);
+        const uint32_t so = uniform((uint32_t)(ONE ? min(j, nt - 1) : j) * (uint32_t)np * 4u);
         const float2 a = ld2(r_in1, 4u * kc0, so), b = ld2(r_e, 4u * kc0, so), l = ld2(r_ly, 4u * kc0, so);
-        const bool in = j < nt;
+        const bool in = !ONE || j < nt;
         d[m][0] = in ? a.x : 0.f;
         d[m][1] = in ? a.y : 0.f;
         ez[m][0] = in ? b.x : 0.f;
@@ -186,11 +196,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
         const StageCoef cf = coefs[e.coef_off + j0 + i];
         const float nnu = (float)(-cf.nu), g = (float)(cf.cL + cf.cLY0);
         const int q = i & 1;
-        *(float2*)&xch[q][0][w][2 * lane] = make_float2(d[0][0], d[0][1]);
-        *(float2*)&xch[q][1][w][2 * lane] = make_float2(d[RPT - 1][0], d[RPT - 1][1]);
+        *(float2*)&xch[q][0][w + 1][2 * lane] = make_float2(d[0][0], d[0][1]);
+        *(float2*)&xch[q][1][w + 1][2 * lane] = make_float2(d[RPT - 1][0], d[RPT - 1][1]);
         __syncthreads();
-        const float2 nn = w > 0 ? *(const float2*)&xch[q][1][w - 1][2 * lane] : make_float2(0.f, 0.f);
-        const float2 ss = w < NW - 1 ? *(const float2*)&xch[q][0][w + 1][2 * lane] : make_float2(0.f, 0.f);
+        const float2 nn = *(const float2*)&xch[q][1][w][2 * lane];
+        const float2 ss = *(const float2*)&xch[q][0][w + 2][2 * lane];
         float n0 = nn.x, n1 = nn.y;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
@@ -276,8 +286,12 @@ static void launch_cfg(hipStream_t st, const Entry* ents, int n_act, const Stage
 {
     constexpr int TX = 128 - 2 * K, LY = NW * RPT;
     const int nblk = ((np + TX - 1) / TX) * tall_tiles_y(nt, LY, K) * n_act;
-    hipLaunchKernelGGL((diff_mixed_blocked_kernel<K, RPT, NW>), dim3(nblk), dim3(64 * NW), 0, st, ents, coefs,
-                       j0, drow, in1, in2, ly0, out1, out2, B, adv, nt, np);
+    if (nt <= LY)
+        hipLaunchKernelGGL((diff_mixed_blocked_kernel<K, RPT, NW, true>), dim3(nblk), dim3(64 * NW), 0, st, ents,
+                           coefs, j0, drow, in1, in2, ly0, out1, out2, B, adv, nt, np);
+    else
+        hipLaunchKernelGGL((diff_mixed_blocked_kernel<K, RPT, NW, false>), dim3(nblk), dim3(64 * NW), 0, st, ents,
+                           coefs, j0, drow, in1, in2, ly0, out1, out2, B, adv, nt, np);
 }
 
 void launch_diff_mixed_blocked(hipStream_t st, int cfg, const Entry* ents, int n_act, const StageCoef* coefs,
