@@ -32,6 +32,18 @@ __device__ __forceinline__ uint16_t f2bf(float f)
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// two floats -> packed bfloat16 bits (low = a), round to nearest even: the
+// same bits as f2bf for finite inputs, one instruction on gfx950
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf2(float a, float b)
+{
+    f32x2_t v;
+    v.x = a;
+    v.y = b;
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+
 __device__ __forceinline__ int wrapk(int k, int W)
 {
     k %= W;
@@ -425,14 +437,13 @@ __global__ __launch_bounds__(PersistShape<CIN>::NTH) void conv_persist_kernel(co
                     uint16_t* o = buf + (rl * PTX + g * 32 + col) * CTS + (n0 + n) * 32 + 4 * kh;
 #pragma unroll
                     for (int q4 = 0; q4 < 4; ++q4) {
-                        uint32_t h[4];
+                        float v[4];
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            float v = acc[m][g][n][4 * q4 + i] + (MODE == 1 ? 0.f : bcol[n][4 * q4 + i]);
-                            if (MODE != 1) v = v > 0.f ? v : 0.f;
-                            h[i] = f2bf(v);
+                            v[i] = acc[m][g][n][4 * q4 + i] + (MODE == 1 ? 0.f : bcol[n][4 * q4 + i]);
+                            if (MODE != 1) v[i] = v[i] > 0.f ? v[i] : 0.f;
                         }
-                        *(uint2*)(o + 8 * q4) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+                        *(uint2*)(o + 8 * q4) = make_uint2(pack_bf2(v[0], v[1]), pack_bf2(v[2], v[3]));
                     }
                 }
         }
