@@ -126,7 +126,7 @@ __device__ __forceinline__ void tall_rows(int t, int n, int nt, int LY, int K, i
 // the south pole read the pole row and are set to zero; with more tiles
 // every staged row exists.
 template <int K, int RPT, int NW, bool ONE>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void diff_mixed_blocked_kernel(
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 16 ? 8 : NW == 12 ? 6 : 4))) void diff_mixed_blocked_kernel(
     const Entry* __restrict__ ents, const StageCoef* __restrict__ coefs, int j0,
     const DiffRow<double>* __restrict__ drow, const float* __restrict__ in1, const float* __restrict__ in2,
     const float* __restrict__ ly0, float* __restrict__ out1, float* __restrict__ out2,
@@ -259,12 +259,16 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) vo
 
 // ------------------------------------------------------------ configurations
 // (K, rows per wave, waves); tx = 128 - 2K owned columns, ty = NW RPT - 2K
-// rows owned by an interior row tile.
+// rows owned by an interior row tile.  Twelve-wave blocks of 8-row strips
+// (78 registers) and sixteen-wave blocks of 6-row strips (62) hold the same
+// 128 x 96 region as eight waves of 12 rows, so two blocks share a compute
+// unit at six or eight waves per SIMD.
 struct MixedCfg {
     int k, rpt, nw;
 };
 static const MixedCfg kCfgMixed[] = {{8, 16, 8}, {12, 16, 8}, {6, 16, 8}, {8, 12, 8}, {12, 12, 8},
-                                     {10, 12, 8}, {8, 8, 8},  {4, 8, 8},  {8, 4, 8},  {4, 4, 8}};
+                                     {10, 12, 8}, {8, 8, 8},  {4, 8, 8},  {8, 4, 8},  {4, 4, 8},
+                                     {12, 8, 12}, {10, 8, 12}, {12, 6, 16}};
 
 int mixed_config_count() { return (int)(sizeof kCfgMixed / sizeof kCfgMixed[0]); }
 
@@ -310,7 +314,10 @@ void launch_diff_mixed_blocked(hipStream_t st, int cfg, const Entry* ents, int n
     case 6: M1(8, 8, 8); break;
     case 7: M1(4, 8, 8); break;
     case 8: M1(8, 4, 8); break;
-    default: M1(4, 4, 8); break;
+    case 9: M1(4, 4, 8); break;
+    case 10: M1(12, 8, 12); break;
+    case 11: M1(10, 8, 12); break;
+    default: M1(12, 6, 16); break;
     }
 #undef M1
 }
