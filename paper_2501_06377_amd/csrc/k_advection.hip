@@ -13,7 +13,11 @@
 // The kernels evaluate the paper's formulas with no FMA contraction (the
 // library is built with -ffp-contract=off) except that each one-sided WENO
 // value is formed with one division (the nonlinear weights' common factor
-// cancelled), which changes results only at the rounding level.
+// cancelled), which changes results only at the rounding level.  The FP32
+// increment path (MIXED) divides with the hardware reciprocal (about one
+// ulp) and lets the compiler fuse its multiply-adds in the WENO values: its
+// rounding is FP32's anyway, and the divisions were most of its vector-ALU
+// work.
 //
 // Flow attenuation (eq. flow_attenuation): the face velocities of one
 // advection advance are scaled by 1 - tanh(m/B0), m the mean of |B| over the
@@ -70,6 +74,36 @@ __device__ __forceinline__ T weno_face(T lm2, T lm1, T lm0, T lpm1, T lp0, T lpp
     T up = (v0p * p0p + v1p * p1p) / (v0p + v1p);
     return up + um;
 }
+
+// FP32: the same formulas, the division by the hardware reciprocal and the
+// multiply-adds fused.
+template <>
+__device__ __forceinline__ float weno_face<float>(float lm2, float lm1, float lm0, float lpm1, float lp0,
+                                                  float lpp1, const WenoConst<float>& c)
+{
+#pragma clang fp contract(fast)
+    const float one = 1.f, four = 4.f;
+    const float p0m = (one + c.half) * lm1 - c.half * lm2;
+    const float p1m = c.half * lm1 + c.half * lm0;
+    const float t0m = c.half * (lm1 - lm2), t1m = c.half * (lm0 - lm1);
+    const float b0m = four * t0m * t0m, b1m = four * t1m * t1m;
+    const float a2m = (c.eps + b0m) * (c.eps + b0m), bb2m = (c.eps + b1m) * (c.eps + b1m);
+    const float v0m = c.third * bb2m, v1m = c.twothird * a2m;
+    const float um = (v0m * p0m + v1m * p1m) * __builtin_amdgcn_rcpf(v0m + v1m);
+
+    const float p0p = (one + c.half) * lp0 - c.half * lpp1;
+    const float p1p = c.half * lp0 + c.half * lpm1;
+    const float t0p = c.half * (lpp1 - lp0), t1p = c.half * (lp0 - lpm1);
+    const float b0p = four * t0p * t0p, b1p = four * t1p * t1p;
+    const float a2p = (c.eps + b0p) * (c.eps + b0p), bb2p = (c.eps + b1p) * (c.eps + b1p);
+    const float v0p = c.third * bb2p, v1p = c.twothird * a2p;
+    const float up = (v0p * p0p + v1p * p1p) * __builtin_amdgcn_rcpf(v0p + v1p);
+    return up + um;
+}
+
+// a / b: exact division in FP64, the hardware reciprocal in FP32 (b > 0)
+__device__ __forceinline__ double adv_div(double a, double b) { return a / b; }
+__device__ __forceinline__ float adv_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 // Upwind face flux: F = v (1/2)[(1-uw) B_right + (1+uw) B_left], uw = sign(v).
 template <typename T>
@@ -250,8 +284,8 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
         const int tj = idx / ATX, c = idx - (idx / ATX) * ATX;
         const int j = j0 + tj, k = k0 + c;
         if (j >= nt || k >= np) continue;
-        const T dthf = (g.sf[j + 1] * fth[tj + 1][c] - g.sf[j] * fth[tj][c]) / g.den_th[j];
-        const T dphf = (fph[tj][c + 1] - fph[tj][c]) / g.den_ph[j];
+        const T dthf = adv_div(g.sf[j + 1] * fth[tj + 1][c] - g.sf[j] * fth[tj][c], g.den_th[j]);
+        const T dphf = adv_div(fph[tj][c + 1] - fph[tj][c], g.den_ph[j]);
         const T op = dthf + dphf;
         const size_t i = base + (size_t)j * np + k;
         if constexpr (MIXED) {
