@@ -4,6 +4,8 @@
 // Reductions are deterministic: every block reduces a fixed, strided set of
 // cells in a fixed tree order into a partial record, and one block per
 // realization then reduces the partials in a fixed order.  No float atomics.
+#include <algorithm>
+
 #include "sft_internal.h"
 
 namespace sft {
@@ -13,6 +15,21 @@ constexpr int RB = 256;   // threads per reduction block
 __device__ __forceinline__ double load_any(const void* p, int dtype, size_t i)
 {
     return dtype == 1 ? (double)((const float*)p)[i] : ((const double*)p)[i];
+}
+
+// F from the disk-centre cosine m of row j (eq. data_assim_f).
+__device__ __forceinline__ double weight_of_mu(const AssimReal& a, double m, int j, const double* lat_row)
+{
+    double f = 0.0;
+    if (m > a.mu_lim && fabs(lat_row[j]) < a.lat_lim_rad) {
+        if (a.alpha == 4.0) {
+            const double m2 = m * m;
+            f = m2 * m2;
+        } else {
+            f = pow(m, a.alpha);
+        }
+    }
+    return f;
 }
 
 // Weight F at cell (j, k) for realization parameters a (eq. data_assim_f).
@@ -30,16 +47,7 @@ __device__ __forceinline__ double weight_at(const AssimReal& a, const void* weig
         const double ph = (k + 0.5) * dph;
         m = sb0 * ct_row[j] + cb0 * st_row[j] * cos(ph - l0);
     }
-    double f = 0.0;
-    if (m > a.mu_lim && fabs(lat_row[j]) < a.lat_lim_rad) {
-        if (a.alpha == 4.0) {
-            const double m2 = m * m;
-            f = m2 * m2;
-        } else {
-            f = pow(m, a.alpha);
-        }
-    }
-    return f;
+    return weight_of_mu(a, m, j, lat_row);
 }
 
 // Block-wide fixed-order sum of two values into red[0], red[1].
@@ -107,7 +115,10 @@ __global__ __launch_bounds__(RB) void assim_reduce_kernel(const double* __restri
 
 // Balanced realizations: B += dB / r (dB > 0) or dB * r (dB <= 0), with dB
 // read back or, when dB is NULL, formed again exactly as the delta pass
-// formed it.  Others: B = F data + (1 - F) B.
+// formed it.  Others: B = F data + (1 - F) B.  A thread owns one column k
+// over a group of rows (block x = column chunk + RB-wide chunk count x row
+// group), so the disk weight's cos(phi_k - L0) is formed once per column
+// and group; every cell's F is the value weight_at gives.
 __global__ __launch_bounds__(RB) void assim_apply_kernel(
     const AssimReal* __restrict__ ar, const void* data, const void* weight, int dtype, int kind,
     double sb0, double cb0, double l0, double* __restrict__ B, const double* __restrict__ dB,
@@ -116,26 +127,29 @@ __global__ __launch_bounds__(RB) void assim_apply_kernel(
 {
     const int r = blockIdx.y;
     const AssimReal a = ar[r];
-    const size_t cells = (size_t)nt * np;
-    const size_t base = (size_t)r * cells;
-    for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < cells; i += (size_t)gridDim.x * RB) {
+    const size_t base = (size_t)r * nt * np;
+    const int ncx = (np + RB - 1) / RB, nry = gridDim.x / ncx;
+    const int ry = blockIdx.x / ncx, k = (blockIdx.x - ry * ncx) * RB + threadIdx.x;
+    if (k >= np || ry >= nry) return;
+    const int j0 = (int)((long)nt * ry / nry), j1 = (int)((long)nt * (ry + 1) / nry);
+    double cph = 0.0;
+    if (kind == 2) {
+        const double dph = 2.0 * M_PI / np;
+        const double ph = (k + 0.5) * dph;
+        cph = cos(ph - l0);
+    }
+    const double rr = a.balance ? ratio[r] : 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const size_t i = (size_t)j * np + k;
+        double F;
+        if (kind == 0) F = load_any(weight, dtype, i);
+        else if (kind == 1) F = weight_of_mu(a, load_any(weight, dtype, i), j, lat_row);
+        else F = weight_of_mu(a, sb0 * ct_row[j] + cb0 * st_row[j] * cph, j, lat_row);
         if (a.balance) {
-            const double rr = ratio[r];
-            double d;
-            if (dB) {
-                d = dB[base + i];
-            } else {
-                const int j = (int)(i / np), k = (int)(i - (size_t)j * np);
-                const double F = weight_at(a, weight, dtype, kind, sb0, cb0, l0, i, j, k, np, st_row, ct_row,
-                                           lat_row);
-                d = F * (load_any(data, dtype, i) - B[base + i]);
-            }
+            double d = dB ? dB[base + i] : F * (load_any(data, dtype, i) - B[base + i]);
             if (rr != 0.0) d = d > 0.0 ? d / rr : d * rr;
             B[base + i] = B[base + i] + d;
         } else {
-            const int j = (int)(i / np), k = (int)(i - (size_t)j * np);
-            const double F = weight_at(a, weight, dtype, kind, sb0, cb0, l0, i, j, k, np, st_row,
-                                       ct_row, lat_row);
             B[base + i] = F * load_any(data, dtype, i) + (1.0 - F) * B[base + i];
         }
     }
@@ -161,7 +175,11 @@ void launch_assim_apply(hipStream_t st, int R, const AssimReal* ar, const void* 
                         double* B, const double* dB, const double* ratio, const double* st_row,
                         const double* ct_row, const double* lat_row, int nblk, int nt, int np)
 {
-    hipLaunchKernelGGL(assim_apply_kernel, dim3(nblk, R), dim3(RB), 0, st, ar, data, weight, dtype,
+    // column chunks x row groups, about 2048 blocks over the class
+    (void)nblk;
+    const int ncx = (np + RB - 1) / RB;
+    int nry = (int)std::min<long>(nt, std::max<long>(1, 2048 / ((long)ncx * R)));
+    hipLaunchKernelGGL(assim_apply_kernel, dim3(ncx * nry, R), dim3(RB), 0, st, ar, data, weight, dtype,
                        kind, sb0, cb0, l0, B, dB, ratio, st_row, ct_row, lat_row, nt, np);
 }
 
