@@ -6,8 +6,10 @@
 // Owner map.  A block of NW waves stages a 128-column x LY-row region
 // (LY = NW x RPT): lane l holds columns 2l and 2l + 1, wave w the RPT rows
 // w RPT .. w RPT + RPT - 1.  Per cell the increment d, its last change e and
-// L(Y0) live in registers (3 x 2 x RPT values per lane); a row's new values
-// overwrite its old ones once the next row has read them.  The west
+// L(Y0) live in registers (3 x 2 x RPT values per lane).  A stage first
+// forms every row's new change e in place (each reads the old d of its
+// neighbours), then adds the changes to the increments, so no row's old
+// value has to be kept aside while its neighbour reads it.  The west
 // neighbour of column 0 and the east neighbour of column 1 come from the
 // adjacent lanes through whole-wave DPP shifts, folded into the add that
 // forms their sum; north / south inside a strip are the lane's own
@@ -22,10 +24,12 @@
 // [0, LY) and owns [0, LY - K), the last stages [nt - LY, nt) and owns from
 // its start + K to nt, and the ones between stage [o - K, o + TY + K) and own
 // [o, o + TY), TY = LY - 2K.  The staged values next to a non-pole edge go
-// stale one row per stage (the rows beyond read as zero: a stable, bounded
-// error), so after k <= K stages the owned rows are exact.  Every staged
-// row is updated at every stage: skipping the stale ones would put a branch
-// around each row's in-place update.  With
+// stale one row per stage (the rows beyond read as zero), so after k <= K
+// stages the owned rows are exact.  Stage i forms no change for the rows it
+// leaves stale (a scalar row mask per strip and stage; a skipped row adds
+// its previous change, a value no exact row reads again): the stale band
+// of a K-stage launch is about K rows at each non-pole edge.  The stale
+// columns cannot be skipped (they are lanes of the same wave).  With
 // nt <= LY one tile holds the whole sphere plus rows beyond the south pole,
 // which start at zero, take the pole row's coefficients and meet the pole
 // row only through its zero pole-face coefficient.
@@ -192,32 +196,44 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 1
         ly[m][1] = in ? l.y : 0.f;
     }
 
+    // a staged edge that is not a pole loses one exact row per stage: stage
+    // i leaves rows [0, i] (top) and [LY - 1 - i, LY) (bottom) stale
+    const bool top = nty > 1 && by > 0, bot = nty > 1 && by < nty - 1;
     for (int i = 0; i < kk; ++i) {
         const StageCoef cf = coefs[e.coef_off + j0 + i];
         const float nnu = (float)(-cf.nu), g = (float)(cf.cL + cf.cLY0);
         const int q = i & 1;
+        const int rlo = top ? i + 1 : 0, rhi = bot ? LY - 1 - i : LY;
         *(float2*)&xch[q][0][w + 1][2 * lane] = make_float2(d[0][0], d[0][1]);
         *(float2*)&xch[q][1][w + 1][2 * lane] = make_float2(d[RPT - 1][0], d[RPT - 1][1]);
         __syncthreads();
         const float2 nn = *(const float2*)&xch[q][1][w][2 * lane];
         const float2 ss = *(const float2*)&xch[q][0][w + 2][2 * lane];
-        float n0 = nn.x, n1 = nn.y;
+        // rows m of this strip with rlo <= w RPT + m < rhi, as a scalar mask
+        const int mlo = max(rlo - w * RPT, 0), mhi = min(rhi - w * RPT, RPT);
+        const uint32_t vm = mlo < mhi ? ((1u << mhi) - 1u) & ~((1u << mlo) - 1u) : 0u;
+        // the changes first (each reads the old d of its neighbours and
+        // replaces its own e), then the increments of every row: a skipped
+        // row adds its previous change, a value no exact row reads again
+        // the strip's coefficient rows through one vector address (a scalar
+        // one is copied to a vector register again in every branch)
+        const float4* cr = &cft[i][0] + (threadIdx.x >> 6) * RPT;
 #pragma unroll
         for (int m = 0; m < RPT; ++m) {
-            const float4 f = cft[i][w * RPT + m];
+            if (!(vm & (1u << m))) continue;
+            const float4 f = cr[m];
             const float c0 = d[m][0], c1 = d[m][1];
-            const float s0 = m < RPT - 1 ? d[m + 1][0] : ss.x;
-            const float s1 = m < RPT - 1 ? d[m + 1][1] : ss.y;
+            const float n0 = m > 0 ? d[m - 1][0] : nn.x, n1 = m > 0 ? d[m - 1][1] : nn.y;
+            const float s0 = m < RPT - 1 ? d[m + 1][0] : ss.x, s1 = m < RPT - 1 ? d[m + 1][1] : ss.y;
             // column 0: west = column 1 of the lane before; column 1: east =
             // column 0 of the lane after (zero past the wave)
-            const float e0 = sts_fold(f, nnu, g, lane_west(c1) + c1, n0, c0, s0, ez[m][0], ly[m][0]);
-            const float e1 = sts_fold(f, nnu, g, c0 + lane_east(c0), n1, c1, s1, ez[m][1], ly[m][1]);
-            ez[m][0] = e0;
-            ez[m][1] = e1;
-            d[m][0] = c0 + e0;
-            d[m][1] = c1 + e1;
-            n0 = c0;
-            n1 = c1;
+            ez[m][0] = sts_fold(f, nnu, g, lane_west(c1) + c1, n0, c0, s0, ez[m][0], ly[m][0]);
+            ez[m][1] = sts_fold(f, nnu, g, c0 + lane_east(c0), n1, c1, s1, ez[m][1], ly[m][1]);
+        }
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) {
+            d[m][0] += ez[m][0];
+            d[m][1] += ez[m][1];
         }
     }
 
@@ -259,16 +275,20 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 1
 
 // ------------------------------------------------------------ configurations
 // (K, rows per wave, waves); tx = 128 - 2K owned columns, ty = NW RPT - 2K
-// rows owned by an interior row tile.  Twelve-wave blocks of 8-row strips
-// (78 registers) and sixteen-wave blocks of 6-row strips (62) hold the same
-// 128 x 96 region as eight waves of 12 rows, so two blocks share a compute
-// unit at six or eight waves per SIMD.
+// rows owned by an interior row tile.  Sixteen-wave blocks of 6-row strips
+// (52 registers) hold 128 x 96 cells, of 8-row strips (63) 128 x 128, two
+// blocks per compute unit at eight waves per SIMD.  A launch's loads and
+// stores take a fixed share of its time that more stages per launch spread
+// over more work, while the halo grows with K: 14 to 18 stages on the
+// 128 x 128 region balance the two on 1024 x 2048 grids.
 struct MixedCfg {
     int k, rpt, nw;
 };
 static const MixedCfg kCfgMixed[] = {{8, 16, 8}, {12, 16, 8}, {6, 16, 8}, {8, 12, 8}, {12, 12, 8},
                                      {10, 12, 8}, {8, 8, 8},  {4, 8, 8},  {8, 4, 8},  {4, 4, 8},
-                                     {12, 8, 12}, {10, 8, 12}, {12, 6, 16}};
+                                     {12, 8, 12}, {10, 8, 12}, {12, 6, 16}, {14, 6, 16}, {16, 6, 16},
+                                     {18, 6, 16}, {16, 8, 12}, {12, 8, 16}, {16, 8, 16}, {18, 8, 16},
+                                     {20, 8, 16}, {14, 8, 16}};
 
 int mixed_config_count() { return (int)(sizeof kCfgMixed / sizeof kCfgMixed[0]); }
 
@@ -317,7 +337,16 @@ void launch_diff_mixed_blocked(hipStream_t st, int cfg, const Entry* ents, int n
     case 9: M1(4, 4, 8); break;
     case 10: M1(12, 8, 12); break;
     case 11: M1(10, 8, 12); break;
-    default: M1(12, 6, 16); break;
+    case 12: M1(12, 6, 16); break;
+    case 13: M1(14, 6, 16); break;
+    case 14: M1(16, 6, 16); break;
+    case 15: M1(18, 6, 16); break;
+    case 16: M1(16, 8, 12); break;
+    case 17: M1(12, 8, 16); break;
+    case 18: M1(16, 8, 16); break;
+    case 19: M1(18, 8, 16); break;
+    case 20: M1(20, 8, 16); break;
+    default: M1(14, 8, 16); break;
     }
 #undef M1
 }

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -868,6 +869,9 @@ sft_status choose_tile(sft_ctx* c, GridClass* g)
             launch_diff_stage_mixed(c->stream, d_ents, R, d_coefs, 10, g->dr64, g->B, g->A[0], g->A[1],
                                     g->A[2], g->A[3], g->A[4], g->A[2], nt, np);
         }, 4);
+    // SFT_TUNE_LOG set: the candidates' times per stage go to stderr
+    const bool log = std::getenv("SFT_TUNE_LOG") != nullptr;
+    if (log) std::fprintf(stderr, "sft tile tuning %dx%d x%d: one stage per launch %.2f us\n", nt, np, R, 1e3f * best);
     for (int cfg = 0; cfg < fused_config_count(mixed); ++cfg) {
         const int K = fused_config_k(mixed, cfg);
         float t;
@@ -881,6 +885,7 @@ sft_status choose_tile(sft_ctx* c, GridClass* g)
                 launch_diff_fused(c->stream, true, cfg, d_ents, R, d_coefs, 10, g->dr64, g->A[1],
                                   g->A[2], nullptr, g->A[3], g->A[4], g->A[5], g->B, g->A[0], nt, np);
             }, 3);
+        if (log) std::fprintf(stderr, "  tile %2d (K %2d): %.2f us per stage\n", cfg, K, 1e3f * t / K);
         if (t / K < best) {
             best = t / K;
             best_cfg = cfg;
