@@ -162,11 +162,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 1
     const int jw = jl0 + w * RPT;   // global row of the strip's first cell
 
     // folded coefficients of the kk stages for every staged row (rows beyond
-    // the south pole take the pole row's)
+    // the south pole take the pole row's): a thread per row, the stage's
+    // coefficients scalar loads
     const DiffRow<double>* dr = drow + (size_t)e.r * nt;
-    for (int idx = threadIdx.x; idx < kk * LY; idx += 64 * NW) {
-        const int i = idx / LY, row = idx - i * LY;
-        cft[i][row] = fold_row(coefs[e.coef_off + j0 + i], dr[min(jl0 + row, nt - 1)]);
+    for (int row = threadIdx.x; row < LY; row += 64 * NW) {
+        const DiffRow<double> rr = dr[min(jl0 + row, nt - 1)];
+        for (int i = 0; i < kk; ++i) cft[i][row] = fold_row(coefs[e.coef_off + j0 + i], rr);
     }
     for (int idx = threadIdx.x; idx < 4 * LX; idx += 64 * NW) {
         const int q = idx / (2 * LX), h = (idx / LX) & 1, c = idx % LX;
