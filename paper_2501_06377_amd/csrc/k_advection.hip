@@ -5,7 +5,8 @@
 // combination (Sec. "Advection temporal schemes"), fused in one LDS-tiled
 // kernel per stage.
 //
-// Tile: ATY rows x ATX columns of output cells per 256-thread block, staged
+// Tile: TY rows x ATX columns of output cells per 256-thread block (TY =
+// PLAIN_TY for the static flow, ATT_TY for the attenuated one), staged
 // in LDS with a 2-cell halo (WENO3 needs cells i-2..i+1 for face i-1/2); phi
 // wraps periodically, rows outside the sphere are never used by a face flux
 // (pole faces carry no flux, pole-adjacent faces are upwind).
@@ -32,10 +33,12 @@
 namespace sft {
 
 constexpr int ATX = 64;
-constexpr int ATY = 8;
 constexpr int AH = 2;
 constexpr int AW = ATX + 2 * AH;
-constexpr int AHT = ATY + 2 * AH;
+// tile rows: the static-flow kernels stage 1.25x their output rows; the
+// attenuated kernels keep four face and factor arrays in LDS as well
+constexpr int PLAIN_TY = 16;
+constexpr int ATT_TY = 8;
 
 __device__ __forceinline__ int wrap_col(int k, int np)
 {
@@ -116,19 +119,18 @@ __device__ __forceinline__ T upwind_face(T v, T bl, T br)
 }
 
 // LDS of the attenuated-flow variant: phi faces k0-4 .. k0+ATX+4 of the tile
-// rows, theta faces j0-4 .. j0+ATY+4 of the tile columns, and per-cell LLF
+// rows, theta faces j0-4 .. j0+TY+4 of the tile columns, and per-cell LLF
 // split factors of the staged cells.
 constexpr int AVW = ATX + 9;
-constexpr int AVH = ATY + 9;
-template <typename T, bool ATT>
+template <typename T, bool ATT, int TY>
 struct AttLds {
 };
-template <typename T>
-struct AttLds<T, true> {
-    T vp[ATY][AVW];
-    T vt[AVH][ATX];
-    T cpM[ATY][AW], cpP[ATY][AW];
-    T ctM[AHT][ATX], ctP[AHT][ATX];
+template <typename T, int TY>
+struct AttLds<T, true, TY> {
+    T vp[TY][AVW];
+    T vt[TY + 9][ATX];
+    T cpM[TY][AW], cpP[TY][AW];
+    T ctM[TY + 2 * AH][ATX], ctP[TY + 2 * AH][ATX];
 };
 
 // MIXED = false: T = double, stage values read from fin (FP64 fields).
@@ -137,18 +139,19 @@ struct AttLds<T, true> {
 // ATT = true   : face velocities from vphf / vthf ([R][nt][np] each: phi face
 //                k of row j lies between cells k-1 and k; theta face j lies
 //                between rows j-1 and j) instead of the per-row constants.
-template <typename T, bool MIXED, bool ATT>
+template <typename T, bool MIXED, bool ATT, int TY>
 __global__ __launch_bounds__(256) void adv_stage_kernel(
     const Entry* __restrict__ ents, int stage, int time_scheme, int upwind,
     const AdvRow<T>* __restrict__ rows, Geom<T> g, WenoConst<T> wth, WenoConst<T> wph,
     const double* __restrict__ fn, const T* __restrict__ fin, T* __restrict__ fout,
     const T* __restrict__ vphf, const T* __restrict__ vthf, int nt, int np)
 {
+    constexpr int ATY = TY, AHT = TY + 2 * AH, AVH = TY + 9;
     __shared__ T tile[AHT][AW];
     __shared__ T fph[ATY][ATX + 1];
     __shared__ T fth[ATY + 1][ATX];
     __shared__ T cthM[AHT], cthP[AHT];
-    __shared__ AttLds<T, ATT> al;
+    __shared__ AttLds<T, ATT, TY> al;
 
     const Entry e = ents[blockIdx.z];
     const size_t base = (size_t)e.r * nt * np;
@@ -464,8 +467,8 @@ void launch_adv_stage_f64(hipStream_t st, const Entry* ents, int n_ent, int stag
                           WenoConst<double> wth, WenoConst<double> wph, const double* fn,
                           const double* fin, double* fout, int nt, int np)
 {
-    dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
-    hipLaunchKernelGGL((adv_stage_kernel<double, false, false>), grid, dim3(256), 0, st, ents, stage,
+    dim3 grid((np + ATX - 1) / ATX, (nt + PLAIN_TY - 1) / PLAIN_TY, n_ent);
+    hipLaunchKernelGGL((adv_stage_kernel<double, false, false, PLAIN_TY>), grid, dim3(256), 0, st, ents, stage,
                        time_scheme, upwind, rows, g, wth, wph, fn, fin, fout, nullptr, nullptr, nt,
                        np);
 }
@@ -475,8 +478,8 @@ void launch_adv_stage_mixed(hipStream_t st, const Entry* ents, int n_ent, int st
                             WenoConst<float> wth, WenoConst<float> wph, double* fn,
                             const float* din, float* dout, int nt, int np)
 {
-    dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
-    hipLaunchKernelGGL((adv_stage_kernel<float, true, false>), grid, dim3(256), 0, st, ents, stage,
+    dim3 grid((np + ATX - 1) / ATX, (nt + PLAIN_TY - 1) / PLAIN_TY, n_ent);
+    hipLaunchKernelGGL((adv_stage_kernel<float, true, false, PLAIN_TY>), grid, dim3(256), 0, st, ents, stage,
                        time_scheme, upwind, rows, g, wth, wph, fn, din, dout, nullptr, nullptr, nt, np);
 }
 
@@ -504,8 +507,8 @@ void launch_adv_stage_att_f64(hipStream_t st, const Entry* ents, int n_ent, int 
                               const double* fn, const double* fin, double* fout, const double* vphf,
                               const double* vthf, int nt, int np)
 {
-    dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
-    hipLaunchKernelGGL((adv_stage_kernel<double, false, true>), grid, dim3(256), 0, st, ents, stage,
+    dim3 grid((np + ATX - 1) / ATX, (nt + ATT_TY - 1) / ATT_TY, n_ent);
+    hipLaunchKernelGGL((adv_stage_kernel<double, false, true, ATT_TY>), grid, dim3(256), 0, st, ents, stage,
                        time_scheme, upwind, rows, g, wth, wph, fn, fin, fout, vphf, vthf, nt, np);
 }
 
@@ -515,8 +518,8 @@ void launch_adv_stage_att_mixed(hipStream_t st, const Entry* ents, int n_ent, in
                                 double* fn, const float* din, float* dout, const float* vphf,
                                 const float* vthf, int nt, int np)
 {
-    dim3 grid((np + ATX - 1) / ATX, (nt + ATY - 1) / ATY, n_ent);
-    hipLaunchKernelGGL((adv_stage_kernel<float, true, true>), grid, dim3(256), 0, st, ents, stage,
+    dim3 grid((np + ATX - 1) / ATX, (nt + ATT_TY - 1) / ATT_TY, n_ent);
+    hipLaunchKernelGGL((adv_stage_kernel<float, true, true, ATT_TY>), grid, dim3(256), 0, st, ents, stage,
                        time_scheme, upwind, rows, g, wth, wph, fn, din, dout, vphf, vthf, nt, np);
 }
 
