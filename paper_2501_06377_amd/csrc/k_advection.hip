@@ -151,6 +151,11 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
     __shared__ T fph[ATY][ATX + 1];
     __shared__ T fth[ATY + 1][ATX];
     __shared__ T cthM[AHT], cthP[AHT];
+    // per tile row: phi split factors, v_phi, sin(theta) dphi; per theta
+    // face j0 .. j0 + TY: v_theta, sin at the face, and the row's
+    // sin(theta) dtheta
+    __shared__ T rph[ATY][4];
+    __shared__ T rth[ATY + 1][3];
     __shared__ AttLds<T, ATT, TY> al;
 
     const Entry e = ents[blockIdx.z];
@@ -159,22 +164,97 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
     const AdvRow<T>* rw = rows + (size_t)e.r * (nt + 1);
     const int tid = threadIdx.x;
 
-    for (int idx = tid; idx < AHT * AW; idx += 256) {
+    // per-row constants into registers first (their loads overlap the tile's)
+    T q0 = T(0), q1 = T(0), q2 = T(0), q3 = T(0), q4 = T(0), q5 = T(0), q6 = T(0);
+    if (tid < ATY + 1) {
+        const int j = j0 + tid;
+        if (j < nt) {
+            q0 = rw[j].cphM;
+            q1 = rw[j].cphP;
+            q2 = rw[j].vph;
+            q3 = g.den_ph[j];
+            q6 = g.den_th[j];
+        }
+        if (j <= nt) {
+            q4 = rw[j].vth;
+            q5 = g.sf[j];
+        }
+    } else if (!ATT && tid >= 64 && tid < 64 + AHT) {
+        const int j = j0 + tid - 64 - AH;
+        if (j >= 0 && j < nt) {
+            q0 = rw[j].cthM;
+            q1 = rw[j].cthP;
+        }
+    }
+
+    // the staged cells: every load issued before any is waited for (rows
+    // beyond the poles read a pole row and are set to zero)
+    constexpr int NL = (AHT * AW + 255) / 256;
+    size_t si[NL];
+    bool sin[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int idx = min(tid + 256 * u, AHT * AW - 1);
         const int tj = idx / AW, tk = idx - (idx / AW) * AW;
         const int j = j0 + tj - AH;
-        const int k = wrap_col(k0 + tk - AH, np);
-        T v = T(0);
-        if (j >= 0 && j < nt) {
-            const size_t i = base + (size_t)j * np + k;
-            if constexpr (MIXED) {
-                double x = fn[i];
-                if (stage > 0) x += (double)fin[i];
-                v = (T)x;
-            } else {
-                v = fin[i];
-            }
+        si[u] = base + (size_t)min(max(j, 0), nt - 1) * np + wrap_col(k0 + tk - AH, np);
+        sin[u] = j >= 0 && j < nt;
+    }
+    T sv[NL];
+    if constexpr (MIXED) {
+        double x[NL];
+#pragma unroll
+        for (int u = 0; u < NL; ++u) x[u] = fn[si[u]];
+        if (stage > 0) {
+            float f[NL];
+#pragma unroll
+            for (int u = 0; u < NL; ++u) f[u] = fin[si[u]];
+#pragma unroll
+            for (int u = 0; u < NL; ++u) x[u] += (double)f[u];
         }
-        tile[tj][tk] = v;
+#pragma unroll
+        for (int u = 0; u < NL; ++u) sv[u] = sin[u] ? (T)x[u] : T(0);
+    } else {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) sv[u] = fin[si[u]];
+#pragma unroll
+        for (int u = 0; u < NL; ++u) sv[u] = sin[u] ? sv[u] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int idx = tid + 256 * u;
+        if (idx < AHT * AW) tile[idx / AW][idx - (idx / AW) * AW] = sv[u];
+    }
+    if (tid < ATY + 1) {
+        if (tid < ATY) {
+            rph[tid][0] = q0;
+            rph[tid][1] = q1;
+            rph[tid][2] = q2;
+            rph[tid][3] = q3;
+        }
+        rth[tid][0] = q4;
+        rth[tid][1] = q5;
+        rth[tid][2] = q6;
+    } else if (!ATT && tid >= 64 && tid < 64 + AHT) {
+        cthM[tid - 64] = q0;
+        cthP[tid - 64] = q1;
+    }
+    // what the stage combination reads besides the fluxes (MIXED: the
+    // increment of the stage input; FP64: the state fn), loaded now so the
+    // flux work hides its latency
+    constexpr int NO = ATY * ATX / 256;
+    static_assert(NO * 256 == ATY * ATX, "whole rows of output cells per thread pass");
+    T pre[NO];
+    const bool need = MIXED ? (stage > 0 && time_scheme != 1)
+                            : ((time_scheme == 2 && stage > 0) || (time_scheme == 0 && stage == 2));
+    if (need) {
+#pragma unroll
+        for (int u = 0; u < NO; ++u) {
+            const int idx = tid + 256 * u, tj = idx / ATX, c = idx - (idx / ATX) * ATX;
+            const size_t i = base + (size_t)min(j0 + tj, nt - 1) * np + min(k0 + c, np - 1);
+            if constexpr (MIXED) pre[u] = fin[i];
+            else pre[u] = (T)fn[i];
+        }
     }
     if constexpr (ATT) {
         for (int idx = tid; idx < ATY * AVW; idx += 256) {
@@ -194,15 +274,6 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
             else if (f > 0 && f < nt) v = vthf[base + (size_t)f * np + wrap_col(k0 + c, np)];
             al.vt[q][c] = v;
         }
-    } else if (tid < AHT) {
-        const int j = j0 + tid - AH;
-        T m = T(0), p = T(0);
-        if (j >= 0 && j < nt) {
-            m = rw[j].cthM;
-            p = rw[j].cthP;
-        }
-        cthM[tid] = m;
-        cthP[tid] = p;
     }
     __syncthreads();
     if constexpr (ATT) {
@@ -244,12 +315,11 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
                                   t[3] * p[3], wph);
                 }
             } else {
-                const AdvRow<T> a = rw[j];
+                const T cm = rph[tj][0], cp = rph[tj][1];
                 if (upwind) {
-                    F = upwind_face(a.vph, t[1], t[2]);
+                    F = upwind_face(rph[tj][2], t[1], t[2]);
                 } else {
-                    F = weno_face(t[0] * a.cphM, t[1] * a.cphM, t[2] * a.cphM, t[1] * a.cphP,
-                                  t[2] * a.cphP, t[3] * a.cphP, wph);
+                    F = weno_face(t[0] * cm, t[1] * cm, t[2] * cm, t[1] * cp, t[2] * cp, t[3] * cp, wph);
                 }
             }
         }
@@ -265,7 +335,7 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
             const T bm1 = tile[fj + 1][tc], b0 = tile[fj + 2][tc];   // rows f-1, f
             if (upwind || f == 1 || f == nt - 1) {
                 if constexpr (ATT) F = upwind_face(al.vt[fj + 4][c], bm1, b0);
-                else F = upwind_face(rw[f].vth, bm1, b0);
+                else F = upwind_face(rth[fj][0], bm1, b0);
             } else {
                 const T bm2 = tile[fj][tc], bp1 = tile[fj + 3][tc];  // rows f-2, f+1
                 if constexpr (ATT) {
@@ -283,12 +353,13 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
     __syncthreads();
 
     const T hdt = T(0.5) * (T)e.dt;
-    for (int idx = tid; idx < ATY * ATX; idx += 256) {
-        const int tj = idx / ATX, c = idx - (idx / ATX) * ATX;
+#pragma unroll
+    for (int u = 0; u < NO; ++u) {
+        const int idx = tid + 256 * u, tj = idx / ATX, c = idx - (idx / ATX) * ATX;
         const int j = j0 + tj, k = k0 + c;
         if (j >= nt || k >= np) continue;
-        const T dthf = adv_div(g.sf[j + 1] * fth[tj + 1][c] - g.sf[j] * fth[tj][c], g.den_th[j]);
-        const T dphf = adv_div(fph[tj][c + 1] - fph[tj][c], g.den_ph[j]);
+        const T dthf = adv_div(rth[tj + 1][1] * fth[tj + 1][c] - rth[tj][1] * fth[tj][c], rth[tj][2]);
+        const T dphf = adv_div(fph[tj][c + 1] - fph[tj][c], rph[tj][3]);
         const T op = dthf + dphf;
         const size_t i = base + (size_t)j * np + k;
         if constexpr (MIXED) {
@@ -300,16 +371,16 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
                 // SSPRK(3,3) in increments of fn: d1 = -dt A, d2 = d1/4 - (dt/4) A,
                 // d3 = 2 d2/3 - (2 dt/3) A
                 if (stage == 0) d = -(dt * op);
-                else if (stage == 1) d = T(0.25) * fin[i] - (T(0.25) * dt) * op;
-                else d = (T(2) / T(3)) * fin[i] - ((T(2) / T(3)) * dt) * op;
+                else if (stage == 1) d = T(0.25) * pre[u] - (T(0.25) * dt) * op;
+                else d = (T(2) / T(3)) * pre[u] - ((T(2) / T(3)) * dt) * op;
             } else if (stage == 0) {
                 d = -(hdt * op);
             } else if (stage == 1) {
-                d = fin[i] - hdt * op;
+                d = pre[u] - hdt * op;
             } else if (stage == 2) {
-                d = (T(1) / T(3)) * fin[i] - ((T(1) / T(6)) * dt) * op;
+                d = (T(1) / T(3)) * pre[u] - ((T(1) / T(6)) * dt) * op;
             } else {
-                d = fin[i] - hdt * op;
+                d = pre[u] - hdt * op;
             }
             fout[i] = d;
         } else {
@@ -322,10 +393,10 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
                 // SSPRK(3,3): f1 = fn - dt A(fn), f2 = 3/4 fn + 1/4 f1 - 1/4 dt A(f1),
                 // fn+1 = 1/3 fn + 2/3 f2 - 2/3 dt A(f2)
                 if (stage == 0) v = cur - dt * op;
-                else if (stage == 1) v = 0.75 * (T)fn[i] + 0.25 * cur - 0.25 * dt * op;
-                else v = (T(1) / T(3)) * (T)fn[i] + (T(2) / T(3)) * cur - (T(2) / T(3)) * dt * op;
+                else if (stage == 1) v = 0.75 * pre[u] + 0.25 * cur - 0.25 * dt * op;
+                else v = (T(1) / T(3)) * pre[u] + (T(2) / T(3)) * cur - (T(2) / T(3)) * dt * op;
             } else if (stage == 2) {
-                v = (T(2) / T(3)) * (T)fn[i] + (T(1) / T(3)) * cur - ((T(1) / T(6)) * dt) * op;
+                v = (T(2) / T(3)) * pre[u] + (T(1) / T(3)) * cur - ((T(1) / T(6)) * dt) * op;
             } else {
                 v = cur - hdt * op;
             }
