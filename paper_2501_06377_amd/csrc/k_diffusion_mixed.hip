@@ -35,8 +35,9 @@
 // row only through its zero pole-face coefficient.
 //
 // Coefficients.  The block folds the stage coefficients into its rows once
-// (fold_row, FP64 rounded to FP32) into an LDS table of K x LY quads, read
-// back as wave-wide broadcasts.  The unfused stage kernel uses the same
+// (fold_row, FP64 rounded to FP32; one thread per staged row, so all other
+// waves issue their field loads at once) into an LDS table of K x LY quads,
+// read back as wave-wide broadcasts.  The unfused stage kernel uses the same
 // fold_row and sts_fold, so every configuration gives the same bits.
 //
 // Memory.  Fields are addressed through buffer resources based at the
