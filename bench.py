@@ -95,6 +95,9 @@ def parse():
                     help="precision workload: skip the FP64 run that the FP32-mixed result is compared with")
     ap.add_argument("--sts-fuse", type=int, default=0, choices=(0, 1),
                     help="1: one diffusion stage per launch (the unfused kernel)")
+    ap.add_argument("--class-tiles", default=None,
+                    help="comma-separated diffusion tile shape per grid class, in class order "
+                         "(sft_set_class_tile; -1 = one stage per launch), instead of the autotuner's")
     ap.add_argument("--att-cfl", type=int, default=0, choices=(0, 1),
                     help="with --att-b0: 1 = per-step CFL limit of the attenuated flow")
     ap.add_argument("--obs", choices=("truth", "sheared"), default="truth",
@@ -674,10 +677,17 @@ def main():
     R = w.n_real
     okw = dict(sts_fuse=args.sts_fuse, att_cfl=args.att_cfl)
 
+    class_tiles = [int(x) for x in args.class_tiles.split(",")] if args.class_tiles else None
+    if class_tiles is not None and len(class_tiles) != len(w.classes):
+        raise SystemExit(f"--class-tiles needs {len(w.classes)} values, one per grid class")
+
     def make(lanes, tile=None):
         e = sft.Ensemble(precision=prec, use_graphs=1 if graphs and not in_region else 0,
                          sts_tile=args.sts_tile if tile is None else tile, lanes=lanes, **rfe_gpu, **okw)
-        return e, [e.add_grid(nt, np_, reals) for nt, np_, reals in w.classes]
+        gids = [e.add_grid(nt, np_, reals) for nt, np_, reals in w.classes]
+        for g, t in zip(gids, class_tiles or []):
+            e.set_class_tile(g, t)
+        return e, gids
 
     def run(ens, gids, n_steps):
         for h in range(1, n_steps + 1):

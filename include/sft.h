@@ -426,6 +426,18 @@ sft_status sft_tile_info(int32_t precision, int32_t index, int32_t* tx, int32_t*
  * first advance. */
 sft_status sft_tile_choice(sft_ctx* ctx, int32_t grid_id, int32_t* index);
 
+/* Fixes the diffusion-stage kernel of one grid class: blocked tile shape
+ * `index` of the context's precision (see sft_tile_info), or -1 for one
+ * stage per launch, in place of the autotuner's choice (and of the sts_tile
+ * and sts_fuse options) for that class from the next advance on.  Cached
+ * plans and captured graphs are dropped.  Every shape computes bitwise the
+ * same fields; only speed changes (a caller that needs reproducible launch
+ * shapes per class, for instance under a profiler, fixes them here).
+ * Errors: SFT_ERR_ARG (bad grid or index), SFT_ERR_UNSUPPORTED (a blocked
+ * FP32 shape on a class whose FP64 state needs 32-bit byte offsets beyond
+ * 2^32). */
+sft_status sft_set_class_tile(sft_ctx* ctx, int32_t grid_id, int32_t index);
+
 /* Releases the context and its device memory (after waiting for its work). */
 sft_status sft_destroy(sft_ctx* ctx);
 

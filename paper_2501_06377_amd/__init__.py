@@ -176,6 +176,9 @@ class Ensemble:
         self._chk(self.L.sft_tile_choice(self.ctx, gid, ctypes.byref(v)), "sft_tile_choice")
         return v.value
 
+    def set_class_tile(self, gid: int, index: int):
+        self._chk(self.L.sft_set_class_tile(self.ctx, gid, int(index)), "sft_set_class_tile")
+
     def close(self):
         if self.ctx:
             self.L.sft_destroy(self.ctx)

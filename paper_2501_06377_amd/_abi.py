@@ -85,6 +85,7 @@ SIGNATURES = {
     "sft_get_timing": (_I, [_P, _I, ctypes.POINTER(_D), _PI64, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "sft_tile_info": (_I, [_I, _I, _PI, _PI, _PI, _PI]),
     "sft_tile_choice": (_I, [_P, _I, _PI]),
+    "sft_set_class_tile": (_I, [_P, _I, _I]),
     "sft_destroy": (_I, [_P]),
     "sft_net_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, _P]),
     "sft_net_param_count": (_I, [_P, _PI64]),

@@ -2134,6 +2134,20 @@ sft_status sft_tile_choice(sft_ctx* c, int32_t gid, int32_t* index)
     return SFT_OK;
 }
 
+sft_status sft_set_class_tile(sft_ctx* c, int32_t gid, int32_t index)
+{
+    if (!c || gid < 0 || gid >= (int)c->grids.size()) return SFT_ERR_ARG;
+    const bool mixed = c->opt.precision == SFT_FP32_MIXED;
+    if (index < -1 || index >= fused_config_count(mixed)) return fail(c, SFT_ERR_ARG, "bad tile index %d", index);
+    GridClass* g = c->grids[gid];
+    if (mixed && index >= 0 && g->cells() * sizeof(double) > 0xFFFFFFFFull)
+        return fail(c, SFT_ERR_UNSUPPORTED, "blocked FP32 stages need nt*np*8 < 2^32 bytes (grid %dx%d)", g->nt,
+                    g->np);
+    drop_plans(c);
+    g->tile = index;
+    return SFT_OK;
+}
+
 sft_status sft_destroy(sft_ctx* c)
 {
     if (!c) return SFT_ERR_ARG;

@@ -276,6 +276,46 @@ def test_uneven_classes_in_one_context(prec, graphs):
             assert prec == 0 or max_rel(got[c][r], ref[r]) <= TOL32
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_class_tiles_bitwise_equal_autotuned(prec):
+    """sft_set_class_tile fixes each class's diffusion kernel (a blocked shape,
+    one stage per launch, another blocked shape) after a first advance has
+    captured graphs with the autotuner's choices: the fields stay bitwise
+    those of the autotuned run, the choices read back, and an index past the
+    table is refused."""
+    import paper_2501_06377_amd as sft
+    say(f"case per-class tiles precision {prec}")
+    classes = [(24, 48, reals_mix(2)), (40, 80, reals_mix(3)), (64, 128, reals_mix(2, nu=(900.0, 300.0)))]
+    fields = [np.stack([random_field(nt, np_, 6, 190 + 10 * c + i) for i in range(len(rs))])
+              for c, (nt, np_, rs) in enumerate(classes)]
+    hours = [1.0, 2.0, 3.5]
+    ref, _ = run_classes(classes, fields, hours, precision=prec, use_graphs=1)
+    n = 0
+    while sft.tile_info(prec, n) is not None:
+        n += 1
+    pick = [n - 1, -1, 0]
+    ens = sft.Ensemble(precision=prec, use_graphs=1)
+    gids = []
+    for (nt, np_, rs), B0 in zip(classes, fields):
+        g = ens.add_grid(nt, np_, rs)
+        ens.set_states(g, B0)
+        gids.append(g)
+    ens.advance(hours[0])
+    for g, t in zip(gids, pick):
+        ens.set_class_tile(g, t)
+    for h in hours[1:]:
+        ens.advance(h)
+    for g, t, (nt, np_, _), want in zip(gids, pick, classes, ref):
+        assert ens.tile_choice(g) == t
+        same = np.array_equal(ens.get_states(g), want)
+        say(f"  class {nt}x{np_} tile {t}: bitwise {same}")
+        assert same
+    with pytest.raises(sft.SftError):
+        ens.set_class_tile(gids[0], n)
+    with pytest.raises(sft.SftError):
+        ens.set_class_tile(len(gids), 0)
+
+
 def test_full_size_flux_balanced_assimilation_f64():
     """Flux-balanced mu^4 assimilation (eqs. data_assim_deltab, fluxbal) on
     the ensemble workload's 512 x 1024 grid, where the FP64 sums of the
