@@ -220,6 +220,30 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
 #pragma unroll
         for (int u = 0; u < NL; ++u) sv[u] = sin[u] ? sv[u] : T(0);
     }
+    // attenuated flow: the tile's face velocities, loaded with its cells
+    // (faces outside 0..nt take no part in any window; the pole faces keep
+    // the static flow's value)
+    constexpr int NVP = ATT ? (ATY * AVW + 255) / 256 : 1, NVT = ATT ? (AVH * ATX + 255) / 256 : 1;
+    T vpv[NVP], vtv[NVT];
+    if constexpr (ATT) {
+#pragma unroll
+        for (int u = 0; u < NVP; ++u) {
+            const int idx = min(tid + 256 * u, ATY * AVW - 1);
+            const int tj = idx / AVW, q = idx - (idx / AVW) * AVW;
+            const int j = j0 + tj;
+            const T v = vphf[base + (size_t)min(j, nt - 1) * np + wrap_col(k0 - 4 + q, np)];
+            vpv[u] = j < nt ? v : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < NVT; ++u) {
+            const int idx = min(tid + 256 * u, AVH * ATX - 1);
+            const int q = idx / ATX, c = idx - (idx / ATX) * ATX;
+            const int f = j0 - 4 + q;
+            const T vf = vthf[base + (size_t)min(max(f, 1), nt - 1) * np + wrap_col(k0 + c, np)];
+            const T vs = rw[min(max(f, 0), nt)].vth;
+            vtv[u] = (f == 0 || f == nt) ? vs : ((f > 0 && f < nt) ? vf : T(0));
+        }
+    }
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
         const int idx = tid + 256 * u;
@@ -257,22 +281,15 @@ __global__ __launch_bounds__(256) void adv_stage_kernel(
         }
     }
     if constexpr (ATT) {
-        for (int idx = tid; idx < ATY * AVW; idx += 256) {
-            const int tj = idx / AVW, q = idx - (idx / AVW) * AVW;
-            const int j = j0 + tj;
-            T v = T(0);
-            if (j < nt) v = vphf[base + (size_t)j * np + wrap_col(k0 - 4 + q, np)];
-            al.vp[tj][q] = v;
+#pragma unroll
+        for (int u = 0; u < NVP; ++u) {
+            const int idx = tid + 256 * u;
+            if (idx < ATY * AVW) al.vp[idx / AVW][idx - (idx / AVW) * AVW] = vpv[u];
         }
-        // faces outside 0..nt take no part in any window; the pole faces
-        // keep the static flow's value
-        for (int idx = tid; idx < AVH * ATX; idx += 256) {
-            const int q = idx / ATX, c = idx - (idx / ATX) * ATX;
-            const int f = j0 - 4 + q;
-            T v = T(0);
-            if (f == 0 || f == nt) v = rw[f].vth;
-            else if (f > 0 && f < nt) v = vthf[base + (size_t)f * np + wrap_col(k0 + c, np)];
-            al.vt[q][c] = v;
+#pragma unroll
+        for (int u = 0; u < NVT; ++u) {
+            const int idx = tid + 256 * u;
+            if (idx < AVH * ATX) al.vt[idx / ATX][idx - (idx / ATX) * ATX] = vtv[u];
         }
     }
     __syncthreads();
